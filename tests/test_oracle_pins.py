@@ -1,0 +1,457 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these checks re-types an oracle formula: each compares the oracle with
+a value printed in the paper, a published generator's output, an exact
+enumeration, a closed form derived from Lemma 1, a special case that reduces
+to an ordinary matrix product, or a statistical property with a bound.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+import synthetic
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# Hash: SplitMix64 reading of the random choices
+# ---------------------------------------------------------------------------
+
+def test_splitmix64_published_stream():
+    # First three outputs of SplitMix64 seeded with 0, as produced by the
+    # public-domain reference generator (Steele, Lea & Flood 2014; the
+    # splitmix64.c of Vigna): widely reproduced test values.
+    expect = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert [oracle.splitmix64_nth(0, j) for j in range(3)] == expect
+
+
+def test_hash_counter_layout():
+    # block index lives above bit 40 of the counter, the column index below.
+    assert oracle.hash_word(7, 0, 5) == oracle.splitmix64_nth(7, 5)
+    assert oracle.hash_word(7, 3, 5) == oracle.splitmix64_nth(7, (3 << 40) | 5)
+
+
+@pytest.mark.parametrize("b", [256, 1000, 7])
+def test_hash_buckets_uniform(b):
+    # Algorithm "Calculating Count-sketch": buckets uniform on [1, b].
+    n = 1 << 16
+    h, _ = oracle.hash_tables(1234, 3, n, b)
+    assert h.min() >= 0 and h.max() < b
+    for blk in range(3):
+        counts = np.bincount(h[blk], minlength=b)
+        chi2 = float(np.sum((counts - n / b) ** 2 / (n / b)))
+        assert stats.chi2.sf(chi2, b - 1) > 1e-4, (blk, chi2)
+
+
+def test_hash_signs_fair():
+    # Algorithm "Calculating Count-sketch": each sign -1 with probability 1/2.
+    n = 1 << 16
+    _, s = oracle.hash_tables(99, 4, n, 64)
+    for blk in range(4):
+        mean = float(s[blk].astype(np.float64).mean())
+        assert abs(mean) < 5.0 / np.sqrt(n)
+
+
+def test_hash_blocks_independent():
+    # Lemma 2 needs independent blocks: cross-block bucket collisions occur at
+    # rate 1/b and signs agree at rate 1/2.
+    n, b = 1 << 16, 64
+    h, s = oracle.hash_tables(5, 2, n, b)
+    p = 1.0 / b
+    rate = float(np.mean(h[0] == h[1]))
+    assert abs(rate - p) < 5 * np.sqrt(p * (1 - p) / n)
+    agree = float(np.mean(s[0] == s[1]))
+    assert abs(agree - 0.5) < 5 * np.sqrt(0.25 / n)
+    # the bucket and sign of one (block, index) are independent too
+    rate_pos = float(np.mean(h[0][s[0] > 0] < b // 2))
+    assert abs(rate_pos - 0.5) < 5 * np.sqrt(0.25 / (n / 2))
+
+
+def test_hash_depends_on_seed():
+    h0, s0 = oracle.hash_tables(1, 1, 4096, 128)
+    h1, s1 = oracle.hash_tables(2, 1, 4096, 128)
+    assert np.mean(h0 == h1) < 0.05
+
+
+# ---------------------------------------------------------------------------
+# The paper's worked example (Section 4.1, Eq. (count_sketch_example))
+# ---------------------------------------------------------------------------
+
+def _load_example():
+    sections, cur = {}, None
+    with open(os.path.join(GOLDEN, "count_sketch_example.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("["):
+                cur = line.strip("[]")
+                sections[cur] = []
+            else:
+                sections[cur].append(line)
+    ST = np.array([[float(v) for v in row.split()] for row in sections["printed_ST"]])
+    buckets = {}
+    for row in sections["buckets"]:
+        key, cols = row.split(":")
+        buckets[int(key)] = [int(c) for c in cols.split()]
+    strag = {}
+    for row in sections["straggler"]:
+        key, cols = row.split(":")
+        strag[int(key)] = [int(c) for c in cols.split()]
+    return ST, buckets, strag
+
+
+def _example_tables():
+    ST, buckets, _ = _load_example()
+    n, b = ST.shape[1], ST.shape[0]
+    h = np.full((1, n), -1, dtype=np.int32)
+    for bucket, cols in buckets.items():
+        for c in cols:
+            h[0, c - 1] = bucket - 1          # 1-based in the paper, 0-based here
+    assert np.all(h >= 0)
+    sigma = np.array([[int(ST[h[0, k], k]) for k in range(n)]], dtype=np.int8)
+    return ST, h, sigma, b
+
+
+def test_example_prose_matches_printed_matrix():
+    ST, buckets, _ = _load_example()
+    assert ST.shape == (3, 9)
+    # every column of S_c^T holds exactly one +-1: one bucket, one sign
+    assert np.all(np.sum(ST != 0, axis=0) == 1)
+    assert set(np.unique(ST)) <= {-1.0, 0.0, 1.0}
+    for bucket, cols in buckets.items():
+        nz = sorted(int(c) + 1 for c in np.flatnonzero(ST[bucket - 1]))
+        assert nz == sorted(cols)
+
+
+def test_example_sketch_of_identity_is_printed_matrix():
+    ST, h, sigma, b = _example_tables()
+    I = np.eye(9)
+    np.testing.assert_array_equal(oracle.sketch_cols(I, h, sigma, b), ST.T)
+    np.testing.assert_array_equal(oracle.sketch_rows(I, h, sigma, b), ST)
+
+
+def test_example_sketch_equals_product_with_printed_matrix():
+    ST, h, sigma, b = _example_tables()
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((5, 9))
+    B = rng.standard_normal((9, 4))
+    np.testing.assert_allclose(oracle.sketch_cols(A, h, sigma, b), A @ ST.T, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(oracle.sketch_rows(B, h, sigma, b), ST @ B, rtol=0, atol=1e-14)
+
+
+def test_example_straggler_loses_exactly_its_columns():
+    # Losing output column 3 of the sketch discards input columns 3, 8, 9 and
+    # nothing else.
+    _, _, strag = _load_example()
+    _, h, sigma, b = _example_tables()
+    lost = [c - 1 for c in strag[3]]
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((6, 9))
+    A2 = A.copy()
+    A2[:, lost] = rng.standard_normal((6, len(lost)))   # change only the lost columns
+    S1 = oracle.sketch_cols(A, h, sigma, b)
+    S2 = oracle.sketch_cols(A2, h, sigma, b)
+    np.testing.assert_array_equal(S1[:, :2], S2[:, :2])  # buckets 1 and 2 unaffected
+    assert np.all(S1[:, 2] != S2[:, 2])
+    A3 = A.copy()
+    keep_cols = [k for k in range(9) if k not in lost]
+    A3[:, keep_cols] = 0.0
+    assert np.all(oracle.sketch_cols(A3, h, sigma, b)[:, :2] == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Sketch as a matrix (Eq. (sketch_matrix)); special cases of the product
+# ---------------------------------------------------------------------------
+
+def test_sketch_of_identity_is_the_sketch_matrix():
+    n, b, nblk = 50, 8, 3
+    h, s = oracle.hash_tables(11, nblk, n, b)
+    S = oracle.literal_blocks(h, s, b)
+    # each row of every block holds one +-1
+    assert np.all(np.sum(S != 0, axis=1) == nblk)
+    np.testing.assert_array_equal(oracle.sketch_cols(np.eye(n), h, s, b), S)
+    np.testing.assert_array_equal(oracle.sketch_rows(np.eye(n), h, s, b), S.T)
+
+
+def test_sketch_is_linear():
+    n, b, nblk = 40, 8, 2
+    h, s = oracle.hash_tables(12, nblk, n, b)
+    rng = np.random.default_rng(5)
+    X, Y = rng.standard_normal((7, n)), rng.standard_normal((7, n))
+    lhs = oracle.sketch_cols(2.0 * X - 3.0 * Y, h, s, b)
+    rhs = 2.0 * oracle.sketch_cols(X, h, s, b) - 3.0 * oracle.sketch_cols(Y, h, s, b)
+    np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-12)
+    P, Q = rng.standard_normal((n, 5)), rng.standard_normal((n, 5))
+    lhs = oracle.sketch_rows(P + 0.5 * Q, h, s, b)
+    rhs = oracle.sketch_rows(P, h, s, b) + 0.5 * oracle.sketch_rows(Q, h, s, b)
+    np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("N,e", [(1, 0), (3, 1)])
+def test_exact_product_when_blocks_are_signed_permutations(N, e):
+    # b = n and every h_i a permutation: S_i S_i^T = I, so C = AB exactly.
+    m, n, l = 9, 32, 7
+    rng = np.random.default_rng(6)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    h = np.stack([rng.permutation(n) for _ in range(N + e)]).astype(np.int32)
+    s = rng.choice(np.array([-1, 1], dtype=np.int8), size=(N + e, n))
+    keep = oracle.default_keep(N, e)
+    C = oracle.sketched_matmul(A, B, n, N, e, keep=keep, h=h, sigma=s)
+    np.testing.assert_allclose(C, A @ B, rtol=1e-12, atol=1e-12)
+
+
+def test_b_one_gives_rank_one_sum():
+    # b = 1: every index shares bucket 0, so A S_i = A sigma_i and
+    # S_i^T B = sigma_i^T B, and C = (1/K) sum_i (A sigma_i)(sigma_i^T B).
+    m, n, l, N, e = 6, 20, 5, 3, 1
+    rng = np.random.default_rng(7)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    h, s = oracle.hash_tables(21, N + e, n, 1)
+    assert np.all(h == 0)
+    keep = synthetic.random_keep(N, e, 3)
+    C = oracle.sketched_matmul(A, B, 1, N, e, keep=keep, h=h, sigma=s)
+    ref = np.zeros((m, l))
+    for i in np.flatnonzero(keep):
+        sv = s[i].astype(np.float64)
+        ref += np.outer(A @ sv, sv @ B)
+    ref /= keep.sum()
+    np.testing.assert_allclose(C, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_product_is_mean_of_single_block_products():
+    m, n, l, b, N, e = 8, 64, 6, 8, 3, 2
+    rng = np.random.default_rng(8)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    h, s = oracle.hash_tables(31, N + e, n, b)
+    keep = np.array([1, 0, 1, 1, 0], dtype=np.uint8)
+    C = oracle.sketched_matmul(A, B, b, N, e, keep=keep, h=h, sigma=s)
+    parts = []
+    for i in np.flatnonzero(keep):
+        one = np.zeros(N + e, dtype=np.uint8)
+        one[i] = 1
+        parts.append(oracle.sketched_matmul(A, B, b, N, e, keep=one, h=h, sigma=s))
+    np.testing.assert_allclose(C, np.mean(parts, axis=0), rtol=1e-12, atol=1e-12)
+
+
+def test_oracle_matches_literal_dense_definition():
+    m, n, l, b, N, e = 10, 60, 7, 8, 4, 1
+    rng = np.random.default_rng(9)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    h, s = oracle.hash_tables(41, N + e, n, b)
+    keep = synthetic.random_keep(N, e, 41)
+    assert keep.sum() == N
+    C = oracle.sketched_matmul(A, B, b, N, e, keep=keep, h=h, sigma=s)
+    L = oracle.literal_product(A, B, h, s, b, N, keep)
+    np.testing.assert_allclose(C, L, rtol=1e-12, atol=1e-12)
+
+
+def test_sampled_entries_agree_with_full_product():
+    m, n, l, b, N, e = 12, 80, 9, 16, 3, 1
+    A, B = synthetic.gaussian_pair(m, n, l, 2, dtype=np.float32)
+    keep = synthetic.random_keep(N, e, 2)
+    C = oracle.sketched_matmul(A, B, b, N, e, seed=2, keep=keep)
+    rows = np.array([0, 3, 11, 5, 5])
+    cols = np.array([0, 8, 2, 2, 7])
+    v = oracle.sampled_entries(A, B, rows, cols, b, N, e, seed=2, keep=keep)
+    np.testing.assert_allclose(v, C[rows, cols], rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Lemma 1 / Lemma 2 by exhaustive enumeration of every sketch
+# ---------------------------------------------------------------------------
+
+def _all_single_block_tables(n, b):
+    hs, ss = [], []
+    for hv in itertools.product(range(b), repeat=n):
+        for sv in itertools.product((-1, 1), repeat=n):
+            hs.append(hv)
+            ss.append(sv)
+    return np.array(hs, dtype=np.int32), np.array(ss, dtype=np.int8)
+
+
+def _lemma1_variance(x, y, b):
+    # Lemma 1: Var = (1/b) (sum_{j != l} x_j^2 y_l^2 + sum_{j != l} x_j y_j x_l y_l)
+    n = len(x)
+    t1 = sum(x[j] ** 2 * y[l] ** 2 for j in range(n) for l in range(n) if j != l)
+    t2 = sum(x[j] * y[j] * x[l] * y[l] for j in range(n) for l in range(n) if j != l)
+    return (t1 + t2) / b
+
+
+@pytest.mark.parametrize("n,b", [(4, 2), (5, 3), (3, 4)])
+def test_lemma1_exact_mean_and_variance(n, b):
+    rng = np.random.default_rng(10 + n)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    h, s = _all_single_block_tables(n, b)
+    cnt = h.shape[0]
+    xa = oracle.sketch_cols(x[None, :], h, s, b).reshape(cnt, b)
+    yb = oracle.sketch_rows(y[:, None], h, s, b).reshape(cnt, b)
+    v = np.sum(xa * yb, axis=1)                     # x^T S_c S_c^T y per sketch
+    assert abs(v.mean() - x @ y) < 1e-12 * (1 + abs(x @ y))
+    var = float(np.mean((v - x @ y) ** 2))
+    assert var == pytest.approx(_lemma1_variance(x, y, b), rel=1e-10)
+    # and the two upper bounds stated with it
+    assert var <= ((x @ y) ** 2 + (x @ x) * (y @ y)) / b + 1e-12
+    assert var <= 2.0 / b * (x @ x) * (y @ y) + 1e-12
+
+
+def test_lemma2_exact_mean_and_variance_two_blocks():
+    # S = N^{-1/2}(S_1, S_2) with independent blocks: mean x^T y, variance
+    # Var_1 / N, within the 2/d bound (d = N b).
+    n, b, N = 3, 2, 2
+    rng = np.random.default_rng(20)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    h1, s1 = _all_single_block_tables(n, b)
+    vals = []
+    for i in range(h1.shape[0]):
+        for j in range(h1.shape[0]):
+            h = np.stack([h1[i], h1[j]])
+            s = np.stack([s1[i], s1[j]])
+            vals.append(oracle.sketched_matmul(x[None, :], y[:, None], b, N, 0, h=h, sigma=s)[0, 0])
+    vals = np.array(vals)
+    assert abs(vals.mean() - x @ y) < 1e-12
+    var = float(np.mean((vals - x @ y) ** 2))
+    assert var == pytest.approx(_lemma1_variance(x, y, b) / N, rel=1e-10)
+    assert var <= 2.0 / (N * b) * (x @ x) * (y @ y)
+
+
+def _second_moment_closed_form(A, B, b, K):
+    """E||A S S^T B - AB||_F^2 for K kept independent count-sketch blocks of
+    width b (sum of Lemma 1's variance over all entries of AB, divided by K):
+    (||A||^2 ||B||^2 + ||AB||^2 - 2 sum_k ||A[:,k]||^2 ||B[k,:]||^2) / (K b)."""
+    A = np.asarray(A, np.float64)
+    B = np.asarray(B, np.float64)
+    AB = A @ B
+    cross = float(np.sum(np.sum(A * A, axis=0) * np.sum(B * B, axis=1)))
+    return (oracle.frob2(A) * oracle.frob2(B) + oracle.frob2(AB) - 2.0 * cross) / (K * b)
+
+
+def test_second_moment_exact_enumeration():
+    m, n, l, b = 3, 3, 2, 2
+    rng = np.random.default_rng(21)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    AB = A @ B
+    h1, s1 = _all_single_block_tables(n, b)
+    errs = []
+    for i in range(h1.shape[0]):
+        C = oracle.sketched_matmul(A, B, b, 1, 0, h=h1[i:i + 1], sigma=s1[i:i + 1])
+        errs.append(oracle.frob2(C - AB))
+    assert float(np.mean(errs)) == pytest.approx(_second_moment_closed_form(A, B, b, 1), rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Statistical behaviour over hash seeds (Lemma 2, Lemma 3, main theorem)
+# ---------------------------------------------------------------------------
+
+def _seed_runs(A, B, b, N, e, T, keep=None, seed0=1000):
+    return [oracle.sketched_matmul(A, B, b, N, e, seed=seed0 + t, keep=keep) for t in range(T)]
+
+
+def test_second_moment_monte_carlo_matches_closed_form():
+    m, n, l, b, N, e = 8, 64, 6, 4, 2, 1
+    rng = np.random.default_rng(22)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    keep = oracle.default_keep(N, e)
+    Cs = _seed_runs(A, B, b, N, e, 600, keep=keep)
+    AB = A @ B
+    mc = float(np.mean([oracle.frob2(C - AB) for C in Cs]))
+    assert mc == pytest.approx(_second_moment_closed_form(A, B, b, N), rel=0.12)
+
+
+def test_unbiased_mean_over_seeds():
+    # Lemma 2: E[A S S^T B] = AB; E||mean_T - AB||^2 = E1 / T exactly.
+    m, n, l, b, N, e = 8, 64, 6, 4, 2, 1
+    rng = np.random.default_rng(23)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    T = 400
+    Cs = _seed_runs(A, B, b, N, e, T, keep=oracle.default_keep(N, e))
+    E1 = _second_moment_closed_form(A, B, b, N)
+    dev = oracle.frob2(np.mean(Cs, axis=0) - A @ B)
+    assert dev <= 3.0 * E1 / T
+
+
+def test_extra_kept_blocks_need_one_over_k():
+    # K = N + e kept blocks: weight 1/K keeps the product unbiased; weight 1/N
+    # would inflate it by K/N, which this check would see.
+    m, n, l, b, N, e = 8, 64, 6, 4, 2, 1
+    rng = np.random.default_rng(24)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    T = 400
+    keep = np.ones(N + e, dtype=np.uint8)
+    Cs = _seed_runs(A, B, b, N, e, T, keep=keep)
+    AB = A @ B
+    E1 = _second_moment_closed_form(A, B, b, N + e)
+    mean = np.mean(Cs, axis=0)
+    assert oracle.frob2(mean - AB) <= 3.0 * E1 / T
+    wrong = mean * (N + e) / N
+    assert oracle.frob2(wrong - AB) > 10.0 * E1 / T
+
+
+def test_lemma3_bound_holds():
+    # E||AB - A S S^T B||^2 <= (2/d) ||A||^2 ||B||^2, d = N b.
+    m, n, l, b, N, e = 10, 128, 8, 8, 3, 1
+    rng = np.random.default_rng(25)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    bound = 2.0 / (N * b) * oracle.frob2(A) * oracle.frob2(B)
+    assert _second_moment_closed_form(A, B, b, N) <= bound
+    Cs = _seed_runs(A, B, b, N, e, 200, keep=oracle.default_keep(N, e))
+    mc = float(np.mean([oracle.frob2(C - A @ B) for C in Cs]))
+    assert mc <= bound
+
+
+def test_main_theorem_tail():
+    # d = 2/(eps theta) gives P(err^2 > eps ||A||^2 ||B||^2) <= theta, with e
+    # blocks ignored.
+    m, n, l, b, N, e = 12, 200, 10, 8, 4, 2
+    d = N * b
+    theta = 0.25
+    eps = 2.0 / (d * theta)
+    rng = np.random.default_rng(26)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    T = 300
+    thr = eps * oracle.frob2(A) * oracle.frob2(B)
+    AB = A @ B
+    exceed = 0
+    for t in range(T):
+        keep = synthetic.random_keep(N, e, 500 + t)
+        C = oracle.sketched_matmul(A, B, b, N, e, seed=500 + t, keep=keep)
+        exceed += oracle.frob2(C - AB) > thr
+    assert exceed / T <= theta + 3 * np.sqrt(theta * (1 - theta) / T)
+
+
+def test_graceful_degradation_more_losses_more_error():
+    # Dropping more blocks than provisioned still gives an unbiased product
+    # with larger error (section 4.1, "graceful degradation").
+    m, n, l, b, N, e = 8, 128, 6, 8, 4, 0
+    rng = np.random.default_rng(27)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    AB = A @ B
+    err = {}
+    for K in (4, 2, 1):
+        keep = np.zeros(N, dtype=np.uint8)
+        keep[:K] = 1
+        errs = [oracle.frob2(oracle.sketched_matmul(A, B, b, N, e, seed=700 + t, keep=keep) - AB)
+                for t in range(150)]
+        err[K] = float(np.mean(errs))
+        assert err[K] == pytest.approx(_second_moment_closed_form(A, B, b, K), rel=0.25)
+    assert err[4] < err[2] < err[1]
+
+
+def test_config1_error_level():
+    # 256x4096 by 4096x256 Gaussian, b=256, N=4, e=1 with one random block
+    # dropped: one instance's error sits near the closed-form expectation.
+    m, n, l, b, N, e, seed = 256, 4096, 256, 256, 4, 1, 1
+    A, B = synthetic.gaussian_pair(m, n, l, seed)
+    keep = synthetic.random_keep(N, e, seed)
+    C = oracle.sketched_matmul(A, B, b, N, e, seed=seed, keep=keep)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    AB = A64 @ B64
+    err2 = oracle.frob2(C - AB)
+    expect = _second_moment_closed_form(A64, B64, b, N)
+    assert err2 == pytest.approx(expect, rel=0.2)
+    assert err2 <= 2.0 / (N * b) * oracle.frob2(A64) * oracle.frob2(B64)
