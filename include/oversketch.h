@@ -1,0 +1,186 @@
+/*
+ * oversketch.h -- C ABI of liboversketch.so, an MI355X (gfx950) library for
+ * OverSketch's approximate matrix product  C ~= A * S * S^T * B
+ * (Gupta, Wang, Courtade, Ramchandran, "OverSketch: Approximate Matrix
+ * Multiplication for the Cloud").
+ *
+ * The method (Section 4.1):
+ *   - A is m x n, B is n x l.
+ *   - S = N^{-1/2} (S_1, ..., S_{N+e}) (Eq. (sketch_matrix)) is a row of N+e
+ *     independent count-sketch blocks S_i, each n x b: every index k in
+ *     [0, n) is sent to one bucket h_i(k) in [0, b) with a sign
+ *     sigma_i(k) = +-1 (Algorithm "Calculating Count-sketch of a matrix A").
+ *   - A_tilde = A S and B_tilde = S^T B are formed block by block (Algorithm
+ *     "Over sketching A in parallel"), and the product is assembled from any
+ *     N of the N+e blocks (Algorithm "OverSketch", termination step).  On one
+ *     GPU a host keep-mask stands in for the blocks that straggled.
+ *
+ * Readings of the paper used by this library:
+ *   - Normalisation: the result is (1/K) * sum over kept blocks i of
+ *     (A S_i)(S_i^T B), K = number of kept blocks.  This equals the paper's
+ *     N^{-1/2} * N^{-1/2} whenever K = N and stays unbiased when K != N.
+ *   - Random source: bucket and sign of (block i, index k) come from
+ *     SplitMix64 (Steele, Lea & Flood 2014) evaluated at state
+ *     seed + (ctr + 1) * 0x9E3779B97F4A7C15 with ctr = (i << 40) | k:
+ *     h = ((word >> 32) * b) >> 32, sigma = (word & 1) ? -1 : +1.
+ *     Explicit buckets and signs may be supplied instead (os_sketch.h/sigma).
+ *   - Indices are 0-based.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are FP32, row-major, with a leading dimension ("ld", in
+ *     elements) >= the number of columns.  Matrices sketched along their
+ *     rows' contiguous dimension (A; X of os_sketch_cols; B when column-major)
+ *     and every sketch matrix need a 16-byte aligned base pointer and a
+ *     leading dimension that is a multiple of 4, else OS_EALIGN.  A row-major
+ *     B (X of os_sketch_rows) and the product C need only 4-byte alignment
+ *     and any leading dimension >= their column count.  The dimension that is not sketched (rows of A, columns of B)
+ *     is limited to OS_MAX_ROWS, the sketched one (n) to 2^40 - 1.
+ *   - A launch that can be issued always is: an invalid shape is reported
+ *     as OS_EINVAL before anything is enqueued.
+ *   - Device pointers are HIP device memory owned by the caller; the library
+ *     never allocates device memory and never retains a pointer past return.
+ *     Host pointers (keep masks) are read before the call returns.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     on it and the call returns; outputs are valid once the stream has
+ *     completed.  Validation happens before anything is enqueued: on any
+ *     error nothing is launched and the outputs are untouched.
+ *   - No C++ exception crosses this interface.  Entry points are thread-safe
+ *     (no mutable global state apart from a once-initialised device query).
+ *
+ * Sketched-matrix layout ("block-padded"): a sketch with `nst` stored blocks
+ * of width b is a row-major matrix with nst * bp columns, bp =
+ * os_block_stride(b) = b rounded up to a multiple of 32.  Stored block j
+ * occupies columns [j*bp, j*bp + b); columns [j*bp + b, (j+1)*bp) are written
+ * as zero.  With kept_only = 0 every one of the N+e blocks is stored (block i
+ * at position i); with kept_only = 1 only the kept blocks are stored, in
+ * ascending block order (the "straggler-resilient sketching" remark of
+ * Section 4.1: blocks dropped at sketch time are treated as stragglers).
+ */
+#ifndef OVERSKETCH_H
+#define OVERSKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int os_status;
+
+#define OS_OK          0   /* success */
+#define OS_EINVAL     -1   /* a size, count or parameter outside its range */
+#define OS_ENULL      -2   /* a required pointer is NULL */
+#define OS_EALIGN     -3   /* a pointer is not 16-byte aligned or an ld not a multiple of 4 */
+#define OS_EWORKSPACE -4   /* workspace NULL, misaligned (256 B) or smaller than required */
+#define OS_EHIP       -5   /* the HIP runtime reported an error (os_last_hip_error) */
+#define OS_ENOKEEP    -6   /* the keep mask keeps no block */
+
+#define OS_MAX_BLOCKS 256      /* upper limit on N + e */
+#define OS_MAX_B      8192     /* upper limit on the block width b */
+#define OS_MAX_ROWS   (1LL << 24) /* upper limit on m, l and the sketched operands' row/column counts */
+
+/* Sketch description.  b in [1, OS_MAX_B], N >= 1, e >= 0, N + e <=
+ * OS_MAX_BLOCKS.  When h is non-NULL, sigma must be non-NULL too and both
+ * are DEVICE arrays [N+e][n] (row i = block i) holding explicit buckets in
+ * [0, b) and signs in {-1, +1}; the seed is then ignored.  Explicit values
+ * are not range-checked on the device: out-of-range buckets are clamped into
+ * [0, b) and any sign < 0 counts as -1, so a bad table gives a wrong result,
+ * never an out-of-bounds access. */
+typedef struct os_sketch {
+    uint64_t seed;
+    int32_t b;
+    int32_t N;
+    int32_t e;
+    const int32_t* h;
+    const int8_t* sigma;
+} os_sketch;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* os_status_string(os_status status);
+
+/* hipError_t of the most recent OS_EHIP returned on the calling thread
+ * (0 if none). */
+int os_last_hip_error(void);
+
+/* Column stride of one stored block in a sketched matrix:
+ * b rounded up to a multiple of 32 (0 if b < 1). */
+int32_t os_block_stride(int32_t b);
+
+/* Bytes of the packed hash table for an n-long sketched dimension:
+ * (N+e) * round_up(n, 4) * 4.  0 on invalid arguments. */
+size_t os_table_bytes(const os_sketch* sk, int64_t n);
+
+/* Step "hash" of the path -- the random choices of Algorithm "Calculating
+ * Count-sketch of a matrix A" for all N+e blocks, materialised:
+ * h_out[i*n + k] = bucket h_i(k) in [0, b), sigma_out[i*n + k] = sigma_i(k).
+ * h_out: DEVICE int32 [(N+e) * n]; sigma_out: DEVICE int8 [(N+e) * n].
+ * n in [1, 2^40).  With explicit tables in `sk` the (clamped) values are
+ * copied. */
+os_status os_hash_fill(const os_sketch* sk, int64_t n, int32_t* h_out, int8_t* sigma_out,
+                       void* stream);
+
+/* Packed hash table consumed by the sketch kernels: table[i*nt + k] for
+ * block i < N+e, k < n, nt = round_up(n, 4); entry = h_i(k) | (sigma_i(k) < 0) << 31,
+ * padding entries (n <= k < nt) are 0.  table: DEVICE, os_table_bytes(sk, n)
+ * bytes, 16-byte aligned. */
+os_status os_sketch_table(const os_sketch* sk, int64_t n, uint32_t* table, void* stream);
+
+/* Step "sketch A's columns" (Algorithm "Over sketching A in parallel" with
+ * Algorithm "Calculating Count-sketch" per block): for a row-major X
+ * (rows x n, ld ldx) and every stored block j (block index s_j),
+ *   out[r][j*bp + c] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[r][k],
+ * i.e. out = [X S_{s_0}, X S_{s_1}, ...] without the N^{-1/2} factor.
+ * table: from os_sketch_table for the same sk and n.  keep_host: HOST uint8
+ * [N+e] (nonzero = kept) or NULL (= blocks [0, N) kept); it only matters when
+ * kept_only != 0.  out: DEVICE rows x ldo, ldo >= nst*bp.  The same routine
+ * sketches the rows of a column-major matrix (pass its transpose). */
+os_status os_sketch_cols(const os_sketch* sk, const uint32_t* table, const float* X,
+                         int64_t rows, int64_t n, int64_t ldx, const uint8_t* keep_host,
+                         int kept_only, float* out, int64_t ldo, void* stream);
+
+/* Step "sketch B's rows" (S^T B, the same sketch applied from the left,
+ * Section 4): for a row-major X (n x cols, ld ldx) and every stored block j,
+ *   outT[q][j*bp + c] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[k][q],
+ * i.e. outT = (S_{s_j}^T X)^T stored as a cols x (nst*bp) row-major matrix
+ * (the inner dimension contiguous, as the block product consumes it).
+ * Other arguments as in os_sketch_cols; outT: DEVICE cols x ldo. */
+os_status os_sketch_rows(const os_sketch* sk, const uint32_t* table, const float* X,
+                         int64_t n, int64_t cols, int64_t ldx, const uint8_t* keep_host,
+                         int kept_only, float* outT, int64_t ldo, void* stream);
+
+/* Step "grouped product over the kept blocks" (Algorithm "OverSketch":
+ * computation phase plus reduction phase, Fig. (bMM)):
+ *   C = (1/K) * sum_{j : keep[j]} At_j * Bt_j^T,
+ * At: DEVICE m x (nst*bp) sketch of A (ld ldat), Bt: DEVICE l x (nst*bp)
+ * transposed sketch of B (ld ldbt), both block-padded with nst stored blocks
+ * of width b; keep_host: HOST uint8 [nst] over the STORED blocks, or NULL
+ * (= all stored blocks kept); K = number kept.  C: DEVICE m x l (ld ldc),
+ * overwritten.  FP32 inputs, FP32 MFMA accumulation. */
+os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
+                       int64_t m, int64_t l, int32_t b, int32_t nst,
+                       const uint8_t* keep_host, float* C, int64_t ldc, void* stream);
+
+/* Workspace bytes os_matmul needs: packed table + sketch of A + transposed
+ * sketch of B (each region 256-byte aligned).  0 on invalid arguments. */
+size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
+                                 int kept_only);
+
+/* The whole path: C ~= (1/K) * sum_{kept i} (A S_i)(S_i^T B)
+ * (Algorithm "OverSketch" on one GPU).  A: DEVICE m x n row-major (lda).
+ * B: DEVICE n x l; b_col_major = 0 -> row-major with ld ldb >= l;
+ * b_col_major = 1 -> column-major, element (k, q) at B[q*ldb + k], ldb >= n.
+ * keep_host: HOST uint8 [N+e] or NULL (= blocks [0, N) kept).  kept_only != 0
+ * skips the dropped blocks already in the sketch step.  C: DEVICE m x l
+ * (ldc).  workspace: DEVICE, 256-byte aligned, >= os_matmul_workspace_bytes.
+ * Enqueues: table, sketch of A, sketch of B, block product. */
+os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const float* B,
+                    int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
+                    const uint8_t* keep_host, int kept_only, float* C, int64_t ldc,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OVERSKETCH_H */

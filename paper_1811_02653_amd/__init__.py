@@ -1,0 +1,303 @@
+"""MI355X (gfx950) OverSketch: the sketched matrix product C ~= A S S^T B.
+
+Python binding of ``liboversketch.so`` (see ``include/oversketch.h``).  This
+module only marshals arguments: torch tensors supply device pointers and the
+current HIP stream, NumPy arrays supply host keep-masks, and every step of the
+computation runs in the library's HIP kernels.  If the library is not built,
+every call raises ``OversketchError``; there is no fallback path.
+
+Build with ``python -m paper_1811_02653_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "OversketchError", "lib", "block_stride", "hash_fill", "sketch_table", "sketch_cols",
+    "sketch_rows", "gemm_kept", "matmul", "workspace_bytes", "stored_count",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboversketch.so")
+
+OS_OK = 0
+OS_MAX_BLOCKS = 256
+OS_MAX_B = 8192
+
+
+class OversketchError(RuntimeError):
+    """Raised for a non-OS_OK status or when the HIP library is missing."""
+
+    def __init__(self, msg, status=None):
+        super().__init__(msg)
+        self.status = status
+
+
+class _Sketch(ctypes.Structure):
+    _fields_ = [
+        ("seed", ctypes.c_uint64),
+        ("b", ctypes.c_int32),
+        ("N", ctypes.c_int32),
+        ("e", ctypes.c_int32),
+        ("h", ctypes.c_void_p),
+        ("sigma", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liboversketch.so (raises OversketchError if not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OversketchError("liboversketch.so is not built (python -m paper_1811_02653_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, i32, vp, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+    sk = ctypes.POINTER(_Sketch)
+    L.os_status_string.restype = ctypes.c_char_p
+    L.os_status_string.argtypes = [ctypes.c_int]
+    L.os_last_hip_error.restype = ctypes.c_int
+    L.os_last_hip_error.argtypes = []
+    L.os_block_stride.restype = i32
+    L.os_block_stride.argtypes = [i32]
+    L.os_table_bytes.restype = sz
+    L.os_table_bytes.argtypes = [sk, i64]
+    L.os_hash_fill.restype = ctypes.c_int
+    L.os_hash_fill.argtypes = [sk, i64, vp, vp, vp]
+    L.os_sketch_table.restype = ctypes.c_int
+    L.os_sketch_table.argtypes = [sk, i64, vp, vp]
+    L.os_sketch_cols.restype = ctypes.c_int
+    L.os_sketch_cols.argtypes = [sk, vp, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
+    L.os_sketch_rows.restype = ctypes.c_int
+    L.os_sketch_rows.argtypes = [sk, vp, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
+    L.os_gemm_kept.restype = ctypes.c_int
+    L.os_gemm_kept.argtypes = [vp, i64, vp, i64, i64, i64, i32, i32, vp, vp, i64, vp]
+    L.os_matmul_workspace_bytes.restype = sz
+    L.os_matmul_workspace_bytes.argtypes = [sk, i64, i64, i64, ctypes.c_int]
+    L.os_matmul.restype = ctypes.c_int
+    L.os_matmul.argtypes = [sk, vp, i64, vp, i64, ctypes.c_int, i64, i64, i64, vp, ctypes.c_int,
+                            vp, i64, vp, sz, vp]
+    _lib = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != OS_OK:
+        L = lib()
+        msg = L.os_status_string(status).decode()
+        if status == -5:
+            msg += " (hipError_t %d)" % L.os_last_hip_error()
+        raise OversketchError("%s: %s" % (what, msg), status)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require_cuda(t, name, dtype=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise OversketchError("%s must be a CUDA (HIP) tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise OversketchError("%s must be %s, got %s" % (name, dtype, t.dtype))
+
+
+def _row_major(t, name):
+    """(rows, cols, ld) of a 2-D tensor with unit column stride."""
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise OversketchError("%s must be 2-D with unit column stride" % name)
+    rows, cols = t.shape
+    # a single row never uses its leading dimension: report an aligned one
+    return rows, cols, t.stride(0) if rows > 1 else (cols + 3) // 4 * 4
+
+
+def _sketch(b, N, e, seed, h=None, sigma=None):
+    s = _Sketch()
+    s.seed = int(seed) & (2**64 - 1)
+    s.b, s.N, s.e = int(b), int(N), int(e)
+    s.h = None
+    s.sigma = None
+    if (h is None) != (sigma is None):
+        raise OversketchError("explicit h and sigma go together")
+    if h is not None:
+        torch = _torch()
+        _require_cuda(h, "h", torch.int32)
+        _require_cuda(sigma, "sigma", torch.int8)
+        if not (h.is_contiguous() and sigma.is_contiguous()) or h.shape != sigma.shape:
+            raise OversketchError("h and sigma must be contiguous [N+e, n] tensors")
+        if h.shape[0] != N + e:
+            raise OversketchError("h must have N+e rows")
+        s.h = h.data_ptr()
+        s.sigma = sigma.data_ptr()
+    return s
+
+
+def _mask(keep, count):
+    if keep is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(keep, dtype=np.uint8).reshape(-1))
+    if arr.size != count:
+        raise OversketchError("keep mask needs %d entries, got %d" % (count, arr.size))
+    return arr, arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def block_stride(b: int) -> int:
+    """Columns taken by one stored block (b rounded up to a multiple of 32)."""
+    return int(lib().os_block_stride(int(b)))
+
+
+def stored_count(N: int, e: int, keep=None, kept_only: bool = False) -> int:
+    """Blocks a sketch stores: N+e, or the number kept when kept_only."""
+    if not kept_only:
+        return N + e
+    if keep is None:
+        return N
+    return int(np.count_nonzero(np.asarray(keep)))
+
+
+def hash_fill(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None):
+    """Buckets (int32) and signs (int8), each [N+e, n], computed on the GPU."""
+    torch = _torch()
+    s = _sketch(b, N, e, seed, h, sigma)
+    h_out = torch.empty((N + e, n), dtype=torch.int32, device=device)
+    s_out = torch.empty((N + e, n), dtype=torch.int8, device=device)
+    _check(lib().os_hash_fill(ctypes.byref(s), n, _ptr(h_out), _ptr(s_out), _stream(stream)),
+           "os_hash_fill")
+    return h_out, s_out
+
+
+def sketch_table(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None):
+    """Packed hash table [N+e, round_up(n, 4)] as int32 (bit 31 = negative sign)."""
+    torch = _torch()
+    s = _sketch(b, N, e, seed, h, sigma)
+    nt = (n + 3) // 4 * 4
+    table = torch.empty((N + e, nt), dtype=torch.int32, device=device)
+    _check(lib().os_sketch_table(ctypes.byref(s), n, _ptr(table), _stream(stream)),
+           "os_sketch_table")
+    return table
+
+
+def sketch_cols(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, table=None,
+                out=None, stream=None):
+    """[X S_i ...] for the stored blocks: rows x (nst * block_stride(b))."""
+    torch = _torch()
+    _require_cuda(X, "X", torch.float32)
+    rows, n, ldx = _row_major(X, "X")
+    if table is None:
+        table = sketch_table(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
+    s = _sketch(b, N, e, seed, h, sigma)
+    width = stored_count(N, e, keep, kept_only) * block_stride(b)
+    if out is None:
+        out = torch.empty((rows, width), dtype=torch.float32, device=X.device)
+    _require_cuda(out, "out", torch.float32)
+    _, _, ldo = _row_major(out, "out")
+    _, pk = _mask(keep, N + e)
+    _check(lib().os_sketch_cols(ctypes.byref(s), _ptr(table), _ptr(X), rows, n, ldx, pk,
+                                int(bool(kept_only)), _ptr(out), ldo, _stream(stream)),
+           "os_sketch_cols")
+    return out
+
+
+def sketch_rows(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, table=None,
+                out=None, stream=None):
+    """(S_i^T X)^T for the stored blocks: cols x (nst * block_stride(b))."""
+    torch = _torch()
+    _require_cuda(X, "X", torch.float32)
+    n, cols, ldx = _row_major(X, "X")
+    if table is None:
+        table = sketch_table(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
+    s = _sketch(b, N, e, seed, h, sigma)
+    width = stored_count(N, e, keep, kept_only) * block_stride(b)
+    if out is None:
+        out = torch.empty((cols, width), dtype=torch.float32, device=X.device)
+    _require_cuda(out, "out", torch.float32)
+    _, _, ldo = _row_major(out, "out")
+    _, pk = _mask(keep, N + e)
+    _check(lib().os_sketch_rows(ctypes.byref(s), _ptr(table), _ptr(X), n, cols, ldx, pk,
+                                int(bool(kept_only)), _ptr(out), ldo, _stream(stream)),
+           "os_sketch_rows")
+    return out
+
+
+def gemm_kept(At, Bt, b, keep=None, out=None, stream=None):
+    """(1/K) sum over kept stored blocks j of At_j Bt_j^T (m x l)."""
+    torch = _torch()
+    _require_cuda(At, "At", torch.float32)
+    _require_cuda(Bt, "Bt", torch.float32)
+    m, wa, lda = _row_major(At, "At")
+    l, wb, ldb = _row_major(Bt, "Bt")
+    bp = block_stride(b)
+    if wa != wb or wa % bp:
+        raise OversketchError("At and Bt must both hold nst * block_stride(b) columns")
+    nst = wa // bp
+    if out is None:
+        out = torch.empty((m, l), dtype=torch.float32, device=At.device)
+    _require_cuda(out, "out", torch.float32)
+    _, _, ldc = _row_major(out, "out")
+    _, pk = _mask(keep, nst)
+    _check(lib().os_gemm_kept(_ptr(At), lda, _ptr(Bt), ldb, m, l, int(b), nst, pk, _ptr(out), ldc,
+                              _stream(stream)), "os_gemm_kept")
+    return out
+
+
+def workspace_bytes(m, n, l, b, N, e, kept_only=False) -> int:
+    s = _sketch(b, N, e, 0)
+    return int(lib().os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, int(bool(kept_only))))
+
+
+def matmul(A, B, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, out=None,
+           workspace=None, stream=None):
+    """OverSketch product C ~= (1/K) sum_{kept i} (A S_i)(S_i^T B).
+
+    A: m x n float32 with unit column stride.  B: n x l float32, either with
+    unit column stride (row-major) or unit row stride (column-major, e.g. the
+    transpose of a contiguous l x n tensor).  keep: host mask over the N+e
+    blocks (None = the first N).  workspace: optional uint8 CUDA tensor of at
+    least workspace_bytes(...) bytes.
+    """
+    torch = _torch()
+    _require_cuda(A, "A", torch.float32)
+    _require_cuda(B, "B", torch.float32)
+    m, n, lda = _row_major(A, "A")
+    if B.dim() != 2 or B.shape[0] != n:
+        raise OversketchError("B must be n x l")
+    l = B.shape[1]
+    if B.stride(1) == 1 and (B.stride(0) != 1 or l == 1 and n > 1):
+        b_col_major, ldb = 0, B.stride(0) if n > 1 else (l + 3) // 4 * 4
+    elif B.stride(0) == 1:
+        b_col_major, ldb = 1, B.stride(1) if l > 1 else (n + 3) // 4 * 4
+    else:
+        raise OversketchError("B must have a unit stride in one dimension")
+    s = _sketch(b, N, e, seed, h, sigma)
+    need = int(lib().os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, int(bool(kept_only))))
+    if need == 0:
+        raise OversketchError("invalid sizes for os_matmul")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+    if out is None:
+        out = torch.empty((m, l), dtype=torch.float32, device=A.device)
+    _require_cuda(out, "out", torch.float32)
+    _, _, ldc = _row_major(out, "out")
+    _, pk = _mask(keep, N + e)
+    _check(lib().os_matmul(ctypes.byref(s), _ptr(A), lda, _ptr(B), ldb, b_col_major, m, n, l, pk,
+                           int(bool(kept_only)), _ptr(out), ldc, _ptr(workspace),
+                           workspace.numel() * workspace.element_size(), _stream(stream)),
+           "os_matmul")
+    return out

@@ -1,0 +1,148 @@
+"""The C-ABI library: it loads, exports every entry point the header declares,
+and rejects invalid arguments before touching the GPU (host-only checks; no
+compute call is made here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1811_02653_amd as osk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "oversketch.h")
+
+OS_OK, OS_EINVAL, OS_ENULL, OS_EALIGN, OS_EWORKSPACE, OS_EHIP, OS_ENOKEEP = 0, -1, -2, -3, -4, -5, -6
+
+# A fake, 256-byte-aligned "device" address: validation never dereferences it
+# and every call below fails validation before any launch.
+FAKE = ctypes.c_void_p(1 << 20)
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\*?\s+\*?(os_[a-z_]+)\(", text, re.M)))
+
+
+def _sk(b=64, N=4, e=1, seed=1):
+    s = osk._Sketch()
+    s.seed, s.b, s.N, s.e, s.h, s.sigma = seed, b, N, e, None, None
+    return s
+
+
+@pytest.fixture(scope="module")
+def L():
+    return osk.lib()
+
+
+def test_header_declares_the_path(L):
+    names = _declared()
+    for want in ["os_hash_fill", "os_sketch_table", "os_sketch_cols", "os_sketch_rows",
+                 "os_gemm_kept", "os_matmul", "os_matmul_workspace_bytes", "os_status_string",
+                 "os_last_hip_error", "os_block_stride", "os_table_bytes"]:
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    for code in (OS_OK, OS_EINVAL, OS_ENULL, OS_EALIGN, OS_EWORKSPACE, OS_EHIP, OS_ENOKEEP):
+        assert L.os_status_string(code)
+    assert L.os_status_string(123) == b"unknown os_status"
+    assert L.os_last_hip_error() == 0
+
+
+def test_block_stride(L):
+    assert [L.os_block_stride(b) for b in (0, 1, 31, 32, 33, 256, 1000, 1024)] == \
+        [0, 32, 32, 32, 64, 256, 1024, 1024]
+
+
+def test_table_and_workspace_bytes(L):
+    s = _sk(b=1000, N=8, e=2)
+    assert L.os_table_bytes(ctypes.byref(s), 32769) == 10 * 32772 * 4
+    m, n, l = 300, 32769, 77
+    ws = L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 0)
+    r256 = lambda x: (x + 255) // 256 * 256
+    assert ws == r256(10 * 32772 * 4) + r256(m * 10 * 1024 * 4) + r256(l * 10 * 1024 * 4)
+    bad = _sk(b=0)
+    assert L.os_table_bytes(ctypes.byref(bad), 10) == 0
+    assert L.os_matmul_workspace_bytes(ctypes.byref(bad), 1, 1, 1, 0) == 0
+
+
+@pytest.mark.parametrize("b,N,e", [(0, 1, 0), (8193, 1, 0), (4, 0, 1), (4, 2, -1), (4, 200, 57)])
+def test_sketch_parameters_rejected(L, b, N, e):
+    s = _sk(b=b, N=N, e=e)
+    assert L.os_sketch_table(ctypes.byref(s), 10, FAKE, None) == OS_EINVAL
+    assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 16, 0, 4, 16, 4, None, 0, FAKE, 4, FAKE,
+                       1 << 30, None) == OS_EINVAL
+
+
+def test_null_and_half_explicit_tables(L):
+    assert L.os_sketch_table(None, 10, FAKE, None) == OS_ENULL
+    s = _sk()
+    s.h = 1 << 20          # explicit buckets without signs
+    assert L.os_hash_fill(ctypes.byref(s), 10, FAKE, FAKE, None) == OS_ENULL
+    s = _sk()
+    assert L.os_hash_fill(ctypes.byref(s), 10, None, FAKE, None) == OS_ENULL
+    assert L.os_sketch_cols(ctypes.byref(s), None, FAKE, 4, 16, 16, None, 0, FAKE, 320, None) == OS_ENULL
+
+
+def test_sizes_rejected(L):
+    s = _sk()
+    assert L.os_hash_fill(ctypes.byref(s), 0, FAKE, FAKE, None) == OS_EINVAL
+    assert L.os_hash_fill(ctypes.byref(s), 1 << 40, FAKE, FAKE, None) == OS_EINVAL
+    # lda < n
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, FAKE, 4, 16, 12, None, 0, FAKE, 320, None) == OS_EINVAL
+    # output narrower than nst * bp (5 blocks * 64)
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, FAKE, 4, 16, 16, None, 0, FAKE, 316, None) == OS_EINVAL
+    # rows beyond the limit
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, FAKE, (1 << 24) + 1, 16, 16, None, 0, FAKE, 320,
+                            None) == OS_EINVAL
+    # ldc < l
+    assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, None, 0, FAKE, 7, FAKE,
+                       1 << 30, None) == OS_EINVAL
+
+
+def test_alignment_rejected(L):
+    s = _sk()
+    odd = ctypes.c_void_p((1 << 20) + 4)
+    assert L.os_sketch_table(ctypes.byref(s), 10, odd, None) == OS_EALIGN
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, odd, 4, 16, 16, None, 0, FAKE, 320, None) == OS_EALIGN
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, FAKE, 4, 15, 15, None, 0, FAKE, 320, None) == OS_EALIGN
+    # the row-sketch input only needs 4-byte alignment: its failure here is the output's ld
+    assert L.os_sketch_rows(ctypes.byref(s), FAKE, odd, 16, 4, 5, None, 0, FAKE, 322, None) == OS_EALIGN
+    assert L.os_gemm_kept(FAKE, 64, FAKE, 64, 4, 4, 64, 1, None, ctypes.c_void_p((1 << 20) + 2), 4,
+                          None) == OS_EALIGN
+
+
+def test_keep_mask_rejected(L):
+    s = _sk(N=2, e=1)
+    none = np.zeros(3, dtype=np.uint8)
+    p = none.ctypes.data_as(ctypes.c_void_p)
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, FAKE, 4, 16, 16, p, 1, FAKE, 320, None) == OS_ENOKEEP
+    assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, p, 0, FAKE, 8, FAKE,
+                       1 << 30, None) == OS_ENOKEEP
+    assert L.os_gemm_kept(FAKE, 192, FAKE, 192, 4, 4, 64, 3, p, FAKE, 4, None) == OS_ENOKEEP
+
+
+def test_workspace_rejected(L):
+    s = _sk()
+    need = L.os_matmul_workspace_bytes(ctypes.byref(s), 4, 16, 8, 0)
+    assert need > 0
+    assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, None, 0, FAKE, 8, None,
+                       need, None) == OS_EWORKSPACE
+    assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, None, 0, FAKE, 8, FAKE,
+                       need - 1, None) == OS_EWORKSPACE
+    assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, None, 0, FAKE, 8,
+                       ctypes.c_void_p((1 << 20) + 16), need, None) == OS_EWORKSPACE
+
+
+def test_binding_refuses_host_tensors():
+    torch = pytest.importorskip("torch")
+    A = torch.zeros(4, 16)
+    with pytest.raises(osk.OversketchError):
+        osk.matmul(A, torch.zeros(16, 4), b=4, N=2, e=0)

@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs and the same sketch.
+
+Tolerances (FP32 path against the FP64 oracle):
+  - buckets and signs: bit-exact;
+  - sketches of permutation / identity inputs (one term per bucket): bit-exact;
+  - sketches of random inputs: relative Frobenius error <= 1e-6 per block
+    (an FP32 sum of about n/b terms);
+  - the product C: relative Frobenius error <= 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1811_02653_amd as osk  # noqa: E402
+
+SKETCH_TOL = 1e-6
+PRODUCT_TOL = 1e-5
+
+
+def dev(x, ld=None):
+    """Host array -> CUDA float32 tensor view with leading dimension ld
+    (rounded up to a multiple of 4 by default)."""
+    x = np.asarray(x, dtype=np.float32)
+    rows, cols = x.shape
+    if ld is None:
+        ld = (cols + 3) // 4 * 4
+    buf = torch.zeros((rows, ld), dtype=torch.float32, device="cuda")
+    buf[:, :cols] = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    return buf[:, :cols]
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(x, y):
+    return oracle.rel_frob(x, y)
+
+
+def unpad(S, nst, b):
+    """Drop the per-block padding columns of a block-padded sketch."""
+    bp = osk.block_stride(b)
+    S = np.asarray(S)
+    assert S.shape[1] == nst * bp
+    for j in range(nst):
+        assert np.all(S[:, j * bp + b:(j + 1) * bp] == 0), "padding columns must be zero"
+    return np.concatenate([S[:, j * bp:j * bp + b] for j in range(nst)], axis=1)
+
+
+def stored_blocks(N, e, keep, kept_only):
+    if not kept_only:
+        return list(range(N + e))
+    if keep is None:
+        return list(range(N))
+    return [int(i) for i in np.flatnonzero(keep)]
+
+
+# ---------------------------------------------------------------------------
+# hash
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,b,N,e,n", [(0, 256, 4, 1, 4096), (12345, 1000, 8, 2, 1003),
+                                          (2**63 + 7, 7, 1, 0, 5), (99, 1, 3, 3, 64)])
+def test_hash_bit_exact(seed, b, N, e, n):
+    h, s = osk.hash_fill(n, b, N, e, seed=seed)
+    ho, so = oracle.hash_tables(seed, N + e, n, b)
+    np.testing.assert_array_equal(h.cpu().numpy(), ho)
+    np.testing.assert_array_equal(s.cpu().numpy(), so)
+
+
+def test_packed_table_matches_hash():
+    n, b, N, e, seed = 1001, 100, 3, 2, 5
+    t = osk.sketch_table(n, b, N, e, seed=seed).cpu().numpy().view(np.uint32)
+    ho, so = oracle.hash_tables(seed, N + e, n, b)
+    assert t.shape == (N + e, 1004)
+    np.testing.assert_array_equal(t[:, :n] & 0x7FFFFFFF, ho)
+    np.testing.assert_array_equal(np.where(t[:, :n] >> 31, -1, 1), so)
+    assert np.all(t[:, n:] == 0)
+
+
+def test_explicit_tables_pass_through():
+    n, b, N, e = 50, 8, 2, 1
+    rng = np.random.default_rng(1)
+    h = rng.integers(0, b, size=(N + e, n)).astype(np.int32)
+    s = rng.choice(np.array([-1, 1], np.int8), size=(N + e, n))
+    hd, sd = osk.hash_fill(n, b, N, e, h=torch.from_numpy(h).cuda(), sigma=torch.from_numpy(s).cuda())
+    np.testing.assert_array_equal(hd.cpu().numpy(), h)
+    np.testing.assert_array_equal(sd.cpu().numpy(), s)
+
+
+# ---------------------------------------------------------------------------
+# sketches
+# ---------------------------------------------------------------------------
+
+def test_paper_worked_example_on_gpu():
+    # Section 4.1, Eq. (count_sketch_example): h (1-based) = 2 2 3 1 1 2 1 3 3,
+    # signs + - + + - + - - -; sketching I_9 gives the printed S_c.
+    h = np.array([[1, 1, 2, 0, 0, 1, 0, 2, 2]], dtype=np.int32)
+    s = np.array([[1, -1, 1, 1, -1, 1, -1, -1, -1]], dtype=np.int8)
+    ST = np.array([[0, 0, 0, 1, -1, 0, -1, 0, 0],
+                   [1, -1, 0, 0, 0, 1, 0, 0, 0],
+                   [0, 0, 1, 0, 0, 0, 0, -1, -1]], dtype=np.float64)
+    hd, sd = torch.from_numpy(h).cuda(), torch.from_numpy(s).cuda()
+    I9 = np.eye(9)
+    out = host(osk.sketch_cols(dev(I9), 3, 1, 0, h=hd, sigma=sd))
+    np.testing.assert_array_equal(unpad(out, 1, 3), ST.T)
+    outT = host(osk.sketch_rows(dev(I9), 3, 1, 0, h=hd, sigma=sd))
+    np.testing.assert_array_equal(unpad(outT, 1, 3), ST.T)
+
+
+@pytest.mark.parametrize("kept_only", [False, True])
+@pytest.mark.parametrize("b", [64, 100, 1024])
+def test_sketch_of_identity_is_bit_exact(b, kept_only):
+    n, N, e, seed = 700, 3, 2, 17
+    keep = synthetic.random_keep(N, e, seed)
+    h, s = oracle.hash_tables(seed, N + e, n, b)
+    S = oracle.literal_blocks(h, s, b)                       # n x (N+e)*b
+    blocks = stored_blocks(N, e, keep, kept_only)
+    expect = np.concatenate([S[:, i * b:(i + 1) * b] for i in blocks], axis=1)
+    I = dev(np.eye(n))
+    out = host(osk.sketch_cols(I, b, N, e, seed=seed, keep=keep, kept_only=kept_only))
+    np.testing.assert_array_equal(unpad(out, len(blocks), b), expect)
+    outT = host(osk.sketch_rows(I, b, N, e, seed=seed, keep=keep, kept_only=kept_only))
+    np.testing.assert_array_equal(unpad(outT, len(blocks), b), expect)
+
+
+@pytest.mark.parametrize("rows,n,b,N,e", [(37, 1003, 100, 3, 2), (256, 4096, 256, 4, 1),
+                                          (9, 33, 1, 2, 1), (5, 3000, 1024, 2, 0),
+                                          (70, 520, 64, 10, 2)])
+def test_sketch_cols_random(rows, n, b, N, e):
+    seed = rows + n
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((rows, n)).astype(np.float32)
+    out = unpad(host(osk.sketch_cols(dev(X), b, N, e, seed=seed)), N + e, b)
+    h, s = oracle.hash_tables(seed, N + e, n, b)
+    ref = oracle.sketch_cols(X, h, s, b)
+    for i in range(N + e):
+        assert rel(out[:, i * b:(i + 1) * b], ref[:, i * b:(i + 1) * b]) <= SKETCH_TOL
+
+
+@pytest.mark.parametrize("n,cols,b,N,e", [(1003, 77, 100, 3, 2), (4096, 256, 256, 4, 1),
+                                          (33, 9, 1, 2, 1), (3000, 40, 1024, 2, 0),
+                                          (520, 130, 64, 10, 2)])
+def test_sketch_rows_random(n, cols, b, N, e):
+    seed = n + cols
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, cols)).astype(np.float32)
+    outT = unpad(host(osk.sketch_rows(dev(X, ld=cols + 3), b, N, e, seed=seed)), N + e, b)
+    h, s = oracle.hash_tables(seed, N + e, n, b)
+    ref = oracle.sketch_rows(X, h, s, b).T                    # cols x (N+e)*b
+    for i in range(N + e):
+        assert rel(outT[:, i * b:(i + 1) * b], ref[:, i * b:(i + 1) * b]) <= SKETCH_TOL
+
+
+def test_sketch_cols_is_deterministic():
+    X = dev(np.random.default_rng(3).standard_normal((64, 5000)))
+    a = host(osk.sketch_cols(X, 256, 4, 1, seed=3))
+    b = host(osk.sketch_cols(X, 256, 4, 1, seed=3))
+    np.testing.assert_array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# grouped product over kept blocks
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,l,b,nst", [(256, 256, 256, 5), (300, 77, 100, 3), (1, 1, 32, 1),
+                                       (513, 255, 64, 4), (64, 700, 1024, 2)])
+def test_gemm_kept_vs_oracle(m, l, b, nst):
+    rng = np.random.default_rng(m * 7 + l)
+    bp = osk.block_stride(b)
+    At = np.zeros((m, nst * bp), np.float32)
+    Bt = np.zeros((l, nst * bp), np.float32)
+    for j in range(nst):
+        At[:, j * bp:j * bp + b] = rng.standard_normal((m, b))
+        Bt[:, j * bp:j * bp + b] = rng.standard_normal((l, b))
+    keep = np.ones(nst, np.uint8)
+    if nst > 1:
+        keep[rng.integers(nst)] = 0
+    C = host(osk.gemm_kept(dev(At), dev(Bt), b, keep=keep))
+    ref = oracle.block_product(unpad(At, nst, b), unpad(Bt, nst, b).T, b, keep)
+    assert rel(C, ref) <= PRODUCT_TOL
+
+
+# ---------------------------------------------------------------------------
+# the whole path
+# ---------------------------------------------------------------------------
+
+def _matmul_case(m, n, l, b, N, e, seed, keep, kept_only, col_major, data="gauss"):
+    if data == "gauss":
+        A, B = synthetic.gaussian_pair(m, n, l, seed)
+    else:
+        A, B = synthetic.lowrank_pair(m, n, l, seed, rank=8)
+    Ad = dev(A)
+    if col_major:
+        Bd = dev(B.T).t()              # n x l view with unit row stride
+    else:
+        Bd = dev(B, ld=l + 1)
+    C = host(osk.matmul(Ad, Bd, b, N, e, seed=seed, keep=keep, kept_only=kept_only))
+    ref = oracle.sketched_matmul(A, B, b, N, e, seed=seed, keep=keep)
+    return C, ref, A, B
+
+
+@pytest.mark.parametrize("kept_only", [False, True])
+@pytest.mark.parametrize("col_major", [False, True])
+def test_matmul_config1(kept_only, col_major):
+    # 256x4096 by 4096x256, b=256, N=4, e=1, one random block dropped.
+    seed = 1
+    keep = synthetic.random_keep(4, 1, seed)
+    C, ref, _, _ = _matmul_case(256, 4096, 256, 256, 4, 1, seed, keep, kept_only, col_major)
+    assert rel(C, ref) <= PRODUCT_TOL
+
+
+@pytest.mark.parametrize("m,n,l,b,N,e,drop", [
+    (300, 1001, 77, 100, 3, 1, 1),     # ragged everywhere
+    (513, 2050, 257, 64, 4, 2, 3),     # more losses than provisioned (K < N)
+    (129, 777, 384, 32, 2, 2, 0),      # K > N: all N+e kept
+    (1, 50, 1, 1, 1, 0, 0),            # degenerate sizes
+    (40, 3, 33, 8, 2, 1, 1),           # n < b
+])
+def test_matmul_ragged_and_masks(m, n, l, b, N, e, drop):
+    seed = m + n
+    keep = synthetic.random_keep(N, e, seed, drop=drop)
+    for kept_only in (False, True):
+        C, ref, _, _ = _matmul_case(m, n, l, b, N, e, seed, keep, kept_only, col_major=False)
+        assert rel(C, ref) <= PRODUCT_TOL, (kept_only, rel(C, ref))
+
+
+def test_matmul_exact_with_permutation_sketch():
+    # b = n and h a permutation in every block: S_i S_i^T = I, C = AB.
+    m, n, l, N = 96, 256, 80, 2
+    rng = np.random.default_rng(4)
+    A, B = synthetic.gaussian_pair(m, n, l, 4)
+    h = np.stack([rng.permutation(n) for _ in range(N)]).astype(np.int32)
+    s = rng.choice(np.array([-1, 1], np.int8), size=(N, n))
+    C = host(osk.matmul(dev(A), dev(B), n, N, 0, h=torch.from_numpy(h).cuda(),
+                        sigma=torch.from_numpy(s).cuda()))
+    AB = A.astype(np.float64) @ B.astype(np.float64)
+    assert rel(C, AB) <= PRODUCT_TOL
+
+
+def test_kept_only_equals_faithful():
+    m, n, l, b, N, e, seed = 200, 3000, 150, 128, 4, 2, 8
+    A, B = synthetic.gaussian_pair(m, n, l, seed)
+    keep = synthetic.random_keep(N, e, seed)
+    c1 = host(osk.matmul(dev(A), dev(B), b, N, e, seed=seed, keep=keep, kept_only=False))
+    c2 = host(osk.matmul(dev(A), dev(B), b, N, e, seed=seed, keep=keep, kept_only=True))
+    assert rel(c1, c2) <= 1e-6
+
+
+def test_error_paths_raise():
+    A = dev(np.ones((4, 16)))
+    B = dev(np.ones((16, 4)))
+    with pytest.raises(osk.OversketchError):
+        osk.matmul(A, B, 4, 2, 1, keep=np.zeros(3, np.uint8))
+    with pytest.raises(osk.OversketchError):
+        osk.matmul(A, B, 0, 2, 1)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(osk.OversketchError):
+        osk.matmul(A, B, 4, 2, 1, workspace=small)
