@@ -27,34 +27,41 @@
  *   - Indices are 0-based.
  *
  * Conventions for every entry point:
- *   - Matrices are FP32, row-major, with a leading dimension ("ld", in
- *     elements) >= the number of columns.  Matrices sketched along their
- *     rows' contiguous dimension (A; X of os_sketch_cols; B when column-major)
- *     and every sketch matrix need a 16-byte aligned base pointer and a
- *     leading dimension that is a multiple of 4, else OS_EALIGN.  A row-major
- *     B (X of os_sketch_rows) and the product C need only 4-byte alignment
- *     and any leading dimension >= their column count.  The dimension that is not sketched (rows of A, columns of B)
- *     is limited to OS_MAX_ROWS, the sketched one (n) to 2^40 - 1.
- *   - A launch that can be issued always is: an invalid shape is reported
- *     as OS_EINVAL before anything is enqueued.
+ *   - Matrices are FP32 and row-major with a leading dimension ("ld", in
+ *     elements) >= their column count.  A matrix read 16 bytes at a time
+ *     (A, a column-major B, the X of os_sketch_cols, and every sketch) needs a
+ *     16-byte aligned base and an ld that is a multiple of 4; a row-major B
+ *     (the X of os_sketch_rows) and the product C need only 4-byte
+ *     alignment.  Violations return OS_EALIGN.
+ *   - Size limits: the sketched dimension n <= OS_MAX_N; the other dimension
+ *     of each operand (m, l) <= OS_MAX_ROWS; a row-major B (the X of
+ *     os_sketch_rows) must span at most 2 GiB ((n-1)*ldb + l floats), larger
+ *     ones are passed column-major.
  *   - Device pointers are HIP device memory owned by the caller; the library
  *     never allocates device memory and never retains a pointer past return.
  *     Host pointers (keep masks) are read before the call returns.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
  *     on it and the call returns; outputs are valid once the stream has
- *     completed.  Validation happens before anything is enqueued: on any
- *     error nothing is launched and the outputs are untouched.
- *   - No C++ exception crosses this interface.  Entry points are thread-safe
- *     (no mutable global state apart from a once-initialised device query).
+ *     completed.  Every argument check happens before anything is enqueued:
+ *     on any error nothing is launched and no output is touched.
+ *   - No C++ exception crosses this interface.  No entry point keeps mutable
+ *     global state; the only per-thread state is os_last_hip_error.
  *
- * Sketched-matrix layout ("block-padded"): a sketch with `nst` stored blocks
- * of width b is a row-major matrix with nst * bp columns, bp =
- * os_block_stride(b) = b rounded up to a multiple of 32.  Stored block j
- * occupies columns [j*bp, j*bp + b); columns [j*bp + b, (j+1)*bp) are written
- * as zero.  With kept_only = 0 every one of the N+e blocks is stored (block i
- * at position i); with kept_only = 1 only the kept blocks are stored, in
- * ascending block order (the "straggler-resilient sketching" remark of
- * Section 4.1: blocks dropped at sketch time are treated as stragglers).
+ * Sketch layout ("bucket-major"): a sketch of a matrix with L lines (rows of
+ * A, columns of B) over nst stored blocks is a row-major (nst * bp) x L
+ * matrix, bp = os_block_stride(b) = b rounded up to a multiple of 32: row
+ * j*bp + c holds bucket c of stored block j for every line -- i.e. the sketch
+ * of A is (A S)^T and the sketch of B is S^T B, each without the N^{-1/2}
+ * factor.  Rows j*bp + b .. (j+1)*bp - 1 are written as zero.  With
+ * kept_only = 0 every one of the N+e blocks is stored (block i at position
+ * i); with kept_only = 1 only the kept blocks are stored, in ascending block
+ * order (the "straggler-resilient sketching" remark of Section 4.1: blocks
+ * dropped at sketch time count as stragglers).
+ *
+ * Prepared sketch: an opaque device buffer holding, for all N+e blocks, the
+ * bucket/sign of every index and, per block, the indices grouped by bucket
+ * range.  It depends only on (seed or explicit tables, b, N, e, n), not on a
+ * keep mask, and can be reused by every sketch call with the same values.
  */
 #ifndef OVERSKETCH_H
 #define OVERSKETCH_H
@@ -71,22 +78,22 @@ typedef int os_status;
 #define OS_OK          0   /* success */
 #define OS_EINVAL     -1   /* a size, count or parameter outside its range */
 #define OS_ENULL      -2   /* a required pointer is NULL */
-#define OS_EALIGN     -3   /* a pointer is not 16-byte aligned or an ld not a multiple of 4 */
-#define OS_EWORKSPACE -4   /* workspace NULL, misaligned (256 B) or smaller than required */
+#define OS_EALIGN     -3   /* a pointer or leading dimension misaligned (see conventions) */
+#define OS_EWORKSPACE -4   /* workspace / prepared buffer missing or smaller than required */
 #define OS_EHIP       -5   /* the HIP runtime reported an error (os_last_hip_error) */
 #define OS_ENOKEEP    -6   /* the keep mask keeps no block */
 
-#define OS_MAX_BLOCKS 256      /* upper limit on N + e */
-#define OS_MAX_B      8192     /* upper limit on the block width b */
-#define OS_MAX_ROWS   (1LL << 24) /* upper limit on m, l and the sketched operands' row/column counts */
+#define OS_MAX_BLOCKS 256                   /* upper limit on N + e */
+#define OS_MAX_B      8192                  /* upper limit on the block width b */
+#define OS_MAX_N      (2147483647LL - 64LL) /* upper limit on the sketched dimension n */
+#define OS_MAX_ROWS   16777216LL            /* upper limit on m and l */
 
 /* Sketch description.  b in [1, OS_MAX_B], N >= 1, e >= 0, N + e <=
  * OS_MAX_BLOCKS.  When h is non-NULL, sigma must be non-NULL too and both
  * are DEVICE arrays [N+e][n] (row i = block i) holding explicit buckets in
- * [0, b) and signs in {-1, +1}; the seed is then ignored.  Explicit values
- * are not range-checked on the device: out-of-range buckets are clamped into
- * [0, b) and any sign < 0 counts as -1, so a bad table gives a wrong result,
- * never an out-of-bounds access. */
+ * [0, b) and signs in {-1, +1}; the seed is then ignored.  Explicit buckets
+ * outside [0, b) are clamped into it and any negative sign counts as -1, so a
+ * bad table gives a wrong result, never an out-of-bounds access. */
 typedef struct os_sketch {
     uint64_t seed;
     int32_t b;
@@ -103,66 +110,70 @@ const char* os_status_string(os_status status);
  * (0 if none). */
 int os_last_hip_error(void);
 
-/* Column stride of one stored block in a sketched matrix:
- * b rounded up to a multiple of 32 (0 if b < 1). */
+/* Rows taken by one stored block in a sketch: b rounded up to a multiple of
+ * 32 (0 if b < 1). */
 int32_t os_block_stride(int32_t b);
 
-/* Bytes of the packed hash table for an n-long sketched dimension:
- * (N+e) * round_up(n, 4) * 4.  0 on invalid arguments. */
-size_t os_table_bytes(const os_sketch* sk, int64_t n);
-
-/* Step "hash" of the path -- the random choices of Algorithm "Calculating
- * Count-sketch of a matrix A" for all N+e blocks, materialised:
+/* Step "hash": the random choices of Algorithm "Calculating Count-sketch of
+ * a matrix A" for all N+e blocks, materialised on the device:
  * h_out[i*n + k] = bucket h_i(k) in [0, b), sigma_out[i*n + k] = sigma_i(k).
- * h_out: DEVICE int32 [(N+e) * n]; sigma_out: DEVICE int8 [(N+e) * n].
- * n in [1, 2^40).  With explicit tables in `sk` the (clamped) values are
- * copied. */
+ * h_out: DEVICE int32 [(N+e) * n] (4-byte aligned); sigma_out: DEVICE int8
+ * [(N+e) * n].  With explicit tables the clamped values are copied. */
 os_status os_hash_fill(const os_sketch* sk, int64_t n, int32_t* h_out, int8_t* sigma_out,
                        void* stream);
 
-/* Packed hash table consumed by the sketch kernels: table[i*nt + k] for
- * block i < N+e, k < n, nt = round_up(n, 4); entry = h_i(k) | (sigma_i(k) < 0) << 31,
- * padding entries (n <= k < nt) are 0.  table: DEVICE, os_table_bytes(sk, n)
- * bytes, 16-byte aligned. */
-os_status os_sketch_table(const os_sketch* sk, int64_t n, uint32_t* table, void* stream);
+/* Bytes of the prepared sketch for an n-long sketched dimension (0 on
+ * invalid arguments). */
+size_t os_sketch_prepare_bytes(const os_sketch* sk, int64_t n);
+
+/* Step "hash" as the sketch kernels consume it: fills the prepared sketch
+ * (buckets and signs of all N+e blocks, then every block's indices grouped
+ * by bucket range, ascending).  prep: DEVICE, 256-byte aligned, >=
+ * os_sketch_prepare_bytes(sk, n) bytes (else OS_EWORKSPACE). */
+os_status os_sketch_prepare(const os_sketch* sk, int64_t n, void* prep, size_t prep_bytes,
+                            void* stream);
 
 /* Step "sketch A's columns" (Algorithm "Over sketching A in parallel" with
- * Algorithm "Calculating Count-sketch" per block): for a row-major X
- * (rows x n, ld ldx) and every stored block j (block index s_j),
- *   out[r][j*bp + c] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[r][k],
- * i.e. out = [X S_{s_0}, X S_{s_1}, ...] without the N^{-1/2} factor.
- * table: from os_sketch_table for the same sk and n.  keep_host: HOST uint8
- * [N+e] (nonzero = kept) or NULL (= blocks [0, N) kept); it only matters when
- * kept_only != 0.  out: DEVICE rows x ldo, ldo >= nst*bp.  The same routine
- * sketches the rows of a column-major matrix (pass its transpose). */
-os_status os_sketch_cols(const os_sketch* sk, const uint32_t* table, const float* X,
-                         int64_t rows, int64_t n, int64_t ldx, const uint8_t* keep_host,
-                         int kept_only, float* out, int64_t ldo, void* stream);
+ * Algorithm "Calculating Count-sketch" per block) for a row-major X
+ * (rows x n, ld ldx), bucket-major output:
+ *   out[j*bp + c][r] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[r][k]
+ * for every stored block j (sketch block s_j), i.e. out = (X S_{s_j})^T
+ * stacked over j.  Each bucket is summed in ascending k in FP32.
+ * prep: a prepared sketch for the same sk and n.  keep_host: HOST uint8
+ * [N+e] (nonzero = kept) or NULL (= blocks [0, N)); it selects the stored
+ * blocks when kept_only != 0.  out: DEVICE (nst*bp) x rows, ld ldo >= rows.
+ * A column-major matrix is sketched along its columns by passing its
+ * transpose. */
+os_status os_sketch_cols(const os_sketch* sk, const void* prep, size_t prep_bytes,
+                         const float* X, int64_t rows, int64_t n, int64_t ldx,
+                         const uint8_t* keep_host, int kept_only, float* out, int64_t ldo,
+                         void* stream);
 
-/* Step "sketch B's rows" (S^T B, the same sketch applied from the left,
- * Section 4): for a row-major X (n x cols, ld ldx) and every stored block j,
- *   outT[q][j*bp + c] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[k][q],
- * i.e. outT = (S_{s_j}^T X)^T stored as a cols x (nst*bp) row-major matrix
- * (the inner dimension contiguous, as the block product consumes it).
- * Other arguments as in os_sketch_cols; outT: DEVICE cols x ldo. */
-os_status os_sketch_rows(const os_sketch* sk, const uint32_t* table, const float* X,
-                         int64_t n, int64_t cols, int64_t ldx, const uint8_t* keep_host,
-                         int kept_only, float* outT, int64_t ldo, void* stream);
+/* Step "sketch B's rows" (S^T B: the same sketch applied from the left,
+ * Section 4) for a row-major X (n x cols, ld ldx):
+ *   out[j*bp + c][q] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[k][q],
+ * i.e. out = S_{s_j}^T X stacked over j.  Other arguments as in
+ * os_sketch_cols; out: DEVICE (nst*bp) x cols, ld ldo >= cols. */
+os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_bytes,
+                         const float* X, int64_t n, int64_t cols, int64_t ldx,
+                         const uint8_t* keep_host, int kept_only, float* out, int64_t ldo,
+                         void* stream);
 
 /* Step "grouped product over the kept blocks" (Algorithm "OverSketch":
  * computation phase plus reduction phase, Fig. (bMM)):
- *   C = (1/K) * sum_{j : keep[j]} At_j * Bt_j^T,
- * At: DEVICE m x (nst*bp) sketch of A (ld ldat), Bt: DEVICE l x (nst*bp)
- * transposed sketch of B (ld ldbt), both block-padded with nst stored blocks
- * of width b; keep_host: HOST uint8 [nst] over the STORED blocks, or NULL
- * (= all stored blocks kept); K = number kept.  C: DEVICE m x l (ld ldc),
- * overwritten.  FP32 inputs, FP32 MFMA accumulation. */
+ *   C = (1/K) * sum_{j : keep[j]} At_j^T * Bt_j,
+ * At: DEVICE (nst*bp) x m bucket-major sketch of A (ld ldat >= m), Bt: DEVICE
+ * (nst*bp) x l bucket-major sketch of B (ld ldbt >= l), At_j / Bt_j = their
+ * rows j*bp .. j*bp + bp - 1; keep_host: HOST uint8 [nst] over the STORED
+ * blocks, or NULL (= all stored blocks); K = number kept.  C: DEVICE m x l
+ * (ld ldc >= l), overwritten.  FP32 inputs, FP32 MFMA accumulation. */
 os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
                        int64_t m, int64_t l, int32_t b, int32_t nst,
                        const uint8_t* keep_host, float* C, int64_t ldc, void* stream);
 
-/* Workspace bytes os_matmul needs: packed table + sketch of A + transposed
- * sketch of B (each region 256-byte aligned).  0 on invalid arguments. */
+/* Workspace bytes os_matmul needs (prepared sketch + both sketches, sized
+ * for all N+e blocks, so one workspace serves any mask).  0 on invalid
+ * arguments. */
 size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
                                  int kept_only);
 
@@ -173,7 +184,7 @@ size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int6
  * keep_host: HOST uint8 [N+e] or NULL (= blocks [0, N) kept).  kept_only != 0
  * skips the dropped blocks already in the sketch step.  C: DEVICE m x l
  * (ldc).  workspace: DEVICE, 256-byte aligned, >= os_matmul_workspace_bytes.
- * Enqueues: table, sketch of A, sketch of B, block product. */
+ * Enqueues: prepare, sketch of A, sketch of B, block product. */
 os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const float* B,
                     int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
                     const uint8_t* keep_host, int kept_only, float* C, int64_t ldc,

@@ -16,7 +16,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "OversketchError", "lib", "block_stride", "hash_fill", "sketch_table", "sketch_cols",
+    "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "sketch_cols",
     "sketch_rows", "gemm_kept", "matmul", "workspace_bytes", "stored_count",
 ]
 
@@ -66,16 +66,16 @@ def lib():
     L.os_last_hip_error.argtypes = []
     L.os_block_stride.restype = i32
     L.os_block_stride.argtypes = [i32]
-    L.os_table_bytes.restype = sz
-    L.os_table_bytes.argtypes = [sk, i64]
     L.os_hash_fill.restype = ctypes.c_int
     L.os_hash_fill.argtypes = [sk, i64, vp, vp, vp]
-    L.os_sketch_table.restype = ctypes.c_int
-    L.os_sketch_table.argtypes = [sk, i64, vp, vp]
+    L.os_sketch_prepare_bytes.restype = sz
+    L.os_sketch_prepare_bytes.argtypes = [sk, i64]
+    L.os_sketch_prepare.restype = ctypes.c_int
+    L.os_sketch_prepare.argtypes = [sk, i64, vp, sz, vp]
     L.os_sketch_cols.restype = ctypes.c_int
-    L.os_sketch_cols.argtypes = [sk, vp, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
+    L.os_sketch_cols.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
     L.os_sketch_rows.restype = ctypes.c_int
-    L.os_sketch_rows.argtypes = [sk, vp, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
+    L.os_sketch_rows.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
     L.os_gemm_kept.restype = ctypes.c_int
     L.os_gemm_kept.argtypes = [vp, i64, vp, i64, i64, i64, i32, i32, vp, vp, i64, vp]
     L.os_matmul_workspace_bytes.restype = sz
@@ -183,70 +183,80 @@ def hash_fill(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None
     return h_out, s_out
 
 
-def sketch_table(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None):
-    """Packed hash table [N+e, round_up(n, 4)] as int32 (bit 31 = negative sign)."""
+def sketch_prepare(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None):
+    """Prepared sketch (opaque uint8 device buffer) for an n-long sketched dimension."""
     torch = _torch()
     s = _sketch(b, N, e, seed, h, sigma)
-    nt = (n + 3) // 4 * 4
-    table = torch.empty((N + e, nt), dtype=torch.int32, device=device)
-    _check(lib().os_sketch_table(ctypes.byref(s), n, _ptr(table), _stream(stream)),
-           "os_sketch_table")
-    return table
+    nbytes = int(lib().os_sketch_prepare_bytes(ctypes.byref(s), n))
+    if nbytes == 0:
+        raise OversketchError("invalid sketch parameters")
+    prep = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    _check(lib().os_sketch_prepare(ctypes.byref(s), n, _ptr(prep), nbytes, _stream(stream)),
+           "os_sketch_prepare")
+    return prep
 
 
-def sketch_cols(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, table=None,
+def _bucket_major_out(out, rows, lines, device):
+    torch = _torch()
+    if out is None:
+        buf = torch.empty((rows, (lines + 3) // 4 * 4), dtype=torch.float32, device=device)
+        return buf[:, :lines]
+    _require_cuda(out, "out", torch.float32)
+    if tuple(out.shape) != (rows, lines):
+        raise OversketchError("out must be %d x %d" % (rows, lines))
+    return out
+
+
+def sketch_cols(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, prep=None,
                 out=None, stream=None):
-    """[X S_i ...] for the stored blocks: rows x (nst * block_stride(b))."""
+    """Bucket-major (X S_i)^T for the stored blocks: (nst * block_stride(b)) x rows."""
     torch = _torch()
     _require_cuda(X, "X", torch.float32)
     rows, n, ldx = _row_major(X, "X")
-    if table is None:
-        table = sketch_table(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
+    if prep is None:
+        prep = sketch_prepare(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
     s = _sketch(b, N, e, seed, h, sigma)
-    width = stored_count(N, e, keep, kept_only) * block_stride(b)
-    if out is None:
-        out = torch.empty((rows, width), dtype=torch.float32, device=X.device)
-    _require_cuda(out, "out", torch.float32)
+    height = stored_count(N, e, keep, kept_only) * block_stride(b)
+    out = _bucket_major_out(out, height, rows, X.device)
     _, _, ldo = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
-    _check(lib().os_sketch_cols(ctypes.byref(s), _ptr(table), _ptr(X), rows, n, ldx, pk,
-                                int(bool(kept_only)), _ptr(out), ldo, _stream(stream)),
+    _check(lib().os_sketch_cols(ctypes.byref(s), _ptr(prep), prep.numel(), _ptr(X), rows, n, ldx,
+                                pk, int(bool(kept_only)), _ptr(out), ldo, _stream(stream)),
            "os_sketch_cols")
     return out
 
 
-def sketch_rows(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, table=None,
+def sketch_rows(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, prep=None,
                 out=None, stream=None):
-    """(S_i^T X)^T for the stored blocks: cols x (nst * block_stride(b))."""
+    """Bucket-major S_i^T X for the stored blocks: (nst * block_stride(b)) x cols."""
     torch = _torch()
     _require_cuda(X, "X", torch.float32)
     n, cols, ldx = _row_major(X, "X")
-    if table is None:
-        table = sketch_table(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
+    if prep is None:
+        prep = sketch_prepare(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
     s = _sketch(b, N, e, seed, h, sigma)
-    width = stored_count(N, e, keep, kept_only) * block_stride(b)
-    if out is None:
-        out = torch.empty((cols, width), dtype=torch.float32, device=X.device)
-    _require_cuda(out, "out", torch.float32)
+    height = stored_count(N, e, keep, kept_only) * block_stride(b)
+    out = _bucket_major_out(out, height, cols, X.device)
     _, _, ldo = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
-    _check(lib().os_sketch_rows(ctypes.byref(s), _ptr(table), _ptr(X), n, cols, ldx, pk,
-                                int(bool(kept_only)), _ptr(out), ldo, _stream(stream)),
+    _check(lib().os_sketch_rows(ctypes.byref(s), _ptr(prep), prep.numel(), _ptr(X), n, cols, ldx,
+                                pk, int(bool(kept_only)), _ptr(out), ldo, _stream(stream)),
            "os_sketch_rows")
     return out
 
 
 def gemm_kept(At, Bt, b, keep=None, out=None, stream=None):
-    """(1/K) sum over kept stored blocks j of At_j Bt_j^T (m x l)."""
+    """(1/K) sum over kept stored blocks j of At_j^T Bt_j (m x l), At and Bt
+    bucket-major sketches ((nst * block_stride(b)) x m and x l)."""
     torch = _torch()
     _require_cuda(At, "At", torch.float32)
     _require_cuda(Bt, "Bt", torch.float32)
-    m, wa, lda = _row_major(At, "At")
-    l, wb, ldb = _row_major(Bt, "Bt")
+    ha, m, lda = _row_major(At, "At")
+    hb, l, ldb = _row_major(Bt, "Bt")
     bp = block_stride(b)
-    if wa != wb or wa % bp:
-        raise OversketchError("At and Bt must both hold nst * block_stride(b) columns")
-    nst = wa // bp
+    if ha != hb or ha % bp:
+        raise OversketchError("At and Bt must both hold nst * block_stride(b) rows")
+    nst = ha // bp
     if out is None:
         out = torch.empty((m, l), dtype=torch.float32, device=At.device)
     _require_cuda(out, "out", torch.float32)

@@ -1,7 +1,8 @@
 // gemm.hip -- grouped FP32 MFMA product over the kept sketch blocks.
 //
-// Computes C = scale * sum_{j kept} At_j * Bt_j^T, where At_j (m x bp) and
-// Bt_j (l x bp) are the j-th column blocks of the sketches of A and B^T.
+// Computes C = scale * sum_{j kept} At_j^T * Bt_j, where At_j (bp x m) and
+// Bt_j (bp x l) are the j-th row blocks of the bucket-major sketches
+// (A S)^T and S^T B.
 // This is the computation phase and the reduction phase of Algorithm
 // "OverSketch" fused into one K loop: the paper's b x b worker products
 // A_tilde(i,k) B_tilde(k,j) for the blocks that returned (Fig. (bMM)) are
@@ -12,13 +13,14 @@
 //   - 256 x 256 output tile per workgroup of 4 waves; each wave owns a
 //     128 x 128 sub-tile = 4 x 4 MFMA blocks of 32 x 32 (256 accumulators
 //     per lane, kept in AGPRs).
-//   - K steps of 32: both operands are K-contiguous, staged through LDS with
-//     a padded row stride of 36 floats (conflict-free 128-bit reads); the
-//     next step's tile is prefetched into registers during the MFMAs.
+//   - K steps of 32: both operands are K-major (a K row holds 256 contiguous
+//     m or l values, read as 1 KiB per wave instruction), staged through LDS
+//     with a row stride of 260 floats so the two lane halves of an operand
+//     read (k and k + 8) fall in disjoint banks; the next step's tile is
+//     prefetched into registers during the MFMAs.
 //   - Within a 16-deep half step, lane half h of every MFMA reads k = 8h + kk
-//     (kk = 0..7), so each lane fetches its 8 operand values of a half step
-//     with two 128-bit LDS reads; A and B use the same k order, so the dot
-//     products are unchanged (only their summation order differs).
+//     (kk = 0..7); A and B use the same k order, so the dot products are
+//     unchanged (only their summation order differs).
 //   - Workgroup -> tile mapping keeps neighbouring tiles on one XCD (shared
 //     L2) and rasterises in groups of 4 tile rows.
 #include "internal.h"
@@ -31,7 +33,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int BM = 256;
 constexpr int BN = 256;
 constexpr int BK = 32;
-constexpr int LDK = BK + 4;     // padded LDS row stride (floats)
+constexpr int LDT = 260;        // LDS row stride (floats) of a K row of a tile
 constexpr int kThreads = 256;
 constexpr int kGroupM = 4;
 
@@ -40,29 +42,29 @@ __device__ __forceinline__ int64_t xcd_task(int64_t L, int64_t tasks) {
     return (L % 8) * (tasks / 8) + L / 8;
 }
 
-// Global -> register tile loads: thread t covers rows t/8 + 32*i (i < 8) and
-// the 4 floats starting at column 4*(t%8) of the 32-wide K step.
+// Global -> register tile loads: wave w covers K rows 8w .. 8w+7 of the step;
+// lane L the 4 values at column 4L of the 256-wide tile.  Columns at or past
+// `ncols` load zero (a float4 that starts below ncols stays inside the row,
+// whose leading dimension is a multiple of 4 and >= ncols).
 __device__ __forceinline__ void load_tile(float4 (&r)[8], const float* __restrict__ base,
-                                          int64_t ld, int64_t row0, int64_t nrows, int64_t kcol,
+                                          int64_t ld, int64_t col0, int64_t ncols, int64_t krow,
                                           int tid) {
-    const int lr = tid >> 3;
-    const int lq = tid & 7;
+    const int w = tid >> 6;
+    const int64_t col = col0 + 4 * (tid & 63);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int64_t row = row0 + lr + 32 * i;
-        if (row < nrows)
-            r[i] = *reinterpret_cast<const float4*>(base + row * ld + kcol + 4 * lq);
+        if (col < ncols)
+            r[i] = *reinterpret_cast<const float4*>(base + (krow + 8 * w + i) * ld + col);
         else
             r[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
 __device__ __forceinline__ void store_tile(float* __restrict__ s, const float4 (&r)[8], int tid) {
-    const int lr = tid >> 3;
-    const int lq = tid & 7;
+    const int w = tid >> 6;
+    const int c = 4 * (tid & 63);
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-        *reinterpret_cast<float4*>(s + (lr + 32 * i) * LDK + 4 * lq) = r[i];
+    for (int i = 0; i < 8; ++i) *reinterpret_cast<float4*>(s + (8 * w + i) * LDT + c) = r[i];
 }
 
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
@@ -70,8 +72,8 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
                       int64_t ldbt, int64_t m, int64_t l, int32_t bp, BlockList kept,
                       int32_t nkept, float scale, float* __restrict__ C, int64_t ldc,
                       int32_t tilesM, int32_t tilesN) {
-    __shared__ __align__(16) float As[BM * LDK];
-    __shared__ __align__(16) float Bs[BN * LDK];
+    __shared__ __align__(16) float As[BK * LDT];
+    __shared__ __align__(16) float Bs[BK * LDT];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -101,15 +103,16 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
     const int tpb = bp / BK;                       // K steps per block
     const int total = nkept * tpb;
     int kb = 0, kt = 0;
-    int64_t kcol = (int64_t)kept.idx[0] * bp;
+    int64_t krow = (int64_t)kept.idx[0] * bp;
 
     float4 ra[8], rb[8];
-    load_tile(ra, At, ldat, row0, m, kcol, tid);
-    load_tile(rb, Bt, ldbt, col0, l, kcol, tid);
+    load_tile(ra, At, ldat, row0, m, krow, tid);
+    load_tile(rb, Bt, ldbt, col0, l, krow, tid);
 
-    const int arow = wm * 128 + (lane & 31);
-    const int brow = wn * 128 + (lane & 31);
-    const int koff = (lane >> 5) * 8;
+    // operand element (k, lane's m or n) lives at [k * LDT + col]
+    const int acol = wm * 128 + (lane & 31);
+    const int bcol = wn * 128 + (lane & 31);
+    const int krow_lane = 8 * (lane >> 5);
 
     for (int t = 0; t < total; ++t) {
         __syncthreads();
@@ -119,34 +122,35 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
         if (++kt == tpb) {
             kt = 0;
             ++kb;
-            kcol = (kb < nkept) ? (int64_t)kept.idx[kb] * bp : 0;
+            krow = (kb < nkept) ? (int64_t)kept.idx[kb] * bp : 0;
         } else {
-            kcol += BK;
+            krow += BK;
         }
         if (t + 1 < total) {
-            load_tile(ra, At, ldat, row0, m, kcol, tid);
-            load_tile(rb, Bt, ldbt, col0, l, kcol, tid);
+            load_tile(ra, At, ldat, row0, m, krow, tid);
+            load_tile(rb, Bt, ldbt, col0, l, krow, tid);
         }
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
 #pragma unroll
             for (int quad = 0; quad < 2; ++quad) {
-                float4 a[4], b[4];
+                float a[4][4], b[4][4];
+                const int k0 = half * 16 + krow_lane + 4 * quad;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    a[i] = *reinterpret_cast<const float4*>(As + (arow + 32 * i) * LDK + half * 16 + koff + 4 * quad);
-                    b[i] = *reinterpret_cast<const float4*>(Bs + (brow + 32 * i) * LDK + half * 16 + koff + 4 * quad);
-                }
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        a[i][kk] = As[(k0 + kk) * LDT + acol + 32 * i];
+                        b[i][kk] = Bs[(k0 + kk) * LDT + bcol + 32 * i];
+                    }
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const float av = kk == 0 ? a[i].x : kk == 1 ? a[i].y : kk == 2 ? a[i].z : a[i].w;
-                            const float bv = kk == 0 ? b[j].x : kk == 1 ? b[j].y : kk == 2 ? b[j].z : b[j].w;
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[i][j], 0, 0, 0);
-                        }
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[j][kk],
+                                                                             acc[i][j], 0, 0, 0);
             }
         }
     }

@@ -32,40 +32,38 @@ hipError_t launch_hash_fill(uint64_t seed, const int32_t* h_in, const int8_t* si
                             int32_t nblk, int64_t n, int32_t b, int32_t* h_out,
                             int8_t* sigma_out, hipStream_t s);
 
-// Launch shapes of the sketch kernels, chosen on the host before anything is
-// enqueued (valid == false: the shape does not fit; nothing may be launched).
-struct ColsPlan {
-    bool valid;
-    int rw;          // rows owned by one wave (1, 2, 4)
-    int g;           // blocks held in LDS per workgroup
-    int64_t nslices; // workgroups per row group
-    int64_t tasks;   // workgroups
-    size_t lds;      // dynamic LDS bytes
-};
-struct RowsPlan {
-    bool valid;
-    int wc;          // columns per workgroup strip (power of two <= 64)
-    int g;
-    int64_t nslices;
-    int64_t tasks;
-    size_t lds;
-};
-// rw / g / wc = 0 choose automatically.
-ColsPlan plan_sketch_cols(int64_t rows, int32_t nst, int32_t bp, int rw = 0, int g = 0);
-RowsPlan plan_sketch_rows(int64_t cols, int32_t nst, int32_t bp, int wc = 0, int g = 0);
+// Bucket lists (see sketch.hip): buckets of a block are split into ranges
+// of kBucketRange; one wave owns one (block, range).
+constexpr int kBucketRange = 32;
+constexpr int kListBatch = 8;
+
+// Longest sketched dimension (list entries hold k as 32 bits).
+constexpr int64_t kMaxSketchedLen = OS_MAX_N;
+
+int32_t list_ranges(int32_t bp);
+// Bytes of the list structure for nblk blocks of padded width bp.
+size_t list_bytes(int32_t nblk, int64_t n, int32_t bp);
+// Lists for every block i < nblk of a packed table.
+hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
+                              int32_t bp, void* lists, hipStream_t s);
+// Shapes a sketch launch supports (lines = the dimension that is not sketched).
+bool plan_sketch_ok(int64_t lines, int32_t nst, int32_t bp, int64_t n);
+// The row-major sketch additionally needs X to span at most 2 GiB.
+bool plan_sketch_rows_ok(int64_t n, int64_t cols, int64_t ldx, int32_t nst, int32_t bp);
+// out (nst*bp x cols, ld ldo) = S^T X for X n x cols row-major; stored block
+// j is sketch block bl.idx[j]; lists built for nblk blocks.
+hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t ldx,
+                              const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
+                              const void* lists, float* out, int64_t ldo, hipStream_t s);
+// out (nst*bp x rows, ld ldo) = (X S)^T for X rows x n row-major.
+hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,
+                              const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
+                              const void* lists, float* out, int64_t ldo, hipStream_t s);
+
 bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp);
 
-hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,
-                              const uint32_t* table, int64_t nt, const BlockList& bl,
-                              int32_t nst, int32_t bp, float* out, int64_t ldo,
-                              const ColsPlan& plan, hipStream_t s);
-hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t ldx,
-                              const uint32_t* table, int64_t nt, const BlockList& bl,
-                              int32_t nst, int32_t bp, float* outT, int64_t ldo,
-                              const RowsPlan& plan, hipStream_t s);
-
-// C = scale * sum over the kept stored blocks (bl.idx[0 .. nkept)) of
-// At_j * Bt_j^T.
+// C = scale * sum over the kept stored blocks (kept.idx[0 .. nkept)) of
+// At_j^T * Bt_j, with At (nst*bp x m) and Bt (nst*bp x l) bucket-major.
 hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
                             int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                             int32_t nkept, float scale, float* C, int64_t ldc, hipStream_t s);

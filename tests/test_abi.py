@@ -38,9 +38,9 @@ def L():
 
 def test_header_declares_the_path(L):
     names = _declared()
-    for want in ["os_hash_fill", "os_sketch_table", "os_sketch_cols", "os_sketch_rows",
-                 "os_gemm_kept", "os_matmul", "os_matmul_workspace_bytes", "os_status_string",
-                 "os_last_hip_error", "os_block_stride", "os_table_bytes"]:
+    for want in ["os_hash_fill", "os_sketch_prepare_bytes", "os_sketch_prepare", "os_sketch_cols",
+                 "os_sketch_rows", "os_gemm_kept", "os_matmul", "os_matmul_workspace_bytes",
+                 "os_status_string", "os_last_hip_error", "os_block_stride"]:
         assert want in names
 
 
@@ -61,47 +61,61 @@ def test_block_stride(L):
         [0, 32, 32, 32, 64, 256, 1024, 1024]
 
 
-def test_table_and_workspace_bytes(L):
+def test_prepare_and_workspace_bytes(L):
     s = _sk(b=1000, N=8, e=2)
-    assert L.os_table_bytes(ctypes.byref(s), 32769) == 10 * 32772 * 4
-    m, n, l = 300, 32769, 77
-    ws = L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 0)
+    n = 32769
+    prep = L.os_sketch_prepare_bytes(ctypes.byref(s), n)
     r256 = lambda x: (x + 255) // 256 * 256
-    assert ws == r256(10 * 32772 * 4) + r256(m * 10 * 1024 * 4) + r256(l * 10 * 1024 * 4)
+    P = 1024 // 32
+    table = 10 * 32772 * 4
+    lists = r256(10 * P * 4) + r256(10 * (P + 1) * 4) + r256(10 * (n + 8) * 8)
+    assert prep == r256(table) + lists
+    m, l = 300, 77
+    ws = L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 0)
+    assert ws == r256(prep) + r256(10 * 1024 * 300 * 4) + r256(10 * 1024 * 80 * 4)
     bad = _sk(b=0)
-    assert L.os_table_bytes(ctypes.byref(bad), 10) == 0
+    assert L.os_sketch_prepare_bytes(ctypes.byref(bad), 10) == 0
     assert L.os_matmul_workspace_bytes(ctypes.byref(bad), 1, 1, 1, 0) == 0
+    assert L.os_sketch_prepare_bytes(ctypes.byref(s), 0) == 0
 
 
 @pytest.mark.parametrize("b,N,e", [(0, 1, 0), (8193, 1, 0), (4, 0, 1), (4, 2, -1), (4, 200, 57)])
 def test_sketch_parameters_rejected(L, b, N, e):
     s = _sk(b=b, N=N, e=e)
-    assert L.os_sketch_table(ctypes.byref(s), 10, FAKE, None) == OS_EINVAL
+    assert L.os_sketch_prepare(ctypes.byref(s), 10, FAKE, 1 << 30, None) == OS_EINVAL
     assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 16, 0, 4, 16, 4, None, 0, FAKE, 4, FAKE,
                        1 << 30, None) == OS_EINVAL
 
 
+BIG = 1 << 30   # a prepared-buffer size that always suffices here
+
+
 def test_null_and_half_explicit_tables(L):
-    assert L.os_sketch_table(None, 10, FAKE, None) == OS_ENULL
+    assert L.os_sketch_prepare(None, 10, FAKE, BIG, None) == OS_ENULL
     s = _sk()
     s.h = 1 << 20          # explicit buckets without signs
     assert L.os_hash_fill(ctypes.byref(s), 10, FAKE, FAKE, None) == OS_ENULL
     s = _sk()
     assert L.os_hash_fill(ctypes.byref(s), 10, None, FAKE, None) == OS_ENULL
-    assert L.os_sketch_cols(ctypes.byref(s), None, FAKE, 4, 16, 16, None, 0, FAKE, 320, None) == OS_ENULL
+    assert L.os_sketch_cols(ctypes.byref(s), None, BIG, FAKE, 4, 16, 16, None, 0, FAKE, 4, None) == OS_ENULL
 
 
 def test_sizes_rejected(L):
     s = _sk()
     assert L.os_hash_fill(ctypes.byref(s), 0, FAKE, FAKE, None) == OS_EINVAL
-    assert L.os_hash_fill(ctypes.byref(s), 1 << 40, FAKE, FAKE, None) == OS_EINVAL
+    assert L.os_hash_fill(ctypes.byref(s), 1 << 31, FAKE, FAKE, None) == OS_EINVAL
     # lda < n
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, FAKE, 4, 16, 12, None, 0, FAKE, 320, None) == OS_EINVAL
-    # output narrower than nst * bp (5 blocks * 64)
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, FAKE, 4, 16, 16, None, 0, FAKE, 316, None) == OS_EINVAL
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 16, 12, None, 0, FAKE, 4, None) == OS_EINVAL
+    # output ld < rows (output is (5 blocks * 64) x rows)
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 8, 16, 16, None, 0, FAKE, 4, None) == OS_EINVAL
     # rows beyond the limit
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, FAKE, (1 << 24) + 1, 16, 16, None, 0, FAKE, 320,
-                            None) == OS_EINVAL
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, (1 << 24) + 1, 16, 16, None, 0, FAKE,
+                            1 << 25, None) == OS_EINVAL
+    # prepared buffer too small
+    need = L.os_sketch_prepare_bytes(ctypes.byref(s), 16)
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, need - 1, FAKE, 4, 16, 16, None, 0, FAKE, 4,
+                            None) == OS_EWORKSPACE
+    assert L.os_sketch_prepare(ctypes.byref(s), 16, FAKE, need - 1, None) == OS_EWORKSPACE
     # ldc < l
     assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, None, 0, FAKE, 7, FAKE,
                        1 << 30, None) == OS_EINVAL
@@ -110,12 +124,14 @@ def test_sizes_rejected(L):
 def test_alignment_rejected(L):
     s = _sk()
     odd = ctypes.c_void_p((1 << 20) + 4)
-    assert L.os_sketch_table(ctypes.byref(s), 10, odd, None) == OS_EALIGN
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, odd, 4, 16, 16, None, 0, FAKE, 320, None) == OS_EALIGN
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, FAKE, 4, 15, 15, None, 0, FAKE, 320, None) == OS_EALIGN
-    # the row-sketch input only needs 4-byte alignment: its failure here is the output's ld
-    assert L.os_sketch_rows(ctypes.byref(s), FAKE, odd, 16, 4, 5, None, 0, FAKE, 322, None) == OS_EALIGN
-    assert L.os_gemm_kept(FAKE, 64, FAKE, 64, 4, 4, 64, 1, None, ctypes.c_void_p((1 << 20) + 2), 4,
+    assert L.os_sketch_prepare(ctypes.byref(s), 10, ctypes.c_void_p((1 << 20) + 16), BIG,
+                               None) == OS_EALIGN
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, odd, 4, 16, 16, None, 0, FAKE, 4, None) == OS_EALIGN
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 15, 15, None, 0, FAKE, 4, None) == OS_EALIGN
+    # the row-sketch input only needs 4-byte alignment: here the failure is the output's ld
+    assert L.os_sketch_rows(ctypes.byref(s), FAKE, BIG, odd, 16, 4, 5, None, 0, FAKE, 6, None) == OS_EALIGN
+    assert L.os_sketch_rows(ctypes.byref(s), FAKE, BIG, odd, 16, 4, 5, None, 0, odd, 4, None) == OS_EALIGN
+    assert L.os_gemm_kept(FAKE, 4, FAKE, 4, 4, 4, 64, 1, None, ctypes.c_void_p((1 << 20) + 2), 4,
                           None) == OS_EALIGN
 
 
@@ -123,10 +139,10 @@ def test_keep_mask_rejected(L):
     s = _sk(N=2, e=1)
     none = np.zeros(3, dtype=np.uint8)
     p = none.ctypes.data_as(ctypes.c_void_p)
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, FAKE, 4, 16, 16, p, 1, FAKE, 320, None) == OS_ENOKEEP
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 16, 16, p, 1, FAKE, 4, None) == OS_ENOKEEP
     assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, p, 0, FAKE, 8, FAKE,
                        1 << 30, None) == OS_ENOKEEP
-    assert L.os_gemm_kept(FAKE, 192, FAKE, 192, 4, 4, 64, 3, p, FAKE, 4, None) == OS_ENOKEEP
+    assert L.os_gemm_kept(FAKE, 4, FAKE, 4, 4, 4, 64, 3, p, FAKE, 4, None) == OS_ENOKEEP
 
 
 def test_workspace_rejected(L):

@@ -45,13 +45,14 @@ def rel(x, y):
 
 
 def unpad(S, nst, b):
-    """Drop the per-block padding columns of a block-padded sketch."""
+    """Bucket-major sketch ((nst * bp) x L) -> (L x nst*b) with the per-block
+    padding rows dropped (they must be zero): the oracle's column layout."""
     bp = osk.block_stride(b)
     S = np.asarray(S)
-    assert S.shape[1] == nst * bp
+    assert S.shape[0] == nst * bp
     for j in range(nst):
-        assert np.all(S[:, j * bp + b:(j + 1) * bp] == 0), "padding columns must be zero"
-    return np.concatenate([S[:, j * bp:j * bp + b] for j in range(nst)], axis=1)
+        assert np.all(S[j * bp + b:(j + 1) * bp, :] == 0), "padding rows must be zero"
+    return np.concatenate([S[j * bp:j * bp + b, :] for j in range(nst)], axis=0).T
 
 
 def stored_blocks(N, e, keep, kept_only):
@@ -75,14 +76,22 @@ def test_hash_bit_exact(seed, b, N, e, n):
     np.testing.assert_array_equal(s.cpu().numpy(), so)
 
 
-def test_packed_table_matches_hash():
+def test_prepared_sketch_is_reusable():
+    # one prepared buffer serves both sketch kinds and any mask
     n, b, N, e, seed = 1001, 100, 3, 2, 5
-    t = osk.sketch_table(n, b, N, e, seed=seed).cpu().numpy().view(np.uint32)
-    ho, so = oracle.hash_tables(seed, N + e, n, b)
-    assert t.shape == (N + e, 1004)
-    np.testing.assert_array_equal(t[:, :n] & 0x7FFFFFFF, ho)
-    np.testing.assert_array_equal(np.where(t[:, :n] >> 31, -1, 1), so)
-    assert np.all(t[:, n:] == 0)
+    prep = osk.sketch_prepare(n, b, N, e, seed=seed)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((20, n)).astype(np.float32)
+    keep = np.array([1, 0, 1, 1, 0], np.uint8)
+    a = host(osk.sketch_cols(dev(X), b, N, e, seed=seed, prep=prep, keep=keep, kept_only=True))
+    c = host(osk.sketch_cols(dev(X), b, N, e, seed=seed, keep=keep, kept_only=True))
+    np.testing.assert_array_equal(a, c)
+    h, s = oracle.hash_tables(seed, N + e, n, b)
+    ref = oracle.sketch_cols(X, h, s, b)
+    kept = [0, 2, 3]
+    got = unpad(a, 3, b)
+    for jj, i in enumerate(kept):
+        assert rel(got[:, jj * b:(jj + 1) * b], ref[:, i * b:(i + 1) * b]) <= SKETCH_TOL
 
 
 def test_explicit_tables_pass_through():
@@ -110,9 +119,9 @@ def test_paper_worked_example_on_gpu():
     hd, sd = torch.from_numpy(h).cuda(), torch.from_numpy(s).cuda()
     I9 = np.eye(9)
     out = host(osk.sketch_cols(dev(I9), 3, 1, 0, h=hd, sigma=sd))
-    np.testing.assert_array_equal(unpad(out, 1, 3), ST.T)
+    np.testing.assert_array_equal(unpad(out, 1, 3), ST.T)        # I S_c = S_c
     outT = host(osk.sketch_rows(dev(I9), 3, 1, 0, h=hd, sigma=sd))
-    np.testing.assert_array_equal(unpad(outT, 1, 3), ST.T)
+    np.testing.assert_array_equal(unpad(outT, 1, 3).T, ST)       # S_c^T I = S_c^T
 
 
 @pytest.mark.parametrize("kept_only", [False, True])
@@ -126,9 +135,9 @@ def test_sketch_of_identity_is_bit_exact(b, kept_only):
     expect = np.concatenate([S[:, i * b:(i + 1) * b] for i in blocks], axis=1)
     I = dev(np.eye(n))
     out = host(osk.sketch_cols(I, b, N, e, seed=seed, keep=keep, kept_only=kept_only))
-    np.testing.assert_array_equal(unpad(out, len(blocks), b), expect)
+    np.testing.assert_array_equal(unpad(out, len(blocks), b), expect)          # I S
     outT = host(osk.sketch_rows(I, b, N, e, seed=seed, keep=keep, kept_only=kept_only))
-    np.testing.assert_array_equal(unpad(outT, len(blocks), b), expect)
+    np.testing.assert_array_equal(unpad(outT, len(blocks), b).T, expect.T)     # S^T I
 
 
 @pytest.mark.parametrize("rows,n,b,N,e", [(37, 1003, 100, 3, 2), (256, 4096, 256, 4, 1),
@@ -154,7 +163,7 @@ def test_sketch_rows_random(n, cols, b, N, e):
     X = rng.standard_normal((n, cols)).astype(np.float32)
     outT = unpad(host(osk.sketch_rows(dev(X, ld=cols + 3), b, N, e, seed=seed)), N + e, b)
     h, s = oracle.hash_tables(seed, N + e, n, b)
-    ref = oracle.sketch_rows(X, h, s, b).T                    # cols x (N+e)*b
+    ref = oracle.sketch_rows(X, h, s, b).T                    # cols x (N+e)*b, as unpad gives
     for i in range(N + e):
         assert rel(outT[:, i * b:(i + 1) * b], ref[:, i * b:(i + 1) * b]) <= SKETCH_TOL
 
@@ -175,11 +184,11 @@ def test_sketch_cols_is_deterministic():
 def test_gemm_kept_vs_oracle(m, l, b, nst):
     rng = np.random.default_rng(m * 7 + l)
     bp = osk.block_stride(b)
-    At = np.zeros((m, nst * bp), np.float32)
-    Bt = np.zeros((l, nst * bp), np.float32)
+    At = np.zeros((nst * bp, m), np.float32)        # bucket-major sketch of A
+    Bt = np.zeros((nst * bp, l), np.float32)        # bucket-major sketch of B
     for j in range(nst):
-        At[:, j * bp:j * bp + b] = rng.standard_normal((m, b))
-        Bt[:, j * bp:j * bp + b] = rng.standard_normal((l, b))
+        At[j * bp:j * bp + b, :] = rng.standard_normal((b, m))
+        Bt[j * bp:j * bp + b, :] = rng.standard_normal((b, l))
     keep = np.ones(nst, np.uint8)
     if nst > 1:
         keep[rng.integers(nst)] = 0
