@@ -1,0 +1,241 @@
+"""Benchmark of the sketched product C ~= A S S^T B on one MI355X.
+
+One step = the whole path through the C ABI (os_matmul: prepare the sketch,
+sketch A's columns, sketch B's rows, grouped FP32 MFMA product over the kept
+blocks) on resident synthetic inputs:
+
+    A 8192 x 32768 and B 32768 x 8192, each a rank-64 Gaussian factor product
+    (shared factor) plus N(0, 0.1^2) noise, FP32; count-sketch blocks of width
+    b = 1024, N = 8 needed + e = 2 extra, 2 random blocks dropped by the keep
+    mask.
+
+Reported (one JSON line): effective TFLOP/s = 2 m n l / t_step, the roofline
+of the dominant kernel (the MFMA block product, timed with HIP events on its
+own stream), per-stage times, the relative Frobenius error against the FP64
+exact AB, the exact FP32 GEMM on the same GPU (torch.matmul) as the
+comparator, and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sketched AB eff. TFLOP/s (2mnl/t) at fixed rel-Frob err vs exact GEMM, 1 GPU"
+FP32_MFMA_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix peak
+HBM_PEAK_GBS = 8000.0               # MI355X HBM3E peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--m", type=int, default=8192)
+    p.add_argument("--n", type=int, default=32768)
+    p.add_argument("--l", type=int, default=8192)
+    p.add_argument("--b", type=int, default=1024)
+    p.add_argument("--N", type=int, default=8)
+    p.add_argument("--e", type=int, default=2)
+    p.add_argument("--drop", type=int, default=2)
+    p.add_argument("--seed", type=int, default=2)
+    p.add_argument("--kept-only", action="store_true")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-rows", type=int, default=6144,
+                   help="rows of A and columns of B in the CPU oracle sample")
+    return p.parse_args()
+
+
+def event_time_ms(torch, fn, reps, stream):
+    """Average duration of fn() over reps launches, HIP events on `stream`."""
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        fn()
+        start.record(stream)
+        for _ in range(reps):
+            fn()
+        stop.record(stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1811_02653_amd as osk
+    import synthetic
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    osk.lib()    # fails loudly when the HIP library is not built
+
+    m, n, l, b, N, e = args.m, args.n, args.l, args.b, args.N, args.e
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    A_h, B_h = synthetic.lowrank_pair(m, n, l, args.seed, rank=64, noise=0.1)
+    keep = synthetic.random_keep(N, e, args.seed, drop=args.drop)
+    log("inputs generated in %.1f s; keep mask %s" % (time.time() - t0, keep.tolist()))
+    A = torch.from_numpy(A_h).to(dev)
+    B = torch.from_numpy(B_h).to(dev)
+    C = torch.empty((m, l), dtype=torch.float32, device=dev)
+    ws = torch.empty(osk.workspace_bytes(m, n, l, b, N, e, kept_only=args.kept_only),
+                     dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        osk.matmul(A, B, b, N, e, seed=args.seed, keep=keep, kept_only=args.kept_only, out=C,
+                   workspace=ws, stream=stream)
+
+    # ---- timed region: K whole-path steps
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_per_step = 1e3 * t_total / args.steps
+    eff_tflops = 2.0 * m * n * l / (ms_per_step * 1e-3) / 1e12
+    log("step %.3f ms -> %.1f eff TFLOP/s" % (ms_per_step, eff_tflops))
+
+    # ---- per-stage times (same kernels, called one stage at a time)
+    bp = osk.block_stride(b)
+    nst = osk.stored_count(N, e, keep, args.kept_only)
+    K = int(np.count_nonzero(keep))
+    prep = osk.sketch_prepare(n, b, N, e, seed=args.seed)
+    At = torch.empty((nst * bp, (m + 3) // 4 * 4), dtype=torch.float32, device=dev)[:, :m]
+    Bt = torch.empty((nst * bp, (l + 3) // 4 * 4), dtype=torch.float32, device=dev)[:, :l]
+    stored_keep = None if args.kept_only else keep      # mask over the stored blocks
+    reps = max(3, args.steps)
+    t_prep = event_time_ms(torch, lambda: osk.sketch_prepare(n, b, N, e, seed=args.seed,
+                                                             stream=stream), reps, stream)
+    t_sa = event_time_ms(torch, lambda: osk.sketch_cols(A, b, N, e, seed=args.seed, keep=keep,
+                                                        kept_only=args.kept_only, prep=prep,
+                                                        out=At, stream=stream), reps, stream)
+    t_sb = event_time_ms(torch, lambda: osk.sketch_rows(B, b, N, e, seed=args.seed, keep=keep,
+                                                        kept_only=args.kept_only, prep=prep,
+                                                        out=Bt, stream=stream), reps, stream)
+    t_gemm = event_time_ms(torch, lambda: osk.gemm_kept(At, Bt, b, keep=stored_keep, out=C,
+                                                        stream=stream), reps, stream)
+    gemm_flops = 2.0 * m * l * K * bp
+    gemm_tflops = gemm_flops / (t_gemm * 1e-3) / 1e12
+    sketch_bytes_a = 4.0 * (m * n + m * nst * bp)
+    sketch_bytes_b = 4.0 * (n * l + l * nst * bp)
+    log("stages: prepare %.3f, sketch A %.3f, sketch B %.3f, gemm %.3f ms" %
+        (t_prep, t_sa, t_sb, t_gemm))
+
+    # ---- accuracy against the exact FP64 product (computed on the GPU)
+    step()
+    torch.cuda.synchronize()
+    AB = torch.matmul(A.double(), B.double())
+    Cd = C.double()
+    diff2 = torch.sum((Cd - AB) ** 2).item()
+    ab2 = torch.sum(AB ** 2).item()
+    a2 = torch.sum(A.double() ** 2).item()
+    b2 = torch.sum(B.double() ** 2).item()
+    rel_err = (diff2 / ab2) ** 0.5
+    norm_err2 = diff2 / (a2 * b2)
+    del AB, Cd
+    torch.cuda.empty_cache()
+
+    # ---- exact FP32 GEMM on the same GPU (vendor library) as the comparator
+    Cx = torch.empty((m, l), dtype=torch.float32, device=dev)
+    t_exact = event_time_ms(torch, lambda: torch.matmul(A, B, out=Cx), 3, stream)
+    del Cx
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
+    cpu = None
+    sample_err = None
+    if not args.no_cpu:
+        import oracle
+        r = min(args.cpu_rows, m, l)
+        A_s = A_h[:r, :]
+        B_s = B_h[:, :r]
+        t0 = time.perf_counter()
+        C_ref = oracle.sketched_matmul(A_s, B_s, b, N, e, seed=args.seed, keep=keep)
+        t_cpu = time.perf_counter() - t0
+        cpu_tflops = 2.0 * r * n * r / t_cpu / 1e12
+        cpu = {"value": cpu_tflops, "unit": "TFLOP/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "C[:%d, :%d] of the same product (A[:%d, :] and B[:, :%d], same sketch "
+                         "and mask), FP64 plain loops, %.1f s" % (r, r, r, r, t_cpu)}
+        sample_err = oracle.rel_frob(C[:r, :r].cpu().numpy(), C_ref)
+        log("cpu oracle sample: %.1f s, rel-Frob GPU vs oracle on the sample %.2e" %
+            (t_cpu, sample_err))
+
+    out = {
+        "metric": METRIC,
+        "value": eff_tflops,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "sketched product A %dx%d . B %dx%d, rank-64 Gaussian factor products "
+                        "+ N(0,0.1^2) noise, b=%d, N=%d, e=%d, %d random blocks dropped%s"
+                        % (m, n, n, l, b, N, e, args.drop,
+                           ", dropped blocks skipped at sketch time" if args.kept_only else ""),
+            "m": m, "n": n, "l": l, "b": b, "N": N, "e": e, "kept_blocks": K,
+            "keep_mask": keep.tolist(), "seed": args.seed, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "kernel": "gemm_kept (FP32 v_mfma_f32_32x32x2_f32)",
+            "bound": "mfma",
+            "achieved": gemm_tflops,
+            "peak": FP32_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": gemm_tflops / FP32_MFMA_PEAK_TFLOPS,
+            "traffic": None,
+            "algorithmic_flops_per_launch": gemm_flops,
+            "avg_launch_ms": t_gemm,
+        },
+        "cpu_baseline": cpu,
+        "stages_ms": {"prepare": t_prep, "sketch_A": t_sa, "sketch_B": t_sb, "gemm": t_gemm},
+        "sketch_roofline": {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "sketch_A_achieved": sketch_bytes_a / (t_sa * 1e-3) / 1e9,
+            "sketch_B_achieved": sketch_bytes_b / (t_sb * 1e-3) / 1e9,
+            "sketch_A_frac": sketch_bytes_a / (t_sa * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "sketch_B_frac": sketch_bytes_b / (t_sb * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        },
+        "error": {"rel_frob_vs_exact_fp64": rel_err,
+                  "normalised_err2": norm_err2,
+                  "rel_frob_vs_oracle_sample": sample_err},
+        "exact_gemm": {"kind": "torch.matmul FP32 (hipBLASLt)", "ms": t_exact,
+                       "tflops": 2.0 * m * n * l / (t_exact * 1e-3) / 1e12,
+                       "speedup_of_sketched": t_exact / ms_per_step},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

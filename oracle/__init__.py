@@ -52,6 +52,8 @@ def _load():
     lib = ctypes.CDLL(_LIB)
     i64, u64 = ctypes.c_int64, ctypes.c_uint64
     vp = ctypes.c_void_p
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
     lib.oracle_splitmix64_nth.restype = u64
     lib.oracle_splitmix64_nth.argtypes = [u64, u64]
     lib.oracle_hash_word.restype = u64
@@ -78,6 +80,11 @@ def _p(a: np.ndarray):
 def _f64(x) -> np.ndarray:
     """FP64 C-contiguous copy-if-needed (FP32 -> FP64 is exact)."""
     return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().oracle_num_threads())
 
 
 # ---------------------------------------------------------------------------

@@ -45,8 +45,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define GOLDEN_GAMMA 0x9E3779B97F4A7C15ULL
+
+/* Threads the OpenMP loops below run on. */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* SplitMix64 output for state value `state` (the generator first advances
  * its state by the golden-ratio increment, then applies this finaliser). */
