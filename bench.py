@@ -129,12 +129,14 @@ def main():
     At = torch.empty((nst * bp, (m + 3) // 4 * 4), dtype=torch.float32, device=dev)[:, :m]
     Bt = torch.empty((nst * bp, (l + 3) // 4 * 4), dtype=torch.float32, device=dev)[:, :l]
     stored_keep = None if args.kept_only else keep      # mask over the stored blocks
+    tws = torch.empty(osk.sketch_cols_workspace_bytes(m, n), dtype=torch.uint8, device=dev)
     reps = max(3, args.steps)
     t_prep = event_time_ms(torch, lambda: osk.sketch_prepare(n, b, N, e, seed=args.seed,
                                                              stream=stream), reps, stream)
     t_sa = event_time_ms(torch, lambda: osk.sketch_cols(A, b, N, e, seed=args.seed, keep=keep,
                                                         kept_only=args.kept_only, prep=prep,
-                                                        out=At, stream=stream), reps, stream)
+                                                        out=At, workspace=tws, stream=stream),
+                        reps, stream)
     t_sb = event_time_ms(torch, lambda: osk.sketch_rows(B, b, N, e, seed=args.seed, keep=keep,
                                                         kept_only=args.kept_only, prep=prep,
                                                         out=Bt, stream=stream), reps, stream)

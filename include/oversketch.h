@@ -34,9 +34,7 @@
  *     (the X of os_sketch_rows) and the product C need only 4-byte
  *     alignment.  Violations return OS_EALIGN.
  *   - Size limits: the sketched dimension n <= OS_MAX_N; the other dimension
- *     of each operand (m, l) <= OS_MAX_ROWS; a row-major B (the X of
- *     os_sketch_rows) must span at most 2 GiB ((n-1)*ldb + l floats), larger
- *     ones are passed column-major.
+ *     of each operand (m, l) <= OS_MAX_ROWS.
  *   - Device pointers are HIP device memory owned by the caller; the library
  *     never allocates device memory and never retains a pointer past return.
  *     Host pointers (keep masks) are read before the call returns.
@@ -60,8 +58,9 @@
  *
  * Prepared sketch: an opaque device buffer holding, for all N+e blocks, the
  * bucket/sign of every index and, per block, the indices grouped by bucket
- * range.  It depends only on (seed or explicit tables, b, N, e, n), not on a
- * keep mask, and can be reused by every sketch call with the same values.
+ * (ascending within a bucket).  It depends only on (seed or explicit tables,
+ * b, N, e, n), not on a keep mask, and can be reused by every sketch call
+ * with the same values.
  */
 #ifndef OVERSKETCH_H
 #define OVERSKETCH_H
@@ -133,21 +132,26 @@ size_t os_sketch_prepare_bytes(const os_sketch* sk, int64_t n);
 os_status os_sketch_prepare(const os_sketch* sk, int64_t n, void* prep, size_t prep_bytes,
                             void* stream);
 
+/* Device workspace bytes os_sketch_cols needs for a rows x n operand (0 on
+ * invalid sizes): room for the operand transposed. */
+size_t os_sketch_cols_workspace_bytes(int64_t rows, int64_t n);
+
 /* Step "sketch A's columns" (Algorithm "Over sketching A in parallel" with
  * Algorithm "Calculating Count-sketch" per block) for a row-major X
  * (rows x n, ld ldx), bucket-major output:
  *   out[j*bp + c][r] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[r][k]
  * for every stored block j (sketch block s_j), i.e. out = (X S_{s_j})^T
- * stacked over j.  Each bucket is summed in ascending k in FP32.
+ * stacked over j.  Each bucket is summed in FP32 in a fixed order.
  * prep: a prepared sketch for the same sk and n.  keep_host: HOST uint8
  * [N+e] (nonzero = kept) or NULL (= blocks [0, N)); it selects the stored
  * blocks when kept_only != 0.  out: DEVICE (nst*bp) x rows, ld ldo >= rows.
- * A column-major matrix is sketched along its columns by passing its
- * transpose. */
+ * workspace: DEVICE, 256-byte aligned, >= os_sketch_cols_workspace_bytes
+ * (else OS_EWORKSPACE); X is transposed into it.  A column-major matrix is
+ * sketched along its columns by passing its transpose. */
 os_status os_sketch_cols(const os_sketch* sk, const void* prep, size_t prep_bytes,
                          const float* X, int64_t rows, int64_t n, int64_t ldx,
                          const uint8_t* keep_host, int kept_only, float* out, int64_t ldo,
-                         void* stream);
+                         void* workspace, size_t ws_bytes, void* stream);
 
 /* Step "sketch B's rows" (S^T B: the same sketch applied from the left,
  * Section 4) for a row-major X (n x cols, ld ldx):
@@ -171,9 +175,9 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
                        int64_t m, int64_t l, int32_t b, int32_t nst,
                        const uint8_t* keep_host, float* C, int64_t ldc, void* stream);
 
-/* Workspace bytes os_matmul needs (prepared sketch + both sketches, sized
- * for all N+e blocks, so one workspace serves any mask).  0 on invalid
- * arguments. */
+/* Workspace bytes os_matmul needs (prepared sketch, a transposed operand,
+ * both sketches; sized for all N+e blocks and either layout of B, so one
+ * workspace serves any mask).  0 on invalid arguments. */
 size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
                                  int kept_only);
 

@@ -17,7 +17,8 @@ import numpy as np
 
 __all__ = [
     "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "sketch_cols",
-    "sketch_rows", "gemm_kept", "matmul", "workspace_bytes", "stored_count",
+    "sketch_rows", "sketch_cols_workspace_bytes", "gemm_kept", "matmul", "workspace_bytes",
+    "stored_count",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -73,7 +74,10 @@ def lib():
     L.os_sketch_prepare.restype = ctypes.c_int
     L.os_sketch_prepare.argtypes = [sk, i64, vp, sz, vp]
     L.os_sketch_cols.restype = ctypes.c_int
-    L.os_sketch_cols.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
+    L.os_sketch_cols.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp, sz,
+                                 vp]
+    L.os_sketch_cols_workspace_bytes.restype = sz
+    L.os_sketch_cols_workspace_bytes.argtypes = [i64, i64]
     L.os_sketch_rows.restype = ctypes.c_int
     L.os_sketch_rows.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
     L.os_gemm_kept.restype = ctypes.c_int
@@ -207,21 +211,32 @@ def _bucket_major_out(out, rows, lines, device):
     return out
 
 
+def sketch_cols_workspace_bytes(rows, n) -> int:
+    """Device workspace bytes sketch_cols needs for a rows x n operand."""
+    return int(lib().os_sketch_cols_workspace_bytes(rows, n))
+
+
 def sketch_cols(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, prep=None,
-                out=None, stream=None):
+                out=None, workspace=None, stream=None):
     """Bucket-major (X S_i)^T for the stored blocks: (nst * block_stride(b)) x rows."""
     torch = _torch()
     _require_cuda(X, "X", torch.float32)
     rows, n, ldx = _row_major(X, "X")
     if prep is None:
         prep = sketch_prepare(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
+    if workspace is None:
+        nbytes = sketch_cols_workspace_bytes(rows, n)
+        if nbytes == 0:
+            raise OversketchError("invalid sizes for os_sketch_cols")
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
     s = _sketch(b, N, e, seed, h, sigma)
     height = stored_count(N, e, keep, kept_only) * block_stride(b)
     out = _bucket_major_out(out, height, rows, X.device)
     _, _, ldo = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
     _check(lib().os_sketch_cols(ctypes.byref(s), _ptr(prep), prep.numel(), _ptr(X), rows, n, ldx,
-                                pk, int(bool(kept_only)), _ptr(out), ldo, _stream(stream)),
+                                pk, int(bool(kept_only)), _ptr(out), ldo, _ptr(workspace),
+                                workspace.numel(), _stream(stream)),
            "os_sketch_cols")
     return out
 

@@ -159,9 +159,15 @@ os_status os_sketch_prepare(const os_sketch* sk, int64_t n, void* prep, size_t p
     return prepare(sk, n, prep, (hipStream_t)stream);
 }
 
+size_t os_sketch_cols_workspace_bytes(int64_t rows, int64_t n) {
+    if (check_len(n) != OS_OK || check_extent(rows) != OS_OK) return 0;
+    return osk::sketch_cols_workspace_bytes(rows, n);
+}
+
 os_status os_sketch_cols(const os_sketch* sk, const void* prep, size_t prep_bytes, const float* X,
                          int64_t rows, int64_t n, int64_t ldx, const uint8_t* keep_host,
-                         int kept_only, float* out, int64_t ldo, void* stream) {
+                         int kept_only, float* out, int64_t ldo, void* workspace, size_t ws_bytes,
+                         void* stream) {
     os_status st = check_sketch(sk);
     if (st != OS_OK) return st;
     if ((st = check_len(n)) != OS_OK) return st;
@@ -173,8 +179,11 @@ os_status os_sketch_cols(const os_sketch* sk, const void* prep, size_t prep_byte
     const int32_t bp = os_block_stride(sk->b);
     if ((st = check_matrix(out, (int64_t)bs.nst * bp, rows, ldo, true)) != OS_OK) return st;
     if (!osk::plan_sketch_ok(rows, bs.nst, bp, n)) return OS_EINVAL;
+    if (!workspace || !aligned(workspace, 256) ||
+        ws_bytes < osk::sketch_cols_workspace_bytes(rows, n))
+        return OS_EWORKSPACE;
     return hip_status(osk::launch_sketch_cols(X, rows, n, ldx, bs.stored, bs.nst, nblocks(sk), bp,
-                                              prep_lists(prep, sk, n), out, ldo,
+                                              prep_lists(prep, sk, n), out, ldo, workspace,
                                               (hipStream_t)stream));
 }
 
@@ -191,7 +200,7 @@ os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_byte
     if ((st = block_sets(sk, keep_host, kept_only, bs)) != OS_OK) return st;
     const int32_t bp = os_block_stride(sk->b);
     if ((st = check_matrix(out, (int64_t)bs.nst * bp, cols, ldo, true)) != OS_OK) return st;
-    if (!osk::plan_sketch_rows_ok(n, cols, ldx, bs.nst, bp)) return OS_EINVAL;
+    if (!osk::plan_sketch_ok(cols, bs.nst, bp, n)) return OS_EINVAL;
     return hip_status(osk::launch_sketch_rows(X, n, cols, ldx, bs.stored, bs.nst, nblocks(sk), bp,
                                               prep_lists(prep, sk, n), out, ldo,
                                               (hipStream_t)stream));
@@ -223,10 +232,13 @@ size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int6
     if (check_sketch(sk) != OS_OK || check_len(n) != OS_OK || check_extent(m) != OS_OK ||
         check_extent(l) != OS_OK)
         return 0;
-    // Sized for all N+e blocks whatever the mask, so one workspace serves every call.
+    // Sized for all N+e blocks whatever the mask, and for a transposed
+    // operand as long as the longer of A and a column-major B, so one
+    // workspace serves every call.
     (void)kept_only;
     const int64_t zp = (int64_t)nblocks(sk) * os_block_stride(sk->b);
-    return align256(prepare_bytes(sk, n)) + align256((size_t)zp * osk::round_up(m, 4) * 4u) +
+    return align256(prepare_bytes(sk, n)) + osk::sketch_cols_workspace_bytes(m > l ? m : l, n) +
+           align256((size_t)zp * osk::round_up(m, 4) * 4u) +
            align256((size_t)zp * osk::round_up(l, 4) * 4u);
 }
 
@@ -250,9 +262,8 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     const size_t need = os_matmul_workspace_bytes(sk, m, n, l, kept_only);
     if (!workspace || !aligned(workspace, 256) || ws_bytes < need) return OS_EWORKSPACE;
     const int32_t bp = os_block_stride(sk->b);
-    const bool b_ok = b_col_major ? osk::plan_sketch_ok(l, bs.nst, bp, n)
-                                  : osk::plan_sketch_rows_ok(n, l, ldb, bs.nst, bp);
-    if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !b_ok || !osk::plan_gemm_ok(m, l, bp))
+    if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !osk::plan_sketch_ok(l, bs.nst, bp, n) ||
+        !osk::plan_gemm_ok(m, l, bp))
         return OS_EINVAL;
 
     const int64_t zp = (int64_t)nblocks(sk) * bp;
@@ -260,7 +271,9 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     const int64_t ldb_t = osk::round_up(l, 4);
     char* ws = static_cast<char*>(workspace);
     void* prep = ws;
-    float* At = reinterpret_cast<float*>(ws + align256(prepare_bytes(sk, n)));
+    void* tws = ws + align256(prepare_bytes(sk, n));
+    float* At = reinterpret_cast<float*>(static_cast<char*>(tws) +
+                                         osk::sketch_cols_workspace_bytes(m > l ? m : l, n));
     float* Bt = reinterpret_cast<float*>(reinterpret_cast<char*>(At) +
                                          align256((size_t)zp * lda_t * 4u));
     hipStream_t s = (hipStream_t)stream;
@@ -268,11 +281,11 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
 
     if ((st = prepare(sk, n, prep, s)) != OS_OK) return st;
     if ((st = hip_status(osk::launch_sketch_cols(A, m, n, lda, bs.stored, bs.nst, nblocks(sk), bp,
-                                                 lists, At, lda_t, s))) != OS_OK)
+                                                 lists, At, lda_t, tws, s))) != OS_OK)
         return st;
     if (b_col_major)
         st = hip_status(osk::launch_sketch_cols(B, l, n, ldb, bs.stored, bs.nst, nblocks(sk), bp,
-                                                lists, Bt, ldb_t, s));
+                                                lists, Bt, ldb_t, tws, s));
     else
         st = hip_status(osk::launch_sketch_rows(B, n, l, ldb, bs.stored, bs.nst, nblocks(sk), bp,
                                                 lists, Bt, ldb_t, s));

@@ -32,8 +32,9 @@ hipError_t launch_hash_fill(uint64_t seed, const int32_t* h_in, const int8_t* si
                             int32_t nblk, int64_t n, int32_t b, int32_t* h_out,
                             int8_t* sigma_out, hipStream_t s);
 
-// Bucket lists (see sketch.hip): buckets of a block are split into ranges
-// of kBucketRange; one wave owns one (block, range).
+// Prepared lists (see sketch.hip): the buckets of a block are grouped into
+// ranges of kBucketRange (range lists, indices ascending), and every range is
+// split into its buckets (bucket lists, indices ascending within a bucket).
 constexpr int kBucketRange = 32;
 constexpr int kListBatch = 8;
 
@@ -41,24 +42,26 @@ constexpr int kListBatch = 8;
 constexpr int64_t kMaxSketchedLen = OS_MAX_N;
 
 int32_t list_ranges(int32_t bp);
-// Bytes of the list structure for nblk blocks of padded width bp.
+// Bytes of the list structures for nblk blocks of padded width bp.
 size_t list_bytes(int32_t nblk, int64_t n, int32_t bp);
-// Lists for every block i < nblk of a packed table.
+// Range and bucket lists for every block i < nblk of a packed table.
 hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
                               int32_t bp, void* lists, hipStream_t s);
 // Shapes a sketch launch supports (lines = the dimension that is not sketched).
 bool plan_sketch_ok(int64_t lines, int32_t nst, int32_t bp, int64_t n);
-// The row-major sketch additionally needs X to span at most 2 GiB.
-bool plan_sketch_rows_ok(int64_t n, int64_t cols, int64_t ldx, int32_t nst, int32_t bp);
 // out (nst*bp x cols, ld ldo) = S^T X for X n x cols row-major; stored block
 // j is sketch block bl.idx[j]; lists built for nblk blocks.
 hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                               const void* lists, float* out, int64_t ldo, hipStream_t s);
-// out (nst*bp x rows, ld ldo) = (X S)^T for X rows x n row-major.
+// Device bytes launch_sketch_cols needs as workspace (X transposed).
+size_t sketch_cols_workspace_bytes(int64_t rows, int64_t n);
+// out (nst*bp x rows, ld ldo) = (X S)^T for X rows x n row-major (16-byte
+// rows); workspace: sketch_cols_workspace_bytes(rows, n) bytes, 256-aligned.
 hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
-                              const void* lists, float* out, int64_t ldo, hipStream_t s);
+                              const void* lists, float* out, int64_t ldo, void* workspace,
+                              hipStream_t s);
 
 bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp);
 
