@@ -34,7 +34,8 @@
  *     (the X of os_sketch_rows) and the product C need only 4-byte
  *     alignment.  Violations return OS_EALIGN.
  *   - Size limits: the sketched dimension n <= OS_MAX_N; the other dimension
- *     of each operand (m, l) <= OS_MAX_ROWS.
+ *     of each operand (m, l) <= OS_MAX_ROWS; a row-major B (the X of
+ *     os_sketch_rows) has ld < 2^30.
  *   - Device pointers are HIP device memory owned by the caller; the library
  *     never allocates device memory and never retains a pointer past return.
  *     Host pointers (keep masks) are read before the call returns.

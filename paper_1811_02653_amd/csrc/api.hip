@@ -200,7 +200,7 @@ os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_byte
     if ((st = block_sets(sk, keep_host, kept_only, bs)) != OS_OK) return st;
     const int32_t bp = os_block_stride(sk->b);
     if ((st = check_matrix(out, (int64_t)bs.nst * bp, cols, ldo, true)) != OS_OK) return st;
-    if (!osk::plan_sketch_ok(cols, bs.nst, bp, n)) return OS_EINVAL;
+    if (!osk::plan_sketch_rows_ok(n, cols, ldx, bs.nst, bp)) return OS_EINVAL;
     return hip_status(osk::launch_sketch_rows(X, n, cols, ldx, bs.stored, bs.nst, nblocks(sk), bp,
                                               prep_lists(prep, sk, n), out, ldo,
                                               (hipStream_t)stream));
@@ -262,8 +262,9 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     const size_t need = os_matmul_workspace_bytes(sk, m, n, l, kept_only);
     if (!workspace || !aligned(workspace, 256) || ws_bytes < need) return OS_EWORKSPACE;
     const int32_t bp = os_block_stride(sk->b);
-    if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !osk::plan_sketch_ok(l, bs.nst, bp, n) ||
-        !osk::plan_gemm_ok(m, l, bp))
+    const bool b_ok = b_col_major ? osk::plan_sketch_ok(l, bs.nst, bp, n)
+                                  : osk::plan_sketch_rows_ok(n, l, ldb, bs.nst, bp);
+    if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !b_ok || !osk::plan_gemm_ok(m, l, bp))
         return OS_EINVAL;
 
     const int64_t zp = (int64_t)nblocks(sk) * bp;

@@ -49,6 +49,8 @@ hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int3
                               int32_t bp, void* lists, hipStream_t s);
 // Shapes a sketch launch supports (lines = the dimension that is not sketched).
 bool plan_sketch_ok(int64_t lines, int32_t nst, int32_t bp, int64_t n);
+// The row-major sketch additionally needs a row pitch below 4 GiB.
+bool plan_sketch_rows_ok(int64_t n, int64_t cols, int64_t ldx, int32_t nst, int32_t bp);
 // out (nst*bp x cols, ld ldo) = S^T X for X n x cols row-major; stored block
 // j is sketch block bl.idx[j]; lists built for nblk blocks.
 hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t ldx,

@@ -11,11 +11,11 @@
 // Scheme: the count sketch of a matrix Y whose rows are the sketched index
 // (Y n x L row-major) is a gather-reduce.  The prepared sketch lists, for
 // every (block, bucket), the indices k that hash into the bucket, ascending,
-// with their signs (bucket_split).  One wave produces one bucket row for a
-// strip of W columns: its lanes form 64 / (W/4) row groups of W/4 lanes; per
-// step every group loads the W columns of one listed row with 16-byte loads
-// and adds it with its sign; the groups are combined with cross-lane shuffles
-// at the end.  No atomics, no scatter: every output element is written once.
+// with their signs (bucket_split).  A group of W/4 lanes produces one bucket
+// row for a strip of W columns: it walks the bucket's list, loading the W
+// columns of each listed row with 16-byte loads and adding them with their
+// signs, in ascending k.  No atomics, no scatter, no cross-lane reduction:
+// every output element is summed by one lane and written once.
 //
 // sketch_rows (S^T B, B row-major) is that gather-reduce directly.
 // sketch_cols (A S for A row-major, sketched along its rows) first transposes
@@ -116,10 +116,12 @@ __global__ __launch_bounds__(64) void bucket_split_kernel(const uint32_t* __rest
                                                           const uint2* __restrict__ ent, int64_t n,
                                                           int32_t P, int32_t bp,
                                                           uint32_t* __restrict__ boff,
-                                                          uint2* __restrict__ bent) {
+                                                          uint2* __restrict__ bent,
+                                                          float* __restrict__ zero) {
     const int p = blockIdx.x;
     const int64_t blk = blockIdx.y;
     const int lane = threadIdx.x;
+    if (p == 0 && blk == 0) zero[lane] = 0.f;   // kZeroFloats = 64 = one wave
     const uint32_t beg = off[blk * (P + 1) + p];
     const uint32_t end = off[blk * (P + 1) + p + 1];
     const uint2* le = ent + blk * (n + kBatch);
@@ -208,95 +210,103 @@ __global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict_
 
 // ---------------------------------------------------------------------------
 // Gather-reduce: out[(j*bp + c)*ldo + l] = sum_{k in bucket c of block bl[j]}
-// sign * Y[k][l] for Y n x L row-major (ld ldy).  Workgroup = 4 waves = one
-// range of 32 buckets of one stored block, for one strip of W columns; each
-// wave produces 8 consecutive bucket rows.  Lane = (row group g, column quad
-// q).  kVec: Y 16-byte aligned with ldy a multiple of 4 (16-byte loads;
-// quads past L are clamped and never stored), else four 4-byte loads.
+// sign * Y[k][l] for Y n x L row-major (ld ldy).  A lane group of W/4 lanes
+// owns one bucket row of a strip of W columns (one 16-byte column quad per
+// lane) and walks that bucket's list U rows at a time, in ascending k; a wave
+// holds 64/(W/4) groups (consecutive buckets), a workgroup 4 waves.  Rows past
+// the end of a group's list are masked.  kVec: Y 16-byte aligned
+// with ldy a multiple of 4 (16-byte loads; quads past L are clamped and never
+// stored), else four 4-byte loads per quad.
 // ---------------------------------------------------------------------------
-constexpr int kBucketsPerWave = kRange / 4;
+template <int W>
+struct GatherShape {
+    static constexpr int Q = W / 4;       // lanes per group
+    static constexpr int G = 64 / Q;      // groups (buckets) per wave
+    static constexpr int kBuckets = 4 * G;  // buckets per workgroup
+};
 
 template <int W, bool kVec>
 __global__ __launch_bounds__(256) void gather_kernel(const float* __restrict__ Y, int64_t n,
                                                      int64_t L, int64_t ldy, int32_t bp, int32_t nst,
                                                      BlockList bl, const uint32_t* __restrict__ boff,
                                                      const uint2* __restrict__ bent,
+                                                     const float* __restrict__ zero,
                                                      float* __restrict__ out, int64_t ldo) {
-    constexpr int Q = W / 4;       // lanes per row group
-    constexpr int G = 64 / Q;      // row groups per wave
-    constexpr int U = 4;           // rows per group per step
+    using Sh = GatherShape<W>;
+    constexpr int Q = Sh::Q;
+    constexpr int U = 8;           // rows per group per step
     const int lane = threadIdx.x & 63;
-    const int wave = wave_id();
     const int g = lane / Q;
     const int q = lane % Q;
     const int64_t strips = (L + W - 1) / W;
-    const int64_t ranges = bp / kRange;
-    const int64_t per_strip = (int64_t)nst * ranges;
+    const int64_t groups = (bp + Sh::kBuckets - 1) / Sh::kBuckets;
+    const int64_t per_strip = (int64_t)nst * groups;
     const int64_t task = xcd_task(blockIdx.x, strips * per_strip);
     const int64_t strip = task / per_strip;
     const int64_t rem = task % per_strip;
-    const int j = (int)(rem / ranges);
-    const int c0 = (int)(rem % ranges) * kRange + wave * kBucketsPerWave;
+    const int j = (int)(rem / groups);
+    // with one group per wave the bucket is wave-uniform: its list is then
+    // read with scalar loads
+    const int c = (int)(rem % groups) * Sh::kBuckets +
+                  (Sh::G == 1 ? wave_id() : (int)(threadIdx.x / Q));
+    const bool has = c < bp;
     const int64_t sb = bl.idx[j];
-    const uint32_t* __restrict__ bo = boff + sb * (bp + 1) + c0;
-    const uint2* __restrict__ e = bent + sb * n;
+    const uint32_t beg = has ? boff[sb * (bp + 1) + c] : 0u;
+    const uint32_t cnt = has ? boff[sb * (bp + 1) + c + 1] - beg : 0u;
+    // (an empty list reads entry 0 of the block, always valid, and masks it)
+    const uint2* __restrict__ e = bent + sb * n + (cnt > 0 ? beg : 0u);
+    const uint32_t last = cnt > 0 ? cnt - 1 : 0u;
     const int64_t col = strip * W + 4 * q;
     const int64_t L4 = (L + 3) / 4 * 4;
     const int64_t lcol = kVec ? min(col, L4 - 4) : col;
-    float* o = out + ((int64_t)j * bp + c0) * ldo + col;
 
-    for (int cc = 0; cc < kBucketsPerWave; ++cc, o += ldo) {
-        const uint32_t beg = bo[cc];
-        const uint32_t end = bo[cc + 1];
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (uint32_t base = beg; base < end; base += G * U) {
-            uint2 en[U];
-            bool ok[U];
+    uint32_t most = cnt;           // longest list of the wave
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t i = base + u * G + g;
-                ok[u] = i < end;
-                en[u] = e[ok[u] ? i : beg];
-            }
-            float4 x[U];
+    for (int d = 1; d < 64; d <<= 1) most = max(most, (uint32_t)__shfl_xor((int)most, d));
+
+    // Loads are unconditional: a row past the end of a group's list reads the
+    // 16 zero bytes at `zero` instead, so no branch sits around a load
+    // (branches there make every load wait for the previous ones).
+    const float* yq = Y + lcol;
+    const uint32_t ld4 = (uint32_t)(ldy * 4);   // row pitch in bytes (< 4 GiB, checked at launch)
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (uint32_t it = 0; it < most; it += U) {
+        uint2 en[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const float* p = Y + (int64_t)en[u].x * ldy;
-                if constexpr (kVec) {
-                    x[u] = *reinterpret_cast<const float4*>(p + lcol);
-                } else {
-                    x[u].x = p[min(col + 0, L - 1)];
-                    x[u].y = p[min(col + 1, L - 1)];
-                    x[u].z = p[min(col + 2, L - 1)];
-                    x[u].w = p[min(col + 3, L - 1)];
-                }
-            }
+        for (int u = 0; u < U; ++u) en[u] = e[min(it + u, last)];
+        float4 x[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const float s = __uint_as_float(en[u].y);
-                acc.x = fmaf(s, ok[u] ? x[u].x : 0.f, acc.x);
-                acc.y = fmaf(s, ok[u] ? x[u].y : 0.f, acc.y);
-                acc.z = fmaf(s, ok[u] ? x[u].z : 0.f, acc.z);
-                acc.w = fmaf(s, ok[u] ? x[u].w : 0.f, acc.w);
-            }
-        }
-        // combine the row groups (lanes q, q + Q, q + 2Q, ...)
-#pragma unroll
-        for (int d = Q; d < 64; d <<= 1) {
-            acc.x += __shfl_xor(acc.x, d);
-            acc.y += __shfl_xor(acc.y, d);
-            acc.z += __shfl_xor(acc.z, d);
-            acc.w += __shfl_xor(acc.w, d);
-        }
-        if (g == 0 && col < L) {
-            if (col + 3 < L) {
-                *reinterpret_cast<float4*>(o) = acc;
+        for (int u = 0; u < U; ++u) {
+            const bool ok = it + u < cnt;
+            if constexpr (kVec) {
+                const float* p = reinterpret_cast<const float*>(
+                    reinterpret_cast<const char*>(yq) + (uint64_t)en[u].x * ld4);
+                x[u] = *reinterpret_cast<const float4*>(ok ? p : zero);
             } else {
-                o[0] = acc.x;
-                if (col + 1 < L) o[1] = acc.y;
-                if (col + 2 < L) o[2] = acc.z;
+                const float* p = Y + (int64_t)en[u].x * ldy;
+                x[u].x = *(ok ? p + min(col + 0, L - 1) : zero + 0);
+                x[u].y = *(ok ? p + min(col + 1, L - 1) : zero + 1);
+                x[u].z = *(ok ? p + min(col + 2, L - 1) : zero + 2);
+                x[u].w = *(ok ? p + min(col + 3, L - 1) : zero + 3);
             }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float s = __uint_as_float(en[u].y);   // +-1; masked rows add +-0
+            acc.x = fmaf(s, x[u].x, acc.x);
+            acc.y = fmaf(s, x[u].y, acc.y);
+            acc.z = fmaf(s, x[u].z, acc.z);
+            acc.w = fmaf(s, x[u].w, acc.w);
+        }
+    }
+    if (!has || col >= L) return;
+    float* o = out + ((int64_t)j * bp + c) * ldo + col;
+    if (col + 3 < L) {
+        *reinterpret_cast<float4*>(o) = acc;
+    } else {
+        o[0] = acc.x;
+        if (col + 1 < L) o[1] = acc.y;
+        if (col + 2 < L) o[2] = acc.z;
     }
 }
 
@@ -306,7 +316,9 @@ struct ListView {
     uint2* ent;
     uint32_t* boff;
     uint2* bent;
+    float* zero;     // kZeroFloats zeros (rows past the end of a list read these)
 };
+constexpr int kZeroFloats = 64;
 
 ListView carve_lists(void* lists, int32_t nblk, int64_t n, int32_t bp) {
     const int64_t P = list_ranges(bp);
@@ -321,25 +333,35 @@ ListView carve_lists(void* lists, int32_t nblk, int64_t n, int32_t bp) {
     v.boff = reinterpret_cast<uint32_t*>(base);
     base += round_up((int64_t)nblk * (bp + 1) * 4, 256);
     v.bent = reinterpret_cast<uint2*>(base);
+    base += round_up((int64_t)nblk * n * 8, 256);
+    v.zero = reinterpret_cast<float*>(base);
     return v;
 }
 
-// Column strip width of the gather: 32 columns (128-byte rows) keeps a strip
-// of a 32768-row operand at 4 MiB, one XCD's L2.
-constexpr int kStrip = 32;
+// Column strip width of the gather: 64 columns (256-byte rows, 4 buckets per
+// wave).  Measured on the full-size case against 32 and 256 columns: the
+// sketch of a 32768 x 8192 operand takes 1.44 ms at 64, 1.73 ms at 32 and
+// 1.51 ms at 256.
+constexpr int kStrip = 64;
+
+template <int W>
+int64_t gather_tasks(int64_t L, int32_t nst, int32_t bp) {
+    const int64_t per = GatherShape<W>::kBuckets;
+    return (L + W - 1) / W * nst * ((bp + per - 1) / per);
+}
 
 template <int W>
 hipError_t launch_gather(const float* Y, int64_t n, int64_t L, int64_t ldy, const BlockList& bl,
                          int32_t nst, int32_t bp, const ListView& v, float* out, int64_t ldo,
                          hipStream_t s) {
-    const int64_t tasks = (L + W - 1) / W * nst * (bp / kRange);
+    const int64_t tasks = gather_tasks<W>(L, nst, bp);
     const bool vec = (reinterpret_cast<uintptr_t>(Y) & 15) == 0 && (ldy & 3) == 0;
     if (vec)
         hipLaunchKernelGGL((gather_kernel<W, true>), dim3((unsigned)tasks), dim3(256), 0, s, Y, n, L,
-                           ldy, bp, nst, bl, v.boff, v.bent, out, ldo);
+                           ldy, bp, nst, bl, v.boff, v.bent, v.zero, out, ldo);
     else
         hipLaunchKernelGGL((gather_kernel<W, false>), dim3((unsigned)tasks), dim3(256), 0, s, Y, n,
-                           L, ldy, bp, nst, bl, v.boff, v.bent, out, ldo);
+                           L, ldy, bp, nst, bl, v.boff, v.bent, v.zero, out, ldo);
     return hipGetLastError();
 }
 
@@ -351,7 +373,8 @@ size_t list_bytes(int32_t nblk, int64_t n, int32_t bp) {
     const int64_t P = list_ranges(bp);
     return (size_t)(round_up((int64_t)nblk * P * 4, 256) + round_up((int64_t)nblk * (P + 1) * 4, 256) +
                     round_up((int64_t)nblk * (n + kBatch) * 8, 256) +
-                    round_up((int64_t)nblk * (bp + 1) * 4, 256) + round_up((int64_t)nblk * n * 8, 256));
+                    round_up((int64_t)nblk * (bp + 1) * 4, 256) + round_up((int64_t)nblk * n * 8, 256) +
+                    kZeroFloats * 4);
 }
 
 hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
@@ -365,7 +388,7 @@ hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int3
                        v.off, v.ent);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(bucket_split_kernel, dim3(P, nblk), dim3(64), 0, s, v.off, v.ent, n, P, bp,
-                       v.boff, v.bent);
+                       v.boff, v.bent, v.zero);
     return hipGetLastError();
 }
 
@@ -373,7 +396,7 @@ bool plan_sketch_ok(int64_t lines, int32_t nst, int32_t bp, int64_t n) {
     if (lines < 1 || nst < 1 || nst > OS_MAX_BLOCKS || bp < kBlockAlign || bp % kBlockAlign ||
         n < 1 || n > kMaxSketchedLen)
         return false;
-    const int64_t tasks = (lines + kStrip - 1) / kStrip * nst * (bp / kRange);
+    const int64_t tasks = gather_tasks<kStrip>(lines, nst, bp);
     const int64_t tiles = (n + 63) / 64 * ((lines + 63) / 64);
     return tasks <= 0x7fffffff && tiles <= 0x7fffffff;
 }
@@ -382,10 +405,14 @@ size_t sketch_cols_workspace_bytes(int64_t rows, int64_t n) {
     return (size_t)round_up(n * round_up(rows, 4) * 4, 256);
 }
 
+bool plan_sketch_rows_ok(int64_t n, int64_t cols, int64_t ldx, int32_t nst, int32_t bp) {
+    return plan_sketch_ok(cols, nst, bp, n) && ldx < (int64_t(1) << 30);
+}
+
 hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                               const void* lists, float* out, int64_t ldo, hipStream_t s) {
-    if (!plan_sketch_ok(cols, nst, bp, n)) return hipErrorInvalidValue;
+    if (!plan_sketch_rows_ok(n, cols, ldx, nst, bp)) return hipErrorInvalidValue;
     const ListView v = carve_lists(const_cast<void*>(lists), nblk, n, bp);
     return launch_gather<kStrip>(X, n, cols, ldx, bl, nst, bp, v, out, ldo, s);
 }

@@ -70,7 +70,7 @@ def test_prepare_and_workspace_bytes(L):
     table = 10 * 32772 * 4
     # range lists (counts, offsets, entries) then bucket lists (offsets, entries)
     lists = (r256(10 * P * 4) + r256(10 * (P + 1) * 4) + r256(10 * (n + 8) * 8) +
-             r256(10 * 1025 * 4) + r256(10 * n * 8))
+             r256(10 * 1025 * 4) + r256(10 * n * 8) + 256)     # + 64 zero floats
     assert prep == r256(table) + lists
     m, l = 300, 77
     transposed = r256(n * 300 * 4)          # the longer operand, transposed
