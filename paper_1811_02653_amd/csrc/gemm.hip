@@ -67,13 +67,40 @@ __device__ __forceinline__ void store_tile(float* __restrict__ s, const float4 (
     for (int i = 0; i < 8; ++i) *reinterpret_cast<float4*>(s + (8 * w + i) * LDT + c) = r[i];
 }
 
+// Fragments of one "quad" (4 consecutive k of each lane half) of a 16-deep
+// half step: a[i][kk] = A-tile element (k0 + kk, acol + 32 i), likewise b.
+__device__ __forceinline__ void read_frag(float (&a)[4][4], float (&b)[4][4],
+                                          const float* __restrict__ As,
+                                          const float* __restrict__ Bs, int k0, int acol, int bcol) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            a[i][kk] = As[(k0 + kk) * LDT + acol + 32 * i];
+            b[i][kk] = Bs[(k0 + kk) * LDT + bcol + 32 * i];
+        }
+}
+
+__device__ __forceinline__ void mfma_quad(v16f (&acc)[4][4], const float (&a)[4][4],
+                                          const float (&b)[4][4]) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[j][kk], acc[i][j], 0, 0, 0);
+}
+
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* __restrict__ Bt,
                       int64_t ldbt, int64_t m, int64_t l, int32_t bp, BlockList kept,
                       int32_t nkept, float scale, float* __restrict__ C, int64_t ldc,
                       int32_t tilesM, int32_t tilesN) {
-    __shared__ __align__(16) float As[BK * LDT];
-    __shared__ __align__(16) float Bs[BK * LDT];
+    // two buffers per operand: step t reads buffer t % 2 while the tile of
+    // step t + 1 is stored into the other one
+    __shared__ __align__(16) float As[2][BK * LDT];
+    __shared__ __align__(16) float Bs[2][BK * LDT];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -102,57 +129,55 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
 
     const int tpb = bp / BK;                       // K steps per block
     const int total = nkept * tpb;
-    int kb = 0, kt = 0;
-    int64_t krow = (int64_t)kept.idx[0] * bp;
-
-    float4 ra[8], rb[8];
-    load_tile(ra, At, ldat, row0, m, krow, tid);
-    load_tile(rb, Bt, ldbt, col0, l, krow, tid);
+    // K row of step `step` (kept blocks in order, BK rows per step)
+    auto step_row = [&](int step) -> int64_t {
+        return (int64_t)kept.idx[step / tpb] * bp + (int64_t)(step % tpb) * BK;
+    };
 
     // operand element (k, lane's m or n) lives at [k * LDT + col]
     const int acol = wm * 128 + (lane & 31);
     const int bcol = wn * 128 + (lane & 31);
     const int krow_lane = 8 * (lane >> 5);
+    // first k of quad q (0..3): half q / 2, lane half's 8 rows, 4 per quad
+    auto quad_k = [&](int q) { return (q >> 1) * 16 + krow_lane + 4 * (q & 1); };
 
+    float4 ra[8], rb[8];
+    load_tile(ra, At, ldat, row0, m, step_row(0), tid);
+    load_tile(rb, Bt, ldbt, col0, l, step_row(0), tid);
+    store_tile(As[0], ra, tid);
+    store_tile(Bs[0], rb, tid);
+    if (total > 1) {
+        load_tile(ra, At, ldat, row0, m, step_row(1), tid);
+        load_tile(rb, Bt, ldbt, col0, l, step_row(1), tid);
+    }
+    __syncthreads();
+
+    float fa[4][4], fb[4][4], ga[4][4], gb[4][4];
+    read_frag(fa, fb, As[0], Bs[0], quad_k(0), acol, bcol);
     for (int t = 0; t < total; ++t) {
-        __syncthreads();
-        store_tile(As, ra, tid);
-        store_tile(Bs, rb, tid);
-        __syncthreads();
-        if (++kt == tpb) {
-            kt = 0;
-            ++kb;
-            krow = (kb < nkept) ? (int64_t)kept.idx[kb] * bp : 0;
-        } else {
-            krow += BK;
-        }
+        const int cur = t & 1;
+        const float* as = As[cur];
+        const float* bs = Bs[cur];
+        read_frag(ga, gb, as, bs, quad_k(1), acol, bcol);
+        mfma_quad(acc, fa, fb);
+        read_frag(fa, fb, as, bs, quad_k(2), acol, bcol);
+        mfma_quad(acc, ga, gb);
+        // the next step's tile goes into the other buffer (last read before
+        // the previous step's barrier); the loads for the step after are
+        // issued a whole step ahead of their use
         if (t + 1 < total) {
-            load_tile(ra, At, ldat, row0, m, krow, tid);
-            load_tile(rb, Bt, ldbt, col0, l, krow, tid);
-        }
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-#pragma unroll
-            for (int quad = 0; quad < 2; ++quad) {
-                float a[4][4], b[4][4];
-                const int k0 = half * 16 + krow_lane + 4 * quad;
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        a[i][kk] = As[(k0 + kk) * LDT + acol + 32 * i];
-                        b[i][kk] = Bs[(k0 + kk) * LDT + bcol + 32 * i];
-                    }
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[j][kk],
-                                                                             acc[i][j], 0, 0, 0);
+            store_tile(As[cur ^ 1], ra, tid);
+            store_tile(Bs[cur ^ 1], rb, tid);
+            if (t + 2 < total) {
+                load_tile(ra, At, ldat, row0, m, step_row(t + 2), tid);
+                load_tile(rb, Bt, ldbt, col0, l, step_row(t + 2), tid);
             }
         }
+        read_frag(ga, gb, as, bs, quad_k(3), acol, bcol);
+        mfma_quad(acc, fa, fb);
+        mfma_quad(acc, ga, gb);
+        __syncthreads();
+        if (t + 1 < total) read_frag(fa, fb, As[cur ^ 1], Bs[cur ^ 1], quad_k(0), acol, bcol);
     }
 
     // 32x32 accumulator layout: register r of lane L holds row
