@@ -126,16 +126,15 @@ def main():
     nst = osk.stored_count(N, e, keep, args.kept_only)
     K = int(np.count_nonzero(keep))
     prep = osk.sketch_prepare(n, b, N, e, seed=args.seed)
-    At = torch.empty((nst * bp, (m + 3) // 4 * 4), dtype=torch.float32, device=dev)[:, :m]
-    Bt = torch.empty((nst * bp, (l + 3) // 4 * 4), dtype=torch.float32, device=dev)[:, :l]
+    At = torch.empty((m, nst * bp), dtype=torch.float32, device=dev)
+    Bt = torch.empty((l, nst * bp), dtype=torch.float32, device=dev)
     stored_keep = None if args.kept_only else keep      # mask over the stored blocks
-    tws = torch.empty(osk.sketch_cols_workspace_bytes(m, n), dtype=torch.uint8, device=dev)
     reps = max(3, args.steps)
     t_prep = event_time_ms(torch, lambda: osk.sketch_prepare(n, b, N, e, seed=args.seed,
                                                              stream=stream), reps, stream)
     t_sa = event_time_ms(torch, lambda: osk.sketch_cols(A, b, N, e, seed=args.seed, keep=keep,
                                                         kept_only=args.kept_only, prep=prep,
-                                                        out=At, workspace=tws, stream=stream),
+                                                        out=At, stream=stream),
                         reps, stream)
     t_sb = event_time_ms(torch, lambda: osk.sketch_rows(B, b, N, e, seed=args.seed, keep=keep,
                                                         kept_only=args.kept_only, prep=prep,

@@ -28,14 +28,13 @@
  *
  * Conventions for every entry point:
  *   - Matrices are FP32 and row-major with a leading dimension ("ld", in
- *     elements) >= their column count.  A matrix read 16 bytes at a time
- *     (A, a column-major B, the X of os_sketch_cols, and every sketch) needs a
- *     16-byte aligned base and an ld that is a multiple of 4; a row-major B
- *     (the X of os_sketch_rows) and the product C need only 4-byte
- *     alignment.  Violations return OS_EALIGN.
+ *     elements) >= their column count.  Inputs (A, B, the X of the sketch
+ *     calls) and the product C need 4-byte alignment; a sketch (the output of
+ *     os_sketch_cols / os_sketch_rows, the inputs of os_gemm_kept) is read 16
+ *     bytes at a time and needs a 16-byte aligned base and an ld that is a
+ *     multiple of 4.  Violations return OS_EALIGN.
  *   - Size limits: the sketched dimension n <= OS_MAX_N; the other dimension
- *     of each operand (m, l) <= OS_MAX_ROWS; a row-major B (the X of
- *     os_sketch_rows) has ld < 2^30.
+ *     of each operand (m, l) <= OS_MAX_ROWS.
  *   - Device pointers are HIP device memory owned by the caller; the library
  *     never allocates device memory and never retains a pointer past return.
  *     Host pointers (keep masks) are read before the call returns.
@@ -46,22 +45,25 @@
  *   - No C++ exception crosses this interface.  No entry point keeps mutable
  *     global state; the only per-thread state is os_last_hip_error.
  *
- * Sketch layout ("bucket-major"): a sketch of a matrix with L lines (rows of
- * A, columns of B) over nst stored blocks is a row-major (nst * bp) x L
- * matrix, bp = os_block_stride(b) = b rounded up to a multiple of 32: row
- * j*bp + c holds bucket c of stored block j for every line -- i.e. the sketch
- * of A is (A S)^T and the sketch of B is S^T B, each without the N^{-1/2}
- * factor.  Rows j*bp + b .. (j+1)*bp - 1 are written as zero.  With
- * kept_only = 0 every one of the N+e blocks is stored (block i at position
- * i); with kept_only = 1 only the kept blocks are stored, in ascending block
- * order (the "straggler-resilient sketching" remark of Section 4.1: blocks
- * dropped at sketch time count as stragglers).
+ * Sketch layout ("line-major"): the sketch of a matrix with L lines (rows of
+ * A, columns of B) over nst stored blocks is a row-major L x (nst * bp)
+ * matrix, bp = os_block_stride(b) = b rounded up to a multiple of 32: column
+ * j*bp + c of row r holds bucket c of stored block j for line r -- i.e. the
+ * sketch of A is A S and the sketch of B is (S^T B)^T, each without the
+ * N^{-1/2} factor.  Columns j*bp + b .. (j+1)*bp - 1 are written as zero.
+ * With kept_only = 0 every one of the N+e blocks is stored (block i at
+ * position i); with kept_only = 1 only the kept blocks are stored, in
+ * ascending block order (the "straggler-resilient sketching" remark of
+ * Section 4.1: blocks dropped at sketch time count as stragglers).
  *
  * Prepared sketch: an opaque device buffer holding, for all N+e blocks, the
- * bucket/sign of every index and, per block, the indices grouped by bucket
- * (ascending within a bucket).  It depends only on (seed or explicit tables,
- * b, N, e, n), not on a keep mask, and can be reused by every sketch call
- * with the same values.
+ * bucket/sign of every index and, per block, window of 8192 indices and group
+ * of 64 buckets, the indices of each bucket (ascending), lane-interleaved and
+ * padded to the group's longest bucket.  It depends only on (seed or explicit
+ * tables, b, N, e, n), not on a keep mask, and can be reused by every sketch
+ * call with the same values.  Its size is bounded for ANY tables (a bucket
+ * holding a whole window included): about (N+e) * n * 128 bytes plus
+ * (N+e) * ceil(n / 8192) * (ceil(bp / 64) * 1028) bytes.
  */
 #ifndef OVERSKETCH_H
 #define OVERSKETCH_H
@@ -133,32 +135,27 @@ size_t os_sketch_prepare_bytes(const os_sketch* sk, int64_t n);
 os_status os_sketch_prepare(const os_sketch* sk, int64_t n, void* prep, size_t prep_bytes,
                             void* stream);
 
-/* Device workspace bytes os_sketch_cols needs for a rows x n operand (0 on
- * invalid sizes): room for the operand transposed. */
-size_t os_sketch_cols_workspace_bytes(int64_t rows, int64_t n);
-
 /* Step "sketch A's columns" (Algorithm "Over sketching A in parallel" with
  * Algorithm "Calculating Count-sketch" per block) for a row-major X
- * (rows x n, ld ldx), bucket-major output:
- *   out[j*bp + c][r] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[r][k]
- * for every stored block j (sketch block s_j), i.e. out = (X S_{s_j})^T
- * stacked over j.  Each bucket is summed in FP32 in a fixed order.
+ * (rows x n, ld ldx), line-major output:
+ *   out[r][j*bp + c] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[r][k]
+ * for every stored block j (sketch block s_j), i.e. out = X S_{s_j} side by
+ * side over j.  Each bucket is summed in FP32 in ascending k.
  * prep: a prepared sketch for the same sk and n.  keep_host: HOST uint8
  * [N+e] (nonzero = kept) or NULL (= blocks [0, N)); it selects the stored
- * blocks when kept_only != 0.  out: DEVICE (nst*bp) x rows, ld ldo >= rows.
- * workspace: DEVICE, 256-byte aligned, >= os_sketch_cols_workspace_bytes
- * (else OS_EWORKSPACE); X is transposed into it.  A column-major matrix is
- * sketched along its columns by passing its transpose. */
+ * blocks when kept_only != 0.  out: DEVICE rows x (nst*bp), ld ldo >=
+ * nst*bp.  A column-major matrix is sketched along its rows by passing its
+ * transpose (which is row-major). */
 os_status os_sketch_cols(const os_sketch* sk, const void* prep, size_t prep_bytes,
                          const float* X, int64_t rows, int64_t n, int64_t ldx,
                          const uint8_t* keep_host, int kept_only, float* out, int64_t ldo,
-                         void* workspace, size_t ws_bytes, void* stream);
+                         void* stream);
 
 /* Step "sketch B's rows" (S^T B: the same sketch applied from the left,
- * Section 4) for a row-major X (n x cols, ld ldx):
- *   out[j*bp + c][q] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[k][q],
- * i.e. out = S_{s_j}^T X stacked over j.  Other arguments as in
- * os_sketch_cols; out: DEVICE (nst*bp) x cols, ld ldo >= cols. */
+ * Section 4) for a row-major X (n x cols, ld ldx), line-major output:
+ *   out[q][j*bp + c] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[k][q],
+ * i.e. out = (S_{s_j}^T X)^T side by side over j.  Other arguments as in
+ * os_sketch_cols; out: DEVICE cols x (nst*bp), ld ldo >= nst*bp. */
 os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_bytes,
                          const float* X, int64_t n, int64_t cols, int64_t ldx,
                          const uint8_t* keep_host, int kept_only, float* out, int64_t ldo,
@@ -166,19 +163,20 @@ os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_byte
 
 /* Step "grouped product over the kept blocks" (Algorithm "OverSketch":
  * computation phase plus reduction phase, Fig. (bMM)):
- *   C = (1/K) * sum_{j : keep[j]} At_j^T * Bt_j,
- * At: DEVICE (nst*bp) x m bucket-major sketch of A (ld ldat >= m), Bt: DEVICE
- * (nst*bp) x l bucket-major sketch of B (ld ldbt >= l), At_j / Bt_j = their
- * rows j*bp .. j*bp + bp - 1; keep_host: HOST uint8 [nst] over the STORED
- * blocks, or NULL (= all stored blocks); K = number kept.  C: DEVICE m x l
- * (ld ldc >= l), overwritten.  FP32 inputs, FP32 MFMA accumulation. */
+ *   C = (1/K) * sum_{j : keep[j]} At_j * Bt_j^T,
+ * At: DEVICE m x (nst*bp) line-major sketch of A (ld ldat >= nst*bp), Bt:
+ * DEVICE l x (nst*bp) line-major sketch of B (ld ldbt >= nst*bp), At_j /
+ * Bt_j = their columns j*bp .. j*bp + bp - 1; keep_host: HOST uint8 [nst]
+ * over the STORED blocks, or NULL (= all stored blocks); K = number kept.
+ * C: DEVICE m x l (ld ldc >= l), overwritten.  FP32 inputs, FP32 MFMA
+ * accumulation. */
 os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
                        int64_t m, int64_t l, int32_t b, int32_t nst,
                        const uint8_t* keep_host, float* C, int64_t ldc, void* stream);
 
-/* Workspace bytes os_matmul needs (prepared sketch, a transposed operand,
- * both sketches; sized for all N+e blocks and either layout of B, so one
- * workspace serves any mask).  0 on invalid arguments. */
+/* Workspace bytes os_matmul needs (prepared sketch and both sketches, sized
+ * for all N+e blocks so one workspace serves any mask).  0 on invalid
+ * arguments. */
 size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
                                  int kept_only);
 

@@ -17,8 +17,7 @@ import numpy as np
 
 __all__ = [
     "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "sketch_cols",
-    "sketch_rows", "sketch_cols_workspace_bytes", "gemm_kept", "matmul", "workspace_bytes",
-    "stored_count",
+    "sketch_rows", "gemm_kept", "matmul", "workspace_bytes", "stored_count",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -74,10 +73,7 @@ def lib():
     L.os_sketch_prepare.restype = ctypes.c_int
     L.os_sketch_prepare.argtypes = [sk, i64, vp, sz, vp]
     L.os_sketch_cols.restype = ctypes.c_int
-    L.os_sketch_cols.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp, sz,
-                                 vp]
-    L.os_sketch_cols_workspace_bytes.restype = sz
-    L.os_sketch_cols_workspace_bytes.argtypes = [i64, i64]
+    L.os_sketch_cols.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
     L.os_sketch_rows.restype = ctypes.c_int
     L.os_sketch_rows.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
     L.os_gemm_kept.restype = ctypes.c_int
@@ -200,58 +196,46 @@ def sketch_prepare(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream
     return prep
 
 
-def _bucket_major_out(out, rows, lines, device):
+def _line_major_out(out, lines, width, device):
     torch = _torch()
     if out is None:
-        buf = torch.empty((rows, (lines + 3) // 4 * 4), dtype=torch.float32, device=device)
-        return buf[:, :lines]
+        return torch.empty((lines, width), dtype=torch.float32, device=device)
     _require_cuda(out, "out", torch.float32)
-    if tuple(out.shape) != (rows, lines):
-        raise OversketchError("out must be %d x %d" % (rows, lines))
+    if tuple(out.shape) != (lines, width):
+        raise OversketchError("out must be %d x %d" % (lines, width))
     return out
 
 
-def sketch_cols_workspace_bytes(rows, n) -> int:
-    """Device workspace bytes sketch_cols needs for a rows x n operand."""
-    return int(lib().os_sketch_cols_workspace_bytes(rows, n))
-
-
 def sketch_cols(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, prep=None,
-                out=None, workspace=None, stream=None):
-    """Bucket-major (X S_i)^T for the stored blocks: (nst * block_stride(b)) x rows."""
+                out=None, stream=None):
+    """Line-major X S_i for the stored blocks, side by side: rows x (nst * block_stride(b))."""
     torch = _torch()
     _require_cuda(X, "X", torch.float32)
     rows, n, ldx = _row_major(X, "X")
     if prep is None:
         prep = sketch_prepare(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
-    if workspace is None:
-        nbytes = sketch_cols_workspace_bytes(rows, n)
-        if nbytes == 0:
-            raise OversketchError("invalid sizes for os_sketch_cols")
-        workspace = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
     s = _sketch(b, N, e, seed, h, sigma)
-    height = stored_count(N, e, keep, kept_only) * block_stride(b)
-    out = _bucket_major_out(out, height, rows, X.device)
+    width = stored_count(N, e, keep, kept_only) * block_stride(b)
+    out = _line_major_out(out, rows, width, X.device)
     _, _, ldo = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
     _check(lib().os_sketch_cols(ctypes.byref(s), _ptr(prep), prep.numel(), _ptr(X), rows, n, ldx,
-                                pk, int(bool(kept_only)), _ptr(out), ldo, _ptr(workspace),
-                                workspace.numel(), _stream(stream)),
+                                pk, int(bool(kept_only)), _ptr(out), ldo, _stream(stream)),
            "os_sketch_cols")
     return out
 
 
 def sketch_rows(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, prep=None,
                 out=None, stream=None):
-    """Bucket-major S_i^T X for the stored blocks: (nst * block_stride(b)) x cols."""
+    """Line-major (S_i^T X)^T for the stored blocks, side by side: cols x (nst * block_stride(b))."""
     torch = _torch()
     _require_cuda(X, "X", torch.float32)
     n, cols, ldx = _row_major(X, "X")
     if prep is None:
         prep = sketch_prepare(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
     s = _sketch(b, N, e, seed, h, sigma)
-    height = stored_count(N, e, keep, kept_only) * block_stride(b)
-    out = _bucket_major_out(out, height, cols, X.device)
+    width = stored_count(N, e, keep, kept_only) * block_stride(b)
+    out = _line_major_out(out, cols, width, X.device)
     _, _, ldo = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
     _check(lib().os_sketch_rows(ctypes.byref(s), _ptr(prep), prep.numel(), _ptr(X), n, cols, ldx,
@@ -261,17 +245,17 @@ def sketch_rows(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=No
 
 
 def gemm_kept(At, Bt, b, keep=None, out=None, stream=None):
-    """(1/K) sum over kept stored blocks j of At_j^T Bt_j (m x l), At and Bt
-    bucket-major sketches ((nst * block_stride(b)) x m and x l)."""
+    """(1/K) sum over kept stored blocks j of At_j Bt_j^T (m x l), At and Bt
+    line-major sketches (m x (nst * block_stride(b)) and l x (nst * block_stride(b)))."""
     torch = _torch()
     _require_cuda(At, "At", torch.float32)
     _require_cuda(Bt, "Bt", torch.float32)
-    ha, m, lda = _row_major(At, "At")
-    hb, l, ldb = _row_major(Bt, "Bt")
+    m, wa, lda = _row_major(At, "At")
+    l, wb, ldb = _row_major(Bt, "Bt")
     bp = block_stride(b)
-    if ha != hb or ha % bp:
-        raise OversketchError("At and Bt must both hold nst * block_stride(b) rows")
-    nst = ha // bp
+    if wa != wb or wa % bp:
+        raise OversketchError("At and Bt must both hold nst * block_stride(b) columns")
+    nst = wa // bp
     if out is None:
         out = torch.empty((m, l), dtype=torch.float32, device=At.device)
     _require_cuda(out, "out", torch.float32)

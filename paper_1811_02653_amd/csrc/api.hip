@@ -159,31 +159,22 @@ os_status os_sketch_prepare(const os_sketch* sk, int64_t n, void* prep, size_t p
     return prepare(sk, n, prep, (hipStream_t)stream);
 }
 
-size_t os_sketch_cols_workspace_bytes(int64_t rows, int64_t n) {
-    if (check_len(n) != OS_OK || check_extent(rows) != OS_OK) return 0;
-    return osk::sketch_cols_workspace_bytes(rows, n);
-}
-
 os_status os_sketch_cols(const os_sketch* sk, const void* prep, size_t prep_bytes, const float* X,
                          int64_t rows, int64_t n, int64_t ldx, const uint8_t* keep_host,
-                         int kept_only, float* out, int64_t ldo, void* workspace, size_t ws_bytes,
-                         void* stream) {
+                         int kept_only, float* out, int64_t ldo, void* stream) {
     os_status st = check_sketch(sk);
     if (st != OS_OK) return st;
     if ((st = check_len(n)) != OS_OK) return st;
     if ((st = check_extent(rows)) != OS_OK) return st;
     if ((st = check_prep(sk, n, prep, prep_bytes)) != OS_OK) return st;
-    if ((st = check_matrix(X, rows, n, ldx, true)) != OS_OK) return st;
+    if ((st = check_matrix(X, rows, n, ldx, false)) != OS_OK) return st;
     Blocks bs;
     if ((st = block_sets(sk, keep_host, kept_only, bs)) != OS_OK) return st;
     const int32_t bp = os_block_stride(sk->b);
-    if ((st = check_matrix(out, (int64_t)bs.nst * bp, rows, ldo, true)) != OS_OK) return st;
+    if ((st = check_matrix(out, rows, (int64_t)bs.nst * bp, ldo, true)) != OS_OK) return st;
     if (!osk::plan_sketch_ok(rows, bs.nst, bp, n)) return OS_EINVAL;
-    if (!workspace || !aligned(workspace, 256) ||
-        ws_bytes < osk::sketch_cols_workspace_bytes(rows, n))
-        return OS_EWORKSPACE;
     return hip_status(osk::launch_sketch_cols(X, rows, n, ldx, bs.stored, bs.nst, nblocks(sk), bp,
-                                              prep_lists(prep, sk, n), out, ldo, workspace,
+                                              prep_lists(prep, sk, n), out, ldo,
                                               (hipStream_t)stream));
 }
 
@@ -199,8 +190,8 @@ os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_byte
     Blocks bs;
     if ((st = block_sets(sk, keep_host, kept_only, bs)) != OS_OK) return st;
     const int32_t bp = os_block_stride(sk->b);
-    if ((st = check_matrix(out, (int64_t)bs.nst * bp, cols, ldo, true)) != OS_OK) return st;
-    if (!osk::plan_sketch_rows_ok(n, cols, ldx, bs.nst, bp)) return OS_EINVAL;
+    if ((st = check_matrix(out, cols, (int64_t)bs.nst * bp, ldo, true)) != OS_OK) return st;
+    if (!osk::plan_sketch_ok(cols, bs.nst, bp, n)) return OS_EINVAL;
     return hip_status(osk::launch_sketch_rows(X, n, cols, ldx, bs.stored, bs.nst, nblocks(sk), bp,
                                               prep_lists(prep, sk, n), out, ldo,
                                               (hipStream_t)stream));
@@ -213,8 +204,8 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
     os_status st;
     if ((st = check_extent(m)) != OS_OK || (st = check_extent(l)) != OS_OK) return st;
     const int32_t bp = os_block_stride(b);
-    if ((st = check_matrix(At, (int64_t)nst * bp, m, ldat, true)) != OS_OK) return st;
-    if ((st = check_matrix(Bt, (int64_t)nst * bp, l, ldbt, true)) != OS_OK) return st;
+    if ((st = check_matrix(At, m, (int64_t)nst * bp, ldat, true)) != OS_OK) return st;
+    if ((st = check_matrix(Bt, l, (int64_t)nst * bp, ldbt, true)) != OS_OK) return st;
     if ((st = check_matrix(C, m, l, ldc, false)) != OS_OK) return st;
     BlockList kept;
     int32_t K = 0;
@@ -232,14 +223,12 @@ size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int6
     if (check_sketch(sk) != OS_OK || check_len(n) != OS_OK || check_extent(m) != OS_OK ||
         check_extent(l) != OS_OK)
         return 0;
-    // Sized for all N+e blocks whatever the mask, and for a transposed
-    // operand as long as the longer of A and a column-major B, so one
-    // workspace serves every call.
+    // Sized for all N+e blocks whatever the mask, so one workspace serves
+    // every call.
     (void)kept_only;
     const int64_t zp = (int64_t)nblocks(sk) * os_block_stride(sk->b);
-    return align256(prepare_bytes(sk, n)) + osk::sketch_cols_workspace_bytes(m > l ? m : l, n) +
-           align256((size_t)zp * osk::round_up(m, 4) * 4u) +
-           align256((size_t)zp * osk::round_up(l, 4) * 4u);
+    return align256(prepare_bytes(sk, n)) + align256((size_t)m * zp * 4u) +
+           align256((size_t)l * zp * 4u);
 }
 
 os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const float* B, int64_t ldb,
@@ -250,9 +239,9 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     if (st != OS_OK) return st;
     if ((st = check_len(n)) != OS_OK) return st;
     if ((st = check_extent(m)) != OS_OK || (st = check_extent(l)) != OS_OK) return st;
-    if ((st = check_matrix(A, m, n, lda, true)) != OS_OK) return st;
+    if ((st = check_matrix(A, m, n, lda, false)) != OS_OK) return st;
     if (b_col_major) {
-        if ((st = check_matrix(B, l, n, ldb, true)) != OS_OK) return st;
+        if ((st = check_matrix(B, l, n, ldb, false)) != OS_OK) return st;
     } else {
         if ((st = check_matrix(B, n, l, ldb, false)) != OS_OK) return st;
     }
@@ -262,36 +251,33 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     const size_t need = os_matmul_workspace_bytes(sk, m, n, l, kept_only);
     if (!workspace || !aligned(workspace, 256) || ws_bytes < need) return OS_EWORKSPACE;
     const int32_t bp = os_block_stride(sk->b);
-    const bool b_ok = b_col_major ? osk::plan_sketch_ok(l, bs.nst, bp, n)
-                                  : osk::plan_sketch_rows_ok(n, l, ldb, bs.nst, bp);
-    if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !b_ok || !osk::plan_gemm_ok(m, l, bp))
+    if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !osk::plan_sketch_ok(l, bs.nst, bp, n) ||
+        !osk::plan_gemm_ok(m, l, bp))
         return OS_EINVAL;
 
+    // both sketches use the stored width as leading dimension (a multiple of 32)
+    const int64_t zs = (int64_t)bs.nst * bp;
     const int64_t zp = (int64_t)nblocks(sk) * bp;
-    const int64_t lda_t = osk::round_up(m, 4);
-    const int64_t ldb_t = osk::round_up(l, 4);
     char* ws = static_cast<char*>(workspace);
     void* prep = ws;
-    void* tws = ws + align256(prepare_bytes(sk, n));
-    float* At = reinterpret_cast<float*>(static_cast<char*>(tws) +
-                                         osk::sketch_cols_workspace_bytes(m > l ? m : l, n));
+    float* At = reinterpret_cast<float*>(ws + align256(prepare_bytes(sk, n)));
     float* Bt = reinterpret_cast<float*>(reinterpret_cast<char*>(At) +
-                                         align256((size_t)zp * lda_t * 4u));
+                                         align256((size_t)m * zp * 4u));
     hipStream_t s = (hipStream_t)stream;
     const void* lists = prep_lists(prep, sk, n);
 
     if ((st = prepare(sk, n, prep, s)) != OS_OK) return st;
     if ((st = hip_status(osk::launch_sketch_cols(A, m, n, lda, bs.stored, bs.nst, nblocks(sk), bp,
-                                                 lists, At, lda_t, tws, s))) != OS_OK)
+                                                 lists, At, zs, s))) != OS_OK)
         return st;
     if (b_col_major)
         st = hip_status(osk::launch_sketch_cols(B, l, n, ldb, bs.stored, bs.nst, nblocks(sk), bp,
-                                                lists, Bt, ldb_t, tws, s));
+                                                lists, Bt, zs, s));
     else
         st = hip_status(osk::launch_sketch_rows(B, n, l, ldb, bs.stored, bs.nst, nblocks(sk), bp,
-                                                lists, Bt, ldb_t, s));
+                                                lists, Bt, zs, s));
     if (st != OS_OK) return st;
-    return hip_status(osk::launch_gemm_kept(At, lda_t, Bt, ldb_t, m, l, bp, bs.kept_pos, bs.K,
+    return hip_status(osk::launch_gemm_kept(At, zs, Bt, zs, m, l, bp, bs.kept_pos, bs.K,
                                             1.0f / (float)bs.K, C, ldc, s));
 }
 

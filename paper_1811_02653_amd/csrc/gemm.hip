@@ -1,8 +1,8 @@
 // gemm.hip -- grouped FP32 MFMA product over the kept sketch blocks.
 //
-// Computes C = scale * sum_{j kept} At_j^T * Bt_j, where At_j (bp x m) and
-// Bt_j (bp x l) are the j-th row blocks of the bucket-major sketches
-// (A S)^T and S^T B.
+// Computes C = scale * sum_{j kept} At_j * Bt_j^T, where At_j (m x bp) and
+// Bt_j (l x bp) are the j-th column blocks of the line-major sketches A S
+// and (S^T B)^T.
 // This is the computation phase and the reduction phase of Algorithm
 // "OverSketch" fused into one K loop: the paper's b x b worker products
 // A_tilde(i,k) B_tilde(k,j) for the blocks that returned (Fig. (bMM)) are
@@ -13,14 +13,16 @@
 //   - 256 x 256 output tile per workgroup of 4 waves; each wave owns a
 //     128 x 128 sub-tile = 4 x 4 MFMA blocks of 32 x 32 (256 accumulators
 //     per lane, kept in AGPRs).
-//   - K steps of 32: both operands are K-major (a K row holds 256 contiguous
-//     m or l values, read as 1 KiB per wave instruction), staged through LDS
-//     with a row stride of 260 floats so the two lane halves of an operand
-//     read (k and k + 8) fall in disjoint banks; the next step's tile is
-//     prefetched into registers during the MFMAs.
-//   - Within a 16-deep half step, lane half h of every MFMA reads k = 8h + kk
-//     (kk = 0..7); A and B use the same k order, so the dot products are
-//     unchanged (only their summation order differs).
+//   - K steps of 32: both operands are K-contiguous (a row of the tile is 32
+//     consecutive K values, 128 bytes), loaded with 16-byte coalesced reads
+//     and stored to LDS row by row with a row stride of 36 floats, double
+//     buffered: step t is read from one buffer while step t + 1 is stored
+//     into the other, and step t + 2 is already in flight in registers.
+//   - Lane half h of every MFMA takes k = 16h + kk (kk = 0..15), so a lane
+//     reads its 16 K values of a row as four 16-byte LDS reads; A and B use
+//     the same k order, so the dot products are unchanged (only their
+//     summation order differs).  With the 36-float stride the 16 rows read by
+//     one 16-lane pass fall in disjoint banks.
 //   - Workgroup -> tile mapping keeps neighbouring tiles on one XCD (shared
 //     L2) and rasterises in groups of 4 tile rows.
 #include "internal.h"
@@ -33,7 +35,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int BM = 256;
 constexpr int BN = 256;
 constexpr int BK = 32;
-constexpr int LDT = 260;        // LDS row stride (floats) of a K row of a tile
+constexpr int LDT = 36;         // LDS row stride (floats) of a tile row (32 K values)
 constexpr int kThreads = 256;
 constexpr int kGroupM = 4;
 
@@ -42,54 +44,56 @@ __device__ __forceinline__ int64_t xcd_task(int64_t L, int64_t tasks) {
     return (L % 8) * (tasks / 8) + L / 8;
 }
 
-// Global -> register tile loads: wave w covers K rows 8w .. 8w+7 of the step;
-// lane L the 4 values at column 4L of the 256-wide tile.  Columns at or past
-// `ncols` load zero (a float4 that starts below ncols stays inside the row,
-// whose leading dimension is a multiple of 4 and >= ncols).
-__device__ __forceinline__ void load_tile(float4 (&r)[8], const float* __restrict__ base,
-                                          int64_t ld, int64_t col0, int64_t ncols, int64_t krow,
-                                          int tid) {
-    const int w = tid >> 6;
-    const int64_t col = col0 + 4 * (tid & 63);
+// Global -> register tile loads: thread t covers tile rows t/8 + 32u
+// (u = 0..7) and the 4 K values at 4 (t % 8).  `p` points at row 0 of the
+// tile plus the thread's K offset; rows past `last` (the tile's last row
+// inside the matrix) are clamped to it and their values replaced by zero, so
+// every load is unconditional (a branch around a load would make each use
+// wait for all loads in flight).
+__device__ __forceinline__ void load_tile(float4 (&r)[8], const float* __restrict__ p, int64_t ld,
+                                          int64_t kcol, int rel, int last) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        if (col < ncols)
-            r[i] = *reinterpret_cast<const float4*>(base + (krow + 8 * w + i) * ld + col);
-        else
-            r[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int u = 0; u < 8; ++u) {
+        const int row = min(rel + 32 * u, last);
+        const float4 v = *reinterpret_cast<const float4*>(p + (int64_t)row * ld + kcol);
+        const bool ok = rel + 32 * u <= last;
+        r[u] = make_float4(ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f);
     }
 }
 
 __device__ __forceinline__ void store_tile(float* __restrict__ s, const float4 (&r)[8], int tid) {
-    const int w = tid >> 6;
-    const int c = 4 * (tid & 63);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) *reinterpret_cast<float4*>(s + (8 * w + i) * LDT + c) = r[i];
+    for (int u = 0; u < 8; ++u)
+        *reinterpret_cast<float4*>(s + ((tid >> 3) + 32 * u) * LDT + 4 * (tid & 7)) = r[u];
 }
 
-// Fragments of one "quad" (4 consecutive k of each lane half) of a 16-deep
-// half step: a[i][kk] = A-tile element (k0 + kk, acol + 32 i), likewise b.
-__device__ __forceinline__ void read_frag(float (&a)[4][4], float (&b)[4][4],
+// Fragments of quad q (kk = 4q .. 4q+3) of a step: a[i] = the 4 K values
+// 16h + 4q .. +3 of tile row arow + 32 i (h = lane half), likewise b.
+__device__ __forceinline__ void read_frag(float4 (&a)[4], float4 (&b)[4],
                                           const float* __restrict__ As,
-                                          const float* __restrict__ Bs, int k0, int acol, int bcol) {
+                                          const float* __restrict__ Bs, int q, int arow, int brow,
+                                          int kh) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            a[i][kk] = As[(k0 + kk) * LDT + acol + 32 * i];
-            b[i][kk] = Bs[(k0 + kk) * LDT + bcol + 32 * i];
-        }
+    for (int i = 0; i < 4; ++i) {
+        a[i] = *reinterpret_cast<const float4*>(As + (arow + 32 * i) * LDT + kh + 4 * q);
+        b[i] = *reinterpret_cast<const float4*>(Bs + (brow + 32 * i) * LDT + kh + 4 * q);
+    }
 }
 
-__device__ __forceinline__ void mfma_quad(v16f (&acc)[4][4], const float (&a)[4][4],
-                                          const float (&b)[4][4]) {
+__device__ __forceinline__ float comp(const float4& v, int c) {
+    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
+
+__device__ __forceinline__ void mfma_quad(v16f (&acc)[4][4], const float4 (&a)[4],
+                                          const float4 (&b)[4]) {
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[j][kk], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(a[i], kk), comp(b[j], kk),
+                                                                 acc[i][j], 0, 0, 0);
 }
 
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
@@ -97,10 +101,8 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
                       int64_t ldbt, int64_t m, int64_t l, int32_t bp, BlockList kept,
                       int32_t nkept, float scale, float* __restrict__ C, int64_t ldc,
                       int32_t tilesM, int32_t tilesN) {
-    // two buffers per operand: step t reads buffer t % 2 while the tile of
-    // step t + 1 is stored into the other one
-    __shared__ __align__(16) float As[2][BK * LDT];
-    __shared__ __align__(16) float Bs[2][BK * LDT];
+    __shared__ __align__(16) float As[2][BM * LDT];
+    __shared__ __align__(16) float Bs[2][BN * LDT];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -129,38 +131,43 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
 
     const int tpb = bp / BK;                       // K steps per block
     const int total = nkept * tpb;
-    // K row of step `step` (kept blocks in order, BK rows per step)
-    auto step_row = [&](int step) -> int64_t {
+    // first K column of step `step` (kept blocks in order, BK columns per step)
+    auto step_col = [&](int step) -> int64_t {
         return (int64_t)kept.idx[step / tpb] * bp + (int64_t)(step % tpb) * BK;
     };
 
-    // operand element (k, lane's m or n) lives at [k * LDT + col]
-    const int acol = wm * 128 + (lane & 31);
-    const int bcol = wn * 128 + (lane & 31);
-    const int krow_lane = 8 * (lane >> 5);
-    // first k of quad q (0..3): half q / 2, lane half's 8 rows, 4 per quad
-    auto quad_k = [&](int q) { return (q >> 1) * 16 + krow_lane + 4 * (q & 1); };
+    const int arow = wm * 128 + (lane & 31);
+    const int brow = wn * 128 + (lane & 31);
+    const int kh = 16 * (lane >> 5);
+
+    // the tile rows this thread loads: t/8 + 32u, clamped to the last row
+    // inside the matrix
+    const float* pa = At + row0 * ldat + 4 * (tid & 7);
+    const float* pb = Bt + col0 * ldbt + 4 * (tid & 7);
+    const int rel = tid >> 3;
+    const int alast = (int)min((int64_t)BM - 1, m - 1 - row0);
+    const int blast = (int)min((int64_t)BN - 1, l - 1 - col0);
 
     float4 ra[8], rb[8];
-    load_tile(ra, At, ldat, row0, m, step_row(0), tid);
-    load_tile(rb, Bt, ldbt, col0, l, step_row(0), tid);
+    load_tile(ra, pa, ldat, step_col(0), rel, alast);
+    load_tile(rb, pb, ldbt, step_col(0), rel, blast);
     store_tile(As[0], ra, tid);
     store_tile(Bs[0], rb, tid);
     if (total > 1) {
-        load_tile(ra, At, ldat, row0, m, step_row(1), tid);
-        load_tile(rb, Bt, ldbt, col0, l, step_row(1), tid);
+        load_tile(ra, pa, ldat, step_col(1), rel, alast);
+        load_tile(rb, pb, ldbt, step_col(1), rel, blast);
     }
     __syncthreads();
 
-    float fa[4][4], fb[4][4], ga[4][4], gb[4][4];
-    read_frag(fa, fb, As[0], Bs[0], quad_k(0), acol, bcol);
+    float4 fa[4], fb[4], ga[4], gb[4];
+    read_frag(fa, fb, As[0], Bs[0], 0, arow, brow, kh);
     for (int t = 0; t < total; ++t) {
         const int cur = t & 1;
         const float* as = As[cur];
         const float* bs = Bs[cur];
-        read_frag(ga, gb, as, bs, quad_k(1), acol, bcol);
+        read_frag(ga, gb, as, bs, 1, arow, brow, kh);
         mfma_quad(acc, fa, fb);
-        read_frag(fa, fb, as, bs, quad_k(2), acol, bcol);
+        read_frag(fa, fb, as, bs, 2, arow, brow, kh);
         mfma_quad(acc, ga, gb);
         // the next step's tile goes into the other buffer (last read before
         // the previous step's barrier); the loads for the step after are
@@ -169,15 +176,15 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
             store_tile(As[cur ^ 1], ra, tid);
             store_tile(Bs[cur ^ 1], rb, tid);
             if (t + 2 < total) {
-                load_tile(ra, At, ldat, row0, m, step_row(t + 2), tid);
-                load_tile(rb, Bt, ldbt, col0, l, step_row(t + 2), tid);
+                load_tile(ra, pa, ldat, step_col(t + 2), rel, alast);
+                load_tile(rb, pb, ldbt, step_col(t + 2), rel, blast);
             }
         }
-        read_frag(ga, gb, as, bs, quad_k(3), acol, bcol);
+        read_frag(ga, gb, as, bs, 3, arow, brow, kh);
         mfma_quad(acc, fa, fb);
         mfma_quad(acc, ga, gb);
         __syncthreads();
-        if (t + 1 < total) read_frag(fa, fb, As[cur ^ 1], Bs[cur ^ 1], quad_k(0), acol, bcol);
+        if (t + 1 < total) read_frag(fa, fb, As[cur ^ 1], Bs[cur ^ 1], 0, arow, brow, kh);
     }
 
     // 32x32 accumulator layout: register r of lane L holds row

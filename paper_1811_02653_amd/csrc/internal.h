@@ -32,43 +32,36 @@ hipError_t launch_hash_fill(uint64_t seed, const int32_t* h_in, const int8_t* si
                             int32_t nblk, int64_t n, int32_t b, int32_t* h_out,
                             int8_t* sigma_out, hipStream_t s);
 
-// Prepared lists (see sketch.hip): the buckets of a block are grouped into
-// ranges of kBucketRange (range lists, indices ascending), and every range is
-// split into its buckets (bucket lists, indices ascending within a bucket).
-constexpr int kBucketRange = 32;
-constexpr int kListBatch = 8;
+// Prepared lists (see sketch.hip): for every block, window of
+// kSketchWindow sketched indices and group of 64 buckets, the entries of
+// each bucket (window offset and sign), lane-interleaved and padded.
+constexpr int kSketchWindow = 8192;
 
 // Longest sketched dimension (list entries hold k as 32 bits).
 constexpr int64_t kMaxSketchedLen = OS_MAX_N;
 
-int32_t list_ranges(int32_t bp);
 // Bytes of the list structures for nblk blocks of padded width bp.
 size_t list_bytes(int32_t nblk, int64_t n, int32_t bp);
-// Range and bucket lists for every block i < nblk of a packed table.
+// Lists for every block i < nblk of a packed table.
 hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
                               int32_t bp, void* lists, hipStream_t s);
 // Shapes a sketch launch supports (lines = the dimension that is not sketched).
 bool plan_sketch_ok(int64_t lines, int32_t nst, int32_t bp, int64_t n);
-// The row-major sketch additionally needs a row pitch below 4 GiB.
-bool plan_sketch_rows_ok(int64_t n, int64_t cols, int64_t ldx, int32_t nst, int32_t bp);
-// out (nst*bp x cols, ld ldo) = S^T X for X n x cols row-major; stored block
-// j is sketch block bl.idx[j]; lists built for nblk blocks.
+// out (cols x nst*bp, ld ldo) = (S^T X)^T for X n x cols row-major (ld ldx);
+// stored block j is sketch block bl.idx[j]; lists built for nblk blocks.
 hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                               const void* lists, float* out, int64_t ldo, hipStream_t s);
-// Device bytes launch_sketch_cols needs as workspace (X transposed).
-size_t sketch_cols_workspace_bytes(int64_t rows, int64_t n);
-// out (nst*bp x rows, ld ldo) = (X S)^T for X rows x n row-major (16-byte
-// rows); workspace: sketch_cols_workspace_bytes(rows, n) bytes, 256-aligned.
+// out (rows x nst*bp, ld ldo) = X S for X rows x n row-major (ld ldx).
 hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
-                              const void* lists, float* out, int64_t ldo, void* workspace,
-                              hipStream_t s);
+                              const void* lists, float* out, int64_t ldo, hipStream_t s);
 
 bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp);
 
 // C = scale * sum over the kept stored blocks (kept.idx[0 .. nkept)) of
-// At_j^T * Bt_j, with At (nst*bp x m) and Bt (nst*bp x l) bucket-major.
+// At_j * Bt_j^T, with At (m x nst*bp) and Bt (l x nst*bp) line-major
+// sketches (column block j = columns j*bp .. j*bp + bp - 1).
 hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
                             int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                             int32_t nkept, float scale, float* C, int64_t ldc, hipStream_t s);

@@ -1,37 +1,43 @@
 // sketch.hip -- count-sketch kernels for gfx950.
 //
 // Both sketches apply the blocks of S (Eq. (sketch_matrix)) to one operand:
-// every input element x at sketched index k is added, with sign
-// sigma_i(k), into bucket h_i(k) of every stored block i (Algorithm
-// "Calculating Count-sketch of a matrix A", applied block by block as in
-// Algorithm "Over sketching A in parallel").  Outputs are bucket-major: row
-// j*bp + c of the result holds bucket c of stored block j for every line
-// (the layout of S^T X), which is what the block product reads.
+// every input element x at sketched index k is added, with sign sigma_i(k),
+// into bucket h_i(k) of every stored block i (Algorithm "Calculating
+// Count-sketch of a matrix A", applied block by block as in Algorithm "Over
+// sketching A in parallel").
 //
-// Scheme: the count sketch of a matrix Y whose rows are the sketched index
-// (Y n x L row-major) is a gather-reduce.  The prepared sketch lists, for
-// every (block, bucket), the indices k that hash into the bucket, ascending,
-// with their signs (bucket_split).  A group of W/4 lanes produces one bucket
-// row for a strip of W columns: it walks the bucket's list, loading the W
-// columns of each listed row with 16-byte loads and adding them with their
-// signs, in ascending k.  No atomics, no scatter, no cross-lane reduction:
-// every output element is summed by one lane and written once.
+// A "line" is a vector over the sketched index: a row of A (m lines of
+// length n) or a column of B (l lines of length n).  The sketch of a line is
+// a row of the output: out[line][j*bp + c] = bucket c of stored block j
+// (line-major; the sketch of A is A S, the sketch of B is (S^T B)^T).
 //
-// sketch_rows (S^T B, B row-major) is that gather-reduce directly.
-// sketch_cols (A S for A row-major, sketched along its rows) first transposes
-// A into the caller's workspace (LDS-tiled, coalesced on both sides) and then
-// runs the same gather-reduce on A^T.
+// Scheme (read-once): a workgroup owns kLines = 4 lines and keeps ALL their
+// buckets -- every stored block -- in registers (a pass covers up to
+// 8 * kMaxSlots groups of 64 buckets; wider sketches take several passes).
+// It walks the sketched index in windows of kWin = 8192: the window of its
+// 4 lines is staged in LDS once as kWin float4 (the 4 lines' values at one
+// k side by side), and every lane then adds, for each bucket it owns, the
+// window entries hashed into that bucket: one 16-byte LDS read and four FMAs
+// per entry.  Each input element is read from HBM once.  No atomics: every
+// bucket of every line is summed by one lane, in ascending k.
 //
-// Workgroups are ordered strip-major and spread over the XCDs in contiguous
-// runs, so the workgroups that read one column strip run on one XCD and
-// re-read it from that XCD's L2.
+// Which entries a lane adds comes from the prepared sketch, built once per
+// (seed or tables, b, N, e, n): for every block i, window w and group q of 64
+// consecutive buckets, a lane-interleaved list ("chunks" of 8 entries per
+// lane, 1 KiB per chunk) padded to the longest bucket of the group.  An entry
+// is 16 bits: the window offset of k (bits 0..14) and the sign (bit 15); the
+// padding entry points at a zero row.
 #include "internal.h"
 
 namespace osk {
 namespace {
 
-constexpr int kRange = kBucketRange;   // buckets per range list (32)
-constexpr int kBatch = kListBatch;     // slack at the end of each block's list
+constexpr int kWin = kSketchWindow;    // sketched indices per window (8192)
+constexpr int kLines = 4;              // lines per workgroup
+constexpr int kThreads = 512;          // 8 waves
+constexpr int kWaves = kThreads / 64;
+constexpr int kPerThread = kWin / kThreads;   // window positions staged per thread (16)
+constexpr uint16_t kPad = (uint16_t)kWin;     // entry of the zero row, positive
 
 // Spread consecutive task ids over the 8 XCDs in contiguous runs: task T is
 // run by the workgroup with linear id L where T = (L % 8) * (tasks / 8) + L / 8,
@@ -41,354 +47,351 @@ __device__ __forceinline__ int64_t xcd_task(int64_t L, int64_t tasks) {
     return (L % 8) * (tasks / 8) + L / 8;
 }
 
-// Index of the wave within the workgroup, as a wave-uniform (scalar) value.
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
 __device__ __forceinline__ uint64_t lanes_below() {
     const int lane = threadIdx.x & 63;
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// ---------------------------------------------------------------------------
-// Range lists, built for every sketch block i < nblk.  For block i and range
-// p of kRange buckets:
-//   ent[i*(n+kBatch) + off[i][p] .. off[i][p+1]) = {k, (h - p*kRange) | sign<<31}
-// for every k with h_i(k) in [p*kRange, (p+1)*kRange), k ascending.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void count_lists_kernel(const uint32_t* __restrict__ table,
-                                                         int64_t n, int64_t nt, int32_t P,
-                                                         uint32_t* __restrict__ cnt) {
-    const int p = blockIdx.x;
-    const int j = blockIdx.y;
-    const uint32_t* row = table + (int64_t)j * nt;
-    uint32_t c = 0;
-    for (int64_t k = threadIdx.x; k < n; k += 64)
-        c += (((row[k] & 0x7FFFFFFFu) / kRange) == (uint32_t)p) ? 1u : 0u;
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
 #pragma unroll
-    for (int s = 32; s > 0; s >>= 1) c += __shfl_xor(c, s);
-    if (threadIdx.x == 0) cnt[(int64_t)j * P + p] = c;
+    for (int d = 1; d < 64; d <<= 1) x = max(x, (uint32_t)__shfl_xor((int)x, d));
+    return x;
 }
 
-__global__ __launch_bounds__(64) void fill_lists_kernel(const uint32_t* __restrict__ table, int64_t n,
-                                                        int64_t nt, int32_t P,
-                                                        const uint32_t* __restrict__ cnt,
-                                                        uint32_t* __restrict__ off,
-                                                        uint2* __restrict__ ent) {
-    const int p = blockIdx.x;
-    const int j = blockIdx.y;
+// ---------------------------------------------------------------------------
+// Prepared lists.  One wave per (window w, block i).
+//   hdr[(i*nwin + w)*qn + q] = chunk base (bits 0..15) | chunk count (16..31)
+//     of group q (buckets 64q .. 64q+63) within the (i, w) region;
+//   ell region (i, w) = RC chunks of 64 lanes x 8 entries; lane L of group q
+//     holds the entries of bucket 64q + L at positions 0, 1, ... (entry t in
+//     chunk base + t/8, slot t%8), ascending k, then padding.
+// The per-group chunk counts sum to at most ceil(kw/8) + qn = RC, because the
+// longest bucket of a group holds at most the group's entries.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restrict__ table,
+                                                       int64_t n, int64_t nt, int32_t bp,
+                                                       int32_t qn, int32_t nwin, int64_t RC,
+                                                       uint32_t* __restrict__ hdr,
+                                                       uint16_t* __restrict__ ell) {
+    extern __shared__ uint32_t sm[];
+    uint32_t* cnt = sm;            // [bp] counts, then cursors
+    uint32_t* qbase = sm + bp;     // [qn] chunk base of each group
+    uint32_t* qlen = qbase + qn;   // [qn] chunk count of each group
+    const int w = blockIdx.x;
+    const int64_t i = blockIdx.y;
     const int lane = threadIdx.x;
-    // offset of this range within the block's entries
-    uint32_t before = 0;
-    for (int q = lane; q < p; q += 64) before += cnt[(int64_t)j * P + q];
-#pragma unroll
-    for (int s = 32; s > 0; s >>= 1) before += __shfl_xor(before, s);
-    if (lane == 0) {
-        off[(int64_t)j * (P + 1) + p] = before;
-        if (p == P - 1) off[(int64_t)j * (P + 1) + P] = before + cnt[(int64_t)j * P + p];
-    }
-    const uint32_t* row = table + (int64_t)j * nt;
-    uint2* out = ent + (int64_t)j * (n + kBatch) + before;
-    const uint64_t below = lanes_below();
-    uint32_t pos = 0;
-    for (int64_t k0 = 0; k0 < n; k0 += 64) {
-        const int64_t k = k0 + lane;
-        const uint32_t e = k < n ? row[k] : 0u;
-        const uint32_t h = e & 0x7FFFFFFFu;
-        const bool mine = k < n && h / kRange == (uint32_t)p;
-        const uint64_t mask = __ballot(mine);
-        if (mine) {
-            const uint32_t at = pos + (uint32_t)__popcll(mask & below);
-            out[at] = make_uint2((uint32_t)k, (h - (uint32_t)p * kRange) | (e & 0x80000000u));
+    const int64_t k0 = (int64_t)w * kWin;
+    const int kw = (int)min((int64_t)kWin, n - k0);
+    const uint32_t* row = table + i * nt + k0;
+    uint32_t* H = hdr + (i * nwin + w) * qn;
+    uint16_t* region = ell + (i * nwin + w) * RC * 512;
+
+    for (int c = lane; c < bp; c += 64) cnt[c] = 0;
+    __syncthreads();
+    for (int t = lane; t < kw; t += 64) atomicAdd(&cnt[row[t] & 0x7FFFFFFFu], 1u);
+    __syncthreads();
+
+    uint32_t base = 0;
+    for (int q = 0; q < qn; ++q) {
+        const int c = 64 * q + lane;
+        const uint32_t x = c < bp ? cnt[c] : 0u;
+        const uint32_t nch = (wave_max(x) + 7) / 8;
+        if (lane == 0) {
+            H[q] = base | (nch << 16);
+            qbase[q] = base;
+            qlen[q] = nch;
         }
-        pos += (uint32_t)__popcll(mask);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Bucket lists: a stable split of every range list into its kRange buckets.
-//   boff[i][c] .. boff[i][c+1]   entries of bucket c of block i (boff[i][bp] =
-//                                the block's total)
-//   bent[i*n + t] = {k, sign as +-1.0f}, k ascending within a bucket
-// One wave per (range, block).  Bucket positions share the range list's
-// index space: a range's buckets are a permutation of its list.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void bucket_split_kernel(const uint32_t* __restrict__ off,
-                                                          const uint2* __restrict__ ent, int64_t n,
-                                                          int32_t P, int32_t bp,
-                                                          uint32_t* __restrict__ boff,
-                                                          uint2* __restrict__ bent,
-                                                          float* __restrict__ zero) {
-    const int p = blockIdx.x;
-    const int64_t blk = blockIdx.y;
-    const int lane = threadIdx.x;
-    if (p == 0 && blk == 0) zero[lane] = 0.f;   // kZeroFloats = 64 = one wave
-    const uint32_t beg = off[blk * (P + 1) + p];
-    const uint32_t end = off[blk * (P + 1) + p + 1];
-    const uint2* le = ent + blk * (n + kBatch);
-    const uint64_t below = lanes_below();
-
-    // entries per bucket: lane c < kRange counts bucket c
-    uint32_t count = 0;
-    for (uint32_t a = beg; a < end; a += 64) {
-        const uint32_t i = a + lane;
-        const uint32_t c = i < end ? (le[i].y & (kRange - 1)) : (uint32_t)kRange;
-#pragma unroll
-        for (int b = 0; b < kRange; ++b) {
-            const uint32_t m = (uint32_t)__popcll(__ballot(c == (uint32_t)b));
-            if (lane == b) count += m;
-        }
-    }
-    // exclusive prefix over the buckets of the range
-    uint32_t incl = count;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(incl, d);
-        if (lane >= d) incl += y;
-    }
-    uint32_t next = beg + incl - count;   // next free position of bucket `lane`
-    if (lane < kRange && p * kRange + lane < bp) boff[blk * (bp + 1) + p * kRange + lane] = next;
-    if (p == P - 1 && lane == 0) boff[blk * (bp + 1) + bp] = end;
-
-    uint2* out = bent + blk * n;
-    for (uint32_t a = beg; a < end; a += 64) {
-        const uint32_t i = a + lane;
-        const bool valid = i < end;
-        const uint2 e = valid ? le[i] : make_uint2(0u, 0u);
-        const uint32_t c = valid ? (e.y & (kRange - 1)) : (uint32_t)kRange;
-        uint32_t at = 0;
-#pragma unroll
-        for (int b = 0; b < kRange; ++b) {
-            const uint64_t mask = __ballot(c == (uint32_t)b);
-            const uint32_t start = __shfl(next, b);
-            if (c == (uint32_t)b) at = start + (uint32_t)__popcll(mask & below);
-            if (lane == b) next += (uint32_t)__popcll(mask);
-        }
-        if (valid)
-            out[at] = make_uint2(e.x, __float_as_uint((e.y & 0x80000000u) ? -1.0f : 1.0f));
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Transpose: Y (n x rows, ld ldy) = X^T for X rows x n (ld ldx, 16-byte rows).
-// 64 x 64 tiles through LDS (row stride 65: conflict-free both ways); 256
-// threads, four float4 per thread each way.  Columns of Y at or past `rows`
-// (up to ldy) are written as zero.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict__ X, int64_t rows,
-                                                        int64_t n, int64_t ldx,
-                                                        float* __restrict__ Y, int64_t ldy) {
-    __shared__ float t[64][65];
-    const int tid = threadIdx.x;
-    const int64_t row_tiles = (rows + 63) / 64;
-    const int64_t k0 = (int64_t)blockIdx.x / row_tiles * 64;   // column tile of X (row tile of Y)
-    const int64_t r0 = (int64_t)blockIdx.x % row_tiles * 64;   // row tile of X
-    const int sub = tid >> 4;                      // 0..15
-    const int c4 = 4 * (tid & 15);                 // 0..60
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = sub + 16 * i;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r0 + r < rows && k0 + c4 < n)
-            v = *reinterpret_cast<const float4*>(X + (r0 + r) * ldx + k0 + c4);
-        t[r][c4 + 0] = v.x;
-        t[r][c4 + 1] = v.y;
-        t[r][c4 + 2] = v.z;
-        t[r][c4 + 3] = v.w;
+        base += nch;
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int kr = sub + 16 * i;
-        const int64_t k = k0 + kr;
-        const int64_t col = r0 + c4;
-        if (k < n && col < ldy) {
-            const float4 v = make_float4(t[c4 + 0][kr], t[c4 + 1][kr], t[c4 + 2][kr], t[c4 + 3][kr]);
-            *reinterpret_cast<float4*>(Y + k * ldy + col) = v;
+    for (int c = lane; c < bp; c += 64) cnt[c] = 0;
+    __syncthreads();
+
+    // Stable scatter: chunks of 64 consecutive k; lanes holding the same
+    // bucket ("peers") are found bit by bit with ballots and ranked by lane.
+    int nbits = 1;
+    while ((1 << nbits) < bp) ++nbits;
+    const uint64_t below = lanes_below();
+    for (int t0 = 0; t0 < kw; t0 += 64) {
+        const int t = t0 + lane;
+        const bool valid = t < kw;
+        const uint32_t e = valid ? row[t] : 0u;
+        const uint32_t h = e & 0x7FFFFFFFu;
+        uint64_t peers = __ballot(valid);
+        for (int bit = 0; bit < nbits; ++bit) {
+            const bool set = (h >> bit) & 1u;
+            const uint64_t B = __ballot(valid && set);
+            peers &= set ? B : ~B;
         }
+        uint32_t pos = 0;
+        if (valid) {
+            pos = cnt[h] + (uint32_t)__popcll(peers & below);
+            const uint32_t chunk = qbase[h >> 6] + pos / 8;
+            region[(int64_t)chunk * 512 + (h & 63) * 8 + (pos & 7)] =
+                (uint16_t)(t | ((e >> 31) << 15));
+        }
+        __builtin_amdgcn_wave_barrier();
+        // the highest peer advances the bucket's cursor (one writer per bucket)
+        if (valid && (peers >> lane) == 1ull) cnt[h] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // padding up to each group's chunk count
+    for (int q = 0; q < qn; ++q) {
+        const int c = 64 * q + lane;
+        const uint32_t have = c < bp ? cnt[c] : 0u;
+        const uint32_t len = qlen[q] * 8;
+        const uint32_t qb = qbase[q];
+        for (uint32_t p = have; p < len; ++p)
+            region[(int64_t)(qb + p / 8) * 512 + lane * 8 + (p & 7)] = kPad;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Gather-reduce: out[(j*bp + c)*ldo + l] = sum_{k in bucket c of block bl[j]}
-// sign * Y[k][l] for Y n x L row-major (ld ldy).  A lane group of W/4 lanes
-// owns one bucket row of a strip of W columns (one 16-byte column quad per
-// lane) and walks that bucket's list U rows at a time, in ascending k; a wave
-// holds 64/(W/4) groups (consecutive buckets), a workgroup 4 waves.  Rows past
-// the end of a group's list are masked.  kVec: Y 16-byte aligned
-// with ldy a multiple of 4 (16-byte loads; quads past L are clamped and never
-// stored), else four 4-byte loads per quad.
+// The sketch kernel.
+//   kRowLines = true : lines are rows of X (lines x n, ld ldx); thread stages
+//                      X[line0 + r][k] for r < 4 with four 4-byte loads
+//                      (coalesced across lanes along k).
+//   kRowLines = false: lines are columns of X (n x lines, ld ldx); thread
+//                      stages X[k][line0 .. line0+3] with one 16-byte load when
+//                      vec (X 16-byte aligned, ldx % 4 == 0), else four.
+// Window position k of the staged window is handled by thread k % 512.
 // ---------------------------------------------------------------------------
-template <int W>
-struct GatherShape {
-    static constexpr int Q = W / 4;       // lanes per group
-    static constexpr int G = 64 / Q;      // groups (buckets) per wave
-    static constexpr int kBuckets = 4 * G;  // buckets per workgroup
-};
-
-template <int W, bool kVec>
-__global__ __launch_bounds__(256) void gather_kernel(const float* __restrict__ Y, int64_t n,
-                                                     int64_t L, int64_t ldy, int32_t bp, int32_t nst,
-                                                     BlockList bl, const uint32_t* __restrict__ boff,
-                                                     const uint2* __restrict__ bent,
-                                                     const float* __restrict__ zero,
-                                                     float* __restrict__ out, int64_t ldo) {
-    using Sh = GatherShape<W>;
-    constexpr int Q = Sh::Q;
-    constexpr int U = 8;           // rows per group per step
-    const int lane = threadIdx.x & 63;
-    const int g = lane / Q;
-    const int q = lane % Q;
-    const int64_t strips = (L + W - 1) / W;
-    const int64_t groups = (bp + Sh::kBuckets - 1) / Sh::kBuckets;
-    const int64_t per_strip = (int64_t)nst * groups;
-    const int64_t task = xcd_task(blockIdx.x, strips * per_strip);
-    const int64_t strip = task / per_strip;
-    const int64_t rem = task % per_strip;
-    const int j = (int)(rem / groups);
-    // with one group per wave the bucket is wave-uniform: its list is then
-    // read with scalar loads
-    const int c = (int)(rem % groups) * Sh::kBuckets +
-                  (Sh::G == 1 ? wave_id() : (int)(threadIdx.x / Q));
-    const bool has = c < bp;
-    const int64_t sb = bl.idx[j];
-    const uint32_t beg = has ? boff[sb * (bp + 1) + c] : 0u;
-    const uint32_t cnt = has ? boff[sb * (bp + 1) + c + 1] - beg : 0u;
-    // (an empty list reads entry 0 of the block, always valid, and masks it)
-    const uint2* __restrict__ e = bent + sb * n + (cnt > 0 ? beg : 0u);
-    const uint32_t last = cnt > 0 ? cnt - 1 : 0u;
-    const int64_t col = strip * W + 4 * q;
-    const int64_t L4 = (L + 3) / 4 * 4;
-    const int64_t lcol = kVec ? min(col, L4 - 4) : col;
-
-    uint32_t most = cnt;           // longest list of the wave
+template <bool kRowLines>
+__device__ __forceinline__ void load_window(float4 (&r)[kPerThread], const float* __restrict__ X,
+                                            int64_t lines, int64_t ldx, int64_t line0,
+                                            int64_t k0, int kw, bool vec) {
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) most = max(most, (uint32_t)__shfl_xor((int)most, d));
-
-    // Loads are unconditional: a row past the end of a group's list reads the
-    // 16 zero bytes at `zero` instead, so no branch sits around a load
-    // (branches there make every load wait for the previous ones).
-    const float* yq = Y + lcol;
-    const uint32_t ld4 = (uint32_t)(ldy * 4);   // row pitch in bytes (< 4 GiB, checked at launch)
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (uint32_t it = 0; it < most; it += U) {
-        uint2 en[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) en[u] = e[min(it + u, last)];
-        float4 x[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool ok = it + u < cnt;
-            if constexpr (kVec) {
-                const float* p = reinterpret_cast<const float*>(
-                    reinterpret_cast<const char*>(yq) + (uint64_t)en[u].x * ld4);
-                x[u] = *reinterpret_cast<const float4*>(ok ? p : zero);
+    for (int u = 0; u < kPerThread; ++u) {
+        const int k = tid + u * kThreads;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (k < kw) {
+            const int64_t kk = k0 + k;
+            if constexpr (kRowLines) {
+                const float* p = X + line0 * ldx + kk;
+                v.x = p[0];
+                if (line0 + 1 < lines) v.y = p[ldx];
+                if (line0 + 2 < lines) v.z = p[2 * ldx];
+                if (line0 + 3 < lines) v.w = p[3 * ldx];
             } else {
-                const float* p = Y + (int64_t)en[u].x * ldy;
-                x[u].x = *(ok ? p + min(col + 0, L - 1) : zero + 0);
-                x[u].y = *(ok ? p + min(col + 1, L - 1) : zero + 1);
-                x[u].z = *(ok ? p + min(col + 2, L - 1) : zero + 2);
-                x[u].w = *(ok ? p + min(col + 3, L - 1) : zero + 3);
+                const float* p = X + kk * ldx + line0;
+                if (vec && line0 + 3 < lines) {
+                    v = *reinterpret_cast<const float4*>(p);
+                } else {
+                    v.x = p[0];
+                    if (line0 + 1 < lines) v.y = p[1];
+                    if (line0 + 2 < lines) v.z = p[2];
+                    if (line0 + 3 < lines) v.w = p[3];
+                }
             }
         }
+        r[u] = v;
+    }
+}
+
+__device__ __forceinline__ void add_entry(float4& acc, const float4* __restrict__ win, uint32_t e) {
+    // e: 16-bit entry in the low half; sign bit 15 -> sign of the FP32 +-1.0
+    const float4 v = win[e & 0x7FFFu];
+    const float s = __uint_as_float(0x3F800000u | ((e << 16) & 0x80000000u));
+    acc.x = fmaf(s, v.x, acc.x);
+    acc.y = fmaf(s, v.y, acc.y);
+    acc.z = fmaf(s, v.z, acc.z);
+    acc.w = fmaf(s, v.w, acc.w);
+}
+
+__device__ __forceinline__ void add_chunk(float4& acc, const float4* __restrict__ win, uint4 e) {
+    add_entry(acc, win, e.x);
+    add_entry(acc, win, e.x >> 16);
+    add_entry(acc, win, e.y);
+    add_entry(acc, win, e.y >> 16);
+    add_entry(acc, win, e.z);
+    add_entry(acc, win, e.z >> 16);
+    add_entry(acc, win, e.w);
+    add_entry(acc, win, e.w >> 16);
+}
+
+template <int kSlots, bool kRowLines>
+__global__ __launch_bounds__(kThreads) void sketch_kernel(
+    const float* __restrict__ X, int64_t lines, int64_t n, int64_t ldx, int vec, int32_t bp,
+    int32_t qn, int32_t nwin, int32_t nst, BlockList bl, int64_t RC,
+    const uint32_t* __restrict__ hdr, const uint4* __restrict__ ell, float* __restrict__ out,
+    int64_t ldo, int32_t npass) {
+    __shared__ float4 win[kWin + 1];    // row kWin stays zero
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t groups = (lines + kLines - 1) / kLines;
+    const int64_t task = xcd_task(blockIdx.x, groups * npass);
+    const int64_t line0 = task / npass * kLines;
+    const int pass = (int)(task % npass);
+    const int gslots = nst * qn;         // groups of 64 buckets over the stored blocks
+
+    float4 acc[kSlots];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const float s = __uint_as_float(en[u].y);   // +-1; masked rows add +-0
-            acc.x = fmaf(s, x[u].x, acc.x);
-            acc.y = fmaf(s, x[u].y, acc.y);
-            acc.z = fmaf(s, x[u].z, acc.z);
-            acc.w = fmaf(s, x[u].w, acc.w);
+    for (int s = 0; s < kSlots; ++s) acc[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tid == 0) win[kWin] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    float4 pre[kPerThread];
+    load_window<kRowLines>(pre, X, lines, ldx, line0, 0, (int)min((int64_t)kWin, n), vec);
+    for (int w = 0; w < nwin; ++w) {
+        __syncthreads();                 // the previous window is no longer read
+#pragma unroll
+        for (int u = 0; u < kPerThread; ++u) win[tid + u * kThreads] = pre[u];
+        __syncthreads();
+        if (w + 1 < nwin) {
+            const int64_t k1 = (int64_t)(w + 1) * kWin;
+            load_window<kRowLines>(pre, X, lines, ldx, line0, k1, (int)min((int64_t)kWin, n - k1),
+                                   vec);
+        }
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            const int G = (pass * kSlots + s) * kWaves + wave;   // wave-uniform
+            if (G < gslots) {
+                const int j = G / qn;
+                const int q = G - j * qn;
+                const int64_t i = bl.idx[j];
+                const uint32_t h = hdr[(i * nwin + w) * qn + q];
+                const uint32_t nch = h >> 16;
+                const uint4* __restrict__ ch =
+                    ell + ((i * nwin + w) * RC + (h & 0xFFFFu)) * 64 + lane;
+                if (nch > 0) {
+                    uint4 e = ch[0];
+                    for (uint32_t c = 1; c < nch; ++c) {
+                        const uint4 nx = ch[(int64_t)c * 64];
+                        add_chunk(acc[s], win, e);
+                        e = nx;
+                    }
+                    add_chunk(acc[s], win, e);
+                }
+            }
         }
     }
-    if (!has || col >= L) return;
-    float* o = out + ((int64_t)j * bp + c) * ldo + col;
-    if (col + 3 < L) {
-        *reinterpret_cast<float4*>(o) = acc;
-    } else {
-        o[0] = acc.x;
-        if (col + 1 < L) o[1] = acc.y;
-        if (col + 2 < L) o[2] = acc.z;
+
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        const int G = (pass * kSlots + s) * kWaves + wave;
+        if (G < gslots) {
+            const int j = G / qn;
+            const int c = (G - j * qn) * 64 + lane;
+            if (c < bp) {
+                float* o = out + line0 * ldo + (int64_t)j * bp + c;
+                o[0] = acc[s].x;
+                if (line0 + 1 < lines) o[ldo] = acc[s].y;
+                if (line0 + 2 < lines) o[2 * ldo] = acc[s].z;
+                if (line0 + 3 < lines) o[3 * ldo] = acc[s].w;
+            }
+        }
     }
+}
+
+// Slot counts compiled: 1, 2, 4, 8, 12, 16, 20, 24 (4 registers per slot).
+constexpr int kMaxSlots = 24;
+
+template <int S, bool R>
+hipError_t launch_one(dim3 grid, hipStream_t st, const float* X, int64_t lines, int64_t n,
+                      int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin, int32_t nst,
+                      const BlockList& bl, int64_t RC, const uint32_t* hdr, const uint4* ell,
+                      float* out, int64_t ldo, int32_t npass) {
+    hipLaunchKernelGGL((sketch_kernel<S, R>), grid, dim3(kThreads), 0, st, X, lines, n,
+                       ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass);
+    return hipGetLastError();
+}
+
+template <bool R>
+hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const float* X, int64_t lines,
+                        int64_t n, int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin,
+                        int32_t nst, const BlockList& bl, int64_t RC, const uint32_t* hdr,
+                        const uint4* ell, float* out, int64_t ldo, int32_t npass) {
+#define OSK_SLOT_CASE(S)                                                                     \
+    if (slots <= S)                                                                          \
+        return launch_one<S, R>(grid, st, X, lines, n, ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, \
+                                ell, out, ldo, npass);
+    OSK_SLOT_CASE(1)
+    OSK_SLOT_CASE(2)
+    OSK_SLOT_CASE(4)
+    OSK_SLOT_CASE(8)
+    OSK_SLOT_CASE(12)
+    OSK_SLOT_CASE(16)
+    OSK_SLOT_CASE(20)
+    OSK_SLOT_CASE(24)
+#undef OSK_SLOT_CASE
+    return hipErrorInvalidValue;
+}
+
+struct Plan {
+    int32_t qn;      // groups of 64 buckets per block
+    int32_t nwin;    // windows over the sketched dimension
+    int64_t RC;      // chunks per (block, window) region
+};
+
+Plan plan_of(int64_t n, int32_t bp) {
+    Plan p;
+    p.qn = (bp + 63) / 64;
+    p.nwin = (int32_t)((n + kWin - 1) / kWin);
+    p.RC = (min((int64_t)kWin, n) + 7) / 8 + p.qn;
+    return p;
 }
 
 struct ListView {
-    uint32_t* cnt;
-    uint32_t* off;
-    uint2* ent;
-    uint32_t* boff;
-    uint2* bent;
-    float* zero;     // kZeroFloats zeros (rows past the end of a list read these)
+    uint32_t* hdr;
+    uint4* ell;
 };
-constexpr int kZeroFloats = 64;
 
 ListView carve_lists(void* lists, int32_t nblk, int64_t n, int32_t bp) {
-    const int64_t P = list_ranges(bp);
+    const Plan p = plan_of(n, bp);
     char* base = static_cast<char*>(lists);
     ListView v;
-    v.cnt = reinterpret_cast<uint32_t*>(base);
-    base += round_up((int64_t)nblk * P * 4, 256);
-    v.off = reinterpret_cast<uint32_t*>(base);
-    base += round_up((int64_t)nblk * (P + 1) * 4, 256);
-    v.ent = reinterpret_cast<uint2*>(base);
-    base += round_up((int64_t)nblk * (n + kBatch) * 8, 256);
-    v.boff = reinterpret_cast<uint32_t*>(base);
-    base += round_up((int64_t)nblk * (bp + 1) * 4, 256);
-    v.bent = reinterpret_cast<uint2*>(base);
-    base += round_up((int64_t)nblk * n * 8, 256);
-    v.zero = reinterpret_cast<float*>(base);
+    v.hdr = reinterpret_cast<uint32_t*>(base);
+    base += round_up((int64_t)nblk * p.nwin * p.qn * 4, 256);
+    v.ell = reinterpret_cast<uint4*>(base);
     return v;
 }
 
-// Column strip width of the gather: 64 columns (256-byte rows, 4 buckets per
-// wave).  Measured on the full-size case against 32 and 256 columns: the
-// sketch of a 32768 x 8192 operand takes 1.44 ms at 64, 1.73 ms at 32 and
-// 1.51 ms at 256.
-constexpr int kStrip = 64;
-
-template <int W>
-int64_t gather_tasks(int64_t L, int32_t nst, int32_t bp) {
-    const int64_t per = GatherShape<W>::kBuckets;
-    return (L + W - 1) / W * nst * ((bp + per - 1) / per);
+// Passes and slots per pass for nst stored blocks.
+void pass_plan(int32_t nst, int32_t qn, int32_t* npass, int32_t* slots) {
+    const int64_t gs = (int64_t)nst * qn;
+    const int64_t per = (int64_t)kWaves * kMaxSlots;
+    const int64_t P = (gs + per - 1) / per;
+    const int64_t need = (gs + P - 1) / P;               // groups per pass
+    *npass = (int32_t)P;
+    *slots = (int32_t)((need + kWaves - 1) / kWaves);
 }
 
-template <int W>
-hipError_t launch_gather(const float* Y, int64_t n, int64_t L, int64_t ldy, const BlockList& bl,
-                         int32_t nst, int32_t bp, const ListView& v, float* out, int64_t ldo,
-                         hipStream_t s) {
-    const int64_t tasks = gather_tasks<W>(L, nst, bp);
-    const bool vec = (reinterpret_cast<uintptr_t>(Y) & 15) == 0 && (ldy & 3) == 0;
-    if (vec)
-        hipLaunchKernelGGL((gather_kernel<W, true>), dim3((unsigned)tasks), dim3(256), 0, s, Y, n, L,
-                           ldy, bp, nst, bl, v.boff, v.bent, v.zero, out, ldo);
-    else
-        hipLaunchKernelGGL((gather_kernel<W, false>), dim3((unsigned)tasks), dim3(256), 0, s, Y, n,
-                           L, ldy, bp, nst, bl, v.boff, v.bent, v.zero, out, ldo);
-    return hipGetLastError();
+hipError_t launch_sketch(bool row_lines, const float* X, int64_t lines, int64_t n, int64_t ldx,
+                         const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
+                         const void* lists, float* out, int64_t ldo, hipStream_t s) {
+    const Plan p = plan_of(n, bp);
+    const ListView v = carve_lists(const_cast<void*>(lists), nblk, n, bp);
+    int32_t npass, slots;
+    pass_plan(nst, p.qn, &npass, &slots);
+    const int64_t groups = (lines + kLines - 1) / kLines;
+    const dim3 grid((unsigned)(groups * npass));
+    const int vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (ldx & 3) == 0;
+    if (row_lines)
+        return launch_slots<true>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin, nst, bl,
+                                  p.RC, v.hdr, v.ell, out, ldo, npass);
+    return launch_slots<false>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin, nst, bl,
+                               p.RC, v.hdr, v.ell, out, ldo, npass);
 }
 
 }  // namespace
 
-int32_t list_ranges(int32_t bp) { return (bp + kRange - 1) / kRange; }
-
 size_t list_bytes(int32_t nblk, int64_t n, int32_t bp) {
-    const int64_t P = list_ranges(bp);
-    return (size_t)(round_up((int64_t)nblk * P * 4, 256) + round_up((int64_t)nblk * (P + 1) * 4, 256) +
-                    round_up((int64_t)nblk * (n + kBatch) * 8, 256) +
-                    round_up((int64_t)nblk * (bp + 1) * 4, 256) + round_up((int64_t)nblk * n * 8, 256) +
-                    kZeroFloats * 4);
+    const Plan p = plan_of(n, bp);
+    return (size_t)round_up((int64_t)nblk * p.nwin * p.qn * 4, 256) +
+           (size_t)nblk * (size_t)p.nwin * (size_t)p.RC * 1024u;
 }
 
 hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
                               int32_t bp, void* lists, hipStream_t s) {
-    const int32_t P = list_ranges(bp);
+    const Plan p = plan_of(n, bp);
     const ListView v = carve_lists(lists, nblk, n, bp);
-    hipLaunchKernelGGL(count_lists_kernel, dim3(P, nblk), dim3(64), 0, s, table, n, nt, P, v.cnt);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fill_lists_kernel, dim3(P, nblk), dim3(64), 0, s, table, n, nt, P, v.cnt,
-                       v.off, v.ent);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(bucket_split_kernel, dim3(P, nblk), dim3(64), 0, s, v.off, v.ent, n, P, bp,
-                       v.boff, v.bent, v.zero);
+    const size_t lds = (size_t)(bp + 2 * p.qn) * 4;
+    hipLaunchKernelGGL(ell_build_kernel, dim3((unsigned)p.nwin, (unsigned)nblk), dim3(64), lds, s,
+                       table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
+                       reinterpret_cast<uint16_t*>(v.ell));
     return hipGetLastError();
 }
 
@@ -396,41 +399,25 @@ bool plan_sketch_ok(int64_t lines, int32_t nst, int32_t bp, int64_t n) {
     if (lines < 1 || nst < 1 || nst > OS_MAX_BLOCKS || bp < kBlockAlign || bp % kBlockAlign ||
         n < 1 || n > kMaxSketchedLen)
         return false;
-    const int64_t tasks = gather_tasks<kStrip>(lines, nst, bp);
-    const int64_t tiles = (n + 63) / 64 * ((lines + 63) / 64);
-    return tasks <= 0x7fffffff && tiles <= 0x7fffffff;
-}
-
-size_t sketch_cols_workspace_bytes(int64_t rows, int64_t n) {
-    return (size_t)round_up(n * round_up(rows, 4) * 4, 256);
-}
-
-bool plan_sketch_rows_ok(int64_t n, int64_t cols, int64_t ldx, int32_t nst, int32_t bp) {
-    return plan_sketch_ok(cols, nst, bp, n) && ldx < (int64_t(1) << 30);
+    const Plan p = plan_of(n, bp);
+    int32_t npass, slots;
+    pass_plan(nst, p.qn, &npass, &slots);
+    const int64_t groups = (lines + kLines - 1) / kLines;
+    return groups * npass <= 0x7fffffff && slots <= kMaxSlots;
 }
 
 hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                               const void* lists, float* out, int64_t ldo, hipStream_t s) {
-    if (!plan_sketch_rows_ok(n, cols, ldx, nst, bp)) return hipErrorInvalidValue;
-    const ListView v = carve_lists(const_cast<void*>(lists), nblk, n, bp);
-    return launch_gather<kStrip>(X, n, cols, ldx, bl, nst, bp, v, out, ldo, s);
+    if (!plan_sketch_ok(cols, nst, bp, n)) return hipErrorInvalidValue;
+    return launch_sketch(false, X, cols, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s);
 }
 
 hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
-                              const void* lists, float* out, int64_t ldo, void* workspace,
-                              hipStream_t s) {
+                              const void* lists, float* out, int64_t ldo, hipStream_t s) {
     if (!plan_sketch_ok(rows, nst, bp, n)) return hipErrorInvalidValue;
-    float* Xt = static_cast<float*>(workspace);
-    const int64_t ldt = round_up(rows, 4);
-    const int64_t tiles = (n + 63) / 64 * ((rows + 63) / 64);
-    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)tiles), dim3(256), 0, s, X, rows, n, ldx, Xt,
-                       ldt);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const ListView v = carve_lists(const_cast<void*>(lists), nblk, n, bp);
-    return launch_gather<kStrip>(Xt, n, rows, ldt, bl, nst, bp, v, out, ldo, s);
+    return launch_sketch(true, X, rows, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s);
 }
 
 }  // namespace osk

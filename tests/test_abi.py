@@ -66,18 +66,16 @@ def test_prepare_and_workspace_bytes(L):
     n = 32769
     prep = L.os_sketch_prepare_bytes(ctypes.byref(s), n)
     r256 = lambda x: (x + 255) // 256 * 256
-    P = 1024 // 32
     table = 10 * 32772 * 4
-    # range lists (counts, offsets, entries) then bucket lists (offsets, entries)
-    lists = (r256(10 * P * 4) + r256(10 * (P + 1) * 4) + r256(10 * (n + 8) * 8) +
-             r256(10 * 1025 * 4) + r256(10 * n * 8) + 256)     # + 64 zero floats
+    nwin, qn = 5, 16                          # windows of 8192 indices, groups of 64 buckets
+    rc = 8192 // 8 + qn                       # 1 KiB chunks per (block, window)
+    lists = r256(10 * nwin * qn * 4) + 10 * nwin * rc * 1024
     assert prep == r256(table) + lists
+    small = L.os_sketch_prepare_bytes(ctypes.byref(_sk(b=64, N=1, e=0)), 100)
+    assert small == r256(1 * 100 * 4) + r256(1 * 1 * 1 * 4) + 1 * 1 * ((100 + 7) // 8 + 1) * 1024
     m, l = 300, 77
-    transposed = r256(n * 300 * 4)          # the longer operand, transposed
-    assert L.os_sketch_cols_workspace_bytes(m, n) == transposed
-    assert L.os_sketch_cols_workspace_bytes(0, n) == 0
     ws = L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 0)
-    assert ws == r256(prep) + transposed + r256(10 * 1024 * 300 * 4) + r256(10 * 1024 * 80 * 4)
+    assert ws == r256(prep) + r256(300 * 10 * 1024 * 4) + r256(77 * 10 * 1024 * 4)
     bad = _sk(b=0)
     assert L.os_sketch_prepare_bytes(ctypes.byref(bad), 10) == 0
     assert L.os_matmul_workspace_bytes(ctypes.byref(bad), 1, 1, 1, 0) == 0
@@ -102,33 +100,34 @@ def test_null_and_half_explicit_tables(L):
     assert L.os_hash_fill(ctypes.byref(s), 10, FAKE, FAKE, None) == OS_ENULL
     s = _sk()
     assert L.os_hash_fill(ctypes.byref(s), 10, None, FAKE, None) == OS_ENULL
-    assert L.os_sketch_cols(ctypes.byref(s), None, BIG, FAKE, 4, 16, 16, None, 0, FAKE, 4, FAKE, BIG, None) == OS_ENULL
+    assert L.os_sketch_cols(ctypes.byref(s), None, BIG, FAKE, 4, 16, 16, None, 0, FAKE, 320,
+                            None) == OS_ENULL
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, None, 4, 16, 16, None, 0, FAKE, 320,
+                            None) == OS_ENULL
 
 
 def test_sizes_rejected(L):
-    s = _sk()
+    s = _sk()              # b = 64, N + e = 5: a sketch is 5 * 64 = 320 columns wide
     assert L.os_hash_fill(ctypes.byref(s), 0, FAKE, FAKE, None) == OS_EINVAL
     assert L.os_hash_fill(ctypes.byref(s), 1 << 31, FAKE, FAKE, None) == OS_EINVAL
     # lda < n
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 16, 12, None, 0, FAKE, 4, FAKE, BIG, None) == OS_EINVAL
-    # output ld < rows (output is (5 blocks * 64) x rows)
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 8, 16, 16, None, 0, FAKE, 4, FAKE, BIG, None) == OS_EINVAL
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 16, 12, None, 0, FAKE, 320,
+                            None) == OS_EINVAL
+    # output ld < sketch width
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 8, 16, 16, None, 0, FAKE, 316,
+                            None) == OS_EINVAL
+    assert L.os_sketch_rows(ctypes.byref(s), FAKE, BIG, FAKE, 16, 8, 8, None, 0, FAKE, 316,
+                            None) == OS_EINVAL
     # rows beyond the limit
     assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, (1 << 24) + 1, 16, 16, None, 0, FAKE,
-                            1 << 25, FAKE, BIG, None) == OS_EINVAL
+                            320, None) == OS_EINVAL
     # prepared buffer too small
     need = L.os_sketch_prepare_bytes(ctypes.byref(s), 16)
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, need - 1, FAKE, 4, 16, 16, None, 0, FAKE, 4,
-                            FAKE, BIG, None) == OS_EWORKSPACE
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, need - 1, FAKE, 4, 16, 16, None, 0, FAKE, 320,
+                            None) == OS_EWORKSPACE
     assert L.os_sketch_prepare(ctypes.byref(s), 16, FAKE, need - 1, None) == OS_EWORKSPACE
-    # transpose workspace missing, too small or misaligned
-    wneed = L.os_sketch_cols_workspace_bytes(4, 16)
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 16, 16, None, 0, FAKE, 4, None,
-                            wneed, None) == OS_EWORKSPACE
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 16, 16, None, 0, FAKE, 4, FAKE,
-                            wneed - 1, None) == OS_EWORKSPACE
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 16, 16, None, 0, FAKE, 4,
-                            ctypes.c_void_p((1 << 20) + 16), wneed, None) == OS_EWORKSPACE
+    # gemm operands narrower than nst * bp
+    assert L.os_gemm_kept(FAKE, 60, FAKE, 64, 4, 4, 64, 1, None, FAKE, 4, None) == OS_EINVAL
     # ldc < l
     assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, None, 0, FAKE, 7, FAKE,
                        1 << 30, None) == OS_EINVAL
@@ -139,12 +138,19 @@ def test_alignment_rejected(L):
     odd = ctypes.c_void_p((1 << 20) + 4)
     assert L.os_sketch_prepare(ctypes.byref(s), 10, ctypes.c_void_p((1 << 20) + 16), BIG,
                                None) == OS_EALIGN
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, odd, 4, 16, 16, None, 0, FAKE, 4, FAKE, BIG, None) == OS_EALIGN
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 15, 15, None, 0, FAKE, 4, FAKE, BIG, None) == OS_EALIGN
-    # the row-sketch input only needs 4-byte alignment: here the failure is the output's ld
-    assert L.os_sketch_rows(ctypes.byref(s), FAKE, BIG, odd, 16, 4, 5, None, 0, FAKE, 6, None) == OS_EALIGN
-    assert L.os_sketch_rows(ctypes.byref(s), FAKE, BIG, odd, 16, 4, 5, None, 0, odd, 4, None) == OS_EALIGN
-    assert L.os_gemm_kept(FAKE, 4, FAKE, 4, 4, 4, 64, 1, None, ctypes.c_void_p((1 << 20) + 2), 4,
+    # inputs need only 4-byte alignment: the failures below are the outputs'
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, odd, 4, 15, 15, None, 0, odd, 320,
+                            None) == OS_EALIGN
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, odd, 4, 15, 15, None, 0, FAKE, 322,
+                            None) == OS_EALIGN
+    assert L.os_sketch_rows(ctypes.byref(s), FAKE, BIG, odd, 16, 4, 5, None, 0, FAKE, 321,
+                            None) == OS_EALIGN
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, ctypes.c_void_p((1 << 20) + 2), 4, 16, 16,
+                            None, 0, FAKE, 320, None) == OS_EALIGN
+    # sketches are read 16 bytes at a time by the product
+    assert L.os_gemm_kept(odd, 64, FAKE, 64, 4, 4, 64, 1, None, FAKE, 4, None) == OS_EALIGN
+    assert L.os_gemm_kept(FAKE, 66, FAKE, 64, 4, 4, 64, 1, None, FAKE, 4, None) == OS_EALIGN
+    assert L.os_gemm_kept(FAKE, 64, FAKE, 64, 4, 4, 64, 1, None, ctypes.c_void_p((1 << 20) + 2), 4,
                           None) == OS_EALIGN
 
 
@@ -152,10 +158,11 @@ def test_keep_mask_rejected(L):
     s = _sk(N=2, e=1)
     none = np.zeros(3, dtype=np.uint8)
     p = none.ctypes.data_as(ctypes.c_void_p)
-    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 16, 16, p, 1, FAKE, 4, FAKE, BIG, None) == OS_ENOKEEP
+    assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 4, 16, 16, p, 1, FAKE, 192,
+                            None) == OS_ENOKEEP
     assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, p, 0, FAKE, 8, FAKE,
                        1 << 30, None) == OS_ENOKEEP
-    assert L.os_gemm_kept(FAKE, 4, FAKE, 4, 4, 4, 64, 3, p, FAKE, 4, None) == OS_ENOKEEP
+    assert L.os_gemm_kept(FAKE, 192, FAKE, 192, 4, 4, 64, 3, p, FAKE, 4, None) == OS_ENOKEEP
 
 
 def test_workspace_rejected(L):

@@ -45,14 +45,14 @@ def rel(x, y):
 
 
 def unpad(S, nst, b):
-    """Bucket-major sketch ((nst * bp) x L) -> (L x nst*b) with the per-block
-    padding rows dropped (they must be zero): the oracle's column layout."""
+    """Line-major sketch (L x (nst * bp)) -> (L x nst*b) with the per-block
+    padding columns dropped (they must be zero): the oracle's column layout."""
     bp = osk.block_stride(b)
     S = np.asarray(S)
-    assert S.shape[0] == nst * bp
+    assert S.shape[1] == nst * bp
     for j in range(nst):
-        assert np.all(S[j * bp + b:(j + 1) * bp, :] == 0), "padding rows must be zero"
-    return np.concatenate([S[j * bp:j * bp + b, :] for j in range(nst)], axis=0).T
+        assert np.all(S[:, j * bp + b:(j + 1) * bp] == 0), "padding columns must be zero"
+    return np.concatenate([S[:, j * bp:j * bp + b] for j in range(nst)], axis=1)
 
 
 def stored_blocks(N, e, keep, kept_only):
@@ -184,11 +184,11 @@ def test_sketch_cols_is_deterministic():
 def test_gemm_kept_vs_oracle(m, l, b, nst):
     rng = np.random.default_rng(m * 7 + l)
     bp = osk.block_stride(b)
-    At = np.zeros((nst * bp, m), np.float32)        # bucket-major sketch of A
-    Bt = np.zeros((nst * bp, l), np.float32)        # bucket-major sketch of B
+    At = np.zeros((m, nst * bp), np.float32)        # line-major sketch of A
+    Bt = np.zeros((l, nst * bp), np.float32)        # line-major sketch of B
     for j in range(nst):
-        At[j * bp:j * bp + b, :] = rng.standard_normal((b, m))
-        Bt[j * bp:j * bp + b, :] = rng.standard_normal((b, l))
+        At[:, j * bp:j * bp + b] = rng.standard_normal((m, b))
+        Bt[:, j * bp:j * bp + b] = rng.standard_normal((l, b))
     keep = np.ones(nst, np.uint8)
     if nst > 1:
         keep[rng.integers(nst)] = 0
