@@ -213,7 +213,7 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
         if (!keep_host || keep_host[j]) kept.idx[K++] = j;
     for (int32_t j = K; j < OS_MAX_BLOCKS; ++j) kept.idx[j] = 0;
     if (K == 0) return OS_ENOKEEP;
-    if (!osk::plan_gemm_ok(m, l, bp)) return OS_EINVAL;
+    if (!osk::plan_gemm_ok(m, l, bp, ldat, ldbt)) return OS_EINVAL;
     return hip_status(osk::launch_gemm_kept(At, ldat, Bt, ldbt, m, l, bp, kept, K, 1.0f / (float)K, C,
                                             ldc, (hipStream_t)stream));
 }
@@ -252,7 +252,7 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     if (!workspace || !aligned(workspace, 256) || ws_bytes < need) return OS_EWORKSPACE;
     const int32_t bp = os_block_stride(sk->b);
     if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !osk::plan_sketch_ok(l, bs.nst, bp, n) ||
-        !osk::plan_gemm_ok(m, l, bp))
+        !osk::plan_gemm_ok(m, l, bp, (int64_t)bs.nst * bp, (int64_t)bs.nst * bp))
         return OS_EINVAL;
 
     // both sketches use the stored width as leading dimension (a multiple of 32)

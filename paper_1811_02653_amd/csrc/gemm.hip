@@ -45,20 +45,34 @@ __device__ __forceinline__ int64_t xcd_task(int64_t L, int64_t tasks) {
 }
 
 // Global -> register tile loads: thread t covers tile rows t/8 + 32u
-// (u = 0..7) and the 4 K values at 4 (t % 8).  `p` points at row 0 of the
-// tile plus the thread's K offset; rows past `last` (the tile's last row
-// inside the matrix) are clamped to it and their values replaced by zero, so
-// every load is unconditional (a branch around a load would make each use
-// wait for all loads in flight).
-__device__ __forceinline__ void load_tile(float4 (&r)[8], const float* __restrict__ p, int64_t ld,
-                                          int64_t kcol, int rel, int last) {
+// (u = 0..7) and the 4 K values at 4 (t % 8).  Raw buffer loads: `rsrc`
+// (wave-uniform) describes the tile's first row, `kbyte` (wave-uniform, in
+// SGPRs) is the byte offset of the step's first K column and off[u] (one
+// 32-bit VGPR each) the byte offset of the thread's row u and K quad.  Every
+// offset stays below 2^32 (the leading dimension is at most kMaxSketchLd) and
+// inside the matrix: rows past its end were clamped to its last row when the
+// offsets were made.  Those rows only feed rows or columns of C beyond the
+// matrix, which are never stored, so every load is unconditional and
+// unmasked (a branch or a select on a load would make the wave wait for it).
+__device__ __forceinline__ void load_tile(float4 (&r)[8], __amdgpu_buffer_rsrc_t rsrc,
+                                          uint32_t kbyte, const uint32_t (&off)[8]) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int row = min(rel + 32 * u, last);
-        const float4 v = *reinterpret_cast<const float4*>(p + (int64_t)row * ld + kcol);
-        const bool ok = rel + 32 * u <= last;
-        r[u] = make_float4(ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f);
-    }
+    for (int u = 0; u < 8; ++u)
+        r[u] = __builtin_bit_cast(float4,
+                                  __builtin_amdgcn_raw_buffer_load_b128(rsrc, off[u], kbyte, 0));
+}
+
+// Buffer resource of a matrix starting at p: no stride, no range limit
+// (num_records = 2^32 - 1), the gfx9 data format word.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const float* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, -1, 0x00020000);
+}
+
+__device__ __forceinline__ void tile_offsets(uint32_t (&off)[8], int64_t ld, int rel, int last,
+                                             int kq) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        off[u] = (uint32_t)(((int64_t)min(rel + 32 * u, last) * ld + 4 * kq) * 4);
 }
 
 __device__ __forceinline__ void store_tile(float* __restrict__ s, const float4 (&r)[8], int tid) {
@@ -131,9 +145,10 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
 
     const int tpb = bp / BK;                       // K steps per block
     const int total = nkept * tpb;
-    // first K column of step `step` (kept blocks in order, BK columns per step)
-    auto step_col = [&](int step) -> int64_t {
-        return (int64_t)kept.idx[step / tpb] * bp + (int64_t)(step % tpb) * BK;
+    // byte offset of the first K column of step `step` (kept blocks in order,
+    // BK columns per step)
+    auto step_col = [&](int step) -> uint32_t {    // in bytes
+        return (uint32_t)(((int64_t)kept.idx[step / tpb] * bp + (int64_t)(step % tpb) * BK) * 4);
     };
 
     const int arow = wm * 128 + (lane & 31);
@@ -142,20 +157,20 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
 
     // the tile rows this thread loads: t/8 + 32u, clamped to the last row
     // inside the matrix
-    const float* pa = At + row0 * ldat + 4 * (tid & 7);
-    const float* pb = Bt + col0 * ldbt + 4 * (tid & 7);
-    const int rel = tid >> 3;
-    const int alast = (int)min((int64_t)BM - 1, m - 1 - row0);
-    const int blast = (int)min((int64_t)BN - 1, l - 1 - col0);
+    const __amdgpu_buffer_rsrc_t ra_src = tile_rsrc(At + row0 * ldat);
+    const __amdgpu_buffer_rsrc_t rb_src = tile_rsrc(Bt + col0 * ldbt);
+    uint32_t oa[8], ob[8];
+    tile_offsets(oa, ldat, tid >> 3, (int)min((int64_t)BM - 1, m - 1 - row0), tid & 7);
+    tile_offsets(ob, ldbt, tid >> 3, (int)min((int64_t)BN - 1, l - 1 - col0), tid & 7);
 
     float4 ra[8], rb[8];
-    load_tile(ra, pa, ldat, step_col(0), rel, alast);
-    load_tile(rb, pb, ldbt, step_col(0), rel, blast);
+    load_tile(ra, ra_src, step_col(0), oa);
+    load_tile(rb, rb_src, step_col(0), ob);
     store_tile(As[0], ra, tid);
     store_tile(Bs[0], rb, tid);
     if (total > 1) {
-        load_tile(ra, pa, ldat, step_col(1), rel, alast);
-        load_tile(rb, pb, ldbt, step_col(1), rel, blast);
+        load_tile(ra, ra_src, step_col(1), oa);
+        load_tile(rb, rb_src, step_col(1), ob);
     }
     __syncthreads();
 
@@ -176,8 +191,8 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
             store_tile(As[cur ^ 1], ra, tid);
             store_tile(Bs[cur ^ 1], rb, tid);
             if (t + 2 < total) {
-                load_tile(ra, pa, ldat, step_col(t + 2), rel, alast);
-                load_tile(rb, pb, ldbt, step_col(t + 2), rel, blast);
+                load_tile(ra, ra_src, step_col(t + 2), oa);
+                load_tile(rb, rb_src, step_col(t + 2), ob);
             }
         }
         read_frag(ga, gb, as, bs, 3, arow, brow, kh);
@@ -205,8 +220,9 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
 
 }  // namespace
 
-bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp) {
+bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt) {
     if (m < 1 || l < 1 || bp < BK || bp % BK) return false;
+    if (ldat > kMaxSketchLd || ldbt > kMaxSketchLd) return false;
     const int64_t tilesM = (m + BM - 1) / BM;
     const int64_t tilesN = (l + BN - 1) / BN;
     return tilesM * tilesN <= 0x7fffffff;
@@ -215,7 +231,7 @@ bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp) {
 hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
                             int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                             int32_t nkept, float scale, float* C, int64_t ldc, hipStream_t s) {
-    if (!plan_gemm_ok(m, l, bp) || nkept < 1) return hipErrorInvalidValue;
+    if (!plan_gemm_ok(m, l, bp, ldat, ldbt) || nkept < 1) return hipErrorInvalidValue;
     const int64_t tilesM = (m + BM - 1) / BM;
     const int64_t tilesN = (l + BN - 1) / BN;
     hipLaunchKernelGGL(gemm_kept_kernel, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads), 0, s,

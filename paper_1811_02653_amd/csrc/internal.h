@@ -57,7 +57,10 @@ hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t l
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                               const void* lists, float* out, int64_t ldo, hipStream_t s);
 
-bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp);
+// Longest leading dimension of a sketch read by the block product: byte
+// offsets within a 256-row tile, K offset included, stay below 2^32.
+constexpr int64_t kMaxSketchLd = (int64_t(1) << 22) - 64;
+bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt);
 
 // C = scale * sum over the kept stored blocks (kept.idx[0 .. nkept)) of
 // At_j * Bt_j^T, with At (m x nst*bp) and Bt (l x nst*bp) line-major

@@ -38,6 +38,7 @@ constexpr int kThreads = 512;          // 8 waves
 constexpr int kWaves = kThreads / 64;
 constexpr int kPerThread = kWin / kThreads;   // window positions staged per thread (16)
 constexpr uint16_t kPad = (uint16_t)kWin;     // entry of the zero row, positive
+constexpr int kAhead = 3;              // list chunks of the next slot fetched ahead
 
 // Spread consecutive task ids over the 8 XCDs in contiguous runs: task T is
 // run by the workgroup with linear id L where T = (L % 8) * (tasks / 8) + L / 8,
@@ -162,58 +163,61 @@ template <bool kRowLines>
 __device__ __forceinline__ void load_window(float4 (&r)[kPerThread], const float* __restrict__ X,
                                             int64_t lines, int64_t ldx, int64_t line0,
                                             int64_t k0, int kw, bool vec) {
+    // Every load is unconditional (a branch around a load makes each use wait
+    // for all loads in flight): positions past the window's end are clamped to
+    // its last index (no entry refers to them) and lines past the matrix to
+    // its last line (their sums are never stored).
     const int tid = threadIdx.x;
+    const int64_t l1 = min(line0 + 1, lines - 1) - line0;
+    const int64_t l2 = min(line0 + 2, lines - 1) - line0;
+    const int64_t l3 = min(line0 + 3, lines - 1) - line0;
 #pragma unroll
     for (int u = 0; u < kPerThread; ++u) {
-        const int k = tid + u * kThreads;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (k < kw) {
-            const int64_t kk = k0 + k;
-            if constexpr (kRowLines) {
-                const float* p = X + line0 * ldx + kk;
-                v.x = p[0];
-                if (line0 + 1 < lines) v.y = p[ldx];
-                if (line0 + 2 < lines) v.z = p[2 * ldx];
-                if (line0 + 3 < lines) v.w = p[3 * ldx];
-            } else {
-                const float* p = X + kk * ldx + line0;
-                if (vec && line0 + 3 < lines) {
-                    v = *reinterpret_cast<const float4*>(p);
-                } else {
-                    v.x = p[0];
-                    if (line0 + 1 < lines) v.y = p[1];
-                    if (line0 + 2 < lines) v.z = p[2];
-                    if (line0 + 3 < lines) v.w = p[3];
-                }
-            }
+        const int64_t kk = k0 + min(tid + u * kThreads, kw - 1);
+        if constexpr (kRowLines) {
+            const float* p = X + line0 * ldx + kk;
+            r[u] = make_float4(p[0], p[l1 * ldx], p[l2 * ldx], p[l3 * ldx]);
+        } else {
+            const float* p = X + kk * ldx + line0;
+            if (vec && l3 == 3)      // uniform
+                r[u] = *reinterpret_cast<const float4*>(p);
+            else
+                r[u] = make_float4(p[0], p[l1], p[l2], p[l3]);
         }
-        r[u] = v;
     }
 }
 
-__device__ __forceinline__ void add_entry(float4& acc, const float4* __restrict__ win, uint32_t e) {
-    // e: 16-bit entry in the low half; sign bit 15 -> sign of the FP32 +-1.0
-    const float4 v = win[e & 0x7FFFu];
-    const float s = __uint_as_float(0x3F800000u | ((e << 16) & 0x80000000u));
-    acc.x = fmaf(s, v.x, acc.x);
-    acc.y = fmaf(s, v.y, acc.y);
-    acc.z = fmaf(s, v.z, acc.z);
-    acc.w = fmaf(s, v.w, acc.w);
-}
-
+// Adds the 8 entries of one chunk (16-bit entries, two per word; sign bit 15
+// selects the sign of the FP32 +-1.0 factor).  All eight LDS reads are issued
+// before the first FMA so their latencies overlap.
 __device__ __forceinline__ void add_chunk(float4& acc, const float4* __restrict__ win, uint4 e) {
-    add_entry(acc, win, e.x);
-    add_entry(acc, win, e.x >> 16);
-    add_entry(acc, win, e.y);
-    add_entry(acc, win, e.y >> 16);
-    add_entry(acc, win, e.z);
-    add_entry(acc, win, e.z >> 16);
-    add_entry(acc, win, e.w);
-    add_entry(acc, win, e.w >> 16);
+    const uint32_t w[4] = {e.x, e.y, e.z, e.w};
+    float4 v[8];
+    float s[8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        v[2 * u] = win[w[u] & 0x7FFFu];
+        v[2 * u + 1] = win[(w[u] >> 16) & 0x7FFFu];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        s[2 * u] = __uint_as_float(0x3F800000u | ((w[u] << 16) & 0x80000000u));
+        s[2 * u + 1] = __uint_as_float(0x3F800000u | (w[u] & 0x80000000u));
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        acc.x = fmaf(s[u], v[u].x, acc.x);
+        acc.y = fmaf(s[u], v[u].y, acc.y);
+        acc.z = fmaf(s[u], v[u].z, acc.z);
+        acc.w = fmaf(s[u], v[u].w, acc.w);
+    }
 }
 
+// One workgroup of 8 waves fills a CU's LDS, so each SIMD runs 2 waves: the
+// compiler may use up to 256 VGPRs per lane.
 template <int kSlots, bool kRowLines>
-__global__ __launch_bounds__(kThreads) void sketch_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void sketch_kernel(
     const float* __restrict__ X, int64_t lines, int64_t n, int64_t ldx, int vec, int32_t bp,
     int32_t qn, int32_t nwin, int32_t nst, BlockList bl, int64_t RC,
     const uint32_t* __restrict__ hdr, const uint4* __restrict__ ell, float* __restrict__ out,
@@ -245,26 +249,46 @@ __global__ __launch_bounds__(kThreads) void sketch_kernel(
             load_window<kRowLines>(pre, X, lines, ldx, line0, k1, (int)min((int64_t)kWin, n - k1),
                                    vec);
         }
+        // The list chunks of slot s + 1 (up to kAhead of them) are fetched
+        // while slot s is summed.  Fetches are unconditional: chunk indices
+        // past a slot's count repeat its last chunk, and an unused slot reads
+        // chunk 0 of the first region (never summed).
+        auto slot_list = [&](int s, uint32_t& nch) -> const uint4* {
+            const int G = (pass * kSlots + s) * kWaves + wave;   // wave-uniform
+            nch = 0;
+            if (G >= gslots) return ell + lane;
+            const int j = G / qn;
+            const int q = G - j * qn;
+            const int64_t i = bl.idx[j];
+            const uint32_t h = hdr[(i * nwin + w) * qn + q];
+            nch = h >> 16;
+            return ell + ((i * nwin + w) * RC + (h & 0xFFFFu)) * 64 + lane;
+        };
+        auto fetch = [&](uint4 (&d)[kAhead], const uint4* p, uint32_t nch) {
+            const uint32_t last = nch > 0 ? nch - 1 : 0;
+#pragma unroll
+            for (int c = 0; c < kAhead; ++c) d[c] = p[(int64_t)min((uint32_t)c, last) * 64];
+        };
+        uint4 cur[kAhead], nxt[kAhead];
+        uint32_t ncur, nnxt = 0;
+        const uint4* pcur = slot_list(0, ncur);
+        const uint4* pnxt = pcur;
+        fetch(cur, pcur, ncur);
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
-            const int G = (pass * kSlots + s) * kWaves + wave;   // wave-uniform
-            if (G < gslots) {
-                const int j = G / qn;
-                const int q = G - j * qn;
-                const int64_t i = bl.idx[j];
-                const uint32_t h = hdr[(i * nwin + w) * qn + q];
-                const uint32_t nch = h >> 16;
-                const uint4* __restrict__ ch =
-                    ell + ((i * nwin + w) * RC + (h & 0xFFFFu)) * 64 + lane;
-                if (nch > 0) {
-                    uint4 e = ch[0];
-                    for (uint32_t c = 1; c < nch; ++c) {
-                        const uint4 nx = ch[(int64_t)c * 64];
-                        add_chunk(acc[s], win, e);
-                        e = nx;
-                    }
-                    add_chunk(acc[s], win, e);
-                }
+            if (s + 1 < kSlots) {
+                pnxt = slot_list(s + 1, nnxt);
+                fetch(nxt, pnxt, nnxt);
+            }
+#pragma unroll
+            for (int c = 0; c < kAhead; ++c)
+                if ((uint32_t)c < ncur) add_chunk(acc[s], win, cur[c]);
+            for (uint32_t c = kAhead; c < ncur; ++c) add_chunk(acc[s], win, pcur[(int64_t)c * 64]);
+            if (s + 1 < kSlots) {
+#pragma unroll
+                for (int c = 0; c < kAhead; ++c) cur[c] = nxt[c];
+                ncur = nnxt;
+                pcur = pnxt;
             }
         }
     }
