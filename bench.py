@@ -100,7 +100,7 @@ def main():
     A = torch.from_numpy(A_h).to(dev)
     B = torch.from_numpy(B_h).to(dev)
     C = torch.empty((m, l), dtype=torch.float32, device=dev)
-    ws = torch.empty(osk.workspace_bytes(m, n, l, b, N, e, kept_only=args.kept_only),
+    ws = torch.empty(osk.workspace_bytes(m, n, l, b, N, e),
                      dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -129,6 +129,7 @@ def main():
     At = torch.empty((m, nst * bp), dtype=torch.float32, device=dev)
     Bt = torch.empty((l, nst * bp), dtype=torch.float32, device=dev)
     stored_keep = None if args.kept_only else keep      # mask over the stored blocks
+    tws = torch.empty(osk.sketch_rows_workspace_bytes(n, l), dtype=torch.uint8, device=dev)
     reps = max(3, args.steps)
     t_prep = event_time_ms(torch, lambda: osk.sketch_prepare(n, b, N, e, seed=args.seed,
                                                              stream=stream), reps, stream)
@@ -138,7 +139,8 @@ def main():
                         reps, stream)
     t_sb = event_time_ms(torch, lambda: osk.sketch_rows(B, b, N, e, seed=args.seed, keep=keep,
                                                         kept_only=args.kept_only, prep=prep,
-                                                        out=Bt, stream=stream), reps, stream)
+                                                        out=Bt, workspace=tws, stream=stream),
+                        reps, stream)
     t_gemm = event_time_ms(torch, lambda: osk.gemm_kept(At, Bt, b, keep=stored_keep, out=C,
                                                         stream=stream), reps, stream)
     gemm_flops = 2.0 * m * l * K * bp

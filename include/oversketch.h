@@ -151,15 +151,25 @@ os_status os_sketch_cols(const os_sketch* sk, const void* prep, size_t prep_byte
                          const uint8_t* keep_host, int kept_only, float* out, int64_t ldo,
                          void* stream);
 
+/* Device workspace bytes os_sketch_rows uses, when given one, for an n x
+ * cols operand (0 on invalid sizes): room for the operand transposed. */
+size_t os_sketch_rows_workspace_bytes(int64_t n, int64_t cols);
+
 /* Step "sketch B's rows" (S^T B: the same sketch applied from the left,
  * Section 4) for a row-major X (n x cols, ld ldx), line-major output:
  *   out[q][j*bp + c] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[k][q],
  * i.e. out = (S_{s_j}^T X)^T side by side over j.  Other arguments as in
- * os_sketch_cols; out: DEVICE cols x (nst*bp), ld ldo >= nst*bp. */
+ * os_sketch_cols; out: DEVICE cols x (nst*bp), ld ldo >= nst*bp.
+ * workspace: optional DEVICE buffer (256-byte aligned, >=
+ * os_sketch_rows_workspace_bytes, else OS_EWORKSPACE).  With it, X is first
+ * transposed into the workspace and its rows sketched as by os_sketch_cols
+ * (the faster path: every line is then read as whole cache lines); with
+ * workspace = NULL the columns of X are sketched in place.  Both paths give
+ * the same sums in the same order. */
 os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_bytes,
                          const float* X, int64_t n, int64_t cols, int64_t ldx,
                          const uint8_t* keep_host, int kept_only, float* out, int64_t ldo,
-                         void* stream);
+                         void* workspace, size_t ws_bytes, void* stream);
 
 /* Step "grouped product over the kept blocks" (Algorithm "OverSketch":
  * computation phase plus reduction phase, Fig. (bMM)):
@@ -174,11 +184,12 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
                        int64_t m, int64_t l, int32_t b, int32_t nst,
                        const uint8_t* keep_host, float* C, int64_t ldc, void* stream);
 
-/* Workspace bytes os_matmul needs (prepared sketch and both sketches, sized
- * for all N+e blocks so one workspace serves any mask).  0 on invalid
+/* Workspace bytes os_matmul needs: the prepared sketch and both sketches,
+ * sized for all N+e blocks so one workspace serves any mask, plus, for a
+ * row-major B (b_col_major = 0), B transposed (l x n).  0 on invalid
  * arguments. */
 size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
-                                 int kept_only);
+                                 int b_col_major);
 
 /* The whole path: C ~= (1/K) * sum_{kept i} (A S_i)(S_i^T B)
  * (Algorithm "OverSketch" on one GPU).  A: DEVICE m x n row-major (lda).
@@ -186,8 +197,9 @@ size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int6
  * b_col_major = 1 -> column-major, element (k, q) at B[q*ldb + k], ldb >= n.
  * keep_host: HOST uint8 [N+e] or NULL (= blocks [0, N) kept).  kept_only != 0
  * skips the dropped blocks already in the sketch step.  C: DEVICE m x l
- * (ldc).  workspace: DEVICE, 256-byte aligned, >= os_matmul_workspace_bytes.
- * Enqueues: prepare, sketch of A, sketch of B, block product. */
+ * (ldc).  workspace: DEVICE, 256-byte aligned, >= os_matmul_workspace_bytes
+ * for the same b_col_major.  Enqueues: prepare, sketch of A, (transpose of
+ * a row-major B,) sketch of B, block product. */
 os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const float* B,
                     int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
                     const uint8_t* keep_host, int kept_only, float* C, int64_t ldc,

@@ -17,7 +17,8 @@ import numpy as np
 
 __all__ = [
     "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "sketch_cols",
-    "sketch_rows", "gemm_kept", "matmul", "workspace_bytes", "stored_count",
+    "sketch_rows", "sketch_rows_workspace_bytes", "gemm_kept", "matmul", "workspace_bytes",
+    "stored_count",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -75,7 +76,10 @@ def lib():
     L.os_sketch_cols.restype = ctypes.c_int
     L.os_sketch_cols.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
     L.os_sketch_rows.restype = ctypes.c_int
-    L.os_sketch_rows.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
+    L.os_sketch_rows.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp, sz,
+                                 vp]
+    L.os_sketch_rows_workspace_bytes.restype = sz
+    L.os_sketch_rows_workspace_bytes.argtypes = [i64, i64]
     L.os_gemm_kept.restype = ctypes.c_int
     L.os_gemm_kept.argtypes = [vp, i64, vp, i64, i64, i64, i32, i32, vp, vp, i64, vp]
     L.os_matmul_workspace_bytes.restype = sz
@@ -225,9 +229,18 @@ def sketch_cols(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=No
     return out
 
 
+def sketch_rows_workspace_bytes(n, cols) -> int:
+    """Device workspace bytes of the transposing sketch_rows path."""
+    return int(lib().os_sketch_rows_workspace_bytes(n, cols))
+
+
 def sketch_rows(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, prep=None,
-                out=None, stream=None):
-    """Line-major (S_i^T X)^T for the stored blocks, side by side: cols x (nst * block_stride(b))."""
+                out=None, workspace=None, stream=None):
+    """Line-major (S_i^T X)^T for the stored blocks, side by side: cols x (nst * block_stride(b)).
+
+    workspace: None (sketch X's columns in place), True (allocate one) or a
+    uint8 CUDA tensor of at least sketch_rows_workspace_bytes(n, cols) bytes
+    (X is transposed into it first: the faster path)."""
     torch = _torch()
     _require_cuda(X, "X", torch.float32)
     n, cols, ldx = _row_major(X, "X")
@@ -238,8 +251,13 @@ def sketch_rows(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=No
     out = _line_major_out(out, cols, width, X.device)
     _, _, ldo = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
+    if workspace is True:
+        workspace = torch.empty(sketch_rows_workspace_bytes(n, cols), dtype=torch.uint8,
+                                device=X.device)
+    wp, wn = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel())
     _check(lib().os_sketch_rows(ctypes.byref(s), _ptr(prep), prep.numel(), _ptr(X), n, cols, ldx,
-                                pk, int(bool(kept_only)), _ptr(out), ldo, _stream(stream)),
+                                pk, int(bool(kept_only)), _ptr(out), ldo, wp, wn,
+                                _stream(stream)),
            "os_sketch_rows")
     return out
 
@@ -266,9 +284,10 @@ def gemm_kept(At, Bt, b, keep=None, out=None, stream=None):
     return out
 
 
-def workspace_bytes(m, n, l, b, N, e, kept_only=False) -> int:
+def workspace_bytes(m, n, l, b, N, e, b_col_major=False) -> int:
+    """Device workspace bytes of matmul (B row-major unless b_col_major)."""
     s = _sketch(b, N, e, 0)
-    return int(lib().os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, int(bool(kept_only))))
+    return int(lib().os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, int(bool(b_col_major))))
 
 
 def matmul(A, B, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, out=None,
@@ -295,7 +314,7 @@ def matmul(A, B, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None
     else:
         raise OversketchError("B must have a unit stride in one dimension")
     s = _sketch(b, N, e, seed, h, sigma)
-    need = int(lib().os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, int(bool(kept_only))))
+    need = int(lib().os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, b_col_major))
     if need == 0:
         raise OversketchError("invalid sizes for os_matmul")
     if workspace is None:

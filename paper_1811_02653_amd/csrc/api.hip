@@ -178,9 +178,15 @@ os_status os_sketch_cols(const os_sketch* sk, const void* prep, size_t prep_byte
                                               (hipStream_t)stream));
 }
 
+size_t os_sketch_rows_workspace_bytes(int64_t n, int64_t cols) {
+    if (check_len(n) != OS_OK || check_extent(cols) != OS_OK) return 0;
+    return osk::transpose_bytes(n, cols);
+}
+
 os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_bytes, const float* X,
                          int64_t n, int64_t cols, int64_t ldx, const uint8_t* keep_host,
-                         int kept_only, float* out, int64_t ldo, void* stream) {
+                         int kept_only, float* out, int64_t ldo, void* workspace, size_t ws_bytes,
+                         void* stream) {
     os_status st = check_sketch(sk);
     if (st != OS_OK) return st;
     if ((st = check_len(n)) != OS_OK) return st;
@@ -192,6 +198,16 @@ os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_byte
     const int32_t bp = os_block_stride(sk->b);
     if ((st = check_matrix(out, cols, (int64_t)bs.nst * bp, ldo, true)) != OS_OK) return st;
     if (!osk::plan_sketch_ok(cols, bs.nst, bp, n)) return OS_EINVAL;
+    if (workspace) {
+        if (!aligned(workspace, 256) || ws_bytes < osk::transpose_bytes(n, cols))
+            return OS_EWORKSPACE;
+        hipStream_t s = (hipStream_t)stream;
+        float* Xt = static_cast<float*>(workspace);
+        const int64_t ldt = osk::round_up(n, 4);
+        if ((st = hip_status(osk::launch_transpose(X, n, cols, ldx, Xt, ldt, s))) != OS_OK) return st;
+        return hip_status(osk::launch_sketch_cols(Xt, cols, n, ldt, bs.stored, bs.nst, nblocks(sk),
+                                                  bp, prep_lists(prep, sk, n), out, ldo, s));
+    }
     return hip_status(osk::launch_sketch_rows(X, n, cols, ldx, bs.stored, bs.nst, nblocks(sk), bp,
                                               prep_lists(prep, sk, n), out, ldo,
                                               (hipStream_t)stream));
@@ -219,16 +235,15 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
 }
 
 size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
-                                 int kept_only) {
+                                 int b_col_major) {
     if (check_sketch(sk) != OS_OK || check_len(n) != OS_OK || check_extent(m) != OS_OK ||
         check_extent(l) != OS_OK)
         return 0;
     // Sized for all N+e blocks whatever the mask, so one workspace serves
-    // every call.
-    (void)kept_only;
+    // every call; a row-major B is transposed first.
     const int64_t zp = (int64_t)nblocks(sk) * os_block_stride(sk->b);
     return align256(prepare_bytes(sk, n)) + align256((size_t)m * zp * 4u) +
-           align256((size_t)l * zp * 4u);
+           align256((size_t)l * zp * 4u) + (b_col_major ? 0 : osk::transpose_bytes(n, l));
 }
 
 os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const float* B, int64_t ldb,
@@ -248,7 +263,7 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     if ((st = check_matrix(C, m, l, ldc, false)) != OS_OK) return st;
     Blocks bs;
     if ((st = block_sets(sk, keep_host, kept_only, bs)) != OS_OK) return st;
-    const size_t need = os_matmul_workspace_bytes(sk, m, n, l, kept_only);
+    const size_t need = os_matmul_workspace_bytes(sk, m, n, l, b_col_major);
     if (!workspace || !aligned(workspace, 256) || ws_bytes < need) return OS_EWORKSPACE;
     const int32_t bp = os_block_stride(sk->b);
     if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !osk::plan_sketch_ok(l, bs.nst, bp, n) ||
@@ -263,6 +278,8 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     float* At = reinterpret_cast<float*>(ws + align256(prepare_bytes(sk, n)));
     float* Bt = reinterpret_cast<float*>(reinterpret_cast<char*>(At) +
                                          align256((size_t)m * zp * 4u));
+    float* Bx = reinterpret_cast<float*>(reinterpret_cast<char*>(Bt) +
+                                         align256((size_t)l * zp * 4u));
     hipStream_t s = (hipStream_t)stream;
     const void* lists = prep_lists(prep, sk, n);
 
@@ -270,13 +287,19 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     if ((st = hip_status(osk::launch_sketch_cols(A, m, n, lda, bs.stored, bs.nst, nblocks(sk), bp,
                                                  lists, At, zs, s))) != OS_OK)
         return st;
-    if (b_col_major)
-        st = hip_status(osk::launch_sketch_cols(B, l, n, ldb, bs.stored, bs.nst, nblocks(sk), bp,
-                                                lists, Bt, zs, s));
-    else
-        st = hip_status(osk::launch_sketch_rows(B, n, l, ldb, bs.stored, bs.nst, nblocks(sk), bp,
-                                                lists, Bt, zs, s));
-    if (st != OS_OK) return st;
+    // B's columns are the lines of its sketch: a row-major B is transposed
+    // first, so that both sketches read whole lines (16-byte requests along a
+    // column of a row-major B would each bring in a separate cache line)
+    const float* Bl = B;
+    int64_t ldl = ldb;
+    if (!b_col_major) {
+        ldl = osk::round_up(n, 4);
+        if ((st = hip_status(osk::launch_transpose(B, n, l, ldb, Bx, ldl, s))) != OS_OK) return st;
+        Bl = Bx;
+    }
+    if ((st = hip_status(osk::launch_sketch_cols(Bl, l, n, ldl, bs.stored, bs.nst, nblocks(sk), bp,
+                                                 lists, Bt, zs, s))) != OS_OK)
+        return st;
     return hip_status(osk::launch_gemm_kept(At, zs, Bt, zs, m, l, bp, bs.kept_pos, bs.K,
                                             1.0f / (float)bs.K, C, ldc, s));
 }

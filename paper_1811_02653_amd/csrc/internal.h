@@ -60,6 +60,13 @@ hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t l
 // Longest leading dimension of a sketch read by the block product: byte
 // offsets within a 256-row tile, K offset included, stay below 2^32.
 constexpr int64_t kMaxSketchLd = (int64_t(1) << 22) - 64;
+// Y (cols x rows, ld ldy: a multiple of 4, Y 16-byte aligned) = X^T for X
+// rows x cols row-major (ld ldx); transpose_bytes = the size of Y with ldy =
+// rows rounded up to 4.
+size_t transpose_bytes(int64_t rows, int64_t cols);
+hipError_t launch_transpose(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
+                            int64_t ldy, hipStream_t s);
+
 bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt);
 
 // C = scale * sum over the kept stored blocks (kept.idx[0 .. nkept)) of

@@ -344,6 +344,62 @@ hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const float* X, in
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Transpose: Y (cols x rows, ld ldy) = X^T for X rows x cols (ld ldx).  A
+// workgroup moves one 64 x 64 tile through LDS (row stride 65 floats: the
+// column reads are conflict-free); both sides are coalesced, 16 bytes per
+// lane when `vec` (X 16-byte aligned and ldx % 4 == 0).  Loads are clamped
+// into the matrix and stores are guarded.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict__ X, int64_t rows,
+                                                        int64_t cols, int64_t ldx, int vec,
+                                                        float* __restrict__ Y, int64_t ldy) {
+    __shared__ float t[64][65];
+    const int tid = threadIdx.x;
+    const int64_t col_tiles = (cols + 63) / 64;
+    const int64_t tiles = col_tiles * ((rows + 63) / 64);
+    const int64_t T = xcd_task(blockIdx.x, tiles);
+    const int64_t r0 = T / col_tiles * 64;
+    const int64_t c0 = T % col_tiles * 64;
+    const int sub = tid >> 4;          // 0..15
+    const int q = 4 * (tid & 15);      // 0..60
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = sub + 16 * i;
+        const float* p = X + min(r0 + r, rows - 1) * ldx;
+        float4 v;
+        if (vec && c0 + q + 3 < cols) {
+            v = *reinterpret_cast<const float4*>(p + c0 + q);
+        } else {
+            v.x = p[min(c0 + q + 0, cols - 1)];
+            v.y = p[min(c0 + q + 1, cols - 1)];
+            v.z = p[min(c0 + q + 2, cols - 1)];
+            v.w = p[min(c0 + q + 3, cols - 1)];
+        }
+        t[r][q + 0] = v.x;
+        t[r][q + 1] = v.y;
+        t[r][q + 2] = v.z;
+        t[r][q + 3] = v.w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = sub + 16 * i;          // column of X = row of Y
+        const int64_t yr = c0 + c;
+        const int64_t yc = r0 + q;
+        if (yr >= cols) continue;
+        const float4 v = make_float4(t[q + 0][c], t[q + 1][c], t[q + 2][c], t[q + 3][c]);
+        float* o = Y + yr * ldy + yc;
+        if (yc + 3 < rows) {
+            *reinterpret_cast<float4*>(o) = v;
+        } else {
+            if (yc < rows) o[0] = v.x;
+            if (yc + 1 < rows) o[1] = v.y;
+            if (yc + 2 < rows) o[2] = v.z;
+        }
+    }
+}
+
 struct Plan {
     int32_t qn;      // groups of 64 buckets per block
     int32_t nwin;    // windows over the sketched dimension
@@ -435,6 +491,21 @@ hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t l
                               const void* lists, float* out, int64_t ldo, hipStream_t s) {
     if (!plan_sketch_ok(cols, nst, bp, n)) return hipErrorInvalidValue;
     return launch_sketch(false, X, cols, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s);
+}
+
+size_t transpose_bytes(int64_t rows, int64_t cols) {
+    return (size_t)round_up(cols * round_up(rows, 4) * 4, 256);
+}
+
+hipError_t launch_transpose(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
+                            int64_t ldy, hipStream_t s) {
+    const int64_t tiles = (rows + 63) / 64 * ((cols + 63) / 64);
+    if (tiles > 0x7fffffff || ldy % 4 || (reinterpret_cast<uintptr_t>(Y) & 15))
+        return hipErrorInvalidValue;
+    const int vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (ldx & 3) == 0;
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)tiles), dim3(256), 0, s, X, rows, cols, ldx,
+                       vec, Y, ldy);
+    return hipGetLastError();
 }
 
 hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,

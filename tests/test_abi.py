@@ -39,7 +39,8 @@ def L():
 def test_header_declares_the_path(L):
     names = _declared()
     for want in ["os_hash_fill", "os_sketch_prepare_bytes", "os_sketch_prepare", "os_sketch_cols",
-                 "os_sketch_rows", "os_gemm_kept", "os_matmul", "os_matmul_workspace_bytes",
+                 "os_sketch_rows", "os_sketch_rows_workspace_bytes", "os_gemm_kept", "os_matmul",
+                 "os_matmul_workspace_bytes",
                  "os_status_string", "os_last_hip_error", "os_block_stride"]:
         assert want in names
 
@@ -74,8 +75,12 @@ def test_prepare_and_workspace_bytes(L):
     small = L.os_sketch_prepare_bytes(ctypes.byref(_sk(b=64, N=1, e=0)), 100)
     assert small == r256(1 * 100 * 4) + r256(1 * 1 * 1 * 4) + 1 * 1 * ((100 + 7) // 8 + 1) * 1024
     m, l = 300, 77
-    ws = L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 0)
+    ws = L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 1)      # column-major B
     assert ws == r256(prep) + r256(300 * 10 * 1024 * 4) + r256(77 * 10 * 1024 * 4)
+    transposed = r256(77 * 32772 * 4)                                   # B^T, ld n rounded to 4
+    assert L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 0) == ws + transposed
+    assert L.os_sketch_rows_workspace_bytes(n, l) == transposed
+    assert L.os_sketch_rows_workspace_bytes(0, l) == 0
     bad = _sk(b=0)
     assert L.os_sketch_prepare_bytes(ctypes.byref(bad), 10) == 0
     assert L.os_matmul_workspace_bytes(ctypes.byref(bad), 1, 1, 1, 0) == 0
@@ -117,7 +122,13 @@ def test_sizes_rejected(L):
     assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, 8, 16, 16, None, 0, FAKE, 316,
                             None) == OS_EINVAL
     assert L.os_sketch_rows(ctypes.byref(s), FAKE, BIG, FAKE, 16, 8, 8, None, 0, FAKE, 316,
-                            None) == OS_EINVAL
+                            None, 0, None) == OS_EINVAL
+    # transpose workspace too small or misaligned
+    wneed = L.os_sketch_rows_workspace_bytes(16, 8)
+    assert L.os_sketch_rows(ctypes.byref(s), FAKE, BIG, FAKE, 16, 8, 8, None, 0, FAKE, 320,
+                            FAKE, wneed - 1, None) == OS_EWORKSPACE
+    assert L.os_sketch_rows(ctypes.byref(s), FAKE, BIG, FAKE, 16, 8, 8, None, 0, FAKE, 320,
+                            ctypes.c_void_p((1 << 20) + 16), wneed, None) == OS_EWORKSPACE
     # rows beyond the limit
     assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, FAKE, (1 << 24) + 1, 16, 16, None, 0, FAKE,
                             320, None) == OS_EINVAL
@@ -144,7 +155,7 @@ def test_alignment_rejected(L):
     assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, odd, 4, 15, 15, None, 0, FAKE, 322,
                             None) == OS_EALIGN
     assert L.os_sketch_rows(ctypes.byref(s), FAKE, BIG, odd, 16, 4, 5, None, 0, FAKE, 321,
-                            None) == OS_EALIGN
+                            None, 0, None) == OS_EALIGN
     assert L.os_sketch_cols(ctypes.byref(s), FAKE, BIG, ctypes.c_void_p((1 << 20) + 2), 4, 16, 16,
                             None, 0, FAKE, 320, None) == OS_EALIGN
     # sketches are read 16 bytes at a time by the product
@@ -168,7 +179,7 @@ def test_keep_mask_rejected(L):
 def test_workspace_rejected(L):
     s = _sk()
     need = L.os_matmul_workspace_bytes(ctypes.byref(s), 4, 16, 8, 0)
-    assert need > 0
+    assert need > L.os_matmul_workspace_bytes(ctypes.byref(s), 4, 16, 8, 1) > 0
     assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, None, 0, FAKE, 8, None,
                        need, None) == OS_EWORKSPACE
     assert L.os_matmul(ctypes.byref(s), FAKE, 16, FAKE, 8, 0, 4, 16, 8, None, 0, FAKE, 8, FAKE,

@@ -122,6 +122,8 @@ def test_paper_worked_example_on_gpu():
     np.testing.assert_array_equal(unpad(out, 1, 3), ST.T)        # I S_c = S_c
     outT = host(osk.sketch_rows(dev(I9), 3, 1, 0, h=hd, sigma=sd))
     np.testing.assert_array_equal(unpad(outT, 1, 3).T, ST)       # S_c^T I = S_c^T
+    outT = host(osk.sketch_rows(dev(I9), 3, 1, 0, h=hd, sigma=sd, workspace=True))
+    np.testing.assert_array_equal(unpad(outT, 1, 3).T, ST)
 
 
 @pytest.mark.parametrize("kept_only", [False, True])
@@ -138,6 +140,9 @@ def test_sketch_of_identity_is_bit_exact(b, kept_only):
     np.testing.assert_array_equal(unpad(out, len(blocks), b), expect)          # I S
     outT = host(osk.sketch_rows(I, b, N, e, seed=seed, keep=keep, kept_only=kept_only))
     np.testing.assert_array_equal(unpad(outT, len(blocks), b).T, expect.T)     # S^T I
+    outT = host(osk.sketch_rows(I, b, N, e, seed=seed, keep=keep, kept_only=kept_only,
+                                workspace=True))
+    np.testing.assert_array_equal(unpad(outT, len(blocks), b).T, expect.T)
 
 
 @pytest.mark.parametrize("rows,n,b,N,e", [(37, 1003, 100, 3, 2), (256, 4096, 256, 4, 1),
@@ -161,9 +166,13 @@ def test_sketch_rows_random(n, cols, b, N, e):
     seed = n + cols
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((n, cols)).astype(np.float32)
-    outT = unpad(host(osk.sketch_rows(dev(X, ld=cols + 3), b, N, e, seed=seed)), N + e, b)
     h, s = oracle.hash_tables(seed, N + e, n, b)
     ref = oracle.sketch_rows(X, h, s, b).T                    # cols x (N+e)*b, as unpad gives
+    direct = host(osk.sketch_rows(dev(X, ld=cols + 3), b, N, e, seed=seed))
+    transposed = host(osk.sketch_rows(dev(X, ld=cols + 3), b, N, e, seed=seed, workspace=True))
+    # both paths sum every bucket in ascending k: identical results
+    np.testing.assert_array_equal(direct, transposed)
+    outT = unpad(transposed, N + e, b)
     for i in range(N + e):
         assert rel(outT[:, i * b:(i + 1) * b], ref[:, i * b:(i + 1) * b]) <= SKETCH_TOL
 
