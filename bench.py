@@ -32,6 +32,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "sketched AB eff. TFLOP/s (2mnl/t) at fixed rel-Frob err vs exact GEMM, 1 GPU"
+
+# HBM traffic of one gemm_kept launch at the default workload, from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per
+# dispatch), each scaled by what the counter reads for a plain 1 GiB device
+# copy (bench.py --calibrate-copy: FETCH_SIZE 524300 KiB -> x 2.000,
+# WRITE_SIZE 1048576 KiB -> x 1.000).  Commands and raw figures:
+# profiles/gemm_kept_8192x8192_K8x1024_hbm_traffic.md.  Valid only for the
+# kernel source it was measured on (its SHA-256 below); None otherwise.
+GEMM_TRAFFIC = {
+    "source_sha256": "df1a9655882d736ddfcac11f6032ba34a179b19953d90ad1e351b4ebe4680217",
+    "workload": (8192, 32768, 8192, 1024, 8, 2),
+    "fetch_kib": 1574340.0, "fetch_scale": 2.000,
+    "write_kib": 264192.0, "write_scale": 1.000,
+}
 FP32_MFMA_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix peak
 HBM_PEAK_GBS = 8000.0               # MI355X HBM3E peak
 
@@ -57,7 +71,23 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-rows", type=int, default=6144,
                    help="rows of A and columns of B in the CPU oracle sample")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only run a plain 1 GiB device copy (3 times): the reference kernel "
+                        "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     return p.parse_args()
+
+
+def gemm_traffic_bytes(m, n, l, b, N, e):
+    """Measured HBM bytes per gemm_kept launch, or None if the kernel source
+    or the workload differs from the one the counters were taken on."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1811_02653_amd", "csrc", "gemm.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    t = GEMM_TRAFFIC
+    if sha != t["source_sha256"] or (m, n, l, b, N, e) != t["workload"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
 def event_time_ms(torch, fn, reps, stream):
@@ -89,6 +119,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": 1 << 30,
+                          "bytes_written": 1 << 30, "launches": 3}))
+        return
     osk.lib()    # fails loudly when the HIP library is not built
 
     m, n, l, b, N, e = args.m, args.n, args.l, args.b, args.N, args.e
@@ -217,7 +256,8 @@ def main():
             "peak": FP32_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": gemm_tflops / FP32_MFMA_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": gemm_traffic_bytes(m, n, l, b, N, e),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "algorithmic_flops_per_launch": gemm_flops,
             "avg_launch_ms": t_gemm,
         },
