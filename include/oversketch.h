@@ -86,6 +86,13 @@ typedef int os_status;
 #define OS_ENOKEEP    -6   /* the keep mask keeps no block */
 
 #define OS_MAX_BLOCKS 256                   /* upper limit on N + e */
+
+/* Operand precision of the block product (FP32 accumulation in all).  The
+ * paper's products are FP64; these trade the rounding of the sketched
+ * operands, which is small next to the sketch's own error, for MFMA rate. */
+#define OS_PREC_FP32   0   /* FP32 operands, v_mfma_f32_32x32x2_f32 */
+#define OS_PREC_BF16   1   /* BF16 operands (round to nearest even), v_mfma_f32_32x32x16_bf16 */
+#define OS_PREC_BF16X3 2   /* split BF16: x = hi + lo, product hi*hi' + hi*lo' + lo*hi' */
 #define OS_MAX_B      8192                  /* upper limit on the block width b */
 #define OS_MAX_N      (2147483647LL - 64LL) /* upper limit on the sketched dimension n */
 #define OS_MAX_ROWS   16777216LL            /* upper limit on m and l */
@@ -184,6 +191,32 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
                        int64_t m, int64_t l, int32_t b, int32_t nst,
                        const uint8_t* keep_host, float* C, int64_t ldc, void* stream);
 
+/* Columns taken by one stored block in a sketch of the given precision:
+ * b rounded up to 32 (FP32) or 64 (BF16 forms); 0 on invalid arguments. */
+int32_t os_block_stride_prec(int32_t b, int precision);
+
+/* Low-precision copy of a line-major FP32 sketch S (lines x nst*bp, ld lds,
+ * bp = os_block_stride(b)) for os_gemm_kept_prec.  precision: OS_PREC_BF16
+ * (Q = round-to-nearest-even BF16 of S) or OS_PREC_BF16X3 (Q = [hi | lo],
+ * hi = bf16(S), lo = bf16(S - hi)).  Q: DEVICE BF16, lines x width, width =
+ * nst * bq * (1 or 2), bq = os_block_stride_prec(b, precision), column
+ * j*bq + c = block j, bucket c (zero for c >= b), the low part width/2
+ * columns after the high part; ldq >= width, a multiple of 8; Q 16-byte
+ * aligned. */
+os_status os_sketch_quantize(const float* S, int64_t lines, int64_t lds, int32_t b, int32_t nst,
+                             int precision, void* Q, int64_t ldq, void* stream);
+
+/* Step "grouped product over the kept blocks" with operands of the given
+ * precision: OS_PREC_FP32 is os_gemm_kept; the BF16 forms take the copies
+ * os_sketch_quantize makes (At: m x width, Bt: l x width, leading dimensions
+ * in BF16 values, multiples of 8, 16-byte aligned) and compute
+ *   C = (1/K) * sum_{kept j} hi(A_j) hi(B_j)^T [+ hi(A_j) lo(B_j)^T + lo(A_j) hi(B_j)^T]
+ * with FP32 MFMA accumulation. */
+os_status os_gemm_kept_prec(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                            int64_t m, int64_t l, int32_t b, int32_t nst,
+                            const uint8_t* keep_host, int precision, float* C, int64_t ldc,
+                            void* stream);
+
 /* Workspace bytes os_matmul needs: the prepared sketch and both sketches,
  * sized for all N+e blocks so one workspace serves any mask, plus, for a
  * row-major B (b_col_major = 0), B transposed (l x n).  0 on invalid
@@ -204,6 +237,22 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
                     int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
                     const uint8_t* keep_host, int kept_only, float* C, int64_t ldc,
                     void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes os_matmul_prec needs: those of os_matmul plus, for the
+ * BF16 forms, the quantized copies of both sketches.  0 on invalid
+ * arguments. */
+size_t os_matmul_prec_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
+                                      int b_col_major, int precision);
+
+/* The whole path with the block product in the given precision (os_matmul
+ * is precision OS_PREC_FP32): prepare, sketch of A, (transpose of a
+ * row-major B,) sketch of B, quantization of both sketches (BF16 forms),
+ * block product.  Arguments as in os_matmul; workspace >=
+ * os_matmul_prec_workspace_bytes for the same b_col_major and precision. */
+os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const float* B,
+                         int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
+                         const uint8_t* keep_host, int kept_only, int precision, float* C,
+                         int64_t ldc, void* workspace, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

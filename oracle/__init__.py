@@ -251,6 +251,39 @@ def literal_product(A, B, h, sigma, b: int, N: int, keep) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Reduced-precision operands (the precision direction of the block product;
+# not in the paper, whose products are FP64)
+# ---------------------------------------------------------------------------
+
+def bf16_round(x) -> np.ndarray:
+    """FP32 -> BF16 with round-to-nearest-even, returned as FP32 values.
+
+    BF16 is the upper 16 bits of an FP32 word (1 sign, 8 exponent, 7
+    fraction bits).  Round to nearest even on the dropped 16 bits: add
+    0x7FFF plus the lowest kept bit, then clear the dropped bits.  Overflow
+    carries into the exponent (to infinity above the largest BF16), as the
+    rounding rule requires.  NaNs stay NaN (made quiet)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = x.view(np.uint32).astype(np.uint64)
+    keep_lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + keep_lsb) >> np.uint64(16)) << np.uint64(16)
+    r = r.astype(np.uint32)
+    nan = np.isnan(x)
+    if nan.any():
+        r[nan] = (x.view(np.uint32)[nan] & np.uint32(0xFFFF0000)) | np.uint32(0x00400000)
+    return r.view(np.float32).reshape(x.shape)
+
+
+def bf16_split(x):
+    """(hi, lo) with hi = bf16(x) and lo = bf16(x - hi), FP32 values; x - hi is
+    exact in FP32."""
+    x = np.asarray(x, dtype=np.float32)
+    hi = bf16_round(x)
+    lo = bf16_round((x - hi).astype(np.float32))
+    return hi, lo
+
+
+# ---------------------------------------------------------------------------
 # Error measures (Definition of (eps, theta)-accuracy; Fig. 5b's metric)
 # ---------------------------------------------------------------------------
 

@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "sketch_cols",
     "sketch_rows", "sketch_rows_workspace_bytes", "gemm_kept", "matmul", "workspace_bytes",
-    "stored_count",
+    "stored_count", "PRECISIONS", "block_stride_prec", "sketch_quantize", "gemm_kept_prec",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -27,6 +27,9 @@ LIB_PATH = os.path.join(_HERE, "liboversketch.so")
 OS_OK = 0
 OS_MAX_BLOCKS = 256
 OS_MAX_B = 8192
+
+# operand precisions of the block product (OS_PREC_* in oversketch.h)
+PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 
 
 class OversketchError(RuntimeError):
@@ -87,6 +90,18 @@ def lib():
     L.os_matmul.restype = ctypes.c_int
     L.os_matmul.argtypes = [sk, vp, i64, vp, i64, ctypes.c_int, i64, i64, i64, vp, ctypes.c_int,
                             vp, i64, vp, sz, vp]
+    L.os_block_stride_prec.restype = i32
+    L.os_block_stride_prec.argtypes = [i32, ctypes.c_int]
+    L.os_sketch_quantize.restype = ctypes.c_int
+    L.os_sketch_quantize.argtypes = [vp, i64, i64, i32, i32, ctypes.c_int, vp, i64, vp]
+    L.os_gemm_kept_prec.restype = ctypes.c_int
+    L.os_gemm_kept_prec.argtypes = [vp, i64, vp, i64, i64, i64, i32, i32, vp, ctypes.c_int, vp,
+                                    i64, vp]
+    L.os_matmul_prec_workspace_bytes.restype = sz
+    L.os_matmul_prec_workspace_bytes.argtypes = [sk, i64, i64, i64, ctypes.c_int, ctypes.c_int]
+    L.os_matmul_prec.restype = ctypes.c_int
+    L.os_matmul_prec.argtypes = [sk, vp, i64, vp, i64, ctypes.c_int, i64, i64, i64, vp,
+                                 ctypes.c_int, ctypes.c_int, vp, i64, vp, sz, vp]
     _lib = L
     return L
 
@@ -284,21 +299,75 @@ def gemm_kept(At, Bt, b, keep=None, out=None, stream=None):
     return out
 
 
-def workspace_bytes(m, n, l, b, N, e, b_col_major=False) -> int:
+def _prec(precision) -> int:
+    if precision not in PRECISIONS:
+        raise OversketchError("precision must be one of %s" % sorted(PRECISIONS))
+    return PRECISIONS[precision]
+
+
+def block_stride_prec(b: int, precision: str = "fp32") -> int:
+    """Columns taken by one stored block in a sketch of the given precision."""
+    return int(lib().os_block_stride_prec(int(b), _prec(precision)))
+
+
+def sketch_quantize(S, b, nst, precision="bf16", out=None, stream=None):
+    """BF16 copy of a line-major FP32 sketch (lines x nst*block_stride(b)) for
+    gemm_kept_prec: lines x (nst * block_stride_prec(b)) values, twice that
+    for "bf16x3" (high part, then the residual part)."""
+    torch = _torch()
+    _require_cuda(S, "S", torch.float32)
+    lines, _, lds = _row_major(S, "S")
+    p = _prec(precision)
+    width = nst * block_stride_prec(b, precision) * (2 if precision == "bf16x3" else 1)
+    if out is None:
+        out = torch.empty((lines, width), dtype=torch.bfloat16, device=S.device)
+    _require_cuda(out, "out", torch.bfloat16)
+    _, w, ldq = _row_major(out, "out")
+    if w != width:
+        raise OversketchError("out must have %d columns" % width)
+    _check(lib().os_sketch_quantize(_ptr(S), lines, lds, int(b), int(nst), p, _ptr(out), ldq,
+                                    _stream(stream)), "os_sketch_quantize")
+    return out
+
+
+def gemm_kept_prec(At, Bt, b, nst, precision="bf16", keep=None, out=None, stream=None):
+    """Block product over the kept stored blocks with BF16 operands from
+    sketch_quantize (FP32 accumulation); "fp32" takes FP32 sketches as
+    gemm_kept does."""
+    torch = _torch()
+    p = _prec(precision)
+    dt = torch.float32 if precision == "fp32" else torch.bfloat16
+    _require_cuda(At, "At", dt)
+    _require_cuda(Bt, "Bt", dt)
+    m, _, lda = _row_major(At, "At")
+    l, _, ldb = _row_major(Bt, "Bt")
+    if out is None:
+        out = torch.empty((m, l), dtype=torch.float32, device=At.device)
+    _require_cuda(out, "out", torch.float32)
+    _, _, ldc = _row_major(out, "out")
+    _, pk = _mask(keep, nst)
+    _check(lib().os_gemm_kept_prec(_ptr(At), lda, _ptr(Bt), ldb, m, l, int(b), int(nst), pk, p,
+                                   _ptr(out), ldc, _stream(stream)), "os_gemm_kept_prec")
+    return out
+
+
+def workspace_bytes(m, n, l, b, N, e, b_col_major=False, precision="fp32") -> int:
     """Device workspace bytes of matmul (B row-major unless b_col_major)."""
     s = _sketch(b, N, e, 0)
-    return int(lib().os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, int(bool(b_col_major))))
+    return int(lib().os_matmul_prec_workspace_bytes(ctypes.byref(s), m, n, l,
+                                                    int(bool(b_col_major)), _prec(precision)))
 
 
 def matmul(A, B, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None, out=None,
-           workspace=None, stream=None):
+           workspace=None, stream=None, precision="fp32"):
     """OverSketch product C ~= (1/K) sum_{kept i} (A S_i)(S_i^T B).
 
     A: m x n float32 with unit column stride.  B: n x l float32, either with
     unit column stride (row-major) or unit row stride (column-major, e.g. the
     transpose of a contiguous l x n tensor).  keep: host mask over the N+e
-    blocks (None = the first N).  workspace: optional uint8 CUDA tensor of at
-    least workspace_bytes(...) bytes.
+    blocks (None = the first N).  precision: operands of the block product,
+    "fp32", "bf16" or "bf16x3" (split BF16); FP32 accumulation.  workspace:
+    optional uint8 CUDA tensor of at least workspace_bytes(...) bytes.
     """
     torch = _torch()
     _require_cuda(A, "A", torch.float32)
@@ -313,8 +382,9 @@ def matmul(A, B, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None
         b_col_major, ldb = 1, B.stride(1) if l > 1 else (n + 3) // 4 * 4
     else:
         raise OversketchError("B must have a unit stride in one dimension")
+    p = _prec(precision)
     s = _sketch(b, N, e, seed, h, sigma)
-    need = int(lib().os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, b_col_major))
+    need = int(lib().os_matmul_prec_workspace_bytes(ctypes.byref(s), m, n, l, b_col_major, p))
     if need == 0:
         raise OversketchError("invalid sizes for os_matmul")
     if workspace is None:
@@ -324,8 +394,8 @@ def matmul(A, B, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None
     _require_cuda(out, "out", torch.float32)
     _, _, ldc = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
-    _check(lib().os_matmul(ctypes.byref(s), _ptr(A), lda, _ptr(B), ldb, b_col_major, m, n, l, pk,
-                           int(bool(kept_only)), _ptr(out), ldc, _ptr(workspace),
-                           workspace.numel() * workspace.element_size(), _stream(stream)),
-           "os_matmul")
+    _check(lib().os_matmul_prec(ctypes.byref(s), _ptr(A), lda, _ptr(B), ldb, b_col_major, m, n,
+                                l, pk, int(bool(kept_only)), p, _ptr(out), ldc, _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream)),
+           "os_matmul_prec")
     return out

@@ -110,6 +110,14 @@ os_status check_prep(const os_sketch* sk, int64_t n, const void* prep, size_t pr
     return OS_OK;
 }
 
+bool valid_prec(int p) { return p == OS_PREC_FP32 || p == OS_PREC_BF16 || p == OS_PREC_BF16X3; }
+
+// Columns of a quantized sketch over nst blocks (0 for FP32: no copy).
+int64_t quant_width(int32_t b, int32_t nst, int prec) {
+    if (prec == OS_PREC_FP32) return 0;
+    return (int64_t)nst * osk::block_stride_bf16(b) * (prec == OS_PREC_BF16X3 ? 2 : 1);
+}
+
 }  // namespace
 
 extern "C" {
@@ -229,29 +237,88 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
         if (!keep_host || keep_host[j]) kept.idx[K++] = j;
     for (int32_t j = K; j < OS_MAX_BLOCKS; ++j) kept.idx[j] = 0;
     if (K == 0) return OS_ENOKEEP;
-    if (!osk::plan_gemm_ok(m, l, bp, ldat, ldbt)) return OS_EINVAL;
+    if (!osk::plan_gemm_ok(m, l, bp, ldat, ldbt, 4)) return OS_EINVAL;
     return hip_status(osk::launch_gemm_kept(At, ldat, Bt, ldbt, m, l, bp, kept, K, 1.0f / (float)K, C,
                                             ldc, (hipStream_t)stream));
 }
 
-size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
-                                 int b_col_major) {
-    if (check_sketch(sk) != OS_OK || check_len(n) != OS_OK || check_extent(m) != OS_OK ||
-        check_extent(l) != OS_OK)
-        return 0;
-    // Sized for all N+e blocks whatever the mask, so one workspace serves
-    // every call; a row-major B is transposed first.
-    const int64_t zp = (int64_t)nblocks(sk) * os_block_stride(sk->b);
-    return align256(prepare_bytes(sk, n)) + align256((size_t)m * zp * 4u) +
-           align256((size_t)l * zp * 4u) + (b_col_major ? 0 : osk::transpose_bytes(n, l));
+int32_t os_block_stride_prec(int32_t b, int precision) {
+    if (b < 1 || !valid_prec(precision)) return 0;
+    return precision == OS_PREC_FP32 ? os_block_stride(b) : osk::block_stride_bf16(b);
 }
 
-os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const float* B, int64_t ldb,
-                    int b_col_major, int64_t m, int64_t n, int64_t l, const uint8_t* keep_host,
-                    int kept_only, float* C, int64_t ldc, void* workspace, size_t ws_bytes,
-                    void* stream) {
+os_status os_sketch_quantize(const float* S, int64_t lines, int64_t lds, int32_t b, int32_t nst,
+                             int precision, void* Q, int64_t ldq, void* stream) {
+    if (b < 1 || b > OS_MAX_B || nst < 1 || nst > OS_MAX_BLOCKS) return OS_EINVAL;
+    if (!valid_prec(precision) || precision == OS_PREC_FP32) return OS_EINVAL;
+    os_status st;
+    if ((st = check_extent(lines)) != OS_OK) return st;
+    const int32_t bp = os_block_stride(b);
+    if ((st = check_matrix(S, lines, (int64_t)nst * bp, lds, false)) != OS_OK) return st;
+    const int64_t w = quant_width(b, nst, precision);
+    if (!Q) return OS_ENULL;
+    if (ldq < w) return OS_EINVAL;
+    if (!aligned(Q, 16) || (ldq & 7)) return OS_EALIGN;
+    return hip_status(osk::launch_quant_bf16(S, lines, lds, b, nst, precision == OS_PREC_BF16X3,
+                                             Q, ldq, (hipStream_t)stream));
+}
+
+os_status os_gemm_kept_prec(const void* At, int64_t ldat, const void* Bt, int64_t ldbt, int64_t m,
+                            int64_t l, int32_t b, int32_t nst, const uint8_t* keep_host,
+                            int precision, float* C, int64_t ldc, void* stream) {
+    if (!valid_prec(precision)) return OS_EINVAL;
+    if (precision == OS_PREC_FP32)
+        return os_gemm_kept(static_cast<const float*>(At), ldat, static_cast<const float*>(Bt),
+                            ldbt, m, l, b, nst, keep_host, C, ldc, stream);
+    if (b < 1 || b > OS_MAX_B || nst < 1 || nst > OS_MAX_BLOCKS) return OS_EINVAL;
+    os_status st;
+    if ((st = check_extent(m)) != OS_OK || (st = check_extent(l)) != OS_OK) return st;
+    const int64_t w = quant_width(b, nst, precision);
+    if (!At || !Bt) return OS_ENULL;
+    if (ldat < w || ldbt < w) return OS_EINVAL;
+    if (!aligned(At, 16) || !aligned(Bt, 16) || (ldat & 7) || (ldbt & 7)) return OS_EALIGN;
+    if ((st = check_matrix(C, m, l, ldc, false)) != OS_OK) return st;
+    BlockList kept;
+    int32_t K = 0;
+    for (int32_t j = 0; j < nst; ++j)
+        if (!keep_host || keep_host[j]) kept.idx[K++] = j;
+    for (int32_t j = K; j < OS_MAX_BLOCKS; ++j) kept.idx[j] = 0;
+    if (K == 0) return OS_ENOKEEP;
+    const int32_t bpq = osk::block_stride_bf16(b);
+    if (!osk::plan_gemm_ok(m, l, bpq, ldat, ldbt, 2)) return OS_EINVAL;
+    return hip_status(osk::launch_gemm_kept_bf16(At, ldat, Bt, ldbt, m, l, bpq, kept, K,
+                                                 precision == OS_PREC_BF16X3,
+                                                 (int64_t)nst * bpq, 1.0f / (float)K, C, ldc,
+                                                 (hipStream_t)stream));
+}
+
+size_t os_matmul_prec_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
+                                      int b_col_major, int precision) {
+    if (check_sketch(sk) != OS_OK || check_len(n) != OS_OK || check_extent(m) != OS_OK ||
+        check_extent(l) != OS_OK || !valid_prec(precision))
+        return 0;
+    // Sized for all N+e blocks whatever the mask, so one workspace serves
+    // every call; a row-major B is transposed first; a low-precision product
+    // adds the quantized copies of both sketches.
+    const int64_t zp = (int64_t)nblocks(sk) * os_block_stride(sk->b);
+    const int64_t wq = quant_width(sk->b, nblocks(sk), precision);
+    return align256(prepare_bytes(sk, n)) + align256((size_t)m * zp * 4u) +
+           align256((size_t)l * zp * 4u) + (b_col_major ? 0 : osk::transpose_bytes(n, l)) +
+           align256((size_t)m * wq * 2u) + align256((size_t)l * wq * 2u);
+}
+
+size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
+                                 int b_col_major) {
+    return os_matmul_prec_workspace_bytes(sk, m, n, l, b_col_major, OS_PREC_FP32);
+}
+
+os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const float* B,
+                         int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
+                         const uint8_t* keep_host, int kept_only, int precision, float* C,
+                         int64_t ldc, void* workspace, size_t ws_bytes, void* stream) {
     os_status st = check_sketch(sk);
     if (st != OS_OK) return st;
+    if (!valid_prec(precision)) return OS_EINVAL;
     if ((st = check_len(n)) != OS_OK) return st;
     if ((st = check_extent(m)) != OS_OK || (st = check_extent(l)) != OS_OK) return st;
     if ((st = check_matrix(A, m, n, lda, false)) != OS_OK) return st;
@@ -263,23 +330,32 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     if ((st = check_matrix(C, m, l, ldc, false)) != OS_OK) return st;
     Blocks bs;
     if ((st = block_sets(sk, keep_host, kept_only, bs)) != OS_OK) return st;
-    const size_t need = os_matmul_workspace_bytes(sk, m, n, l, b_col_major);
+    const size_t need = os_matmul_prec_workspace_bytes(sk, m, n, l, b_col_major, precision);
     if (!workspace || !aligned(workspace, 256) || ws_bytes < need) return OS_EWORKSPACE;
     const int32_t bp = os_block_stride(sk->b);
+    const int32_t bpq = osk::block_stride_bf16(sk->b);
+    const int64_t wq = quant_width(sk->b, bs.nst, precision);
+    const bool gemm_ok = precision == OS_PREC_FP32
+                             ? osk::plan_gemm_ok(m, l, bp, (int64_t)bs.nst * bp,
+                                                 (int64_t)bs.nst * bp, 4)
+                             : osk::plan_gemm_ok(m, l, bpq, wq, wq, 2);
     if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !osk::plan_sketch_ok(l, bs.nst, bp, n) ||
-        !osk::plan_gemm_ok(m, l, bp, (int64_t)bs.nst * bp, (int64_t)bs.nst * bp))
+        !gemm_ok)
         return OS_EINVAL;
 
     // both sketches use the stored width as leading dimension (a multiple of 32)
     const int64_t zs = (int64_t)bs.nst * bp;
     const int64_t zp = (int64_t)nblocks(sk) * bp;
+    const int64_t wqp = quant_width(sk->b, nblocks(sk), precision);
     char* ws = static_cast<char*>(workspace);
     void* prep = ws;
-    float* At = reinterpret_cast<float*>(ws + align256(prepare_bytes(sk, n)));
-    float* Bt = reinterpret_cast<float*>(reinterpret_cast<char*>(At) +
-                                         align256((size_t)m * zp * 4u));
-    float* Bx = reinterpret_cast<float*>(reinterpret_cast<char*>(Bt) +
-                                         align256((size_t)l * zp * 4u));
+    char* at_p = ws + align256(prepare_bytes(sk, n));
+    char* bt_p = at_p + align256((size_t)m * zp * 4u);
+    char* bx_p = bt_p + align256((size_t)l * zp * 4u);
+    char* aq_p = bx_p + (b_col_major ? 0 : osk::transpose_bytes(n, l));
+    char* bq_p = aq_p + align256((size_t)m * wqp * 2u);
+    float* At = reinterpret_cast<float*>(at_p);
+    float* Bt = reinterpret_cast<float*>(bt_p);
     hipStream_t s = (hipStream_t)stream;
     const void* lists = prep_lists(prep, sk, n);
 
@@ -294,14 +370,34 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
     int64_t ldl = ldb;
     if (!b_col_major) {
         ldl = osk::round_up(n, 4);
+        float* Bx = reinterpret_cast<float*>(bx_p);
         if ((st = hip_status(osk::launch_transpose(B, n, l, ldb, Bx, ldl, s))) != OS_OK) return st;
         Bl = Bx;
     }
     if ((st = hip_status(osk::launch_sketch_cols(Bl, l, n, ldl, bs.stored, bs.nst, nblocks(sk), bp,
                                                  lists, Bt, zs, s))) != OS_OK)
         return st;
-    return hip_status(osk::launch_gemm_kept(At, zs, Bt, zs, m, l, bp, bs.kept_pos, bs.K,
-                                            1.0f / (float)bs.K, C, ldc, s));
+    if (precision == OS_PREC_FP32)
+        return hip_status(osk::launch_gemm_kept(At, zs, Bt, zs, m, l, bp, bs.kept_pos, bs.K,
+                                                1.0f / (float)bs.K, C, ldc, s));
+    const int split = precision == OS_PREC_BF16X3;
+    if ((st = hip_status(osk::launch_quant_bf16(At, m, zs, sk->b, bs.nst, split, aq_p, wq, s))) !=
+        OS_OK)
+        return st;
+    if ((st = hip_status(osk::launch_quant_bf16(Bt, l, zs, sk->b, bs.nst, split, bq_p, wq, s))) !=
+        OS_OK)
+        return st;
+    return hip_status(osk::launch_gemm_kept_bf16(aq_p, wq, bq_p, wq, m, l, bpq, bs.kept_pos, bs.K,
+                                                 split, (int64_t)bs.nst * bpq,
+                                                 1.0f / (float)bs.K, C, ldc, s));
+}
+
+os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const float* B, int64_t ldb,
+                    int b_col_major, int64_t m, int64_t n, int64_t l, const uint8_t* keep_host,
+                    int kept_only, float* C, int64_t ldc, void* workspace, size_t ws_bytes,
+                    void* stream) {
+    return os_matmul_prec(sk, A, lda, B, ldb, b_col_major, m, n, l, keep_host, kept_only,
+                          OS_PREC_FP32, C, ldc, workspace, ws_bytes, stream);
 }
 
 }  // extern "C"

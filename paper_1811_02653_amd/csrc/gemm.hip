@@ -34,8 +34,8 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int BM = 256;
 constexpr int BN = 256;
-constexpr int BK = 32;
-constexpr int LDT = 36;         // LDS row stride (floats) of a tile row (32 K values)
+constexpr int kStepBytes = 128; // K step: 128 bytes of each tile row (32 FP32 / 64 BF16 values)
+constexpr int LDT = 36;         // LDS row stride (4-byte words) of a tile row
 constexpr int kThreads = 256;
 constexpr int kGroupM = 4;
 
@@ -49,7 +49,7 @@ __device__ __forceinline__ int64_t xcd_task(int64_t L, int64_t tasks) {
 // (wave-uniform) describes the tile's first row, `kbyte` (wave-uniform, in
 // SGPRs) is the byte offset of the step's first K column and off[u] (one
 // 32-bit VGPR each) the byte offset of the thread's row u and K quad.  Every
-// offset stays below 2^32 (the leading dimension is at most kMaxSketchLd) and
+// offset stays below 2^32 (a row is at most kMaxSketchLdBytes long) and
 // inside the matrix: rows past its end were clamped to its last row when the
 // offsets were made.  Those rows only feed rows or columns of C beyond the
 // matrix, which are never stored, so every load is unconditional and
@@ -64,15 +64,15 @@ __device__ __forceinline__ void load_tile(float4 (&r)[8], __amdgpu_buffer_rsrc_t
 
 // Buffer resource of a matrix starting at p: no stride, no range limit
 // (num_records = 2^32 - 1), the gfx9 data format word.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const float* p) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, -1, 0x00020000);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
 }
 
-__device__ __forceinline__ void tile_offsets(uint32_t (&off)[8], int64_t ld, int rel, int last,
-                                             int kq) {
+__device__ __forceinline__ void tile_offsets(uint32_t (&off)[8], int64_t ld_bytes, int rel,
+                                             int last, int kq) {
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-        off[u] = (uint32_t)(((int64_t)min(rel + 32 * u, last) * ld + 4 * kq) * 4);
+        off[u] = (uint32_t)((int64_t)min(rel + 32 * u, last) * ld_bytes + 16 * kq);
 }
 
 __device__ __forceinline__ void store_tile(float* __restrict__ s, const float4 (&r)[8], int tid) {
@@ -98,23 +98,52 @@ __device__ __forceinline__ float comp(const float4& v, int c) {
     return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
 }
 
-__device__ __forceinline__ void mfma_quad(v16f (&acc)[4][4], const float4 (&a)[4],
-                                          const float4 (&b)[4]) {
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Operand precisions of the block product.  A K step is 128 bytes of a tile
+// row in both: 32 FP32 values or 64 BF16 values.  A fragment is 16 bytes:
+// lane half h of quad q holds the K values at byte offset 64h + 16q of the
+// step's row (4 FP32 values feeding four 32x32x2 MFMAs, or 8 BF16 values
+// feeding one 32x32x16 MFMA); A and B use the same K order.
+struct PrecF32 {
+    static constexpr int kElem = 4;
+    __device__ static __forceinline__ void mfma_quad(v16f (&acc)[4][4], const float4 (&a)[4],
+                                                     const float4 (&b)[4]) {
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(a[i], kk), comp(b[j], kk),
+                                                                     acc[i][j], 0, 0, 0);
+    }
+};
+
+struct PrecBF16 {
+    static constexpr int kElem = 2;
+    __device__ static __forceinline__ void mfma_quad(v16f (&acc)[4][4], const float4 (&a)[4],
+                                                     const float4 (&b)[4]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(a[i], kk), comp(b[j], kk),
-                                                                 acc[i][j], 0, 0, 0);
-}
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, a[i]), __builtin_bit_cast(bf16x8, b[j]), acc[i][j],
+                    0, 0, 0);
+    }
+};
 
+// Terms of the K loop: kept block j contributes nsub terms.  Term 0 pairs
+// the A and B columns of the block; with nsub = 3 (split precision), term 1
+// pairs A's block with the low part of B's block (lo_off columns further)
+// and term 2 the low part of A's block with B's block.
+template <typename P>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* __restrict__ Bt,
+void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __restrict__ Bt,
                       int64_t ldbt, int64_t m, int64_t l, int32_t bp, BlockList kept,
-                      int32_t nkept, float scale, float* __restrict__ C, int64_t ldc,
-                      int32_t tilesM, int32_t tilesN) {
+                      int32_t nkept, int32_t nsub, int64_t lo_off, float scale,
+                      float* __restrict__ C, int64_t ldc, int32_t tilesM, int32_t tilesN) {
     __shared__ __align__(16) float As[2][BM * LDT];
     __shared__ __align__(16) float Bs[2][BN * LDT];
 
@@ -143,12 +172,26 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    const int tpb = bp / BK;                       // K steps per block
-    const int total = nkept * tpb;
-    // byte offset of the first K column of step `step` (kept blocks in order,
-    // BK columns per step)
-    auto step_col = [&](int step) -> uint32_t {    // in bytes
-        return (uint32_t)(((int64_t)kept.idx[step / tpb] * bp + (int64_t)(step % tpb) * BK) * 4);
+    constexpr int kStep = kStepBytes / P::kElem;     // K values per step
+    const int tpb = bp / kStep;                       // K steps per term
+    const int total = nkept * nsub * tpb;
+    // byte offsets of the first K column of step `step` in A and in B
+    // (terms in order, kStep columns per step)
+    auto step_a = [&](int step) -> uint32_t {
+        const int term = step / tpb;
+        const int j = term / nsub;
+        const int sub = term - j * nsub;
+        const int64_t c = (int64_t)kept.idx[j] * bp + (int64_t)(step % tpb) * kStep +
+                          (sub == 2 ? lo_off : 0);
+        return (uint32_t)(c * P::kElem);
+    };
+    auto step_b = [&](int step) -> uint32_t {
+        const int term = step / tpb;
+        const int j = term / nsub;
+        const int sub = term - j * nsub;
+        const int64_t c = (int64_t)kept.idx[j] * bp + (int64_t)(step % tpb) * kStep +
+                          (sub == 1 ? lo_off : 0);
+        return (uint32_t)(c * P::kElem);
     };
 
     const int arow = wm * 128 + (lane & 31);
@@ -157,49 +200,50 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
 
     // the tile rows this thread loads: t/8 + 32u, clamped to the last row
     // inside the matrix
-    const __amdgpu_buffer_rsrc_t ra_src = tile_rsrc(At + row0 * ldat);
-    const __amdgpu_buffer_rsrc_t rb_src = tile_rsrc(Bt + col0 * ldbt);
+    const __amdgpu_buffer_rsrc_t ra_src =
+        tile_rsrc(static_cast<const char*>(At) + row0 * ldat * P::kElem);
+    const __amdgpu_buffer_rsrc_t rb_src =
+        tile_rsrc(static_cast<const char*>(Bt) + col0 * ldbt * P::kElem);
     uint32_t oa[8], ob[8];
-    tile_offsets(oa, ldat, tid >> 3, (int)min((int64_t)BM - 1, m - 1 - row0), tid & 7);
-    tile_offsets(ob, ldbt, tid >> 3, (int)min((int64_t)BN - 1, l - 1 - col0), tid & 7);
+    tile_offsets(oa, ldat * P::kElem, tid >> 3, (int)min((int64_t)BM - 1, m - 1 - row0), tid & 7);
+    tile_offsets(ob, ldbt * P::kElem, tid >> 3, (int)min((int64_t)BN - 1, l - 1 - col0), tid & 7);
 
     float4 ra[8], rb[8];
-    load_tile(ra, ra_src, step_col(0), oa);
-    load_tile(rb, rb_src, step_col(0), ob);
+    load_tile(ra, ra_src, step_a(0), oa);
+    load_tile(rb, rb_src, step_b(0), ob);
     store_tile(As[0], ra, tid);
     store_tile(Bs[0], rb, tid);
-    if (total > 1) {
-        load_tile(ra, ra_src, step_col(1), oa);
-        load_tile(rb, rb_src, step_col(1), ob);
-    }
+    load_tile(ra, ra_src, step_a(min(1, total - 1)), oa);
+    load_tile(rb, rb_src, step_b(min(1, total - 1)), ob);
     __syncthreads();
 
     float4 fa[4], fb[4], ga[4], gb[4];
     read_frag(fa, fb, As[0], Bs[0], 0, arow, brow, kh);
+    // The loop body has no branch, so the compiler can spread the LDS stores
+    // and global loads between the MFMAs: on the last two steps the tile
+    // stored (into the buffer no later step reads) and the tile loaded (step
+    // total - 1 again, a valid address) are simply never used.
     for (int t = 0; t < total; ++t) {
         const int cur = t & 1;
         const float* as = As[cur];
         const float* bs = Bs[cur];
         read_frag(ga, gb, as, bs, 1, arow, brow, kh);
-        mfma_quad(acc, fa, fb);
+        P::mfma_quad(acc, fa, fb);
         read_frag(fa, fb, as, bs, 2, arow, brow, kh);
-        mfma_quad(acc, ga, gb);
+        P::mfma_quad(acc, ga, gb);
         // the next step's tile goes into the other buffer (last read before
         // the previous step's barrier); the loads for the step after are
         // issued a whole step ahead of their use
-        if (t + 1 < total) {
-            store_tile(As[cur ^ 1], ra, tid);
-            store_tile(Bs[cur ^ 1], rb, tid);
-            if (t + 2 < total) {
-                load_tile(ra, ra_src, step_col(t + 2), oa);
-                load_tile(rb, rb_src, step_col(t + 2), ob);
-            }
-        }
+        store_tile(As[cur ^ 1], ra, tid);
+        store_tile(Bs[cur ^ 1], rb, tid);
+        const int ahead = min(t + 2, total - 1);
+        load_tile(ra, ra_src, step_a(ahead), oa);
+        load_tile(rb, rb_src, step_b(ahead), ob);
         read_frag(ga, gb, as, bs, 3, arow, brow, kh);
-        mfma_quad(acc, fa, fb);
-        mfma_quad(acc, ga, gb);
+        P::mfma_quad(acc, fa, fb);
+        P::mfma_quad(acc, ga, gb);
         __syncthreads();
-        if (t + 1 < total) read_frag(fa, fb, As[cur ^ 1], Bs[cur ^ 1], 0, arow, brow, kh);
+        read_frag(fa, fb, As[cur ^ 1], Bs[cur ^ 1], 0, arow, brow, kh);
     }
 
     // 32x32 accumulator layout: register r of lane L holds row
@@ -220,9 +264,10 @@ void gemm_kept_kernel(const float* __restrict__ At, int64_t ldat, const float* _
 
 }  // namespace
 
-bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt) {
-    if (m < 1 || l < 1 || bp < BK || bp % BK) return false;
-    if (ldat > kMaxSketchLd || ldbt > kMaxSketchLd) return false;
+bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt, int elem) {
+    const int step = kStepBytes / elem;
+    if (m < 1 || l < 1 || bp < step || bp % step) return false;
+    if (ldat * elem > kMaxSketchLdBytes || ldbt * elem > kMaxSketchLdBytes) return false;
     const int64_t tilesM = (m + BM - 1) / BM;
     const int64_t tilesN = (l + BN - 1) / BN;
     return tilesM * tilesN <= 0x7fffffff;
@@ -231,12 +276,25 @@ bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt) 
 hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
                             int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                             int32_t nkept, float scale, float* C, int64_t ldc, hipStream_t s) {
-    if (!plan_gemm_ok(m, l, bp, ldat, ldbt) || nkept < 1) return hipErrorInvalidValue;
+    if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 4) || nkept < 1) return hipErrorInvalidValue;
     const int64_t tilesM = (m + BM - 1) / BM;
     const int64_t tilesN = (l + BN - 1) / BN;
-    hipLaunchKernelGGL(gemm_kept_kernel, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads), 0, s,
-                       At, ldat, Bt, ldbt, m, l, bp, kept, nkept, scale, C, ldc, (int32_t)tilesM,
-                       (int32_t)tilesN);
+    hipLaunchKernelGGL(gemm_kept_kernel<PrecF32>, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads),
+                       0, s, At, ldat, Bt, ldbt, m, l, bp, kept, nkept, 1, (int64_t)0, scale, C,
+                       ldc, (int32_t)tilesM, (int32_t)tilesN);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                                 int64_t m, int64_t l, int32_t bp, const BlockList& kept,
+                                 int32_t nkept, int split, int64_t lo_off, float scale, float* C,
+                                 int64_t ldc, hipStream_t s) {
+    if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 2) || nkept < 1) return hipErrorInvalidValue;
+    const int64_t tilesM = (m + BM - 1) / BM;
+    const int64_t tilesN = (l + BN - 1) / BN;
+    hipLaunchKernelGGL(gemm_kept_kernel<PrecBF16>, dim3((unsigned)(tilesM * tilesN)),
+                       dim3(kThreads), 0, s, At, ldat, Bt, ldbt, m, l, bp, kept, nkept,
+                       split ? 3 : 1, lo_off, scale, C, ldc, (int32_t)tilesM, (int32_t)tilesN);
     return hipGetLastError();
 }
 

@@ -57,9 +57,9 @@ hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t l
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                               const void* lists, float* out, int64_t ldo, hipStream_t s);
 
-// Longest leading dimension of a sketch read by the block product: byte
+// Longest row pitch (bytes) of a sketch read by the block product: byte
 // offsets within a 256-row tile, K offset included, stay below 2^32.
-constexpr int64_t kMaxSketchLd = (int64_t(1) << 22) - 64;
+constexpr int64_t kMaxSketchLdBytes = (int64_t(1) << 24) - 256;
 // Y (cols x rows, ld ldy: a multiple of 4, Y 16-byte aligned) = X^T for X
 // rows x cols row-major (ld ldx); transpose_bytes = the size of Y with ldy =
 // rows rounded up to 4.
@@ -67,7 +67,9 @@ size_t transpose_bytes(int64_t rows, int64_t cols);
 hipError_t launch_transpose(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
                             int64_t ldy, hipStream_t s);
 
-bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt);
+// Shapes the block product supports for operands of elem bytes per value
+// (4: FP32, 2: BF16); bp must be a multiple of 128 / elem.
+bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt, int elem);
 
 // C = scale * sum over the kept stored blocks (kept.idx[0 .. nkept)) of
 // At_j * Bt_j^T, with At (m x nst*bp) and Bt (l x nst*bp) line-major
@@ -75,5 +77,27 @@ bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt);
 hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
                             int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                             int32_t nkept, float scale, float* C, int64_t ldc, hipStream_t s);
+// The same with BF16 sketches (block stride bp, a multiple of 64; leading
+// dimensions in BF16 values).  split != 0 adds the terms A_j * lo(B_j)^T and
+// lo(A_j) * B_j^T, the low parts lo_off columns after the high parts.
+hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                                 int64_t m, int64_t l, int32_t bp, const BlockList& kept,
+                                 int32_t nkept, int split, int64_t lo_off, float scale, float* C,
+                                 int64_t ldc, hipStream_t s);
+// The same with BF16 sketches (block stride bp, a multiple of 64; leading
+// dimensions in BF16 values).  split != 0 adds the terms A_j * lo(B_j)^T and
+// lo(A_j) * B_j^T, the low parts lo_off columns after the high parts.
+hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                                 int64_t m, int64_t l, int32_t bp, const BlockList& kept,
+                                 int32_t nkept, int split, int64_t lo_off, float scale, float* C,
+                                 int64_t ldc, hipStream_t s);
+
+// BF16 copy of a line-major FP32 sketch (lines x nst*bp, ld lds): block
+// stride block_stride_bf16(b) = b rounded up to 64, the residual part (when
+// split) after the nst blocks of the high part; Q 16-byte aligned, ldq a
+// multiple of 8 and >= nst * bpq * (split ? 2 : 1).
+int32_t block_stride_bf16(int32_t b);
+hipError_t launch_quant_bf16(const float* S, int64_t lines, int64_t lds, int32_t b, int32_t nst,
+                             int split, void* Q, int64_t ldq, hipStream_t s);
 
 }  // namespace osk

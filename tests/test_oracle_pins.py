@@ -455,3 +455,74 @@ def test_config1_error_level():
     expect = _second_moment_closed_form(A64, B64, b, N)
     assert err2 == pytest.approx(expect, rel=0.2)
     assert err2 <= 2.0 / (N * b) * oracle.frob2(A64) * oracle.frob2(B64)
+
+
+# ---------------------------------------------------------------------------
+# BF16 rounding (operands of the reduced-precision block product)
+# ---------------------------------------------------------------------------
+
+def _bf16_nearest_brute(x):
+    """Nearest BF16 value to each FP32 x by enumeration of the two BF16
+    neighbours (truncation and the next BF16 away from zero), ties to the
+    one with an even last kept bit: the definition, written without the
+    add-and-shift trick."""
+    out = np.empty_like(x)
+    for i, v in enumerate(x):
+        bits = int(np.float32(v).view(np.uint32))
+        lo_bits = bits & 0xFFFF0000
+        hi_bits = lo_bits + 0x10000
+        lo = np.uint32(lo_bits).view(np.float32)
+        hi = np.uint32(hi_bits & 0xFFFFFFFF).view(np.float32)
+        dlo = abs(float(v) - float(lo))
+        dhi = abs(float(v) - float(hi)) if np.isfinite(hi) else np.inf
+        if dlo < dhi:
+            out[i] = lo
+        elif dhi < dlo:
+            out[i] = hi
+        else:
+            out[i] = lo if ((lo_bits >> 16) & 1) == 0 else hi
+    return out
+
+
+def test_bf16_round_worked_values():
+    one = 1.0
+    cases = {
+        one: one,
+        one + 2.0 ** -8: one,                      # halfway, 1.0 has an even last bit
+        one + 3 * 2.0 ** -8: one + 2.0 ** -6,      # halfway, rounds up to the even neighbour
+        one + 2.0 ** -8 + 2.0 ** -20: one + 2.0 ** -7,   # above halfway
+        -(one + 2.0 ** -8 + 2.0 ** -20): -(one + 2.0 ** -7),
+        float(np.finfo(np.float32).max): np.inf,   # past the largest BF16 + half an ulp
+        3.0e38: float(np.uint32(0x7F62 << 16).view(np.float32)),
+        0.0: 0.0,
+        2.0 ** -133: 2.0 ** -133,                  # a subnormal that is already BF16
+    }
+    x = np.array(list(cases), dtype=np.float32)
+    want = np.array(list(cases.values()), dtype=np.float32)
+    np.testing.assert_array_equal(oracle.bf16_round(x), want)
+    assert np.isnan(oracle.bf16_round(np.array([np.nan], np.float32)))[0]
+
+
+def test_bf16_round_matches_nearest_value_definition():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(3000).astype(np.float32),
+                        (rng.standard_normal(2000) * 1e-39).astype(np.float32),  # subnormals
+                        np.float32(1.0) + rng.integers(0, 1 << 16, 2000).astype(np.float32)
+                        * np.float32(2.0 ** -23)])
+    np.testing.assert_array_equal(oracle.bf16_round(x), _bf16_nearest_brute(x))
+
+
+def test_bf16_split_recovers_sixteen_bits():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(10000).astype(np.float32)
+    hi, lo = oracle.bf16_split(x)
+    # BF16 keeps 8 significant bits: round to nearest is within 2^-8
+    # relatively, so hi + lo leaves one BF16 rounding of the residual:
+    # |x - hi - lo| <= 2^-8 |x - hi| <= 2^-16 |x| (normal range)
+    assert np.all(oracle.bf16_round(hi) == hi) and np.all(oracle.bf16_round(lo) == lo)
+    xd = np.abs(x.astype(np.float64))
+    assert np.all(np.abs(x.astype(np.float64) - hi) <= 2.0 ** -8 * xd)
+    r = np.abs(x.astype(np.float64) - hi - lo)
+    assert np.all(r <= 2.0 ** -16 * xd)
+    # and the split is not vacuous: the residual term matters
+    assert np.mean(np.abs(x.astype(np.float64) - hi)) > 100 * np.mean(r)
