@@ -47,6 +47,7 @@ GEMM_TRAFFIC = {
     "write_kib": 264192.0, "write_scale": 1.000,
 }
 FP32_MFMA_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix peak
+BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0               # MI355X HBM3E peak
 
 
@@ -71,6 +72,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-rows", type=int, default=6144,
                    help="rows of A and columns of B in the CPU oracle sample")
+    p.add_argument("--no-precision", action="store_true",
+                   help="skip the BF16 / split-BF16 variants of the block product")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 1 GiB device copy (3 times): the reference kernel "
                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -208,6 +211,90 @@ def main():
     t_exact = event_time_ms(torch, lambda: torch.matmul(A, B, out=Cx), 3, stream)
     del Cx
 
+    # ---- reduced-precision block product (BF16 operands, FP32 accumulation):
+    # whole steps, the block product alone, and the error against the exact
+    # FP64 AB, on the same inputs; then the same errors on inputs with
+    # log-normal (sigma = 2) row norms of A and column norms of B
+    precision = None
+    if not args.no_precision:
+        precision = {}
+        AB = torch.matmul(A.double(), B.double())
+        ab_norm = torch.linalg.norm(AB).item()
+        C32 = C.double()
+        for prec in ("bf16", "bf16x3"):
+            wsp = torch.empty(osk.workspace_bytes(m, n, l, b, N, e, precision=prec),
+                              dtype=torch.uint8, device=dev)
+            Cp = torch.empty((m, l), dtype=torch.float32, device=dev)
+
+            def pstep():
+                osk.matmul(A, B, b, N, e, seed=args.seed, keep=keep, kept_only=args.kept_only,
+                           out=Cp, workspace=wsp, stream=stream, precision=prec)
+
+            for _ in range(args.warmup):
+                pstep()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                pstep()
+            torch.cuda.synchronize()
+            p_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+            QA = osk.sketch_quantize(At, b, nst, precision=prec)
+            QB = osk.sketch_quantize(Bt, b, nst, precision=prec)
+            t_q = event_time_ms(torch, lambda: osk.sketch_quantize(At, b, nst, precision=prec,
+                                                                    out=QA, stream=stream),
+                                reps, stream)
+            t_pg = event_time_ms(torch, lambda: osk.gemm_kept_prec(QA, QB, b, nst, precision=prec,
+                                                                    keep=stored_keep, out=Cp,
+                                                                    stream=stream),
+                                 reps, stream)
+            bq = osk.block_stride_prec(b, prec)
+            flops = 2.0 * m * l * K * bq * (3 if prec == "bf16x3" else 1)
+            pstep()
+            torch.cuda.synchronize()
+            Cd = Cp.double()
+            precision[prec] = {
+                "ms_per_step": p_ms,
+                "eff_tflops": 2.0 * m * n * l / (p_ms * 1e-3) / 1e12,
+                "gemm_ms": t_pg,
+                "gemm_tflops": flops / (t_pg * 1e-3) / 1e12,
+                "gemm_frac_of_bf16_peak": flops / (t_pg * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS,
+                "quantize_ms_per_sketch": t_q,
+                "rel_frob_vs_exact_fp64": (torch.linalg.norm(Cd - AB).item() / ab_norm),
+                "rel_frob_vs_fp32_path": (torch.linalg.norm(Cd - C32).item() /
+                                          torch.linalg.norm(C32).item()),
+            }
+            log("%s: step %.3f ms (%.1f eff TFLOP/s), block product %.3f ms (%.1f TFLOP/s), "
+                "error vs exact %.4e" % (prec, p_ms, precision[prec]["eff_tflops"], t_pg,
+                                         precision[prec]["gemm_tflops"],
+                                         precision[prec]["rel_frob_vs_exact_fp64"]))
+            del wsp, QA, QB, Cd
+        del AB, C32
+        torch.cuda.empty_cache()
+        # error on log-normal row / column norms (same shapes, same sketch)
+        A2_h, B2_h = synthetic.lognormal_scaled_pair(m, n, l, args.seed, sigma=2.0)
+        A2 = torch.from_numpy(A2_h).to(dev)
+        B2 = torch.from_numpy(B2_h).to(dev)
+        del A2_h, B2_h
+        AB2 = torch.matmul(A2.double(), B2.double())
+        n2 = torch.linalg.norm(AB2).item()
+        lognormal, vs32 = {}, {}
+        C2 = None
+        for prec in ("fp32", "bf16", "bf16x3"):
+            Cq = osk.matmul(A2, B2, b, N, e, seed=args.seed, keep=keep, precision=prec)
+            torch.cuda.synchronize()
+            lognormal[prec] = torch.linalg.norm(Cq.double() - AB2).item() / n2
+            if prec == "fp32":
+                C2 = Cq.double()
+            else:
+                vs32[prec] = torch.linalg.norm(Cq.double() - C2).item() / torch.linalg.norm(C2).item()
+            del Cq
+        precision["lognormal_rows_cols_sigma2"] = {"rel_frob_vs_exact_fp64": lognormal,
+                                                   "rel_frob_vs_fp32_path": vs32}
+        del C2
+        log("log-normal norms, error vs exact: %s" % lognormal)
+        del A2, B2, AB2
+        torch.cuda.empty_cache()
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
     sample_err = None
@@ -273,6 +360,7 @@ def main():
         "error": {"rel_frob_vs_exact_fp64": rel_err,
                   "normalised_err2": norm_err2,
                   "rel_frob_vs_oracle_sample": sample_err},
+        "precision_variants": precision,
         "exact_gemm": {"kind": "torch.matmul FP32 (hipBLASLt)", "ms": t_exact,
                        "tflops": 2.0 * m * n * l / (t_exact * 1e-3) / 1e12,
                        "speedup_of_sketched": t_exact / ms_per_step},
