@@ -48,6 +48,7 @@ GEMM_TRAFFIC = {
 }
 FP32_MFMA_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
+FP8_MFMA_PEAK_TFLOPS = 5000.0       # MI355X dense FP8 matrix peak
 HBM_PEAK_GBS = 8000.0               # MI355X HBM3E peak
 
 
@@ -211,7 +212,8 @@ def main():
     t_exact = event_time_ms(torch, lambda: torch.matmul(A, B, out=Cx), 3, stream)
     del Cx
 
-    # ---- reduced-precision block product (BF16 operands, FP32 accumulation):
+    # ---- reduced-precision block product (BF16 or FP8 operands with
+    # power-of-two block scales, FP32 accumulation; split forms add residuals):
     # whole steps, the block product alone, and the error against the exact
     # FP64 AB, on the same inputs; then the same errors on inputs with
     # log-normal (sigma = 2) row norms of A and column norms of B
@@ -221,7 +223,7 @@ def main():
         AB = torch.matmul(A.double(), B.double())
         ab_norm = torch.linalg.norm(AB).item()
         C32 = C.double()
-        for prec in ("bf16", "bf16x3"):
+        for prec in ("bf16", "bf16x3", "fp8", "fp8x3"):
             wsp = torch.empty(osk.workspace_bytes(m, n, l, b, N, e, precision=prec),
                               dtype=torch.uint8, device=dev)
             Cp = torch.empty((m, l), dtype=torch.float32, device=dev)
@@ -248,7 +250,8 @@ def main():
                                                                     stream=stream),
                                  reps, stream)
             bq = osk.block_stride_prec(b, prec)
-            flops = 2.0 * m * l * K * bq * (3 if prec == "bf16x3" else 1)
+            flops = 2.0 * m * l * K * bq * (3 if prec.endswith("x3") else 1)
+            peak = FP8_MFMA_PEAK_TFLOPS if prec.startswith("fp8") else BF16_MFMA_PEAK_TFLOPS
             pstep()
             torch.cuda.synchronize()
             Cd = Cp.double()
@@ -257,7 +260,8 @@ def main():
                 "eff_tflops": 2.0 * m * n * l / (p_ms * 1e-3) / 1e12,
                 "gemm_ms": t_pg,
                 "gemm_tflops": flops / (t_pg * 1e-3) / 1e12,
-                "gemm_frac_of_bf16_peak": flops / (t_pg * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS,
+                "gemm_peak_tflops": peak,
+                "gemm_frac_of_peak": flops / (t_pg * 1e-3) / 1e12 / peak,
                 "quantize_ms_per_sketch": t_q,
                 "rel_frob_vs_exact_fp64": (torch.linalg.norm(Cd - AB).item() / ab_norm),
                 "rel_frob_vs_fp32_path": (torch.linalg.norm(Cd - C32).item() /
@@ -279,7 +283,7 @@ def main():
         n2 = torch.linalg.norm(AB2).item()
         lognormal, vs32 = {}, {}
         C2 = None
-        for prec in ("fp32", "bf16", "bf16x3"):
+        for prec in ("fp32", "bf16", "bf16x3", "fp8", "fp8x3"):
             Cq = osk.matmul(A2, B2, b, N, e, seed=args.seed, keep=keep, precision=prec)
             torch.cuda.synchronize()
             lognormal[prec] = torch.linalg.norm(Cq.double() - AB2).item() / n2

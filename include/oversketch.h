@@ -93,6 +93,9 @@ typedef int os_status;
 #define OS_PREC_FP32   0   /* FP32 operands, v_mfma_f32_32x32x2_f32 */
 #define OS_PREC_BF16   1   /* BF16 operands (round to nearest even), v_mfma_f32_32x32x16_bf16 */
 #define OS_PREC_BF16X3 2   /* split BF16: x = hi + lo, product hi*hi' + hi*lo' + lo*hi' */
+#define OS_PREC_FP8    3   /* FP8 E4M3 with an E8M0 (power-of-two) scale per 64 values,
+                              v_mfma_scale_f32_32x32x64_f8f6f4 */
+#define OS_PREC_FP8X3  4   /* split FP8: the residual quantized with its own scales */
 #define OS_MAX_B      8192                  /* upper limit on the block width b */
 #define OS_MAX_N      (2147483647LL - 64LL) /* upper limit on the sketched dimension n */
 #define OS_MAX_ROWS   16777216LL            /* upper limit on m and l */
@@ -192,26 +195,41 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
                        const uint8_t* keep_host, float* C, int64_t ldc, void* stream);
 
 /* Columns taken by one stored block in a sketch of the given precision:
- * b rounded up to 32 (FP32) or 64 (BF16 forms); 0 on invalid arguments. */
+ * b rounded up to 32 (FP32), 64 (BF16 forms) or 128 (FP8 forms); 0 on
+ * invalid arguments. */
 int32_t os_block_stride_prec(int32_t b, int precision);
 
+/* Length of one row of a quantized sketch over nst blocks: BF16 values for
+ * the BF16 forms, bytes for the FP8 forms (codes, then one scale byte per
+ * 64 codes); 0 for OS_PREC_FP32 or invalid arguments. */
+int64_t os_quantized_row(int32_t b, int32_t nst, int precision);
+
 /* Low-precision copy of a line-major FP32 sketch S (lines x nst*bp, ld lds,
- * bp = os_block_stride(b)) for os_gemm_kept_prec.  precision: OS_PREC_BF16
- * (Q = round-to-nearest-even BF16 of S) or OS_PREC_BF16X3 (Q = [hi | lo],
- * hi = bf16(S), lo = bf16(S - hi)).  Q: DEVICE BF16, lines x width, width =
- * nst * bq * (1 or 2), bq = os_block_stride_prec(b, precision), column
- * j*bq + c = block j, bucket c (zero for c >= b), the low part width/2
- * columns after the high part; ldq >= width, a multiple of 8; Q 16-byte
- * aligned. */
+ * bp = os_block_stride(b)) for os_gemm_kept_prec.  bq =
+ * os_block_stride_prec(b, precision); block j of S becomes codes j*bq ..
+ * j*bq + bq - 1 of a row (zero past b), the split forms' residual part
+ * follows at nst*bq.
+ *   OS_PREC_BF16:   hi = round-to-nearest-even BF16 of S;
+ *   OS_PREC_BF16X3: [hi | lo], lo = bf16(S - hi);
+ *   OS_PREC_FP8:    per 64 consecutive values of a row: s = the smallest
+ *                   integer with max|x| <= 448 * 2^s (clamped to
+ *                   [-127, 127]), code = E4M3 round-to-nearest-even of
+ *                   x * 2^-s; the row's scale bytes (s + 127, one per 64
+ *                   codes, in code order) follow its codes;
+ *   OS_PREC_FP8X3:  the same for S and for the residual S - dequant(code).
+ * Q: DEVICE, lines x os_quantized_row(b, nst, precision) (BF16 values or
+ * bytes), ld ldq in the same unit, rows 16-byte aligned (Q 16-byte aligned,
+ * ldq a multiple of 16 bytes). */
 os_status os_sketch_quantize(const float* S, int64_t lines, int64_t lds, int32_t b, int32_t nst,
                              int precision, void* Q, int64_t ldq, void* stream);
 
 /* Step "grouped product over the kept blocks" with operands of the given
- * precision: OS_PREC_FP32 is os_gemm_kept; the BF16 forms take the copies
- * os_sketch_quantize makes (At: m x width, Bt: l x width, leading dimensions
- * in BF16 values, multiples of 8, 16-byte aligned) and compute
+ * precision: OS_PREC_FP32 is os_gemm_kept; the other forms take the copies
+ * os_sketch_quantize makes (At: m rows, Bt: l rows, each
+ * os_quantized_row(b, nst, precision) long, leading dimensions in the same
+ * unit, rows 16-byte aligned) and compute
  *   C = (1/K) * sum_{kept j} hi(A_j) hi(B_j)^T [+ hi(A_j) lo(B_j)^T + lo(A_j) hi(B_j)^T]
- * with FP32 MFMA accumulation. */
+ * (FP8: each 64-value block times its scale) with FP32 MFMA accumulation. */
 os_status os_gemm_kept_prec(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
                             int64_t m, int64_t l, int32_t b, int32_t nst,
                             const uint8_t* keep_host, int precision, float* C, int64_t ldc,

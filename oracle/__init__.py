@@ -283,6 +283,71 @@ def bf16_split(x):
     return hi, lo
 
 
+# FP8 E4M3 (OCP): 1 sign, 4 exponent bits (bias 7), 3 fraction bits; no
+# infinities; the all-ones exponent with fraction 111 is NaN, so the largest
+# finite magnitude is 1.75 * 2^8 = 448; subnormals are m * 2^-9, m = 1..7.
+E4M3_MAX = 448.0
+
+
+def e4m3_values() -> np.ndarray:
+    """The 127 non-negative finite E4M3 magnitudes, indexed by their 7-bit
+    code (exponent << 3 | fraction)."""
+    v = np.empty(127)
+    for code in range(127):
+        e, m = code >> 3, code & 7
+        v[code] = m * 2.0 ** -9 if e == 0 else (1 + m / 8) * 2.0 ** (e - 7)
+    return v
+
+
+def e4m3_round(y) -> np.ndarray:
+    """Nearest E4M3 value to each y (|y| <= 448), ties to the even code."""
+    y = np.asarray(y, dtype=np.float64)
+    vals = e4m3_values()
+    a = np.abs(y)
+    hi = np.clip(np.searchsorted(vals, a), 1, 126)
+    lo = hi - 1
+    dlo, dhi = a - vals[lo], vals[hi] - a
+    pick = np.where(dlo < dhi, lo, np.where(dhi < dlo, hi, np.where(lo % 2 == 0, lo, hi)))
+    return np.sign(y) * vals[pick]
+
+
+def e8m0_scale_exponent(amax: float) -> int:
+    """The smallest integer s with amax <= 448 * 2^s, clamped to [-127, 127]
+    (the power-of-two scale of a block; E8M0 stores s + 127)."""
+    if not amax > 0:
+        return -127
+    s = int(np.floor(np.log2(amax / E4M3_MAX)))
+    while amax > E4M3_MAX * 2.0 ** s:
+        s += 1
+    while amax <= E4M3_MAX * 2.0 ** (s - 1):
+        s -= 1
+    return max(-127, min(127, s))
+
+
+def fp8_block_quantize(x, block: int = 32):
+    """Per row, per `block` consecutive values: the scale exponent s of the
+    block and the dequantized values e4m3_round(x * 2^-s) * 2^s.  Returns
+    (values (FP64, same shape as x), exponents (rows x cols/block))."""
+    x = np.asarray(x, dtype=np.float64)
+    rows, cols = x.shape
+    if cols % block:
+        raise ValueError("columns must be a multiple of the block")
+    xb = x.reshape(rows, cols // block, block)
+    amax = np.abs(xb).max(axis=2)
+    s = np.vectorize(e8m0_scale_exponent, otypes=[np.int64])(amax)
+    sc = np.ldexp(1.0, s)[:, :, None]
+    q = e4m3_round(xb / sc) * sc
+    return q.reshape(rows, cols), s
+
+
+def fp8_split(x, block: int = 32):
+    """(hi, lo): hi the block-quantized x, lo the block-quantized residual
+    x - hi (each with its own scales), FP64 values."""
+    hi, _ = fp8_block_quantize(x, block)
+    lo, _ = fp8_block_quantize(np.asarray(x, np.float64) - hi, block)
+    return hi, lo
+
+
 # ---------------------------------------------------------------------------
 # Error measures (Definition of (eps, theta)-accuracy; Fig. 5b's metric)
 # ---------------------------------------------------------------------------

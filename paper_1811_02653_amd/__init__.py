@@ -18,7 +18,8 @@ import numpy as np
 __all__ = [
     "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "sketch_cols",
     "sketch_rows", "sketch_rows_workspace_bytes", "gemm_kept", "matmul", "workspace_bytes",
-    "stored_count", "PRECISIONS", "block_stride_prec", "sketch_quantize", "gemm_kept_prec",
+    "stored_count", "PRECISIONS", "block_stride_prec", "quantized_row", "sketch_quantize",
+    "gemm_kept_prec",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,7 +30,7 @@ OS_MAX_BLOCKS = 256
 OS_MAX_B = 8192
 
 # operand precisions of the block product (OS_PREC_* in oversketch.h)
-PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp8": 3, "fp8x3": 4}
 
 
 class OversketchError(RuntimeError):
@@ -92,6 +93,8 @@ def lib():
                             vp, i64, vp, sz, vp]
     L.os_block_stride_prec.restype = i32
     L.os_block_stride_prec.argtypes = [i32, ctypes.c_int]
+    L.os_quantized_row.restype = i64
+    L.os_quantized_row.argtypes = [i32, i32, ctypes.c_int]
     L.os_sketch_quantize.restype = ctypes.c_int
     L.os_sketch_quantize.argtypes = [vp, i64, i64, i32, i32, ctypes.c_int, vp, i64, vp]
     L.os_gemm_kept_prec.restype = ctypes.c_int
@@ -143,8 +146,11 @@ def _row_major(t, name):
     if t.dim() != 2 or t.stride(1) != 1:
         raise OversketchError("%s must be 2-D with unit column stride" % name)
     rows, cols = t.shape
-    # a single row never uses its leading dimension: report an aligned one
-    return rows, cols, t.stride(0) if rows > 1 else (cols + 3) // 4 * 4
+    # a single row never uses its leading dimension: report its stride when
+    # that is a valid one, else an aligned one
+    if rows > 1 or t.stride(0) >= cols:
+        return rows, cols, t.stride(0)
+    return rows, cols, (cols + 15) // 16 * 16
 
 
 def _sketch(b, N, e, seed, h=None, sigma=None):
@@ -310,18 +316,28 @@ def block_stride_prec(b: int, precision: str = "fp32") -> int:
     return int(lib().os_block_stride_prec(int(b), _prec(precision)))
 
 
+def quantized_row(b, nst, precision) -> int:
+    """Length of a row of a quantized sketch: BF16 values, or bytes for the
+    FP8 forms (codes, then one scale byte per 64 codes)."""
+    return int(lib().os_quantized_row(int(b), int(nst), _prec(precision)))
+
+
 def sketch_quantize(S, b, nst, precision="bf16", out=None, stream=None):
-    """BF16 copy of a line-major FP32 sketch (lines x nst*block_stride(b)) for
-    gemm_kept_prec: lines x (nst * block_stride_prec(b)) values, twice that
-    for "bf16x3" (high part, then the residual part)."""
+    """Low-precision copy of a line-major FP32 sketch (lines x nst*block_stride(b))
+    for gemm_kept_prec: BF16 (lines x quantized_row) or, for the FP8 forms,
+    uint8 (lines x quantized_row bytes: E4M3 codes, then the E8M0 scales)."""
     torch = _torch()
     _require_cuda(S, "S", torch.float32)
     lines, _, lds = _row_major(S, "S")
     p = _prec(precision)
-    width = nst * block_stride_prec(b, precision) * (2 if precision == "bf16x3" else 1)
+    width = quantized_row(b, nst, precision)
+    fp8 = precision.startswith("fp8")
+    dt = torch.uint8 if fp8 else torch.bfloat16
+    pad = 16 if fp8 else 8                      # rows of 16 bytes
     if out is None:
-        out = torch.empty((lines, width), dtype=torch.bfloat16, device=S.device)
-    _require_cuda(out, "out", torch.bfloat16)
+        out = torch.empty((lines, (width + pad - 1) // pad * pad), dtype=dt,
+                          device=S.device)[:, :width]
+    _require_cuda(out, "out", dt)
     _, w, ldq = _row_major(out, "out")
     if w != width:
         raise OversketchError("out must have %d columns" % width)
@@ -336,7 +352,8 @@ def gemm_kept_prec(At, Bt, b, nst, precision="bf16", keep=None, out=None, stream
     gemm_kept does."""
     torch = _torch()
     p = _prec(precision)
-    dt = torch.float32 if precision == "fp32" else torch.bfloat16
+    dt = {"fp32": torch.float32, "bf16": torch.bfloat16, "bf16x3": torch.bfloat16,
+          "fp8": torch.uint8, "fp8x3": torch.uint8}[precision]
     _require_cuda(At, "At", dt)
     _require_cuda(Bt, "Bt", dt)
     m, _, lda = _row_major(At, "At")

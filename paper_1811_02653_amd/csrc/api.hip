@@ -110,12 +110,29 @@ os_status check_prep(const os_sketch* sk, int64_t n, const void* prep, size_t pr
     return OS_OK;
 }
 
-bool valid_prec(int p) { return p == OS_PREC_FP32 || p == OS_PREC_BF16 || p == OS_PREC_BF16X3; }
+bool valid_prec(int p) { return p >= OS_PREC_FP32 && p <= OS_PREC_FP8X3; }
+bool is_fp8(int p) { return p == OS_PREC_FP8 || p == OS_PREC_FP8X3; }
+bool is_split(int p) { return p == OS_PREC_BF16X3 || p == OS_PREC_FP8X3; }
 
-// Columns of a quantized sketch over nst blocks (0 for FP32: no copy).
+// Block stride of a quantized copy (values).
+int32_t quant_stride(int32_t b, int prec) {
+    return is_fp8(prec) ? osk::block_stride_fp8(b) : osk::block_stride_bf16(b);
+}
+
+// Values (BF16) or bytes (FP8: codes then scale bytes) of one row of a
+// quantized sketch over nst blocks; 0 for FP32 (no copy).
 int64_t quant_width(int32_t b, int32_t nst, int prec) {
     if (prec == OS_PREC_FP32) return 0;
-    return (int64_t)nst * osk::block_stride_bf16(b) * (prec == OS_PREC_BF16X3 ? 2 : 1);
+    if (is_fp8(prec)) return osk::fp8_row_bytes(b, nst, is_split(prec));
+    return (int64_t)nst * osk::block_stride_bf16(b) * (is_split(prec) ? 2 : 1);
+}
+
+// Bytes of one row of a quantized copy with leading dimension ld (values).
+int64_t quant_row_bytes(int64_t ld, int prec) { return ld * (is_fp8(prec) ? 1 : 2); }
+
+// Codes of one row (the FP8 scale bytes start there).
+int64_t quant_codes(int32_t b, int32_t nst, int prec) {
+    return (int64_t)nst * quant_stride(b, prec) * (is_split(prec) ? 2 : 1);
 }
 
 }  // namespace
@@ -244,7 +261,12 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
 
 int32_t os_block_stride_prec(int32_t b, int precision) {
     if (b < 1 || !valid_prec(precision)) return 0;
-    return precision == OS_PREC_FP32 ? os_block_stride(b) : osk::block_stride_bf16(b);
+    return precision == OS_PREC_FP32 ? os_block_stride(b) : quant_stride(b, precision);
+}
+
+int64_t os_quantized_row(int32_t b, int32_t nst, int precision) {
+    if (b < 1 || b > OS_MAX_B || nst < 1 || nst > OS_MAX_BLOCKS || !valid_prec(precision)) return 0;
+    return quant_width(b, nst, precision);
 }
 
 os_status os_sketch_quantize(const float* S, int64_t lines, int64_t lds, int32_t b, int32_t nst,
@@ -258,9 +280,12 @@ os_status os_sketch_quantize(const float* S, int64_t lines, int64_t lds, int32_t
     const int64_t w = quant_width(b, nst, precision);
     if (!Q) return OS_ENULL;
     if (ldq < w) return OS_EINVAL;
-    if (!aligned(Q, 16) || (ldq & 7)) return OS_EALIGN;
-    return hip_status(osk::launch_quant_bf16(S, lines, lds, b, nst, precision == OS_PREC_BF16X3,
-                                             Q, ldq, (hipStream_t)stream));
+    if (!aligned(Q, 16) || (quant_row_bytes(ldq, precision) & 15)) return OS_EALIGN;
+    if (is_fp8(precision))
+        return hip_status(osk::launch_quant_fp8(S, lines, lds, b, nst, is_split(precision), Q, ldq,
+                                                (hipStream_t)stream));
+    return hip_status(osk::launch_quant_bf16(S, lines, lds, b, nst, is_split(precision), Q, ldq,
+                                             (hipStream_t)stream));
 }
 
 os_status os_gemm_kept_prec(const void* At, int64_t ldat, const void* Bt, int64_t ldbt, int64_t m,
@@ -276,7 +301,9 @@ os_status os_gemm_kept_prec(const void* At, int64_t ldat, const void* Bt, int64_
     const int64_t w = quant_width(b, nst, precision);
     if (!At || !Bt) return OS_ENULL;
     if (ldat < w || ldbt < w) return OS_EINVAL;
-    if (!aligned(At, 16) || !aligned(Bt, 16) || (ldat & 7) || (ldbt & 7)) return OS_EALIGN;
+    if (!aligned(At, 16) || !aligned(Bt, 16) || (quant_row_bytes(ldat, precision) & 15) ||
+        (quant_row_bytes(ldbt, precision) & 15))
+        return OS_EALIGN;
     if ((st = check_matrix(C, m, l, ldc, false)) != OS_OK) return st;
     BlockList kept;
     int32_t K = 0;
@@ -284,12 +311,17 @@ os_status os_gemm_kept_prec(const void* At, int64_t ldat, const void* Bt, int64_
         if (!keep_host || keep_host[j]) kept.idx[K++] = j;
     for (int32_t j = K; j < OS_MAX_BLOCKS; ++j) kept.idx[j] = 0;
     if (K == 0) return OS_ENOKEEP;
-    const int32_t bpq = osk::block_stride_bf16(b);
-    if (!osk::plan_gemm_ok(m, l, bpq, ldat, ldbt, 2)) return OS_EINVAL;
+    const int32_t bpq = quant_stride(b, precision);
+    if (!osk::plan_gemm_ok(m, l, bpq, ldat, ldbt, is_fp8(precision) ? 1 : 2)) return OS_EINVAL;
+    if (is_fp8(precision))
+        return hip_status(osk::launch_gemm_kept_fp8(At, ldat, Bt, ldbt,
+                                                    quant_codes(b, nst, precision), m, l, bpq,
+                                                    kept, K, is_split(precision),
+                                                    (int64_t)nst * bpq, 1.0f / (float)K, C, ldc,
+                                                    (hipStream_t)stream));
     return hip_status(osk::launch_gemm_kept_bf16(At, ldat, Bt, ldbt, m, l, bpq, kept, K,
-                                                 precision == OS_PREC_BF16X3,
-                                                 (int64_t)nst * bpq, 1.0f / (float)K, C, ldc,
-                                                 (hipStream_t)stream));
+                                                 is_split(precision), (int64_t)nst * bpq,
+                                                 1.0f / (float)K, C, ldc, (hipStream_t)stream));
 }
 
 size_t os_matmul_prec_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
@@ -301,10 +333,11 @@ size_t os_matmul_prec_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n,
     // every call; a row-major B is transposed first; a low-precision product
     // adds the quantized copies of both sketches.
     const int64_t zp = (int64_t)nblocks(sk) * os_block_stride(sk->b);
-    const int64_t wq = quant_width(sk->b, nblocks(sk), precision);
+    const int64_t qrow = quant_row_bytes(osk::round_up(quant_width(sk->b, nblocks(sk), precision),
+                                                       16), precision);
     return align256(prepare_bytes(sk, n)) + align256((size_t)m * zp * 4u) +
            align256((size_t)l * zp * 4u) + (b_col_major ? 0 : osk::transpose_bytes(n, l)) +
-           align256((size_t)m * wq * 2u) + align256((size_t)l * wq * 2u);
+           align256((size_t)m * qrow) + align256((size_t)l * qrow);
 }
 
 size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
@@ -333,12 +366,13 @@ os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const
     const size_t need = os_matmul_prec_workspace_bytes(sk, m, n, l, b_col_major, precision);
     if (!workspace || !aligned(workspace, 256) || ws_bytes < need) return OS_EWORKSPACE;
     const int32_t bp = os_block_stride(sk->b);
-    const int32_t bpq = osk::block_stride_bf16(sk->b);
-    const int64_t wq = quant_width(sk->b, bs.nst, precision);
+    const int32_t bpq = quant_stride(sk->b, precision);
+    // quantized copies: rows padded to 16 bytes
+    const int64_t wq = osk::round_up(quant_width(sk->b, bs.nst, precision), 16);
     const bool gemm_ok = precision == OS_PREC_FP32
                              ? osk::plan_gemm_ok(m, l, bp, (int64_t)bs.nst * bp,
                                                  (int64_t)bs.nst * bp, 4)
-                             : osk::plan_gemm_ok(m, l, bpq, wq, wq, 2);
+                             : osk::plan_gemm_ok(m, l, bpq, wq, wq, is_fp8(precision) ? 1 : 2);
     if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !osk::plan_sketch_ok(l, bs.nst, bp, n) ||
         !gemm_ok)
         return OS_EINVAL;
@@ -346,14 +380,15 @@ os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const
     // both sketches use the stored width as leading dimension (a multiple of 32)
     const int64_t zs = (int64_t)bs.nst * bp;
     const int64_t zp = (int64_t)nblocks(sk) * bp;
-    const int64_t wqp = quant_width(sk->b, nblocks(sk), precision);
+    const int64_t wqp = quant_row_bytes(
+        osk::round_up(quant_width(sk->b, nblocks(sk), precision), 16), precision);
     char* ws = static_cast<char*>(workspace);
     void* prep = ws;
     char* at_p = ws + align256(prepare_bytes(sk, n));
     char* bt_p = at_p + align256((size_t)m * zp * 4u);
     char* bx_p = bt_p + align256((size_t)l * zp * 4u);
     char* aq_p = bx_p + (b_col_major ? 0 : osk::transpose_bytes(n, l));
-    char* bq_p = aq_p + align256((size_t)m * wqp * 2u);
+    char* bq_p = aq_p + align256((size_t)m * wqp);
     float* At = reinterpret_cast<float*>(at_p);
     float* Bt = reinterpret_cast<float*>(bt_p);
     hipStream_t s = (hipStream_t)stream;
@@ -380,7 +415,20 @@ os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const
     if (precision == OS_PREC_FP32)
         return hip_status(osk::launch_gemm_kept(At, zs, Bt, zs, m, l, bp, bs.kept_pos, bs.K,
                                                 1.0f / (float)bs.K, C, ldc, s));
-    const int split = precision == OS_PREC_BF16X3;
+    const int split = is_split(precision);
+    if (is_fp8(precision)) {
+        if ((st = hip_status(osk::launch_quant_fp8(At, m, zs, sk->b, bs.nst, split, aq_p, wq, s))) !=
+            OS_OK)
+            return st;
+        if ((st = hip_status(osk::launch_quant_fp8(Bt, l, zs, sk->b, bs.nst, split, bq_p, wq, s))) !=
+            OS_OK)
+            return st;
+        return hip_status(osk::launch_gemm_kept_fp8(aq_p, wq, bq_p, wq,
+                                                    quant_codes(sk->b, bs.nst, precision), m, l,
+                                                    bpq, bs.kept_pos, bs.K, split,
+                                                    (int64_t)bs.nst * bpq, 1.0f / (float)bs.K, C,
+                                                    ldc, s));
+    }
     if ((st = hip_status(osk::launch_quant_bf16(At, m, zs, sk->b, bs.nst, split, aq_p, wq, s))) !=
         OS_OK)
         return st;

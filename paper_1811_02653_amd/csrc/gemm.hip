@@ -262,6 +262,174 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP8 (E4M3) operands with one E8M0 scale per 64 K values of a row, on the
+// gfx950 scaled MFMA v_mfma_scale_f32_32x32x64_f8f6f4 (FP32 accumulation; the
+// hardware multiplies the products by the row scales of A and B).  Same
+// tiles, LDS layout and pipeline as the kernel above; a K step is 128 values
+// (one 128-byte row segment, two scale blocks).  Substep q (two per step) is
+// one MFMA per 32x32 block over scale block q: lane half h holds bytes
+// 32h .. 32h + 31 of the block, and both halves pass the block's scale, so
+// the result does not depend on how the MFMA pairs scale bytes with K
+// values.  The B fragments of a substep stay in registers; the A fragments
+// are read one row block ahead.  A row of an operand holds its codes, then
+// one scale byte per 64 codes (`scales` bytes after the row's start).
+// ---------------------------------------------------------------------------
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ i32x8 frag32(const float* __restrict__ T, int row, int byte) {
+    const float4 lo = *reinterpret_cast<const float4*>(
+        reinterpret_cast<const char*>(T) + row * (LDT * 4) + byte);
+    const float4 hi = *reinterpret_cast<const float4*>(
+        reinterpret_cast<const char*>(T) + row * (LDT * 4) + byte + 16);
+    i32x8 v;
+    v[0] = __float_as_int(lo.x); v[1] = __float_as_int(lo.y);
+    v[2] = __float_as_int(lo.z); v[3] = __float_as_int(lo.w);
+    v[4] = __float_as_int(hi.x); v[5] = __float_as_int(hi.y);
+    v[6] = __float_as_int(hi.z); v[7] = __float_as_int(hi.w);
+    return v;
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gemm_kept_fp8_kernel(const uint8_t* __restrict__ At, int64_t ldat, const uint8_t* __restrict__ Bt,
+                          int64_t ldbt, int64_t scales, int64_t m, int64_t l, int32_t bp,
+                          BlockList kept, int32_t nkept, int32_t nsub, int64_t lo_off,
+                          float scale, float* __restrict__ C, int64_t ldc, int32_t tilesM,
+                          int32_t tilesN) {
+    __shared__ __align__(16) float As[2][BM * LDT];
+    __shared__ __align__(16) float Bs[2][BN * LDT];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1;
+    const int wn = wave & 1;
+
+    const int64_t ntiles = (int64_t)tilesM * tilesN;
+    const int64_t T = xcd_task(blockIdx.x, ntiles);
+    const int64_t group = T / ((int64_t)kGroupM * tilesN);
+    const int64_t first_m = group * kGroupM;
+    const int64_t gsz = min((int64_t)kGroupM, (int64_t)tilesM - first_m);
+    const int64_t in_group = T - group * kGroupM * tilesN;
+    const int64_t tm = first_m + in_group % gsz;
+    const int64_t tn = in_group / gsz;
+    const int64_t row0 = tm * BM;
+    const int64_t col0 = tn * BN;
+
+    v16f acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    constexpr int kStep = kStepBytes;                 // 128 FP8 values per step
+    const int tpb = bp / kStep;
+    const int total = nkept * nsub * tpb;
+    auto step_col = [&](int step, int which) -> uint32_t {   // which: 1 = A, 2 = B
+        const int term = step / tpb;
+        const int j = term / nsub;
+        const int sub = term - j * nsub;
+        const int64_t c = (int64_t)kept.idx[j] * bp + (int64_t)(step % tpb) * kStep +
+                          (sub == 3 - which ? lo_off : 0);
+        return (uint32_t)c;
+    };
+
+    const int r32 = lane & 31;
+    const int h = lane >> 5;
+    const int arow = wm * 128 + r32;
+    const int brow = wn * 128 + r32;
+    const int alast = (int)min((int64_t)BM - 1, m - 1 - row0);
+    const int blast = (int)min((int64_t)BN - 1, l - 1 - col0);
+
+    const __amdgpu_buffer_rsrc_t ra_src = tile_rsrc(At + row0 * ldat);
+    const __amdgpu_buffer_rsrc_t rb_src = tile_rsrc(Bt + col0 * ldbt);
+    uint32_t oa[8], ob[8];
+    tile_offsets(oa, ldat, tid >> 3, alast, tid & 7);
+    tile_offsets(ob, ldbt, tid >> 3, blast, tid & 7);
+    // scale bytes (2 blocks = one step) of the lane's fragment rows
+    uint32_t sa_off[4], sb_off[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        sa_off[i] = (uint32_t)((int64_t)min(arow + 32 * i, alast) * ldat + scales);
+        sb_off[i] = (uint32_t)((int64_t)min(brow + 32 * i, blast) * ldbt + scales);
+    }
+    auto load_scales = [&](uint32_t (&wa)[4], uint32_t (&wb)[4], int step) {
+        const uint32_t ka = step_col(step, 1) / kFp8Block, kb = step_col(step, 2) / kFp8Block;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            wa[i] = __builtin_amdgcn_raw_buffer_load_b16(ra_src, sa_off[i], ka, 0);
+            wb[i] = __builtin_amdgcn_raw_buffer_load_b16(rb_src, sb_off[i], kb, 0);
+        }
+    };
+
+    float4 ra[8], rb[8];
+    uint32_t wa[4], wb[4], na[4], nb[4];
+    load_tile(ra, ra_src, step_col(0, 1), oa);
+    load_tile(rb, rb_src, step_col(0, 2), ob);
+    load_scales(wa, wb, 0);
+    store_tile(As[0], ra, tid);
+    store_tile(Bs[0], rb, tid);
+    load_tile(ra, ra_src, step_col(min(1, total - 1), 1), oa);
+    load_tile(rb, rb_src, step_col(min(1, total - 1), 2), ob);
+    __syncthreads();
+
+    for (int t = 0; t < total; ++t) {
+        const int cur = t & 1;
+        const float* as = As[cur];
+        const float* bs = Bs[cur];
+        load_scales(na, nb, min(t + 1, total - 1));
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int byte = 64 * q + 32 * h;
+            const int sh = 8 * q;                    // the substep's scale byte
+            i32x8 fb[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fb[j] = frag32(bs, brow + 32 * j, byte);
+            i32x8 fa = frag32(as, arow, byte);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const i32x8 fn = frag32(as, arow + 32 * min(i + 1, 3), byte);
+                const int sa = (int)((wa[i] >> sh) & 0xFFu);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        fa, fb[j], acc[i][j], 0, 0, 0, sa, 0, (int)((wb[j] >> sh) & 0xFFu));
+                fa = fn;
+            }
+            if (q == 0) {
+                // the next step's tile into the other buffer; the step after
+                // that is loaded a whole step ahead of its use
+                store_tile(As[cur ^ 1], ra, tid);
+                store_tile(Bs[cur ^ 1], rb, tid);
+                const int ahead = min(t + 2, total - 1);
+                load_tile(ra, ra_src, step_col(ahead, 1), oa);
+                load_tile(rb, rb_src, step_col(ahead, 2), ob);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            wa[i] = na[i];
+            wb[i] = nb[i];
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t col = col0 + wn * 128 + j * 32 + r32;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row0 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                if (row < m && col < l) C[row * ldc + col] = acc[i][j][r] * scale;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt, int elem) {
@@ -282,6 +450,20 @@ hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int6
     hipLaunchKernelGGL(gemm_kept_kernel<PrecF32>, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads),
                        0, s, At, ldat, Bt, ldbt, m, l, bp, kept, nkept, 1, (int64_t)0, scale, C,
                        ldc, (int32_t)tilesM, (int32_t)tilesN);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_kept_fp8(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                                int64_t scales, int64_t m, int64_t l, int32_t bp,
+                                const BlockList& kept, int32_t nkept, int split, int64_t lo_off,
+                                float scale, float* C, int64_t ldc, hipStream_t s) {
+    if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 1) || nkept < 1) return hipErrorInvalidValue;
+    const int64_t tilesM = (m + BM - 1) / BM;
+    const int64_t tilesN = (l + BN - 1) / BN;
+    hipLaunchKernelGGL(gemm_kept_fp8_kernel, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads), 0,
+                       s, static_cast<const uint8_t*>(At), ldat, static_cast<const uint8_t*>(Bt),
+                       ldbt, scales, m, l, bp, kept, nkept, split ? 3 : 1, lo_off, scale, C, ldc,
+                       (int32_t)tilesM, (int32_t)tilesN);
     return hipGetLastError();
 }
 

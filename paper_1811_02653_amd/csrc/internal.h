@@ -68,7 +68,7 @@ hipError_t launch_transpose(const float* X, int64_t rows, int64_t cols, int64_t 
                             int64_t ldy, hipStream_t s);
 
 // Shapes the block product supports for operands of elem bytes per value
-// (4: FP32, 2: BF16); bp must be a multiple of 128 / elem.
+// (4: FP32, 2: BF16, 1: FP8); bp must be a multiple of 128 / elem.
 bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt, int elem);
 
 // C = scale * sum over the kept stored blocks (kept.idx[0 .. nkept)) of
@@ -84,6 +84,13 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
                                  int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                                  int32_t nkept, int split, int64_t lo_off, float scale, float* C,
                                  int64_t ldc, hipStream_t s);
+// The same with FP8 copies (launch_quant_fp8 layout: ld in bytes, the scale
+// bytes of a row `scales` bytes after its start; block stride bp a multiple
+// of 128).
+hipError_t launch_gemm_kept_fp8(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                                int64_t scales, int64_t m, int64_t l, int32_t bp,
+                                const BlockList& kept, int32_t nkept, int split, int64_t lo_off,
+                                float scale, float* C, int64_t ldc, hipStream_t s);
 // The same with BF16 sketches (block stride bp, a multiple of 64; leading
 // dimensions in BF16 values).  split != 0 adds the terms A_j * lo(B_j)^T and
 // lo(A_j) * B_j^T, the low parts lo_off columns after the high parts.
@@ -91,6 +98,13 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
                                  int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                                  int32_t nkept, int split, int64_t lo_off, float scale, float* C,
                                  int64_t ldc, hipStream_t s);
+// The same with FP8 copies (launch_quant_fp8 layout: ld in bytes, the scale
+// bytes of a row `scales` bytes after its start; block stride bp a multiple
+// of 128).
+hipError_t launch_gemm_kept_fp8(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                                int64_t scales, int64_t m, int64_t l, int32_t bp,
+                                const BlockList& kept, int32_t nkept, int split, int64_t lo_off,
+                                float scale, float* C, int64_t ldc, hipStream_t s);
 
 // BF16 copy of a line-major FP32 sketch (lines x nst*bp, ld lds): block
 // stride block_stride_bf16(b) = b rounded up to 64, the residual part (when
@@ -99,5 +113,14 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
 int32_t block_stride_bf16(int32_t b);
 hipError_t launch_quant_bf16(const float* S, int64_t lines, int64_t lds, int32_t b, int32_t nst,
                              int split, void* Q, int64_t ldq, hipStream_t s);
+// FP8 (E4M3) copy with one E8M0 scale per kFp8Block values: block stride
+// block_stride_fp8(b) = b rounded up to 128; row = codes (high part, then
+// residual when split), then the scale bytes in the same order:
+// fp8_row_bytes(b, nst, split) bytes; ldq (bytes) a multiple of 16.
+constexpr int kFp8Block = 64;
+int32_t block_stride_fp8(int32_t b);
+int64_t fp8_row_bytes(int32_t b, int32_t nst, int split);
+hipError_t launch_quant_fp8(const float* S, int64_t lines, int64_t lds, int32_t b, int32_t nst,
+                            int split, void* Q, int64_t ldq, hipStream_t s);
 
 }  // namespace osk

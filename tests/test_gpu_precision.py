@@ -26,6 +26,7 @@ import paper_1811_02653_amd as osk  # noqa: E402
 U_BF16 = 2.0 ** -8
 U_SPLIT = 2.0 ** -16
 FP32_TOL = 1e-5
+FP8_BLOCK = 64          # values per E8M0 scale
 
 
 def host(t):
@@ -118,3 +119,133 @@ def test_matmul_bf16_within_rounding_bound(m, n, l, b, N, e):
         assert err <= (2 * u + u * u) * bound + FP32_TOL * nref, (prec, err, bound)
     # the residual terms do recover accuracy
     assert errs["bf16x3"] < errs["bf16"] / 16
+
+
+# ---------------------------------------------------------------------------
+# FP8 E4M3 with one E8M0 scale per 64 values
+# ---------------------------------------------------------------------------
+
+def decode_fp8(Q, b, nst, split):
+    """(values, exponents) of a quantized FP8 copy: the E4M3 codes of each
+    row times 2^s of their 64-value block (FP64), and the block exponents."""
+    Q = np.asarray(Q, dtype=np.uint8)
+    bq = osk.block_stride_prec(b, "fp8")
+    ncode = nst * bq * (2 if split else 1)
+    codes = Q[:, :ncode].astype(np.int64)
+    s = Q[:, ncode:ncode + ncode // FP8_BLOCK].astype(np.int64) - 127
+    mag = oracle.e4m3_values()[codes & 0x7F]
+    val = np.where(codes & 0x80, -mag, mag) * np.repeat(np.ldexp(1.0, s), FP8_BLOCK, axis=1)
+    return val, s
+
+
+def host_u8(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("lines,b,nst", [(37, 100, 3), (256, 256, 5), (5, 1, 2), (64, 1024, 2)])
+def test_quantize_fp8_bit_exact(lines, b, nst, split):
+    rng = np.random.default_rng(lines + b + 1)
+    S = line_major_sketch(rng, lines, b, nst)
+    prec = "fp8x3" if split else "fp8"
+    Q = host_u8(osk.sketch_quantize(torch.from_numpy(S).cuda(), b, nst, precision=prec))
+    assert Q.shape == (lines, osk.quantized_row(b, nst, prec))
+    bp, bq = osk.block_stride(b), osk.block_stride_prec(b, prec)
+    assert bq % 128 == 0 and bq >= b
+    # the oracle's quantization of the same FP32 values, in the copy's layout
+    X = np.zeros((lines, nst * bq))
+    for j in range(nst):
+        X[:, j * bq:j * bq + b] = S[:, j * bp:j * bp + b]
+    hi, s_hi = oracle.fp8_block_quantize(X, FP8_BLOCK)
+    val, s = decode_fp8(Q, b, nst, split)
+    zq = nst * bq
+    np.testing.assert_array_equal(val[:, :zq], hi)
+    np.testing.assert_array_equal(s[:, :zq // FP8_BLOCK], s_hi)
+    if split:
+        lo, s_lo = oracle.fp8_block_quantize(X - hi, FP8_BLOCK)
+        np.testing.assert_array_equal(val[:, zq:], lo)
+        np.testing.assert_array_equal(s[:, zq // FP8_BLOCK:], s_lo)
+
+
+@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("m,l,b,nst", [(256, 256, 256, 5), (300, 77, 100, 3), (1, 1, 32, 1),
+                                       (513, 255, 64, 4), (64, 700, 1024, 2)])
+def test_gemm_kept_fp8_vs_fp64(m, l, b, nst, split):
+    rng = np.random.default_rng(m * 5 + l)
+    prec = "fp8x3" if split else "fp8"
+    SA = line_major_sketch(rng, m, b, nst)
+    SB = line_major_sketch(rng, l, b, nst)
+    keep = np.ones(nst, np.uint8)
+    if nst > 1:
+        keep[rng.integers(nst)] = 0
+    QA = osk.sketch_quantize(torch.from_numpy(SA).cuda(), b, nst, precision=prec)
+    QB = osk.sketch_quantize(torch.from_numpy(SB).cuda(), b, nst, precision=prec)
+    C = host(osk.gemm_kept_prec(QA, QB, b, nst, precision=prec, keep=keep))
+    # reference: FP64 sums of the exact products of the scaled FP8 values
+    qa, _ = decode_fp8(host_u8(QA), b, nst, split)
+    qb, _ = decode_fp8(host_u8(QB), b, nst, split)
+    bq = osk.block_stride_prec(b, prec)
+    zq = nst * bq
+    ref = np.zeros((m, l))
+    mag = np.zeros((m, l))
+    for j in np.flatnonzero(keep):
+        a, bb = qa[:, j * bq:(j + 1) * bq], qb[:, j * bq:(j + 1) * bq]
+        ref += a @ bb.T
+        mag += np.abs(a) @ np.abs(bb).T
+        if split:
+            alo, blo = qa[:, zq + j * bq:zq + (j + 1) * bq], qb[:, zq + j * bq:zq + (j + 1) * bq]
+            ref += a @ blo.T + alo @ bb.T
+            mag += np.abs(a) @ np.abs(blo).T + np.abs(alo) @ np.abs(bb).T
+    K = keep.sum()
+    ref /= K
+    mag /= K
+    # The scaled FP8 MFMA sums 64 exact products per instruction before adding
+    # them to the FP32 accumulator.  That inner sum is not exact FP32: on
+    # gfx950 it carries about 16 significant bits (1.5e-5 relative measured
+    # against the exact FP64 sum of the same FP8 products).  Allow 2^-14 of
+    # the products' magnitude for it, plus one FP32 ulp per accumulation.
+    steps = K * (bq // 64) * (3 if split else 1)
+    err = np.sqrt(oracle.frob2(C - ref))
+    bound = (2.0 ** -14 + steps * 2.0 ** -23) * np.sqrt(oracle.frob2(mag))
+    assert err <= bound, (err, bound, oracle.rel_frob(C, ref))
+    # and it stays far below the FP8 rounding of the operands (2^-4)
+    assert oracle.rel_frob(C, ref) <= 1e-4
+
+
+def _bound_fp8(A, B, b, N, e, seed, keep, u):
+    """|| Ahat Bhat^T / K ||_F with Ahat = |A~| + 2^-10/224 * blockmax / u:
+    the FP8 rounding of an element is at most u |x| + blockmax / 229376
+    (blocks of 64 values along each row of the line-major sketch, as the
+    quantized copy lays them out: the bound only needs blockmax >= the
+    block's true maximum, which a 64-block of the unpadded layout is not;
+    blocks of 32 of the unpadded row give a smaller maximum, so the row
+    maximum is used)."""
+    h, s = oracle.hash_tables(seed, N + e, A.shape[1], b)
+    At = oracle.sketch_cols(A, h, s, b)
+    Bt = oracle.sketch_rows(B, h, s, b).T
+
+    def hat(X):
+        Xa = np.abs(X)
+        rowmax = Xa.max(axis=1, keepdims=True)
+        return Xa + rowmax / 229376.0 / u
+
+    return np.sqrt(oracle.frob2(oracle.block_product(hat(At), hat(Bt).T, b, keep)))
+
+
+@pytest.mark.parametrize("m,n,l,b,N,e", [(256, 4096, 256, 256, 4, 1), (300, 1001, 77, 100, 3, 1)])
+def test_matmul_fp8_within_rounding_bound(m, n, l, b, N, e):
+    seed = m + n
+    A, B = synthetic.gaussian_pair(m, n, l, seed)
+    keep = synthetic.random_keep(N, e, seed)
+    ref = oracle.sketched_matmul(A, B, b, N, e, seed=seed, keep=keep)
+    nref = np.sqrt(oracle.frob2(ref))
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    u = 2.0 ** -4
+    C = host(osk.matmul(Ad, Bd, b, N, e, seed=seed, keep=keep, precision="fp8"))
+    err = np.sqrt(oracle.frob2(C - ref))
+    assert err <= (2 * u + u * u) * _bound_fp8(A, B, b, N, e, seed, keep, u) + FP32_TOL * nref
+    C3 = host(osk.matmul(Ad, Bd, b, N, e, seed=seed, keep=keep, precision="fp8x3"))
+    err3 = np.sqrt(oracle.frob2(C3 - ref))
+    # the residual pass recovers about four more bits
+    assert err3 < err / 8

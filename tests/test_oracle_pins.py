@@ -526,3 +526,60 @@ def test_bf16_split_recovers_sixteen_bits():
     assert np.all(r <= 2.0 ** -16 * xd)
     # and the split is not vacuous: the residual term matters
     assert np.mean(np.abs(x.astype(np.float64) - hi)) > 100 * np.mean(r)
+
+
+# ---------------------------------------------------------------------------
+# FP8 E4M3 with power-of-two block scales
+# ---------------------------------------------------------------------------
+
+def test_e4m3_value_table():
+    v = oracle.e4m3_values()
+    assert v[0] == 0 and v[1] == 2.0 ** -9 and v[7] == 7 * 2.0 ** -9
+    assert v[8] == 2.0 ** -6                 # smallest normal continues the subnormals
+    assert v[0x38] == 1.0 and v[126] == 448.0
+    assert np.all(np.diff(v) > 0)            # codes are ordered by magnitude
+
+
+def test_e4m3_round_worked_values():
+    y = np.array([1.0, 1 + 1 / 16, 1 + 3 / 16, 1 + 1 / 16 + 1e-6, 448.0, -0.5625,
+                  2.0 ** -10, 3 * 2.0 ** -10, 2.0 ** -10 + 1e-9, 0.0])
+    want = np.array([1.0, 1.0, 1.25, 1.125, 448.0, -0.5625,
+                     0.0, 2 * 2.0 ** -9, 2.0 ** -9, 0.0])
+    np.testing.assert_array_equal(oracle.e4m3_round(y), want)
+    v = oracle.e4m3_values()
+    np.testing.assert_array_equal(oracle.e4m3_round(v), v)       # exact values stay
+    np.testing.assert_array_equal(oracle.e4m3_round(-v), -v)
+
+
+def test_e4m3_round_is_nearest():
+    rng = np.random.default_rng(3)
+    y = rng.uniform(-448, 448, 20000) * np.exp(rng.uniform(-14, 0, 20000))
+    q = oracle.e4m3_round(y)
+    v = oracle.e4m3_values()
+    best = np.min(np.abs(np.abs(y)[:, None] - v[None, :]), axis=1)
+    np.testing.assert_array_equal(np.abs(np.abs(y) - np.abs(q)), best)
+
+
+def test_e8m0_scale_exponent():
+    assert oracle.e8m0_scale_exponent(448.0) == 0
+    assert oracle.e8m0_scale_exponent(449.0) == 1
+    assert oracle.e8m0_scale_exponent(896.0) == 1
+    assert oracle.e8m0_scale_exponent(897.0) == 2
+    assert oracle.e8m0_scale_exponent(1.0) == -8        # 448 * 2^-8 = 1.75 >= 1 > 0.875
+    assert oracle.e8m0_scale_exponent(0.0) == -127
+    assert oracle.e8m0_scale_exponent(1e-45) == -127
+
+
+def test_fp8_block_quantize_error_bound():
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((16, 256)) * np.exp(rng.standard_normal((16, 1)) * 3)
+    q, s = oracle.fp8_block_quantize(x)
+    assert s.shape == (16, 8)
+    blockmax = np.repeat(np.abs(x).reshape(16, 8, 32).max(axis=2), 32, axis=1)
+    # normal range: 3 fraction bits (2^-4 relative); below it the step is
+    # 2^(s-9) < blockmax / 224 / 512 -> half a step
+    assert np.all(np.abs(x - q) <= 2.0 ** -4 * np.abs(x) + blockmax / 224 / 1024 + 1e-300)
+    assert np.all(np.abs(q) <= 448.0 * np.repeat(np.ldexp(1.0, s), 32, axis=1))
+    hi, lo = oracle.fp8_split(x)
+    assert np.array_equal(hi, q)
+    assert np.mean(np.abs(x - hi - lo)) < np.mean(np.abs(x - hi)) / 8
