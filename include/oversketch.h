@@ -87,6 +87,10 @@ typedef int os_status;
 
 #define OS_MAX_BLOCKS 256                   /* upper limit on N + e */
 
+/* Element types of an operand read by os_sketch_rows_ex. */
+#define OS_DTYPE_F32  0
+#define OS_DTYPE_BF16 1
+
 /* Operand precision of the block product (FP32 accumulation in all).  The
  * paper's products are FP64; these trade the rounding of the sketched
  * operands, which is small next to the sketch's own error, for MFMA rate. */
@@ -180,6 +184,18 @@ os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_byte
                          const float* X, int64_t n, int64_t cols, int64_t ldx,
                          const uint8_t* keep_host, int kept_only, float* out, int64_t ldo,
                          void* workspace, size_t ws_bytes, void* stream);
+
+/* os_sketch_rows for an X of element type x_dtype: OS_DTYPE_F32 is
+ * os_sketch_rows; OS_DTYPE_BF16 reads a BF16 X (2-byte aligned, ld ldx in
+ * values), converts it exactly to FP32 while transposing it into the
+ * workspace (required: >= os_sketch_rows_workspace_bytes(n, cols)) and
+ * sketches it as os_sketch_rows does, with FP32 sums.  Used for the sketched
+ * weight gradient of a linear layer, X^T S S^T dY with the sketch over the
+ * tokens (the rows of X and dY). */
+os_status os_sketch_rows_ex(const os_sketch* sk, const void* prep, size_t prep_bytes,
+                            const void* X, int x_dtype, int64_t n, int64_t cols, int64_t ldx,
+                            const uint8_t* keep_host, int kept_only, float* out, int64_t ldo,
+                            void* workspace, size_t ws_bytes, void* stream);
 
 /* Step "grouped product over the kept blocks" (Algorithm "OverSketch":
  * computation phase plus reduction phase, Fig. (bMM)):

@@ -84,6 +84,9 @@ def lib():
                                  vp]
     L.os_sketch_rows_workspace_bytes.restype = sz
     L.os_sketch_rows_workspace_bytes.argtypes = [i64, i64]
+    L.os_sketch_rows_ex.restype = ctypes.c_int
+    L.os_sketch_rows_ex.argtypes = [sk, vp, sz, vp, ctypes.c_int, i64, i64, i64, vp, ctypes.c_int,
+                                    vp, i64, vp, sz, vp]
     L.os_gemm_kept.restype = ctypes.c_int
     L.os_gemm_kept.argtypes = [vp, i64, vp, i64, i64, i64, i32, i32, vp, vp, i64, vp]
     L.os_matmul_workspace_bytes.restype = sz
@@ -261,9 +264,13 @@ def sketch_rows(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=No
 
     workspace: None (sketch X's columns in place), True (allocate one) or a
     uint8 CUDA tensor of at least sketch_rows_workspace_bytes(n, cols) bytes
-    (X is transposed into it first: the faster path)."""
+    (X is transposed into it first: the faster path).  X may be float32 or
+    bfloat16; a bfloat16 X always takes the transposing path (converted
+    exactly to FP32, FP32 sums)."""
     torch = _torch()
-    _require_cuda(X, "X", torch.float32)
+    _require_cuda(X, "X")
+    if X.dtype not in (torch.float32, torch.bfloat16):
+        raise OversketchError("X must be float32 or bfloat16")
     n, cols, ldx = _row_major(X, "X")
     if prep is None:
         prep = sketch_prepare(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
@@ -272,14 +279,15 @@ def sketch_rows(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=No
     out = _line_major_out(out, cols, width, X.device)
     _, _, ldo = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
-    if workspace is True:
+    if workspace is True or (workspace is None and X.dtype == torch.bfloat16):
         workspace = torch.empty(sketch_rows_workspace_bytes(n, cols), dtype=torch.uint8,
                                 device=X.device)
     wp, wn = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel())
-    _check(lib().os_sketch_rows(ctypes.byref(s), _ptr(prep), prep.numel(), _ptr(X), n, cols, ldx,
-                                pk, int(bool(kept_only)), _ptr(out), ldo, wp, wn,
-                                _stream(stream)),
-           "os_sketch_rows")
+    dtype = 1 if X.dtype == torch.bfloat16 else 0
+    _check(lib().os_sketch_rows_ex(ctypes.byref(s), _ptr(prep), prep.numel(), _ptr(X), dtype, n,
+                                   cols, ldx, pk, int(bool(kept_only)), _ptr(out), ldo, wp, wn,
+                                   _stream(stream)),
+           "os_sketch_rows_ex")
     return out
 
 

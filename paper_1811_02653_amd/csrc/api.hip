@@ -238,6 +238,37 @@ os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_byte
                                               (hipStream_t)stream));
 }
 
+os_status os_sketch_rows_ex(const os_sketch* sk, const void* prep, size_t prep_bytes,
+                            const void* X, int x_dtype, int64_t n, int64_t cols, int64_t ldx,
+                            const uint8_t* keep_host, int kept_only, float* out, int64_t ldo,
+                            void* workspace, size_t ws_bytes, void* stream) {
+    if (x_dtype == OS_DTYPE_F32)
+        return os_sketch_rows(sk, prep, prep_bytes, static_cast<const float*>(X), n, cols, ldx,
+                              keep_host, kept_only, out, ldo, workspace, ws_bytes, stream);
+    if (x_dtype != OS_DTYPE_BF16) return OS_EINVAL;
+    os_status st = check_sketch(sk);
+    if (st != OS_OK) return st;
+    if ((st = check_len(n)) != OS_OK) return st;
+    if ((st = check_extent(cols)) != OS_OK) return st;
+    if ((st = check_prep(sk, n, prep, prep_bytes)) != OS_OK) return st;
+    if (!X) return OS_ENULL;
+    if (ldx < cols) return OS_EINVAL;
+    if (!aligned(X, 2)) return OS_EALIGN;
+    Blocks bs;
+    if ((st = block_sets(sk, keep_host, kept_only, bs)) != OS_OK) return st;
+    const int32_t bp = os_block_stride(sk->b);
+    if ((st = check_matrix(out, cols, (int64_t)bs.nst * bp, ldo, true)) != OS_OK) return st;
+    if (!osk::plan_sketch_ok(cols, bs.nst, bp, n)) return OS_EINVAL;
+    if (!workspace || !aligned(workspace, 256) || ws_bytes < osk::transpose_bytes(n, cols))
+        return OS_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    float* Xt = static_cast<float*>(workspace);
+    const int64_t ldt = osk::round_up(n, 4);
+    if ((st = hip_status(osk::launch_transpose_bf16(X, n, cols, ldx, Xt, ldt, s))) != OS_OK) return st;
+    return hip_status(osk::launch_sketch_cols(Xt, cols, n, ldt, bs.stored, bs.nst, nblocks(sk), bp,
+                                              prep_lists(prep, sk, n), out, ldo, s));
+}
+
 os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt, int64_t m,
                        int64_t l, int32_t b, int32_t nst, const uint8_t* keep_host, float* C,
                        int64_t ldc, void* stream) {

@@ -66,6 +66,9 @@ constexpr int64_t kMaxSketchLdBytes = (int64_t(1) << 24) - 256;
 size_t transpose_bytes(int64_t rows, int64_t cols);
 hipError_t launch_transpose(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
                             int64_t ldy, hipStream_t s);
+// The same for a BF16 X (values converted exactly to FP32).
+hipError_t launch_transpose_bf16(const void* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
+                                 int64_t ldy, hipStream_t s);
 
 // Shapes the block product supports for operands of elem bytes per value
 // (4: FP32, 2: BF16, 1: FP8); bp must be a multiple of 128 / elem.

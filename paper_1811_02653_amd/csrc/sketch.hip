@@ -345,36 +345,57 @@ hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const float* X, in
 }
 
 // ---------------------------------------------------------------------------
-// Transpose: Y (cols x rows, ld ldy) = X^T for X rows x cols (ld ldx).  A
-// workgroup moves one 64 x 64 tile through LDS (row stride 65 floats: the
-// column reads are conflict-free); both sides are coalesced, 16 bytes per
-// lane when `vec` (X 16-byte aligned and ldx % 4 == 0).  Loads are clamped
+// Transpose: Y (cols x rows, ld ldy, FP32) = X^T for X rows x cols (ld ldx,
+// FP32 or BF16, converted exactly to FP32).  A workgroup moves one 64 x 64
+// tile through LDS (row stride 65 floats: the column reads are
+// conflict-free); both sides are coalesced, 4 values per lane in one load
+// when `vec` (X aligned to 4 values and ldx % 4 == 0).  Loads are clamped
 // into the matrix and stores are guarded.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict__ X, int64_t rows,
+template <typename T>
+__device__ __forceinline__ float4 load4(const T* p, bool vec);
+
+template <>
+__device__ __forceinline__ float4 load4<float>(const float* p, bool vec) {
+    if (vec) return *reinterpret_cast<const float4*>(p);
+    return make_float4(p[0], p[1], p[2], p[3]);
+}
+
+template <>
+__device__ __forceinline__ float4 load4<__bf16>(const __bf16* p, bool vec) {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    if (vec) {
+        const bf16x4 v = *reinterpret_cast<const bf16x4*>(p);
+        return make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    }
+    return make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[3]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ X, int64_t rows,
                                                         int64_t cols, int64_t ldx, int vec,
                                                         float* __restrict__ Y, int64_t ldy) {
     __shared__ float t[64][65];
     const int tid = threadIdx.x;
     const int64_t col_tiles = (cols + 63) / 64;
     const int64_t tiles = col_tiles * ((rows + 63) / 64);
-    const int64_t T = xcd_task(blockIdx.x, tiles);
-    const int64_t r0 = T / col_tiles * 64;
-    const int64_t c0 = T % col_tiles * 64;
+    const int64_t Tk = xcd_task(blockIdx.x, tiles);
+    const int64_t r0 = Tk / col_tiles * 64;
+    const int64_t c0 = Tk % col_tiles * 64;
     const int sub = tid >> 4;          // 0..15
     const int q = 4 * (tid & 15);      // 0..60
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = sub + 16 * i;
-        const float* p = X + min(r0 + r, rows - 1) * ldx;
+        const T* p = X + min(r0 + r, rows - 1) * ldx;
         float4 v;
-        if (vec && c0 + q + 3 < cols) {
-            v = *reinterpret_cast<const float4*>(p + c0 + q);
+        if (c0 + q + 3 < cols) {
+            v = load4<T>(p + c0 + q, vec);
         } else {
-            v.x = p[min(c0 + q + 0, cols - 1)];
-            v.y = p[min(c0 + q + 1, cols - 1)];
-            v.z = p[min(c0 + q + 2, cols - 1)];
-            v.w = p[min(c0 + q + 3, cols - 1)];
+            v.x = (float)p[min(c0 + q + 0, cols - 1)];
+            v.y = (float)p[min(c0 + q + 1, cols - 1)];
+            v.z = (float)p[min(c0 + q + 2, cols - 1)];
+            v.w = (float)p[min(c0 + q + 3, cols - 1)];
         }
         t[r][q + 0] = v.x;
         t[r][q + 1] = v.y;
@@ -497,15 +518,26 @@ size_t transpose_bytes(int64_t rows, int64_t cols) {
     return (size_t)round_up(cols * round_up(rows, 4) * 4, 256);
 }
 
-hipError_t launch_transpose(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
-                            int64_t ldy, hipStream_t s) {
+template <typename T>
+hipError_t launch_transpose_t(const T* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
+                              int64_t ldy, hipStream_t s) {
     const int64_t tiles = (rows + 63) / 64 * ((cols + 63) / 64);
     if (tiles > 0x7fffffff || ldy % 4 || (reinterpret_cast<uintptr_t>(Y) & 15))
         return hipErrorInvalidValue;
-    const int vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (ldx & 3) == 0;
-    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)tiles), dim3(256), 0, s, X, rows, cols, ldx,
-                       vec, Y, ldy);
+    const int vec = (reinterpret_cast<uintptr_t>(X) % (4 * sizeof(T))) == 0 && (ldx & 3) == 0;
+    hipLaunchKernelGGL(transpose_kernel<T>, dim3((unsigned)tiles), dim3(256), 0, s, X, rows, cols,
+                       ldx, vec, Y, ldy);
     return hipGetLastError();
+}
+
+hipError_t launch_transpose(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
+                            int64_t ldy, hipStream_t s) {
+    return launch_transpose_t(X, rows, cols, ldx, Y, ldy, s);
+}
+
+hipError_t launch_transpose_bf16(const void* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
+                                 int64_t ldy, hipStream_t s) {
+    return launch_transpose_t(static_cast<const __bf16*>(X), rows, cols, ldx, Y, ldy, s);
 }
 
 hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,

@@ -1,0 +1,97 @@
+"""The sketched linear layer: exact forward, exact dX, and dW = X^T S S^T dY
+sketched over the tokens (Section 4's product with A = X^T, B = dY), through
+the library's kernels.
+
+  - dW against the FP64 oracle's sketched product on the same sketch
+    (<= 1e-5 relative Frobenius, FP32 and BF16 inputs);
+  - a finite-difference check on a 64 x 32 x 32 layer with a permutation
+    sketch (b = tokens, S S^T = I, so the sketched gradient is the exact
+    one);
+  - unbiasedness: the mean of dW over T independent seeds approaches
+    X^T dY with E||mean - X^T dY||^2 = E_1 / T, E_1 the closed-form second
+    moment of one sketched product (Lemma 1 summed over entries).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1811_02653_amd as osk  # noqa: E402
+from paper_1811_02653_amd.autograd import sketched_linear, sketched_weight_grad  # noqa: E402
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("tokens,d_in,d_out,b,N,e", [(2048, 96, 80, 512, 4, 0),
+                                                     (1000, 64, 33, 128, 3, 1),
+                                                     (300, 17, 256, 64, 2, 2)])
+@pytest.mark.parametrize("dtype", ["float32", "bfloat16"])
+def test_sketched_weight_grad_vs_oracle(tokens, d_in, d_out, b, N, e, dtype):
+    seed = tokens + d_in
+    X, W, dY = synthetic.linear_layer(tokens, d_in, d_out, seed)
+    tdt = getattr(torch, dtype)
+    Xd = torch.from_numpy(X).cuda().to(tdt)
+    Dd = torch.from_numpy(dY).cuda().to(tdt)
+    keep = synthetic.random_keep(N, e, seed)
+    dW = host(sketched_weight_grad(Xd, Dd, b, N, e, seed=seed, keep=keep))
+    # the oracle on exactly the values the GPU read (BF16 -> FP32 is exact)
+    Xh = Xd.float().cpu().numpy()
+    Dh = Dd.float().cpu().numpy()
+    ref = oracle.sketched_matmul(Xh.T, Dh, b, N, e, seed=seed, keep=keep)
+    assert oracle.rel_frob(dW, ref) <= 1e-5
+
+
+def test_finite_difference_with_permutation_sketch():
+    tokens, d_in, d_out = 64, 32, 32
+    X, W, G = synthetic.linear_layer(tokens, d_in, d_out, 11)
+    rng = np.random.default_rng(11)
+    h = rng.permutation(tokens).astype(np.int32)[None, :]
+    s = rng.choice(np.array([-1, 1], np.int8), size=(1, tokens))
+    Xd = torch.from_numpy(X).cuda().requires_grad_(True)
+    Wd = torch.from_numpy(W).cuda().requires_grad_(True)
+    Y = sketched_linear(Xd, Wd, tokens, 1, 0, h=torch.from_numpy(h).cuda(),
+                        sigma=torch.from_numpy(s).cuda())
+    Y.backward(torch.from_numpy(G).cuda())
+    gW, gX = host(Wd.grad), host(Xd.grad)
+    # central differences of L = sum(Y * G) in FP64 at random entries
+    Xf, Wf, Gf = X.astype(np.float64), W.astype(np.float64), G.astype(np.float64)
+    L = lambda Xv, Wv: float(np.sum((Xv @ Wv) * Gf))
+    eps = 1e-3
+    for _ in range(20):
+        i, j = rng.integers(d_in), rng.integers(d_out)
+        E = np.zeros_like(Wf)
+        E[i, j] = eps
+        fd = (L(Xf, Wf + E) - L(Xf, Wf - E)) / (2 * eps)
+        assert abs(gW[i, j] - fd) <= 1e-4 * (1 + abs(fd)), (i, j, gW[i, j], fd)
+        t, k = rng.integers(tokens), rng.integers(d_in)
+        E = np.zeros_like(Xf)
+        E[t, k] = eps
+        fd = (L(Xf + E, Wf) - L(Xf - E, Wf)) / (2 * eps)
+        assert abs(gX[t, k] - fd) <= 1e-4 * (1 + abs(fd)), (t, k, gX[t, k], fd)
+
+
+def test_unbiased_over_seeds():
+    tokens, d_in, d_out, b, N = 512, 24, 20, 64, 2
+    X, _, dY = synthetic.linear_layer(tokens, d_in, d_out, 5)
+    A, B = X.T.astype(np.float64), dY.astype(np.float64)
+    exact = A @ B
+    K = N
+    e1 = (oracle.frob2(A) * oracle.frob2(B) + oracle.frob2(exact)
+          - 2 * np.sum(np.sum(A * A, axis=0) * np.sum(B * B, axis=1))) / (K * b)
+    Xd, Dd = torch.from_numpy(X).cuda(), torch.from_numpy(dY).cuda()
+    T = 200
+    acc = np.zeros_like(exact)
+    for t in range(T):
+        acc += host(sketched_weight_grad(Xd, Dd, b, N, 0, seed=1000 + t))
+    err2 = oracle.frob2(acc / T - exact)
+    assert err2 <= 3 * e1 / T, (err2, e1 / T)
+    # one sketch alone is much further off (the check is not vacuous)
+    one = host(sketched_weight_grad(Xd, Dd, b, N, 0, seed=7))
+    assert oracle.frob2(one - exact) > 10 * err2
