@@ -73,6 +73,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-rows", type=int, default=6144,
                    help="rows of A and columns of B in the CPU oracle sample")
+    p.add_argument("--no-layer", action="store_true",
+                   help="skip the sketched linear layer (backward with a sketched weight gradient)")
     p.add_argument("--no-precision", action="store_true",
                    help="skip the BF16 / split-BF16 variants of the block product")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -299,6 +301,45 @@ def main():
         del A2, B2, AB2
         torch.cuda.empty_cache()
 
+    # ---- sketched linear layer: X 16384 x 4096 and W 4096 x 4096 in BF16,
+    # dY ~ N(0, 1); the weight gradient X^T dY sketched over the 16384 tokens
+    # (b = 512, N = 4, e = 0) against the exact BF16 GEMM
+    layer = None
+    if not args.no_layer:
+        from paper_1811_02653_amd.autograd import sketched_weight_grad
+        T_, din, dout, lb, lN = 16384, 4096, 4096, 512, 4
+        Xl_h, Wl_h, Dl_h = synthetic.linear_layer(T_, din, dout, args.seed)
+        Xl = torch.from_numpy(Xl_h).to(dev).to(torch.bfloat16)
+        Wl = torch.from_numpy(Wl_h).to(dev).to(torch.bfloat16)
+        Dl = torch.from_numpy(Dl_h).to(dev).to(torch.bfloat16)
+        del Xl_h, Wl_h, Dl_h
+        t_fwd = event_time_ms(torch, lambda: torch.matmul(Xl, Wl), reps, stream)
+        t_dx = event_time_ms(torch, lambda: torch.matmul(Dl, Wl.t()), reps, stream)
+        t_dw_exact = event_time_ms(torch, lambda: torch.matmul(Xl.t(), Dl), reps, stream)
+        res = {}
+        dW_exact = torch.matmul(Xl.t().float(), Dl.float()).double()
+        nrm = torch.linalg.norm(dW_exact).item()
+        for prec in ("fp32", "bf16"):
+            t_dw = event_time_ms(torch, lambda: sketched_weight_grad(Xl, Dl, lb, lN, 0,
+                                                                      seed=args.seed,
+                                                                      precision=prec,
+                                                                      stream=stream),
+                                 reps, stream)
+            dW = sketched_weight_grad(Xl, Dl, lb, lN, 0, seed=args.seed, precision=prec)
+            torch.cuda.synchronize()
+            res[prec] = {"dW_ms": t_dw,
+                         "rel_frob_vs_exact": torch.linalg.norm(dW.double() - dW_exact).item() / nrm,
+                         "backward_ms": t_dx + t_dw}
+            del dW
+        layer = {"workload": "X %dx%d, W %dx%d, dY %dx%d in BF16; dW sketched over the tokens, "
+                             "b=%d, N=%d, e=0" % (T_, din, din, dout, T_, dout, lb, lN),
+                 "forward_ms": t_fwd, "dX_ms": t_dx, "dW_exact_bf16_ms": t_dw_exact,
+                 "backward_exact_ms": t_dx + t_dw_exact, "sketched_dW": res}
+        log("layer: forward %.3f ms, dX %.3f ms, exact dW %.3f ms, sketched dW %s" %
+            (t_fwd, t_dx, t_dw_exact, {k: round(v["dW_ms"], 3) for k, v in res.items()}))
+        del Xl, Wl, Dl, dW_exact
+        torch.cuda.empty_cache()
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
     sample_err = None
@@ -365,6 +406,7 @@ def main():
                   "normalised_err2": norm_err2,
                   "rel_frob_vs_oracle_sample": sample_err},
         "precision_variants": precision,
+        "sketched_linear_layer": layer,
         "exact_gemm": {"kind": "torch.matmul FP32 (hipBLASLt)", "ms": t_exact,
                        "tflops": 2.0 * m * n * l / (t_exact * 1e-3) / 1e12,
                        "speedup_of_sketched": t_exact / ms_per_step},
