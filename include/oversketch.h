@@ -210,6 +210,19 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
                        int64_t m, int64_t l, int32_t b, int32_t nst,
                        const uint8_t* keep_host, float* C, int64_t ldc, void* stream);
 
+/* Step "grouped product" with a keep mask per block of C: the paper's
+ * stragglers differ per C block (Algorithm "OverSketch": each b x b block of
+ * C is assembled from the first workers that return for it).  C is divided
+ * into b x b blocks (the last ones partial); block (I, J) keeps the stored
+ * blocks j with cmask[(I * ceil(l/b) + J) * nst + j] != 0 and is
+ *   C_IJ = (1/K_IJ) * sum_{kept j} At_j[I rows] * Bt_j[J rows]^T,
+ * K_IJ = its kept count; a block that keeps none is written as zero.
+ * cmask: DEVICE uint8 [ceil(m/b)][ceil(l/b)][nst] (read by the kernel).
+ * Other arguments as in os_gemm_kept. */
+os_status os_gemm_kept_cmask(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
+                             int64_t m, int64_t l, int32_t b, int32_t nst,
+                             const uint8_t* cmask, float* C, int64_t ldc, void* stream);
+
 /* Columns taken by one stored block in a sketch of the given precision:
  * b rounded up to 32 (FP32), 64 (BF16 forms) or 128 (FP8 forms); 0 on
  * invalid arguments. */
@@ -271,6 +284,14 @@ os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const floa
                     int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
                     const uint8_t* keep_host, int kept_only, float* C, int64_t ldc,
                     void* workspace, size_t ws_bytes, void* stream);
+
+/* The whole path with a keep mask per block of C (see os_gemm_kept_cmask):
+ * all N+e blocks are sketched; cmask: DEVICE uint8 [ceil(m/b)][ceil(l/b)][N+e].
+ * Other arguments and the workspace as in os_matmul. */
+os_status os_matmul_cmask(const os_sketch* sk, const float* A, int64_t lda, const float* B,
+                          int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
+                          const uint8_t* cmask, float* C, int64_t ldc, void* workspace,
+                          size_t ws_bytes, void* stream);
 
 /* Workspace bytes os_matmul_prec needs: those of os_matmul plus, for the
  * BF16 forms, the quantized copies of both sketches.  0 on invalid

@@ -19,7 +19,7 @@ __all__ = [
     "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "sketch_cols",
     "sketch_rows", "sketch_rows_workspace_bytes", "gemm_kept", "matmul", "workspace_bytes",
     "stored_count", "PRECISIONS", "block_stride_prec", "quantized_row", "sketch_quantize",
-    "gemm_kept_prec",
+    "gemm_kept_prec", "gemm_kept_cmask", "matmul_cmask",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -103,6 +103,11 @@ def lib():
     L.os_gemm_kept_prec.restype = ctypes.c_int
     L.os_gemm_kept_prec.argtypes = [vp, i64, vp, i64, i64, i64, i32, i32, vp, ctypes.c_int, vp,
                                     i64, vp]
+    L.os_gemm_kept_cmask.restype = ctypes.c_int
+    L.os_gemm_kept_cmask.argtypes = [vp, i64, vp, i64, i64, i64, i32, i32, vp, vp, i64, vp]
+    L.os_matmul_cmask.restype = ctypes.c_int
+    L.os_matmul_cmask.argtypes = [sk, vp, i64, vp, i64, ctypes.c_int, i64, i64, i64, vp, vp, i64,
+                                  vp, sz, vp]
     L.os_matmul_prec_workspace_bytes.restype = sz
     L.os_matmul_prec_workspace_bytes.argtypes = [sk, i64, i64, i64, ctypes.c_int, ctypes.c_int]
     L.os_matmul_prec.restype = ctypes.c_int
@@ -423,4 +428,71 @@ def matmul(A, B, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None
                                 l, pk, int(bool(kept_only)), p, _ptr(out), ldc, _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream)),
            "os_matmul_prec")
+    return out
+
+
+def _cmask_tensor(cmask, nbI, nbJ, nst, device):
+    torch = _torch()
+    if not isinstance(cmask, torch.Tensor):
+        cmask = torch.from_numpy(np.ascontiguousarray(np.asarray(cmask, dtype=np.uint8)))
+    cmask = cmask.to(device=device, dtype=torch.uint8).contiguous()
+    if tuple(cmask.shape) != (nbI, nbJ, nst):
+        raise OversketchError("cmask must be %d x %d x %d" % (nbI, nbJ, nst))
+    return cmask
+
+
+def gemm_kept_cmask(At, Bt, b, cmask, out=None, stream=None):
+    """Block product with a keep mask per b x b block of C: cmask
+    [ceil(m/b), ceil(l/b), nst] (host array or CUDA tensor)."""
+    torch = _torch()
+    _require_cuda(At, "At", torch.float32)
+    _require_cuda(Bt, "Bt", torch.float32)
+    m, wa, lda = _row_major(At, "At")
+    l, wb, ldb = _row_major(Bt, "Bt")
+    bp = block_stride(b)
+    if wa != wb or wa % bp:
+        raise OversketchError("At and Bt must both hold nst * block_stride(b) columns")
+    nst = wa // bp
+    cm = _cmask_tensor(cmask, -(-m // b), -(-l // b), nst, At.device)
+    if out is None:
+        out = torch.empty((m, l), dtype=torch.float32, device=At.device)
+    _require_cuda(out, "out", torch.float32)
+    _, _, ldc = _row_major(out, "out")
+    _check(lib().os_gemm_kept_cmask(_ptr(At), lda, _ptr(Bt), ldb, m, l, int(b), nst, _ptr(cm),
+                                    _ptr(out), ldc, _stream(stream)), "os_gemm_kept_cmask")
+    return out
+
+
+def matmul_cmask(A, B, b, N, e, cmask, seed=0, h=None, sigma=None, out=None, workspace=None,
+                 stream=None):
+    """OverSketch product with a keep mask per b x b block of C: cmask
+    [ceil(m/b), ceil(l/b), N+e]; every block is sketched."""
+    torch = _torch()
+    _require_cuda(A, "A", torch.float32)
+    _require_cuda(B, "B", torch.float32)
+    m, n, lda = _row_major(A, "A")
+    if B.dim() != 2 or B.shape[0] != n:
+        raise OversketchError("B must be n x l")
+    l = B.shape[1]
+    if B.stride(1) == 1 and (B.stride(0) != 1 or l == 1 and n > 1):
+        b_col_major, ldb = 0, B.stride(0) if n > 1 else (l + 3) // 4 * 4
+    elif B.stride(0) == 1:
+        b_col_major, ldb = 1, B.stride(1) if l > 1 else (n + 3) // 4 * 4
+    else:
+        raise OversketchError("B must have a unit stride in one dimension")
+    s = _sketch(b, N, e, seed, h, sigma)
+    cm = _cmask_tensor(cmask, -(-m // b), -(-l // b), N + e, A.device)
+    need = int(lib().os_matmul_prec_workspace_bytes(ctypes.byref(s), m, n, l, b_col_major, 0))
+    if need == 0:
+        raise OversketchError("invalid sizes for os_matmul_cmask")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+    if out is None:
+        out = torch.empty((m, l), dtype=torch.float32, device=A.device)
+    _require_cuda(out, "out", torch.float32)
+    _, _, ldc = _row_major(out, "out")
+    _check(lib().os_matmul_cmask(ctypes.byref(s), _ptr(A), lda, _ptr(B), ldb, b_col_major, m, n,
+                                 l, _ptr(cm), _ptr(out), ldc, _ptr(workspace),
+                                 workspace.numel() * workspace.element_size(), _stream(stream)),
+           "os_matmul_cmask")
     return out

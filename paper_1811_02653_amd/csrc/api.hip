@@ -290,6 +290,22 @@ os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t l
                                             ldc, (hipStream_t)stream));
 }
 
+os_status os_gemm_kept_cmask(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
+                             int64_t m, int64_t l, int32_t b, int32_t nst,
+                             const uint8_t* cmask, float* C, int64_t ldc, void* stream) {
+    if (b < 1 || b > OS_MAX_B || nst < 1 || nst > OS_MAX_BLOCKS) return OS_EINVAL;
+    os_status st;
+    if ((st = check_extent(m)) != OS_OK || (st = check_extent(l)) != OS_OK) return st;
+    const int32_t bp = os_block_stride(b);
+    if ((st = check_matrix(At, m, (int64_t)nst * bp, ldat, true)) != OS_OK) return st;
+    if ((st = check_matrix(Bt, l, (int64_t)nst * bp, ldbt, true)) != OS_OK) return st;
+    if ((st = check_matrix(C, m, l, ldc, false)) != OS_OK) return st;
+    if (!cmask) return OS_ENULL;
+    if (!osk::plan_gemm_ok(m, l, bp, ldat, ldbt, 4)) return OS_EINVAL;
+    return hip_status(osk::launch_gemm_cmask(At, ldat, Bt, ldbt, m, l, bp, nst, cmask, b, C, ldc,
+                                             (hipStream_t)stream));
+}
+
 int32_t os_block_stride_prec(int32_t b, int precision) {
     if (b < 1 || !valid_prec(precision)) return 0;
     return precision == OS_PREC_FP32 ? os_block_stride(b) : quant_stride(b, precision);
@@ -469,6 +485,59 @@ os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const
     return hip_status(osk::launch_gemm_kept_bf16(aq_p, wq, bq_p, wq, m, l, bpq, bs.kept_pos, bs.K,
                                                  split, (int64_t)bs.nst * bpq,
                                                  1.0f / (float)bs.K, C, ldc, s));
+}
+
+os_status os_matmul_cmask(const os_sketch* sk, const float* A, int64_t lda, const float* B,
+                          int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
+                          const uint8_t* cmask, float* C, int64_t ldc, void* workspace,
+                          size_t ws_bytes, void* stream) {
+    os_status st = check_sketch(sk);
+    if (st != OS_OK) return st;
+    if ((st = check_len(n)) != OS_OK) return st;
+    if ((st = check_extent(m)) != OS_OK || (st = check_extent(l)) != OS_OK) return st;
+    if ((st = check_matrix(A, m, n, lda, false)) != OS_OK) return st;
+    if (b_col_major) {
+        if ((st = check_matrix(B, l, n, ldb, false)) != OS_OK) return st;
+    } else {
+        if ((st = check_matrix(B, n, l, ldb, false)) != OS_OK) return st;
+    }
+    if ((st = check_matrix(C, m, l, ldc, false)) != OS_OK) return st;
+    if (!cmask) return OS_ENULL;
+    // every block is sketched: the blocks each C block keeps differ
+    uint8_t all[OS_MAX_BLOCKS];
+    for (int32_t i = 0; i < nblocks(sk); ++i) all[i] = 1;
+    Blocks bs;
+    if ((st = block_sets(sk, all, 0, bs)) != OS_OK) return st;
+    const size_t need = os_matmul_workspace_bytes(sk, m, n, l, b_col_major);
+    if (!workspace || !aligned(workspace, 256) || ws_bytes < need) return OS_EWORKSPACE;
+    const int32_t bp = os_block_stride(sk->b);
+    const int64_t zs = (int64_t)bs.nst * bp;
+    if (!osk::plan_sketch_ok(m, bs.nst, bp, n) || !osk::plan_sketch_ok(l, bs.nst, bp, n) ||
+        !osk::plan_gemm_ok(m, l, bp, zs, zs, 4))
+        return OS_EINVAL;
+    char* ws = static_cast<char*>(workspace);
+    void* prep = ws;
+    float* At = reinterpret_cast<float*>(ws + align256(prepare_bytes(sk, n)));
+    float* Bt = reinterpret_cast<float*>(reinterpret_cast<char*>(At) + align256((size_t)m * zs * 4u));
+    float* Bx = reinterpret_cast<float*>(reinterpret_cast<char*>(Bt) + align256((size_t)l * zs * 4u));
+    hipStream_t s = (hipStream_t)stream;
+    const void* lists = prep_lists(prep, sk, n);
+    if ((st = prepare(sk, n, prep, s)) != OS_OK) return st;
+    if ((st = hip_status(osk::launch_sketch_cols(A, m, n, lda, bs.stored, bs.nst, nblocks(sk), bp,
+                                                 lists, At, zs, s))) != OS_OK)
+        return st;
+    const float* Bl = B;
+    int64_t ldl = ldb;
+    if (!b_col_major) {
+        ldl = osk::round_up(n, 4);
+        if ((st = hip_status(osk::launch_transpose(B, n, l, ldb, Bx, ldl, s))) != OS_OK) return st;
+        Bl = Bx;
+    }
+    if ((st = hip_status(osk::launch_sketch_cols(Bl, l, n, ldl, bs.stored, bs.nst, nblocks(sk), bp,
+                                                 lists, Bt, zs, s))) != OS_OK)
+        return st;
+    return hip_status(osk::launch_gemm_cmask(At, zs, Bt, zs, m, l, bp, bs.nst, cmask, sk->b, C,
+                                             ldc, s));
 }
 
 os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const float* B, int64_t ldb,

@@ -138,14 +138,30 @@ struct PrecBF16 {
 // the A and B columns of the block; with nsub = 3 (split precision), term 1
 // pairs A's block with the low part of B's block (lo_off columns further)
 // and term 2 the low part of A's block with B's block.
-template <typename P>
+// Per-C-block keep masks (cmask != nullptr, the paper's per-block
+// stragglers): C is divided into cblk x cblk blocks, block (I, J) keeps the
+// stored blocks j with cmask[(I * nbJ + J) * nstm + j] != 0 and is scaled by
+// 1 / (their number); a block that keeps none is written as zero.  Tiles are
+// laid on the C-block grid (ceil(cblk / 256) per block side, the last ones
+// partial), so every tile lies in one block.
+struct CMask {
+    const uint8_t* mask;   // DEVICE [nbI][nbJ][nstm], or nullptr (one kept list)
+    int64_t cblk;
+    int32_t nbJ;
+    int32_t nstm;
+    int32_t tb;            // tiles per block side
+};
+
+template <typename P, bool kMask>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __restrict__ Bt,
                       int64_t ldbt, int64_t m, int64_t l, int32_t bp, BlockList kept,
                       int32_t nkept, int32_t nsub, int64_t lo_off, float scale,
-                      float* __restrict__ C, int64_t ldc, int32_t tilesM, int32_t tilesN) {
+                      float* __restrict__ C, int64_t ldc, int32_t tilesM, int32_t tilesN,
+                      CMask cm) {
     __shared__ __align__(16) float As[2][BM * LDT];
     __shared__ __align__(16) float Bs[2][BN * LDT];
+    __shared__ int32_t klist[kMask ? OS_MAX_BLOCKS + 1 : 1];   // per-tile kept list, count last
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -161,8 +177,37 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
     const int64_t in_group = T - group * kGroupM * tilesN;
     const int64_t tm = first_m + in_group % gsz;
     const int64_t tn = in_group / gsz;
-    const int64_t row0 = tm * BM;
-    const int64_t col0 = tn * BN;
+    int64_t row0 = tm * BM;
+    int64_t col0 = tn * BN;
+    if constexpr (kMask) {
+        // tile (tm, tn) of the C-block grid: block (I, J), tile (ti, tj) in it
+        const int64_t I = tm / cm.tb, J = tn / cm.tb;
+        row0 = I * cm.cblk + (tm % cm.tb) * BM;
+        col0 = J * cm.cblk + (tn % cm.tb) * BN;
+        m = min(m, (I + 1) * cm.cblk);          // rows and columns of this block only
+        l = min(l, (J + 1) * cm.cblk);
+        if (row0 >= m || col0 >= l) return;     // past a partial block's end (uniform)
+        if (tid == 0) {
+            const uint8_t* mk = cm.mask + (I * cm.nbJ + J) * cm.nstm;
+            int32_t k = 0;
+            for (int32_t j = 0; j < cm.nstm; ++j)
+                if (mk[j]) klist[k++] = j;
+            klist[OS_MAX_BLOCKS] = k;
+        }
+        __syncthreads();
+        nkept = __builtin_amdgcn_readfirstlane(klist[OS_MAX_BLOCKS]);
+        if (nkept == 0) {
+            for (int64_t r = row0 + (tid >> 6); r < min(m, row0 + BM); r += kThreads / 64)
+                for (int64_t c = col0 + lane; c < min(l, col0 + BN); c += 64) C[r * ldc + c] = 0.f;
+            return;
+        }
+        scale = 1.0f / (float)nkept;
+    }
+    // kept stored block of term index j
+    auto kept_at = [&](int j) -> int32_t {
+        if constexpr (kMask) return __builtin_amdgcn_readfirstlane(klist[j]);
+        return kept.idx[j];
+    };
 
     v16f acc[4][4];
 #pragma unroll
@@ -181,7 +226,7 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         const int term = step / tpb;
         const int j = term / nsub;
         const int sub = term - j * nsub;
-        const int64_t c = (int64_t)kept.idx[j] * bp + (int64_t)(step % tpb) * kStep +
+        const int64_t c = (int64_t)kept_at(j) * bp + (int64_t)(step % tpb) * kStep +
                           (sub == 2 ? lo_off : 0);
         return (uint32_t)(c * P::kElem);
     };
@@ -189,7 +234,7 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         const int term = step / tpb;
         const int j = term / nsub;
         const int sub = term - j * nsub;
-        const int64_t c = (int64_t)kept.idx[j] * bp + (int64_t)(step % tpb) * kStep +
+        const int64_t c = (int64_t)kept_at(j) * bp + (int64_t)(step % tpb) * kStep +
                           (sub == 1 ? lo_off : 0);
         return (uint32_t)(c * P::kElem);
     };
@@ -447,9 +492,27 @@ hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int6
     if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 4) || nkept < 1) return hipErrorInvalidValue;
     const int64_t tilesM = (m + BM - 1) / BM;
     const int64_t tilesN = (l + BN - 1) / BN;
-    hipLaunchKernelGGL(gemm_kept_kernel<PrecF32>, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads),
-                       0, s, At, ldat, Bt, ldbt, m, l, bp, kept, nkept, 1, (int64_t)0, scale, C,
-                       ldc, (int32_t)tilesM, (int32_t)tilesN);
+    hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, false>), dim3((unsigned)(tilesM * tilesN)),
+                       dim3(kThreads), 0, s, At, ldat, Bt, ldbt, m, l, bp, kept, nkept, 1, (int64_t)0, scale, C,
+                       ldc, (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1});
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
+                             int64_t m, int64_t l, int32_t bp, int32_t nst, const uint8_t* cmask,
+                             int64_t cblk, float* C, int64_t ldc, hipStream_t s) {
+    if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 4) || cblk < 1 || nst < 1 || nst > OS_MAX_BLOCKS)
+        return hipErrorInvalidValue;
+    const int64_t nbI = (m + cblk - 1) / cblk, nbJ = (l + cblk - 1) / cblk;
+    const int64_t tb = (cblk + BM - 1) / BM;
+    const int64_t tilesM = nbI * tb, tilesN = nbJ * tb;
+    if (tilesM * tilesN > 0x7fffffff || nbJ > 0x7fffffff) return hipErrorInvalidValue;
+    BlockList none;
+    for (int j = 0; j < OS_MAX_BLOCKS; ++j) none.idx[j] = 0;
+    hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, true>), dim3((unsigned)(tilesM * tilesN)),
+                       dim3(kThreads), 0, s, At, ldat, Bt, ldbt, m, l, bp, none, 0, 1, (int64_t)0, 1.0f, C, ldc,
+                       (int32_t)tilesM, (int32_t)tilesN,
+                       CMask{cmask, cblk, (int32_t)nbJ, nst, (int32_t)tb});
     return hipGetLastError();
 }
 
@@ -474,9 +537,10 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
     if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 2) || nkept < 1) return hipErrorInvalidValue;
     const int64_t tilesM = (m + BM - 1) / BM;
     const int64_t tilesN = (l + BN - 1) / BN;
-    hipLaunchKernelGGL(gemm_kept_kernel<PrecBF16>, dim3((unsigned)(tilesM * tilesN)),
+    hipLaunchKernelGGL((gemm_kept_kernel<PrecBF16, false>), dim3((unsigned)(tilesM * tilesN)),
                        dim3(kThreads), 0, s, At, ldat, Bt, ldbt, m, l, bp, kept, nkept,
-                       split ? 3 : 1, lo_off, scale, C, ldc, (int32_t)tilesM, (int32_t)tilesN);
+                       split ? 3 : 1, lo_off, scale, C, ldc, (int32_t)tilesM, (int32_t)tilesN,
+                       CMask{nullptr, 0, 0, 0, 1});
     return hipGetLastError();
 }
 

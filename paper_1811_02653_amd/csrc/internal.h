@@ -87,6 +87,12 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
                                  int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                                  int32_t nkept, int split, int64_t lo_off, float scale, float* C,
                                  int64_t ldc, hipStream_t s);
+// FP32 block product with a keep mask per C block: cmask DEVICE [ceil(m/cblk)]
+// [ceil(l/cblk)][nst]; block (I, J) of C (cblk x cblk) = (1/K_IJ) * sum of its
+// kept blocks' products (zero when it keeps none).
+hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
+                             int64_t m, int64_t l, int32_t bp, int32_t nst, const uint8_t* cmask,
+                             int64_t cblk, float* C, int64_t ldc, hipStream_t s);
 // The same with FP8 copies (launch_quant_fp8 layout: ld in bytes, the scale
 // bytes of a row `scales` bytes after its start; block stride bp a multiple
 // of 128).
@@ -101,6 +107,12 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
                                  int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                                  int32_t nkept, int split, int64_t lo_off, float scale, float* C,
                                  int64_t ldc, hipStream_t s);
+// FP32 block product with a keep mask per C block: cmask DEVICE [ceil(m/cblk)]
+// [ceil(l/cblk)][nst]; block (I, J) of C (cblk x cblk) = (1/K_IJ) * sum of its
+// kept blocks' products (zero when it keeps none).
+hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
+                             int64_t m, int64_t l, int32_t bp, int32_t nst, const uint8_t* cmask,
+                             int64_t cblk, float* C, int64_t ldc, hipStream_t s);
 // The same with FP8 copies (launch_quant_fp8 layout: ld in bytes, the scale
 // bytes of a row `scales` bytes after its start; block stride bp a multiple
 // of 128).

@@ -282,3 +282,49 @@ def test_error_paths_raise():
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(osk.OversketchError):
         osk.matmul(A, B, 4, 2, 1, workspace=small)
+
+
+# ---------------------------------------------------------------------------
+# per-C-block keep masks (each b x b block of C keeps its own workers)
+# ---------------------------------------------------------------------------
+
+def _cmask_reference(A, B, b, N, e, seed, cmask):
+    """Per C block: (1/K_IJ) sum of its kept blocks' products on the oracle's
+    sketch; zero where a block keeps none."""
+    h, s = oracle.hash_tables(seed, N + e, A.shape[1], b)
+    At = oracle.sketch_cols(A, h, s, b)
+    Bt = oracle.sketch_rows(B, h, s, b)
+    m, l = A.shape[0], B.shape[1]
+    C = np.zeros((m, l))
+    for I in range(cmask.shape[0]):
+        for J in range(cmask.shape[1]):
+            r, c = slice(I * b, min(m, (I + 1) * b)), slice(J * b, min(l, (J + 1) * b))
+            if cmask[I, J].any():
+                C[r, c] = oracle.block_product(At[r], Bt[:, c], b, cmask[I, J])
+    return C
+
+
+@pytest.mark.parametrize("m,n,l,b,N,e", [(600, 2048, 520, 256, 3, 2),   # tiles = blocks
+                                         (300, 1001, 250, 100, 3, 1),   # block < tile
+                                         (700, 1500, 640, 300, 2, 2)])  # 2 tiles per block side
+def test_matmul_per_block_masks(m, n, l, b, N, e):
+    seed = m + l
+    A, B = synthetic.gaussian_pair(m, n, l, seed)
+    rng = np.random.default_rng(seed)
+    nbI, nbJ = -(-m // b), -(-l // b)
+    cmask = (rng.random((nbI, nbJ, N + e)) < 0.6).astype(np.uint8)
+    cmask[0, 0, :] = 0                      # a block every worker missed: zero
+    cmask[-1, -1, :] = 1                    # a block that kept all N+e (K > N)
+    if nbJ > 1:
+        cmask[0, 1, :] = 0
+        cmask[0, 1, 0] = 1                  # a block with one worker (K < N)
+    C = host(osk.matmul_cmask(dev(A), dev(B, ld=l + 1), b, N, e, cmask, seed=seed))
+    ref = _cmask_reference(A, B, b, N, e, seed, cmask)
+    assert np.all(C[:b, :b] == 0)
+    assert rel(C, ref) <= PRODUCT_TOL
+    # a uniform mask reproduces the global-mask path exactly
+    keep = synthetic.random_keep(N, e, seed)
+    uni = np.broadcast_to(keep, (nbI, nbJ, N + e)).copy()
+    Cu = host(osk.matmul_cmask(dev(A), dev(B, ld=l + 1), b, N, e, uni, seed=seed))
+    Cg = host(osk.matmul(dev(A), dev(B, ld=l + 1), b, N, e, seed=seed, keep=keep))
+    np.testing.assert_array_equal(Cu, Cg)
