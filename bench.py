@@ -77,6 +77,8 @@ def parse():
                    help="skip the sketched linear layer (backward with a sketched weight gradient)")
     p.add_argument("--no-precision", action="store_true",
                    help="skip the BF16 / split-BF16 variants of the block product")
+    p.add_argument("--no-batch", action="store_true",
+                   help="skip the batch of 64 sketched interior-point Hessians")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 1 GiB device copy (3 times): the reference kernel "
                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -108,6 +110,84 @@ def event_time_ms(torch, fn, reps, stream):
         stop.record(stream)
     stop.synchronize()
     return start.elapsed_time(stop) / reps
+
+
+def bench_hessian_batch(torch, osk, args, stream, reps):
+    import synthetic
+    from paper_1811_02653_amd.gram import PRODUCT, PREPARE, SKETCH
+    count, N, e = 64, 6, 1
+    sizes, As, ds = synthetic.hessian_batch_device(count, args.seed)
+    keeps = [synthetic.random_keep(N, e, args.seed + k, drop=1) for k in range(count)]
+    bs = [(m + 1) // 2 for m in sizes]
+    gb = osk.GramBatch(As, ds, b=bs, N=N, e=e, keeps=keeps, seeds=list(range(count)),
+                       stream=stream)
+    tuned_ms = gb.autotune(reps=2, stream=stream)
+    tile, grid = gb.config
+    g = gb.graph()                      # captured on a private stream
+    t_graph = event_time_ms(torch, lambda: g.launch(stream), reps, stream)
+    t_eager = event_time_ms(torch, lambda: gb.run(stream=stream), reps, stream)
+    t_prep = event_time_ms(torch, lambda: gb.run(PREPARE, stream=stream), reps, stream)
+    t_sketch = event_time_ms(torch, lambda: gb.run(SKETCH, stream=stream), reps, stream)
+    t_prod = event_time_ms(torch, lambda: gb.run(PRODUCT, stream=stream), reps, stream)
+    g.close()
+    K = N                                      # one of the N+e blocks dropped per problem
+    exact_flops = sum(2.0 * m * m * 20 * m for m in sizes)
+    # algorithmic flops of the batched product: the upper triangle with the
+    # diagonal, 2*K*b per entry
+    prod_flops = sum(float(m) * (m + 1) * K * b for m, b in zip(sizes, bs))
+    sketch_bytes = sum(4.0 * (m * 20 * m + 20 * m + m * K * osk.block_stride(b))
+                       for m, b in zip(sizes, bs))
+    # exact Hessians (FP32 hipBLASLt) for the error and the exact baseline
+    errs = []
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t_exact = 0.0
+    for k in range(count):
+        t0.record(stream)
+        W = As[k] * torch.sqrt(ds[k])[None, :]
+        Hx = torch.matmul(W, W.t())
+        t1.record(stream)
+        t1.synchronize()
+        t_exact += t0.elapsed_time(t1)
+        errs.append((torch.linalg.norm(gb.H[k].double() - Hx.double()) /
+                     torch.linalg.norm(Hx.double())).item())
+        del W, Hx
+    res = {
+        "workload": "64 interior-point Hessians A_k D_k A_k^T, A_k m_k x 20m_k ~ N(0,1), "
+                    "m_k uniform in [500, 4000], d_k log-uniform in [1e-6, 1e6]; "
+                    "b_k = ceil(m_k/2), N=6, e=1, one block dropped per problem",
+        "m_k": sizes, "input_gb": sum(4.0 * m * 20 * m for m in sizes) / 1e9,
+        "tile": tile, "grid": grid, "autotune_ms": tuned_ms,
+        "ms_per_batch": t_graph, "ms_per_batch_eager": t_eager,
+        "hessians_per_s": count / (t_graph * 1e-3),
+        "eff_tflops": exact_flops / (t_graph * 1e-3) / 1e12,
+        "stages_ms": {"prepare": t_prep, "sketch": t_sketch, "product": t_prod},
+        "product_roofline": {
+            "kernel": "gemm_batch_sym (FP32 v_mfma_f32_32x32x2_f32, persistent, tile %d)" % tile,
+            "bound": "mfma", "unit": "TFLOP/s", "peak": FP32_MFMA_PEAK_TFLOPS,
+            "algorithmic_flops_per_launch": prod_flops,
+            "achieved": prod_flops / (t_prod * 1e-3) / 1e12,
+            "frac": prod_flops / (t_prod * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS},
+        "sketch_roofline": {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "algorithmic_bytes": sketch_bytes,
+            "achieved": sketch_bytes / (t_sketch * 1e-3) / 1e9,
+            "frac": sketch_bytes / (t_sketch * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "exact": {"kind": "torch.matmul FP32 of A_k D_k^{1/2} with its transpose, per problem",
+                  "ms": t_exact, "tflops": exact_flops / (t_exact * 1e-3) / 1e12,
+                  "speedup_of_sketched": t_exact / t_graph},
+        "rel_frob_vs_exact": {"mean": float(np.mean(errs)), "max": float(np.max(errs)),
+                              "min": float(np.min(errs))},
+    }
+    log("hessian batch: tile %d grid %d, %.3f ms per batch (graph), %.3f eager; prepare %.3f, "
+        "sketch %.3f, product %.3f ms (%.1f TFLOP/s); exact %.1f ms; error mean %.3e" %
+        (tile, grid, t_graph, t_eager, t_prep, t_sketch, t_prod,
+         res["product_roofline"]["achieved"], t_exact, res["rel_frob_vs_exact"]["mean"]))
+    gb.close()
+    del gb, As, ds
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -340,6 +420,16 @@ def main():
         del Xl, Wl, Dl, dW_exact
         torch.cuda.empty_cache()
 
+    # ---- batch of 64 sketched interior-point Hessians H_k = A_k D_k A_k^T:
+    # A_k m_k x 20 m_k, m_k uniform in [500, 4000], A_k ~ N(0,1), d_k
+    # log-uniform in [1e-6, 1e6], b_k = ceil(m_k / 2), N = 6, e = 1 with one
+    # block dropped; sketch with D^{1/2} fused, one persistent product launch
+    # over the upper-triangle tiles of all 64, the whole batch replayed as a
+    # HIP graph, tile side autotuned
+    batch = None
+    if not args.no_batch:
+        batch = bench_hessian_batch(torch, osk, args, stream, reps)
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
     sample_err = None
@@ -407,6 +497,7 @@ def main():
                   "rel_frob_vs_oracle_sample": sample_err},
         "precision_variants": precision,
         "sketched_linear_layer": layer,
+        "hessian_batch": batch,
         "exact_gemm": {"kind": "torch.matmul FP32 (hipBLASLt)", "ms": t_exact,
                        "tflops": 2.0 * m * n * l / (t_exact * 1e-3) / 1e12,
                        "speedup_of_sketched": t_exact / ms_per_step},

@@ -309,6 +309,117 @@ os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const
                          const uint8_t* keep_host, int kept_only, int precision, float* C,
                          int64_t ldc, void* workspace, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched sketched Gram matrices: the Hessian sketch of the interior-point
+ * application (Section 5.2, Eq. (int_point) and the Hessian after it).  The
+ * Newton step of the log-barrier LP needs A^T diag(1/(b_i - a_i x)^2) A,
+ * whose square root is diag(1/|b_i - a_i x|) A; it is approximated by the
+ * Gram matrix of the sketched square root, (S^T grad2f^{1/2})^T
+ * (S^T grad2f^{1/2}).  In this library's row-major convention a problem is A
+ * (m x n: the LP's constraint matrix transposed, its n constraints along the
+ * sketched side) and D = diag(d), d_i = 1/(b_i - a_i x)^2, and
+ *   H = (1/K) * sum_{kept i} (A D^{1/2} S_i)(A D^{1/2} S_i)^T,
+ * the OverSketch product of A D^{1/2} with its own transpose.  A batch of
+ * such problems of different sizes runs as: per problem, prepare and sketch
+ * (D^{1/2} applied to A's entries as they are read, only the kept blocks
+ * stored), then ONE persistent launch computing the upper-triangle tiles of
+ * every H (and their mirrors), the tiles spread over the workgroups by a
+ * static largest-first schedule computed on the host.
+ *
+ * Lifetime: a plan is a HOST object.  It copies the problem descriptions
+ * (sizes, sketch parameters, keep masks) and keeps the DEVICE pointers A, d,
+ * H of every problem: they must stay valid while the plan (or a graph made
+ * from it) is used.  The plan's workspace (os_gram_workspace_bytes) holds
+ * the schedule, the prepared sketches and the sketches; os_gram_configure
+ * writes the schedule into it, and os_gram_run / os_gram_graph_create
+ * require the workspace last configured.
+ * ------------------------------------------------------------------------ */
+
+/* One problem of a batch.  sk: its sketch (buckets over n; explicit tables,
+ * if given, are DEVICE [N+e][n]).  A: DEVICE m x n row-major, ld lda, 4-byte
+ * aligned.  d: DEVICE FP32 [n] with d[k] >= 0 (the diagonal of D), or NULL
+ * for D = I.  keep: HOST uint8 [N+e] or NULL (= blocks [0, N)), copied by
+ * os_gram_plan_create.  H: DEVICE m x m row-major, ld ldh >= m, overwritten
+ * (with full = 0 only its tiles on or above the diagonal are written). */
+typedef struct os_gram_problem {
+    os_sketch sk;
+    const float* A;
+    int64_t lda;
+    const float* d;
+    int64_t m;
+    int64_t n;
+    const uint8_t* keep;
+    float* H;
+    int64_t ldh;
+} os_gram_problem;
+
+typedef struct os_gram_plan os_gram_plan;
+
+/* Validates every problem (count in [1, OS_GRAM_MAX_PROBLEMS]) and makes a
+ * plan (*plan_out, released by os_gram_plan_destroy).  full != 0: H is
+ * written whole (the lower triangle mirrored from the upper); full = 0: only
+ * the tiles on or above the diagonal are written.  On error *plan_out is
+ * NULL.  Allocates host memory only. */
+#define OS_GRAM_MAX_PROBLEMS 65536
+os_status os_gram_plan_create(const os_gram_problem* probs, int32_t count, int full,
+                              os_gram_plan** plan_out);
+
+/* Releases a plan (NULL is ignored).  Graphs made from it stay valid. */
+void os_gram_plan_destroy(os_gram_plan* plan);
+
+/* DEVICE workspace bytes the plan needs (256-byte aligned base); one size
+ * serves every tile configuration.  0 for a NULL plan. */
+size_t os_gram_workspace_bytes(const os_gram_plan* plan);
+
+/* Chooses the tile side of the batched product (128 or 256; 0 = 256) and
+ * its number of persistent workgroups (grid; 0 = as many as fit on the
+ * device at once), computes the static schedule and copies it and the
+ * per-problem descriptors into the workspace.  Synchronizes `stream`
+ * before returning.  OS_EINVAL for another tile or a grid above 65536. */
+os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void* workspace,
+                            size_t ws_bytes, void* stream);
+
+/* The tile side and grid the plan is configured with (0, 0 before
+ * os_gram_configure); either pointer may be NULL. */
+void os_gram_config(const os_gram_plan* plan, int32_t* tile, int32_t* grid);
+
+/* Stages of a batch run (os_gram_run, os_gram_graph_create), OR-ed. */
+#define OS_GRAM_PREPARE 1   /* hash and bucket lists of every problem */
+#define OS_GRAM_SKETCH  2   /* the weighted sketch of every A (kept blocks) */
+#define OS_GRAM_PRODUCT 4   /* the one batched product writing every H */
+#define OS_GRAM_ALL     7
+
+/* Enqueues the given stages (a nonzero subset of OS_GRAM_ALL) of the batch
+ * on `stream`, in the order prepare, sketch, product.  A stage left out
+ * uses what an earlier run left in the workspace (prepared sketches are
+ * reusable while the plan's sketch parameters stand; the sketches while A
+ * and d are unchanged).  Only kernels are enqueued (no copies, no memsets),
+ * so the call can be captured into a graph.  Requires the workspace of the
+ * last os_gram_configure (else OS_EINVAL). */
+os_status os_gram_run(const os_gram_plan* plan, int stages, void* workspace, size_t ws_bytes,
+                      void* stream);
+
+/* Autotuner: configures each candidate (tile 256 and 128, each with its
+ * default grid), times `reps` (>= 1) runs of each after one warm-up run
+ * with HIP events on `stream`, and leaves the plan configured with the
+ * fastest.  Runs every stage of the batch (the H outputs are overwritten).  *best_ms (may
+ * be NULL) receives the fastest average time per run. */
+os_status os_gram_autotune(os_gram_plan* plan, int32_t reps, void* workspace, size_t ws_bytes,
+                           void* stream, float* best_ms);
+
+/* Captures one os_gram_run of the given stages on `stream` (a created
+ * stream, not NULL) into a HIP graph and instantiates it: *graph_out is an
+ * executable graph for os_graph_launch.  The graph uses the plan's current
+ * configuration and workspace. */
+os_status os_gram_graph_create(const os_gram_plan* plan, int stages, void* workspace,
+                               size_t ws_bytes, void* stream, void** graph_out);
+
+/* Launches an executable graph from os_gram_graph_create on `stream`. */
+os_status os_graph_launch(void* graph, void* stream);
+
+/* Releases an executable graph (NULL is ignored). */
+void os_graph_destroy(void* graph);
+
 #ifdef __cplusplus
 }
 #endif

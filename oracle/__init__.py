@@ -224,6 +224,26 @@ def sampled_entries(A, B, rows, cols, b: int, N: int, e: int, seed: int = 0,
     return out
 
 
+def sketched_gram(A, d, b: int, N: int, e: int, seed: int = 0, keep=None,
+                  h=None, sigma=None) -> np.ndarray:
+    """Sketched Hessian of the log-barrier interior-point method (Section 5.2,
+    Eq. (int_point) and the Hessian after it): the Hessian's square root is
+    the constraint matrix with row i scaled by 1/|b_i - a_i x|, and the
+    Hessian is approximated by the Gram matrix of its sketch.  Here A (m x n)
+    is the constraint matrix transposed and d (n, >= 0) the squared scales
+    1/(b_i - a_i x)^2 (None = ones), so the result is the OverSketch product
+    of W = A diag(sqrt(d)) with W^T:
+        H = (1/K) sum_{kept i} (W S_i)(S_i^T W^T)."""
+    A = _f64(A)
+    if d is not None:
+        d = np.asarray(d, dtype=np.float64).reshape(-1)
+        if d.shape[0] != A.shape[1] or np.any(d < 0):
+            raise ValueError("d must hold n nonnegative weights")
+        A = A * np.sqrt(d)[None, :]
+    return sketched_matmul(A, np.ascontiguousarray(A.T), b, N, e, seed=seed, keep=keep,
+                           h=h, sigma=sigma)
+
+
 # ---------------------------------------------------------------------------
 # Literal definitions with a dense sketch matrix (tiny sizes only)
 # ---------------------------------------------------------------------------

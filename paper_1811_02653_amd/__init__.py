@@ -19,7 +19,7 @@ __all__ = [
     "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "sketch_cols",
     "sketch_rows", "sketch_rows_workspace_bytes", "gemm_kept", "matmul", "workspace_bytes",
     "stored_count", "PRECISIONS", "block_stride_prec", "quantized_row", "sketch_quantize",
-    "gemm_kept_prec", "gemm_kept_cmask", "matmul_cmask",
+    "gemm_kept_prec", "gemm_kept_cmask", "matmul_cmask", "GramBatch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -49,6 +49,20 @@ class _Sketch(ctypes.Structure):
         ("e", ctypes.c_int32),
         ("h", ctypes.c_void_p),
         ("sigma", ctypes.c_void_p),
+    ]
+
+
+class _GramProblem(ctypes.Structure):
+    _fields_ = [
+        ("sk", _Sketch),
+        ("A", ctypes.c_void_p),
+        ("lda", ctypes.c_int64),
+        ("d", ctypes.c_void_p),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("keep", ctypes.c_void_p),
+        ("H", ctypes.c_void_p),
+        ("ldh", ctypes.c_int64),
     ]
 
 
@@ -113,6 +127,27 @@ def lib():
     L.os_matmul_prec.restype = ctypes.c_int
     L.os_matmul_prec.argtypes = [sk, vp, i64, vp, i64, ctypes.c_int, i64, i64, i64, vp,
                                  ctypes.c_int, ctypes.c_int, vp, i64, vp, sz, vp]
+    gp = ctypes.POINTER(_GramProblem)
+    L.os_gram_plan_create.restype = ctypes.c_int
+    L.os_gram_plan_create.argtypes = [gp, i32, ctypes.c_int, ctypes.POINTER(vp)]
+    L.os_gram_plan_destroy.restype = None
+    L.os_gram_plan_destroy.argtypes = [vp]
+    L.os_gram_workspace_bytes.restype = sz
+    L.os_gram_workspace_bytes.argtypes = [vp]
+    L.os_gram_configure.restype = ctypes.c_int
+    L.os_gram_configure.argtypes = [vp, i32, i32, vp, sz, vp]
+    L.os_gram_config.restype = None
+    L.os_gram_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.os_gram_run.restype = ctypes.c_int
+    L.os_gram_run.argtypes = [vp, ctypes.c_int, vp, sz, vp]
+    L.os_gram_autotune.restype = ctypes.c_int
+    L.os_gram_autotune.argtypes = [vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
+    L.os_gram_graph_create.restype = ctypes.c_int
+    L.os_gram_graph_create.argtypes = [vp, ctypes.c_int, vp, sz, vp, ctypes.POINTER(vp)]
+    L.os_graph_launch.restype = ctypes.c_int
+    L.os_graph_launch.argtypes = [vp, vp]
+    L.os_graph_destroy.restype = None
+    L.os_graph_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -496,3 +531,6 @@ def matmul_cmask(A, B, b, N, e, cmask, seed=0, h=None, sigma=None, out=None, wor
                                  workspace.numel() * workspace.element_size(), _stream(stream)),
            "os_matmul_cmask")
     return out
+
+
+from .gram import GramBatch  # noqa: E402  (uses the helpers above)

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liboversketch.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["hash.hip", "sketch.hip", "gemm.hip", "quant.hip", "api.hip"]
+SOURCES = ["hash.hip", "sketch.hip", "gemm.hip", "quant.hip", "api.hip", "gram.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -475,6 +475,171 @@ void gemm_kept_fp8_kernel(const uint8_t* __restrict__ At, int64_t ldat, const ui
     }
 }
 
+// ---------------------------------------------------------------------------
+// Grouped symmetric block product for a batch of sketched Gram matrices:
+//   H_k = scale_k * S_k S_k^T, S_k the line-major sketch (m_k rows) of
+//   problem k with only its kept blocks stored, so the sum over the kept
+//   blocks runs over its first ksteps * 32 columns (padding columns are
+//   zero).  One persistent launch over a tile list that holds the
+//   upper-triangle tiles (ti <= tj) of every problem.  Workgroup g takes
+//   tiles starts[g] .. starts[g+1] - 1 (a static schedule balanced on the
+//   host; every wave reaches its end), computing each with the same FP32
+//   MFMA pipeline as above; an off-diagonal tile is also stored
+//   transposed (mirror) when `full`.
+// kWT: MFMA blocks of 32 x 32 per wave side -- 4 (256 x 256 tiles) or 2
+// (128 x 128 tiles: less padding on small problems, two workgroups per CU).
+// ---------------------------------------------------------------------------
+template <int kWT>
+struct TileShape {
+    static constexpr int BT = 64 * kWT;       // tile side
+    static constexpr int kU = BT / 32;        // 16-byte loads per thread per operand
+};
+
+template <int kU>
+__device__ __forceinline__ void load_rows(float4 (&r)[kU], __amdgpu_buffer_rsrc_t rsrc,
+                                          uint32_t kbyte, const uint32_t (&off)[kU]) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+        r[u] = __builtin_bit_cast(float4,
+                                  __builtin_amdgcn_raw_buffer_load_b128(rsrc, off[u], kbyte, 0));
+}
+
+template <int kU>
+__device__ __forceinline__ void row_offsets(uint32_t (&off)[kU], int64_t ld_bytes, int rel,
+                                            int last, int kq) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+        off[u] = (uint32_t)((int64_t)min(rel + 32 * u, last) * ld_bytes + 16 * kq);
+}
+
+template <int kU>
+__device__ __forceinline__ void store_rows(float* __restrict__ s, const float4 (&r)[kU], int tid) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+        *reinterpret_cast<float4*>(s + ((tid >> 3) + 32 * u) * LDT + 4 * (tid & 7)) = r[u];
+}
+
+template <int kWT>
+__device__ __forceinline__ void frag_rows(float4 (&a)[kWT], float4 (&b)[kWT],
+                                          const float* __restrict__ As,
+                                          const float* __restrict__ Bs, int q, int arow, int brow,
+                                          int kh) {
+#pragma unroll
+    for (int i = 0; i < kWT; ++i) {
+        a[i] = *reinterpret_cast<const float4*>(As + (arow + 32 * i) * LDT + kh + 4 * q);
+        b[i] = *reinterpret_cast<const float4*>(Bs + (brow + 32 * i) * LDT + kh + 4 * q);
+    }
+}
+
+template <int kWT>
+__device__ __forceinline__ void mfma_rows(v16f (&acc)[kWT][kWT], const float4 (&a)[kWT],
+                                          const float4 (&b)[kWT]) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int i = 0; i < kWT; ++i)
+#pragma unroll
+            for (int j = 0; j < kWT; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(a[i], kk), comp(b[j], kk),
+                                                                 acc[i][j], 0, 0, 0);
+}
+
+template <int kWT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 5 - kWT)))
+void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
+                           const int4* __restrict__ tiles, const int32_t* __restrict__ starts,
+                           int full) {
+    using TS = TileShape<kWT>;
+    constexpr int BT = TS::BT;
+    constexpr int kU = TS::kU;
+    __shared__ __align__(16) float As[2][BT * LDT];
+    __shared__ __align__(16) float Bs[2][BT * LDT];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1;
+    const int wn = wave & 1;
+    const int arow = wm * (BT / 2) + (lane & 31);
+    const int brow = wn * (BT / 2) + (lane & 31);
+    const int kh = 16 * (lane >> 5);
+
+    const int32_t w_end = starts[blockIdx.x + 1];
+    for (int32_t w = starts[blockIdx.x]; w < w_end; ++w) {
+        const int4 tl = tiles[w];
+        const BatchProblem pr = probs[tl.x];
+        const int64_t m = pr.m;
+        const int64_t row0 = (int64_t)tl.y * BT;
+        const int64_t col0 = (int64_t)tl.z * BT;
+        const int total = pr.ksteps;
+        auto step_col = [](int step) -> uint32_t { return (uint32_t)step * kStepBytes; };
+        const __amdgpu_buffer_rsrc_t ra_src = tile_rsrc(pr.S + row0 * pr.ld);
+        const __amdgpu_buffer_rsrc_t rb_src = tile_rsrc(pr.S + col0 * pr.ld);
+        uint32_t oa[kU], ob[kU];
+        row_offsets<kU>(oa, pr.ld * 4, tid >> 3, (int)min((int64_t)BT - 1, m - 1 - row0), tid & 7);
+        row_offsets<kU>(ob, pr.ld * 4, tid >> 3, (int)min((int64_t)BT - 1, m - 1 - col0), tid & 7);
+
+        v16f acc[kWT][kWT];
+#pragma unroll
+        for (int i = 0; i < kWT; ++i)
+#pragma unroll
+            for (int j = 0; j < kWT; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+        float4 ra[kU], rb[kU];
+        load_rows<kU>(ra, ra_src, step_col(0), oa);
+        load_rows<kU>(rb, rb_src, step_col(0), ob);
+        __syncthreads();                       // the previous tile's last reads are done
+        store_rows<kU>(As[0], ra, tid);
+        store_rows<kU>(Bs[0], rb, tid);
+        load_rows<kU>(ra, ra_src, step_col(min(1, total - 1)), oa);
+        load_rows<kU>(rb, rb_src, step_col(min(1, total - 1)), ob);
+        __syncthreads();
+
+        float4 fa[kWT], fb[kWT], ga[kWT], gb[kWT];
+        frag_rows<kWT>(fa, fb, As[0], Bs[0], 0, arow, brow, kh);
+        for (int t = 0; t < total; ++t) {
+            const int cur = t & 1;
+            const float* as = As[cur];
+            const float* bs = Bs[cur];
+            frag_rows<kWT>(ga, gb, as, bs, 1, arow, brow, kh);
+            mfma_rows<kWT>(acc, fa, fb);
+            frag_rows<kWT>(fa, fb, as, bs, 2, arow, brow, kh);
+            mfma_rows<kWT>(acc, ga, gb);
+            store_rows<kU>(As[cur ^ 1], ra, tid);
+            store_rows<kU>(Bs[cur ^ 1], rb, tid);
+            const int ahead = min(t + 2, total - 1);
+            load_rows<kU>(ra, ra_src, step_col(ahead), oa);
+            load_rows<kU>(rb, rb_src, step_col(ahead), ob);
+            frag_rows<kWT>(ga, gb, as, bs, 3, arow, brow, kh);
+            mfma_rows<kWT>(acc, fa, fb);
+            mfma_rows<kWT>(acc, ga, gb);
+            __syncthreads();
+            frag_rows<kWT>(fa, fb, As[cur ^ 1], Bs[cur ^ 1], 0, arow, brow, kh);
+        }
+
+        const bool mirror = full && tl.y != tl.z;
+#pragma unroll
+        for (int i = 0; i < kWT; ++i) {
+#pragma unroll
+            for (int j = 0; j < kWT; ++j) {
+                const int64_t col = col0 + wn * (BT / 2) + j * 32 + (lane & 31);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t row = row0 + wm * (BT / 2) + i * 32 + 8 * (r >> 2) +
+                                        4 * (lane >> 5) + (r & 3);
+                    if (row < m && col < m) {
+                        const float v = acc[i][j][r] * pr.scale;
+                        pr.H[row * pr.ldh + col] = v;
+                        if (mirror) pr.H[col * pr.ldh + row] = v;
+                    }
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
 
 bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt, int elem) {
@@ -514,6 +679,31 @@ hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int
                        (int32_t)tilesM, (int32_t)tilesN,
                        CMask{cmask, cblk, (int32_t)nbJ, nst, (int32_t)tb});
     return hipGetLastError();
+}
+
+hipError_t launch_gemm_batch_sym(const BatchProblem* probs, const int4* tiles,
+                                 const int32_t* starts, int tile, int full, int32_t grid,
+                                 hipStream_t s) {
+    if (grid < 1) return hipErrorInvalidValue;
+    if (tile == 256)
+        hipLaunchKernelGGL(gemm_batch_sym_kernel<4>, dim3((unsigned)grid), dim3(kThreads), 0, s,
+                           probs, tiles, starts, full);
+    else if (tile == 128)
+        hipLaunchKernelGGL(gemm_batch_sym_kernel<2>, dim3((unsigned)grid), dim3(kThreads), 0, s,
+                           probs, tiles, starts, full);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+int batch_sym_blocks_per_cu(int tile) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (tile == 256)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_batch_sym_kernel<4>, kThreads, 0);
+    else if (tile == 128)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_batch_sym_kernel<2>, kThreads, 0);
+    return e == hipSuccess ? n : 0;
 }
 
 hipError_t launch_gemm_kept_fp8(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,

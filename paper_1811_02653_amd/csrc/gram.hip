@@ -1,0 +1,379 @@
+// gram.hip -- batched sketched Gram matrices (the os_gram_* entry points):
+// the Hessian sketch of the log-barrier interior-point method (Section 5.2,
+// Eq. (int_point) and the Hessian after it), H = (A D^{1/2} S)(A D^{1/2} S)^T
+// / K for a batch of problems of different sizes.
+//
+// Per problem the prepared sketch and the weighted sketch of A's rows (only
+// the kept blocks stored) go to the workspace; then one persistent launch
+// computes the upper-triangle tiles of every H.  Its schedule is made on the
+// host: tiles sorted by cost (the problem's K depth) and each given to the
+// least-loaded workgroup (longest-processing-time-first), stored grouped by
+// workgroup.
+#include <algorithm>
+#include <functional>
+#include <new>
+#include <queue>
+#include <utility>
+#include <vector>
+
+#include "api_common.h"
+
+using namespace osk::api;
+
+struct os_gram_plan {
+    struct Prob {
+        os_sketch sk;
+        const float* A;
+        int64_t lda;
+        const float* d;
+        int64_t m;
+        int64_t n;
+        float* H;
+        int64_t ldh;
+        std::vector<uint8_t> keep;   // N+e flags
+        int32_t K;                   // kept (= stored) blocks
+        int32_t bp;
+        int64_t ld;                  // sketch leading dimension: K * bp
+        size_t prep_off;
+        size_t prep_bytes;
+        size_t sketch_off;
+    };
+    std::vector<Prob> probs;
+    int full = 1;
+    size_t desc_off = 0;
+    size_t tiles_off = 0;
+    size_t starts_off = 0;
+    size_t total = 0;
+    int64_t max_tiles = 0;           // tile list capacity (the 128 tile side)
+    int32_t tile = 0;
+    int32_t grid = 0;
+    const void* ws = nullptr;        // workspace of the last configuration
+};
+
+namespace {
+
+constexpr int32_t kMaxGrid = 65536;
+// Longest tile list (tile side 128) a plan accepts.
+constexpr int64_t kMaxTiles = int64_t(1) << 24;
+// Cost of a tile's epilogue in K steps (one more for a mirrored tile).
+constexpr int64_t kEpilogueCost = 2;
+
+int64_t tiles_of(int64_t m, int tile) {
+    const int64_t t = (m + tile - 1) / tile;
+    return t * (t + 1) / 2;
+}
+
+os_status check_problem(const os_gram_problem& p) {
+    os_status st = check_sketch(&p.sk);
+    if (st != OS_OK) return st;
+    if ((st = check_len(p.n)) != OS_OK) return st;
+    if ((st = check_extent(p.m)) != OS_OK) return st;
+    if ((st = check_matrix(p.A, p.m, p.n, p.lda, false)) != OS_OK) return st;
+    if ((st = check_matrix(p.H, p.m, p.m, p.ldh, false)) != OS_OK) return st;
+    if (p.d && !aligned(p.d, 4)) return OS_EALIGN;
+    return OS_OK;
+}
+
+// Default number of persistent workgroups: as many as are resident at once.
+int32_t default_grid(int tile) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const int per_cu = osk::batch_sym_blocks_per_cu(tile);
+    return (int32_t)std::min<int64_t>((int64_t)cus * std::max(per_cu, 1), kMaxGrid);
+}
+
+os_status check_ws(const os_gram_plan* plan, const void* ws, size_t ws_bytes) {
+    if (!ws) return OS_ENULL;
+    if (!aligned(ws, 256)) return OS_EALIGN;
+    if (ws_bytes < plan->total) return OS_EWORKSPACE;
+    return OS_OK;
+}
+
+char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+os_status enqueue(const os_gram_plan* plan, int stages, void* ws, hipStream_t s) {
+    if (stages & (OS_GRAM_PREPARE | OS_GRAM_SKETCH)) {
+        for (const auto& p : plan->probs) {
+            void* prep = at(ws, p.prep_off);
+            if (stages & OS_GRAM_PREPARE) {
+                const os_status st = prepare(&p.sk, p.n, prep, s);
+                if (st != OS_OK) return st;
+            }
+            if (!(stages & OS_GRAM_SKETCH)) continue;
+            Blocks bs;
+            const os_status st = block_sets(&p.sk, p.keep.data(), 1, bs);
+            if (st != OS_OK) return st;
+            const hipError_t e = osk::launch_sketch_cols(
+                p.A, p.m, p.n, p.lda, bs.stored, bs.nst, nblocks(&p.sk), p.bp,
+                prep_lists(prep, &p.sk, p.n), reinterpret_cast<float*>(at(ws, p.sketch_off)),
+                p.ld, s, p.d);
+            if (e != hipSuccess) return hip_status(e);
+        }
+    }
+    if (!(stages & OS_GRAM_PRODUCT)) return OS_OK;
+    return hip_status(osk::launch_gemm_batch_sym(
+        reinterpret_cast<const osk::BatchProblem*>(at(ws, plan->desc_off)),
+        reinterpret_cast<const int4*>(at(ws, plan->tiles_off)),
+        reinterpret_cast<const int32_t*>(at(ws, plan->starts_off)), plan->tile, plan->full,
+        plan->grid, s));
+}
+
+os_status check_run(const os_gram_plan* plan, int stages, void* ws, size_t ws_bytes) {
+    if (!plan) return OS_ENULL;
+    if (stages < 1 || stages > OS_GRAM_ALL) return OS_EINVAL;
+    const os_status st = check_ws(plan, ws, ws_bytes);
+    if (st != OS_OK) return st;
+    if (plan->tile == 0 || plan->ws != ws) return OS_EINVAL;   // not configured for ws
+    return OS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+os_status os_gram_plan_create(const os_gram_problem* probs, int32_t count, int full,
+                              os_gram_plan** plan_out) {
+    if (!plan_out) return OS_ENULL;
+    *plan_out = nullptr;
+    if (!probs) return OS_ENULL;
+    if (count < 1 || count > OS_GRAM_MAX_PROBLEMS) return OS_EINVAL;
+    os_gram_plan* plan = new (std::nothrow) os_gram_plan;
+    if (!plan) return OS_EINVAL;
+    os_status st = OS_OK;
+    try {
+        plan->full = full != 0;
+        plan->probs.resize((size_t)count);
+        size_t off = align256((size_t)count * sizeof(osk::BatchProblem));
+        plan->desc_off = 0;
+        int64_t ntiles = 0;
+        for (int32_t k = 0; k < count && st == OS_OK; ++k) {
+            const os_gram_problem& p = probs[k];
+            if ((st = check_problem(p)) != OS_OK) break;
+            Blocks bs;
+            if ((st = block_sets(&p.sk, p.keep, 1, bs)) != OS_OK) break;
+            auto& q = plan->probs[(size_t)k];
+            q.sk = p.sk;
+            q.A = p.A;
+            q.lda = p.lda;
+            q.d = p.d;
+            q.m = p.m;
+            q.n = p.n;
+            q.H = p.H;
+            q.ldh = p.ldh;
+            q.keep.resize((size_t)nblocks(&p.sk));
+            bool kept[OS_MAX_BLOCKS];
+            kept_flags(&p.sk, p.keep, kept);
+            for (int32_t i = 0; i < nblocks(&p.sk); ++i) q.keep[(size_t)i] = kept[i] ? 1 : 0;
+            q.K = bs.nst;
+            q.bp = os_block_stride(p.sk.b);
+            q.ld = (int64_t)q.K * q.bp;
+            if (!osk::plan_sketch_ok(p.m, q.K, q.bp, p.n) ||
+                !osk::plan_gemm_ok(p.m, p.m, q.bp, q.ld, q.ld, 4)) {
+                st = OS_EINVAL;
+                break;
+            }
+            ntiles += tiles_of(p.m, 128);
+            if (ntiles > kMaxTiles) {
+                st = OS_EINVAL;
+                break;
+            }
+        }
+        if (st == OS_OK) {
+            plan->max_tiles = ntiles;
+            plan->tiles_off = off;
+            off += align256((size_t)ntiles * sizeof(int4));
+            plan->starts_off = off;
+            off += align256((size_t)(kMaxGrid + 1) * sizeof(int32_t));
+            for (auto& q : plan->probs) {
+                q.prep_off = off;
+                q.prep_bytes = prepare_bytes(&q.sk, q.n);
+                off += align256(q.prep_bytes);
+                q.sketch_off = off;
+                off += align256((size_t)q.m * (size_t)q.ld * sizeof(float));
+            }
+            plan->total = off;
+        }
+    } catch (...) {
+        st = OS_EINVAL;
+    }
+    if (st != OS_OK) {
+        delete plan;
+        return st;
+    }
+    *plan_out = plan;
+    return OS_OK;
+}
+
+void os_gram_plan_destroy(os_gram_plan* plan) { delete plan; }
+
+size_t os_gram_workspace_bytes(const os_gram_plan* plan) { return plan ? plan->total : 0; }
+
+void os_gram_config(const os_gram_plan* plan, int32_t* tile, int32_t* grid) {
+    if (tile) *tile = plan ? plan->tile : 0;
+    if (grid) *grid = plan ? plan->grid : 0;
+}
+
+os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void* workspace,
+                            size_t ws_bytes, void* stream) {
+    if (!plan) return OS_ENULL;
+    if (tile == 0) tile = 256;
+    if ((tile != 128 && tile != 256) || grid < 0 || grid > kMaxGrid) return OS_EINVAL;
+    os_status st = check_ws(plan, workspace, ws_bytes);
+    if (st != OS_OK) return st;
+    if (grid == 0 && (grid = default_grid(tile)) < 1) return hip_status(hipErrorInvalidDevice);
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        const size_t count = plan->probs.size();
+        std::vector<osk::BatchProblem> desc(count);
+        // (cost, problem, tile row, tile col), in problem and tile order
+        struct Item {
+            int64_t cost;
+            int32_t prob, ti, tj;
+        };
+        std::vector<Item> items;
+        items.reserve((size_t)plan->max_tiles);
+        for (size_t k = 0; k < count; ++k) {
+            const auto& q = plan->probs[k];
+            osk::BatchProblem& bp = desc[k];
+            bp.S = reinterpret_cast<const float*>(at(workspace, q.sketch_off));
+            bp.H = q.H;
+            bp.ld = q.ld;
+            bp.ldh = q.ldh;
+            bp.m = q.m;
+            bp.ksteps = (int32_t)(q.ld / osk::kBlockAlign);
+            bp.scale = 1.0f / (float)q.K;
+            const int32_t T = (int32_t)((q.m + tile - 1) / tile);
+            for (int32_t i = 0; i < T; ++i)
+                for (int32_t j = i; j < T; ++j)
+                    items.push_back({bp.ksteps + kEpilogueCost * (1 + (plan->full && i != j)),
+                                     (int32_t)k, i, j});
+        }
+        std::stable_sort(items.begin(), items.end(),
+                         [](const Item& a, const Item& b) { return a.cost > b.cost; });
+        // longest-processing-time-first: each tile to the least-loaded workgroup
+        using Load = std::pair<int64_t, int32_t>;
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+        for (int32_t g = 0; g < grid; ++g) heap.push({0, g});
+        std::vector<int32_t> owner(items.size());
+        std::vector<int32_t> starts((size_t)grid + 1, 0);
+        for (size_t t = 0; t < items.size(); ++t) {
+            Load l = heap.top();
+            heap.pop();
+            owner[t] = l.second;
+            ++starts[(size_t)l.second + 1];
+            heap.push({l.first + items[t].cost, l.second});
+        }
+        for (int32_t g = 0; g < grid; ++g) starts[(size_t)g + 1] += starts[(size_t)g];
+        std::vector<int4> tiles(items.size());
+        std::vector<int32_t> fill(starts.begin(), starts.end() - 1);
+        for (size_t t = 0; t < items.size(); ++t)
+            tiles[(size_t)fill[(size_t)owner[t]]++] =
+                make_int4(items[t].prob, items[t].ti, items[t].tj, 0);
+        hipError_t e = hipMemcpyAsync(at(workspace, plan->desc_off), desc.data(),
+                                      desc.size() * sizeof(osk::BatchProblem),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(at(workspace, plan->tiles_off), tiles.data(),
+                               tiles.size() * sizeof(int4), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(at(workspace, plan->starts_off), starts.data(),
+                               starts.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e);
+    } catch (...) {
+        return OS_EINVAL;
+    }
+    plan->tile = tile;
+    plan->grid = grid;
+    plan->ws = workspace;
+    return OS_OK;
+}
+
+os_status os_gram_run(const os_gram_plan* plan, int stages, void* workspace, size_t ws_bytes,
+                      void* stream) {
+    const os_status st = check_run(plan, stages, workspace, ws_bytes);
+    if (st != OS_OK) return st;
+    return enqueue(plan, stages, workspace, (hipStream_t)stream);
+}
+
+os_status os_gram_autotune(os_gram_plan* plan, int32_t reps, void* workspace, size_t ws_bytes,
+                           void* stream, float* best_ms) {
+    if (!plan) return OS_ENULL;
+    if (reps < 1) return OS_EINVAL;
+    os_status st = check_ws(plan, workspace, ws_bytes);
+    if (st != OS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e != hipSuccess) {
+        if (t0) (void)hipEventDestroy(t0);
+        return hip_status(e);
+    }
+    const int32_t cand[2] = {256, 128};
+    int32_t best_tile = 0;
+    float best = 0.f;
+    for (int32_t c = 0; c < 2 && st == OS_OK; ++c) {
+        if ((st = os_gram_configure(plan, cand[c], 0, workspace, ws_bytes, stream)) != OS_OK) break;
+        if ((st = enqueue(plan, OS_GRAM_ALL, workspace, s)) != OS_OK) break;   // warm-up
+        if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
+        for (int32_t r = 0; r < reps && st == OS_OK; ++r)
+            st = enqueue(plan, OS_GRAM_ALL, workspace, s);
+        if (st != OS_OK) break;
+        float ms = 0.f;
+        if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
+            break;
+        ms /= (float)reps;
+        if (best_tile == 0 || ms < best) {
+            best = ms;
+            best_tile = cand[c];
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return hip_status(e);
+    if (st != OS_OK) return st;
+    if ((st = os_gram_configure(plan, best_tile, 0, workspace, ws_bytes, stream)) != OS_OK)
+        return st;
+    if (best_ms) *best_ms = best;
+    return OS_OK;
+}
+
+os_status os_gram_graph_create(const os_gram_plan* plan, int stages, void* workspace,
+                               size_t ws_bytes, void* stream, void** graph_out) {
+    if (!graph_out) return OS_ENULL;
+    *graph_out = nullptr;
+    os_status st = check_run(plan, stages, workspace, ws_bytes);
+    if (st != OS_OK) return st;
+    if (!stream) return OS_EINVAL;      // the NULL stream cannot be captured
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_status(e);
+    st = enqueue(plan, stages, workspace, s);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (st != OS_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st != OS_OK ? st : hip_status(e);
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_status(e);
+    *graph_out = exec;
+    return OS_OK;
+}
+
+os_status os_graph_launch(void* graph, void* stream) {
+    if (!graph) return OS_ENULL;
+    return hip_status(hipGraphLaunch((hipGraphExec_t)graph, (hipStream_t)stream));
+}
+
+void os_graph_destroy(void* graph) {
+    if (graph) (void)hipGraphExecDestroy((hipGraphExec_t)graph);
+}
+
+}  // extern "C"

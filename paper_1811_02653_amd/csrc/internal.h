@@ -52,10 +52,12 @@ bool plan_sketch_ok(int64_t lines, int32_t nst, int32_t bp, int64_t n);
 hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                               const void* lists, float* out, int64_t ldo, hipStream_t s);
-// out (rows x nst*bp, ld ldo) = X S for X rows x n row-major (ld ldx).
+// out (rows x nst*bp, ld ldo) = X S for X rows x n row-major (ld ldx);
+// with wd (DEVICE [n]) it is X diag(sqrt(wd)) S.
 hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
-                              const void* lists, float* out, int64_t ldo, hipStream_t s);
+                              const void* lists, float* out, int64_t ldo, hipStream_t s,
+                              const float* wd = nullptr);
 
 // Longest row pitch (bytes) of a sketch read by the block product: byte
 // offsets within a 256-row tile, K offset included, stay below 2^32.
@@ -87,12 +89,6 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
                                  int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                                  int32_t nkept, int split, int64_t lo_off, float scale, float* C,
                                  int64_t ldc, hipStream_t s);
-// FP32 block product with a keep mask per C block: cmask DEVICE [ceil(m/cblk)]
-// [ceil(l/cblk)][nst]; block (I, J) of C (cblk x cblk) = (1/K_IJ) * sum of its
-// kept blocks' products (zero when it keeps none).
-hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
-                             int64_t m, int64_t l, int32_t bp, int32_t nst, const uint8_t* cmask,
-                             int64_t cblk, float* C, int64_t ldc, hipStream_t s);
 // The same with FP8 copies (launch_quant_fp8 layout: ld in bytes, the scale
 // bytes of a row `scales` bytes after its start; block stride bp a multiple
 // of 128).
@@ -100,26 +96,36 @@ hipError_t launch_gemm_kept_fp8(const void* At, int64_t ldat, const void* Bt, in
                                 int64_t scales, int64_t m, int64_t l, int32_t bp,
                                 const BlockList& kept, int32_t nkept, int split, int64_t lo_off,
                                 float scale, float* C, int64_t ldc, hipStream_t s);
-// The same with BF16 sketches (block stride bp, a multiple of 64; leading
-// dimensions in BF16 values).  split != 0 adds the terms A_j * lo(B_j)^T and
-// lo(A_j) * B_j^T, the low parts lo_off columns after the high parts.
-hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
-                                 int64_t m, int64_t l, int32_t bp, const BlockList& kept,
-                                 int32_t nkept, int split, int64_t lo_off, float scale, float* C,
-                                 int64_t ldc, hipStream_t s);
 // FP32 block product with a keep mask per C block: cmask DEVICE [ceil(m/cblk)]
 // [ceil(l/cblk)][nst]; block (I, J) of C (cblk x cblk) = (1/K_IJ) * sum of its
 // kept blocks' products (zero when it keeps none).
 hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
                              int64_t m, int64_t l, int32_t bp, int32_t nst, const uint8_t* cmask,
                              int64_t cblk, float* C, int64_t ldc, hipStream_t s);
-// The same with FP8 copies (launch_quant_fp8 layout: ld in bytes, the scale
-// bytes of a row `scales` bytes after its start; block stride bp a multiple
-// of 128).
-hipError_t launch_gemm_kept_fp8(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
-                                int64_t scales, int64_t m, int64_t l, int32_t bp,
-                                const BlockList& kept, int32_t nkept, int split, int64_t lo_off,
-                                float scale, float* C, int64_t ldc, hipStream_t s);
+
+// One problem of a batched symmetric block product (device-resident): the
+// sketch S stores only the kept blocks, so its first ksteps * 32 columns
+// (ksteps = K * bp / 32) are summed over.
+struct BatchProblem {
+    const float* S;      // line-major sketch, m x (K*bp), ld (floats, multiple of 4)
+    float* H;            // output m x m, ld ldh
+    int64_t ld;
+    int64_t ldh;
+    int64_t m;
+    int32_t ksteps;
+    float scale;         // 1 / K
+};
+// H_k = scale_k * S_k S_k^T for every problem in one persistent launch:
+// tiles DEVICE int4 {problem, tile row, tile col >= tile row, 0} for tile
+// side `tile` (256 or 128), grouped by workgroup: workgroup g computes tiles
+// starts[g] .. starts[g+1] - 1 (starts DEVICE [grid + 1]).  full != 0 also
+// writes the mirror of each off-diagonal tile.
+hipError_t launch_gemm_batch_sym(const BatchProblem* probs, const int4* tiles,
+                                 const int32_t* starts, int tile, int full, int32_t grid,
+                                 hipStream_t s);
+// Workgroups of the batched kernel with tile side `tile` that fit on one CU
+// at once (0 on error).
+int batch_sym_blocks_per_cu(int tile);
 
 // BF16 copy of a line-major FP32 sketch (lines x nst*bp, ld lds): block
 // stride block_stride_bf16(b) = b rounded up to 64, the residual part (when

@@ -159,10 +159,13 @@ __global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restric
 //                      vec (X 16-byte aligned, ldx % 4 == 0), else four.
 // Window position k of the staged window is handled by thread k % 512.
 // ---------------------------------------------------------------------------
-template <bool kRowLines>
+// kWeighted: every value at sketched index k is first multiplied by
+// sqrt(wd[k]) (a diagonal weight, as in A D^{1/2} S for a Hessian A D A^T).
+template <bool kRowLines, bool kWeighted = false>
 __device__ __forceinline__ void load_window(float4 (&r)[kPerThread], const float* __restrict__ X,
                                             int64_t lines, int64_t ldx, int64_t line0,
-                                            int64_t k0, int kw, bool vec) {
+                                            int64_t k0, int kw, bool vec,
+                                            const float* __restrict__ wd = nullptr) {
     // Every load is unconditional (a branch around a load makes each use wait
     // for all loads in flight): positions past the window's end are clamped to
     // its last index (no entry refers to them) and lines past the matrix to
@@ -177,6 +180,13 @@ __device__ __forceinline__ void load_window(float4 (&r)[kPerThread], const float
         if constexpr (kRowLines) {
             const float* p = X + line0 * ldx + kk;
             r[u] = make_float4(p[0], p[l1 * ldx], p[l2 * ldx], p[l3 * ldx]);
+            if constexpr (kWeighted) {
+                const float sw = sqrtf(wd[kk]);
+                r[u].x *= sw;
+                r[u].y *= sw;
+                r[u].z *= sw;
+                r[u].w *= sw;
+            }
         } else {
             const float* p = X + kk * ldx + line0;
             if (vec && l3 == 3)      // uniform
@@ -215,13 +225,13 @@ __device__ __forceinline__ void add_chunk(float4& acc, const float4* __restrict_
 
 // One workgroup of 8 waves fills a CU's LDS, so each SIMD runs 2 waves: the
 // compiler may use up to 256 VGPRs per lane.
-template <int kSlots, bool kRowLines>
+template <int kSlots, bool kRowLines, bool kWeighted>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void sketch_kernel(
     const float* __restrict__ X, int64_t lines, int64_t n, int64_t ldx, int vec, int32_t bp,
     int32_t qn, int32_t nwin, int32_t nst, BlockList bl, int64_t RC,
     const uint32_t* __restrict__ hdr, const uint4* __restrict__ ell, float* __restrict__ out,
-    int64_t ldo, int32_t npass) {
+    int64_t ldo, int32_t npass, const float* __restrict__ wd) {
     __shared__ float4 win[kWin + 1];    // row kWin stays zero
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -238,7 +248,8 @@ void sketch_kernel(
     if (tid == 0) win[kWin] = make_float4(0.f, 0.f, 0.f, 0.f);
 
     float4 pre[kPerThread];
-    load_window<kRowLines>(pre, X, lines, ldx, line0, 0, (int)min((int64_t)kWin, n), vec);
+    load_window<kRowLines, kWeighted>(pre, X, lines, ldx, line0, 0, (int)min((int64_t)kWin, n), vec,
+                                      wd);
     for (int w = 0; w < nwin; ++w) {
         __syncthreads();                 // the previous window is no longer read
 #pragma unroll
@@ -246,8 +257,8 @@ void sketch_kernel(
         __syncthreads();
         if (w + 1 < nwin) {
             const int64_t k1 = (int64_t)(w + 1) * kWin;
-            load_window<kRowLines>(pre, X, lines, ldx, line0, k1, (int)min((int64_t)kWin, n - k1),
-                                   vec);
+            load_window<kRowLines, kWeighted>(pre, X, lines, ldx, line0, k1,
+                                              (int)min((int64_t)kWin, n - k1), vec, wd);
         }
         // The list chunks of slot s + 1 (up to kAhead of them) are fetched
         // while slot s is summed.  Fetches are unconditional: chunk indices
@@ -313,25 +324,26 @@ void sketch_kernel(
 // Slot counts compiled: 1, 2, 4, 8, 12, 16, 20, 24 (4 registers per slot).
 constexpr int kMaxSlots = 24;
 
-template <int S, bool R>
+template <int S, bool R, bool W>
 hipError_t launch_one(dim3 grid, hipStream_t st, const float* X, int64_t lines, int64_t n,
                       int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin, int32_t nst,
                       const BlockList& bl, int64_t RC, const uint32_t* hdr, const uint4* ell,
-                      float* out, int64_t ldo, int32_t npass) {
-    hipLaunchKernelGGL((sketch_kernel<S, R>), grid, dim3(kThreads), 0, st, X, lines, n,
-                       ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass);
+                      float* out, int64_t ldo, int32_t npass, const float* wd) {
+    hipLaunchKernelGGL((sketch_kernel<S, R, W>), grid, dim3(kThreads), 0, st, X, lines, n, ldx, vec,
+                       bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass, wd);
     return hipGetLastError();
 }
 
-template <bool R>
+template <bool R, bool W>
 hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const float* X, int64_t lines,
                         int64_t n, int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin,
                         int32_t nst, const BlockList& bl, int64_t RC, const uint32_t* hdr,
-                        const uint4* ell, float* out, int64_t ldo, int32_t npass) {
-#define OSK_SLOT_CASE(S)                                                                     \
-    if (slots <= S)                                                                          \
-        return launch_one<S, R>(grid, st, X, lines, n, ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, \
-                                ell, out, ldo, npass);
+                        const uint4* ell, float* out, int64_t ldo, int32_t npass,
+                        const float* wd) {
+#define OSK_SLOT_CASE(S)                                                                        \
+    if (slots <= S)                                                                             \
+        return launch_one<S, R, W>(grid, st, X, lines, n, ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, \
+                                   ell, out, ldo, npass, wd);
     OSK_SLOT_CASE(1)
     OSK_SLOT_CASE(2)
     OSK_SLOT_CASE(4)
@@ -462,7 +474,8 @@ void pass_plan(int32_t nst, int32_t qn, int32_t* npass, int32_t* slots) {
 
 hipError_t launch_sketch(bool row_lines, const float* X, int64_t lines, int64_t n, int64_t ldx,
                          const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
-                         const void* lists, float* out, int64_t ldo, hipStream_t s) {
+                         const void* lists, float* out, int64_t ldo, hipStream_t s,
+                         const float* wd = nullptr) {
     const Plan p = plan_of(n, bp);
     const ListView v = carve_lists(const_cast<void*>(lists), nblk, n, bp);
     int32_t npass, slots;
@@ -470,11 +483,14 @@ hipError_t launch_sketch(bool row_lines, const float* X, int64_t lines, int64_t 
     const int64_t groups = (lines + kLines - 1) / kLines;
     const dim3 grid((unsigned)(groups * npass));
     const int vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (ldx & 3) == 0;
+    if (wd && row_lines)   // weighted sketches are only taken along rows
+        return launch_slots<true, true>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin,
+                                        nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, wd);
     if (row_lines)
-        return launch_slots<true>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin, nst, bl,
-                                  p.RC, v.hdr, v.ell, out, ldo, npass);
-    return launch_slots<false>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin, nst, bl,
-                               p.RC, v.hdr, v.ell, out, ldo, npass);
+        return launch_slots<true, false>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin,
+                                         nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, nullptr);
+    return launch_slots<false, false>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin, nst,
+                                      bl, p.RC, v.hdr, v.ell, out, ldo, npass, nullptr);
 }
 
 }  // namespace
@@ -542,9 +558,10 @@ hipError_t launch_transpose_bf16(const void* X, int64_t rows, int64_t cols, int6
 
 hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
-                              const void* lists, float* out, int64_t ldo, hipStream_t s) {
+                              const void* lists, float* out, int64_t ldo, hipStream_t s,
+                              const float* wd) {
     if (!plan_sketch_ok(rows, nst, bp, n)) return hipErrorInvalidValue;
-    return launch_sketch(true, X, rows, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s);
+    return launch_sketch(true, X, rows, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s, wd);
 }
 
 }  // namespace osk

@@ -124,3 +124,31 @@ def hessian_batch(count: int, seed: int, m_lo: int = 500, m_hi: int = 4000, rati
         dk = np.exp(rng.uniform(np.log(1e-6), np.log(1e6), size=ratio * mk)).astype(np.float32)
         out.append((Ak, dk))
     return out
+
+
+def hessian_sizes(count: int, seed: int, m_lo: int = 500, m_hi: int = 4000) -> list:
+    """m_k uniform in [m_lo, m_hi] for the device-generated Hessian batch
+    (drawn from ``default_rng([seed, 2])``)."""
+    rng = np.random.default_rng([int(seed), 2])
+    return [int(v) for v in rng.integers(m_lo, m_hi + 1, size=count)]
+
+
+def hessian_batch_device(count: int, seed: int, device="cuda", ratio: int = 20,
+                         m_lo: int = 500, m_hi: int = 4000):
+    """The interior-point Hessian batch drawn on the device (too large to
+    draw on the host at full size): sizes from ``hessian_sizes``, then per
+    problem A_k (m_k x ratio*m_k) i.i.d. N(0,1) and d_k log-uniform in
+    [1e-6, 1e6], both from torch's device generator seeded with ``seed``.
+    Returns (sizes, [A_k], [d_k])."""
+    import torch
+    sizes = hessian_sizes(count, seed, m_lo, m_hi)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    lo, hi = np.log(1e-6), np.log(1e6)
+    As, ds = [], []
+    for m in sizes:
+        n = ratio * m
+        As.append(torch.randn((m, n), generator=gen, device=device, dtype=torch.float32))
+        u = torch.rand(n, generator=gen, device=device, dtype=torch.float64)
+        ds.append(torch.exp(lo + u * (hi - lo)).to(torch.float32))
+    return sizes, As, ds

@@ -193,3 +193,89 @@ def test_binding_refuses_host_tensors():
     A = torch.zeros(4, 16)
     with pytest.raises(osk.OversketchError):
         osk.matmul(A, torch.zeros(16, 4), b=4, N=2, e=0)
+
+
+# ---------------------------------------------------------------------------
+# batched Gram plans (host-only: plan creation validates without the GPU)
+# ---------------------------------------------------------------------------
+
+def _gram(m=300, n=6000, b=150, N=6, e=1, A=FAKE, d=None, keep=None, H=FAKE, lda=None, ldh=None):
+    p = osk._GramProblem()
+    p.sk = _sk(b=b, N=N, e=e)
+    p.A, p.lda = A, (n if lda is None else lda)
+    p.d = d
+    p.m, p.n = m, n
+    p.keep = keep
+    p.H, p.ldh = H, (m if ldh is None else ldh)
+    return p
+
+
+def _create(L, probs, full=1):
+    arr = (osk._GramProblem * max(len(probs), 1))(*probs)
+    h = ctypes.c_void_p()
+    st = L.os_gram_plan_create(arr, len(probs), full, ctypes.byref(h))
+    return st, h
+
+
+def test_gram_plan_rejects_bad_problems(L):
+    none = np.zeros(7, dtype=np.uint8)
+    cases = [
+        ([], OS_EINVAL),
+        ([_gram(b=0)], OS_EINVAL),
+        ([_gram(m=0)], OS_EINVAL),
+        ([_gram(A=None)], OS_ENULL),
+        ([_gram(H=None)], OS_ENULL),
+        ([_gram(A=ctypes.c_void_p((1 << 20) + 2))], OS_EALIGN),
+        ([_gram(d=ctypes.c_void_p((1 << 20) + 1))], OS_EALIGN),
+        ([_gram(lda=10)], OS_EINVAL),
+        ([_gram(ldh=10)], OS_EINVAL),
+        ([_gram(), _gram(keep=none.ctypes.data_as(ctypes.c_void_p))], OS_ENOKEEP),
+    ]
+    for probs, want in cases:
+        st, h = _create(L, probs)
+        assert st == want, (probs, st)
+        assert not h.value
+    h = ctypes.c_void_p(123)
+    assert L.os_gram_plan_create(None, 1, 1, ctypes.byref(h)) == OS_ENULL and not h.value
+    arr = (osk._GramProblem * 1)(_gram())
+    assert L.os_gram_plan_create(arr, 1, 1, None) == OS_ENULL
+    L.os_gram_plan_destroy(None)
+    L.os_graph_destroy(None)
+    assert L.os_graph_launch(None, None) == OS_ENULL
+
+
+def test_gram_workspace_and_unconfigured_plan(L):
+    st, h1 = _create(L, [_gram()])
+    assert st == OS_OK and h1.value
+    st, h2 = _create(L, [_gram(), _gram(m=1000, n=20000, b=500)])
+    assert st == OS_OK
+    w1, w2 = L.os_gram_workspace_bytes(h1), L.os_gram_workspace_bytes(h2)
+    assert w1 % 256 == 0 and w2 % 256 == 0
+    # at least the prepared sketch and the kept-block sketch (m x K*bp FP32)
+    s = _sk(b=150, N=6, e=1)
+    assert w1 >= L.os_sketch_prepare_bytes(ctypes.byref(s), 6000) + 300 * 6 * 160 * 4
+    s2 = _sk(b=500, N=6, e=1)
+    assert w2 - w1 >= L.os_sketch_prepare_bytes(ctypes.byref(s2), 20000) + 1000 * 6 * 512 * 4
+    assert L.os_gram_workspace_bytes(None) == 0
+    t, g = ctypes.c_int32(7), ctypes.c_int32(7)
+    L.os_gram_config(h1, ctypes.byref(t), ctypes.byref(g))
+    assert (t.value, g.value) == (0, 0)
+    ws = ctypes.c_void_p(1 << 30)
+    # not configured yet, or workspace too small / misaligned / NULL
+    assert L.os_gram_run(h1, 7, ws, w1, None) == OS_EINVAL
+    assert L.os_gram_run(h1, 7, ws, w1 - 1, None) == OS_EWORKSPACE
+    assert L.os_gram_run(h1, 7, ctypes.c_void_p((1 << 30) + 64), w1, None) == OS_EALIGN
+    assert L.os_gram_run(h1, 7, None, w1, None) == OS_ENULL
+    assert L.os_gram_run(None, 7, ws, w1, None) == OS_ENULL
+    assert L.os_gram_run(h1, 0, ws, w1, None) == OS_EINVAL        # no stage
+    assert L.os_gram_run(h1, 8, ws, w1, None) == OS_EINVAL
+    # bad tile or grid fails before any device query
+    assert L.os_gram_configure(h1, 64, 0, ws, w1, None) == OS_EINVAL
+    assert L.os_gram_configure(h1, 256, -1, ws, w1, None) == OS_EINVAL
+    assert L.os_gram_configure(h1, 256, 1 << 20, ws, w1, None) == OS_EINVAL
+    assert L.os_gram_autotune(h1, 0, ws, w1, None, None) == OS_EINVAL
+    g = ctypes.c_void_p(5)
+    assert L.os_gram_graph_create(h1, 7, ws, w1, ctypes.c_void_p(1), ctypes.byref(g)) == OS_EINVAL
+    assert not g.value
+    L.os_gram_plan_destroy(h1)
+    L.os_gram_plan_destroy(h2)

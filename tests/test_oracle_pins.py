@@ -583,3 +583,88 @@ def test_fp8_block_quantize_error_bound():
     hi, lo = oracle.fp8_split(x)
     assert np.array_equal(hi, q)
     assert np.mean(np.abs(x - hi - lo)) < np.mean(np.abs(x - hi)) / 8
+
+
+# ---------------------------------------------------------------------------
+# Sketched Hessian / Gram matrix (Section 5.2, Eq. (int_point) and the
+# Hessian after it): H = (1/K) sum_i (A D^{1/2} S_i)(A D^{1/2} S_i)^T
+# ---------------------------------------------------------------------------
+
+def _log_uniform(rng, n, lo=1e-6, hi=1e6):
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), size=n))
+
+
+@pytest.mark.parametrize("N,e", [(1, 0), (2, 1)])
+def test_gram_with_permutation_sketch_is_the_hessian(N, e):
+    # b = n and permutations h_i: S_i S_i^T = I, so H = A D A^T exactly (the
+    # weights enter as D, i.e. D^{1/2} on each side).
+    m, n = 7, 24
+    rng = np.random.default_rng(40)
+    A = rng.standard_normal((m, n))
+    d = _log_uniform(rng, n)
+    h = np.stack([rng.permutation(n) for _ in range(N + e)]).astype(np.int32)
+    s = rng.choice(np.array([-1, 1], dtype=np.int8), size=(N + e, n))
+    H = oracle.sketched_gram(A, d, n, N, e, keep=oracle.default_keep(N, e), h=h, sigma=s)
+    ref = (A * d[None, :]) @ A.T
+    np.testing.assert_allclose(H, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+
+
+def test_gram_zero_weights_remove_their_indices():
+    # d_k = 0 removes index k from the sum: equal to the problem without
+    # those columns (and without their bucket/sign entries), bit for bit.
+    m, n, b, N, e = 5, 40, 6, 3, 1
+    rng = np.random.default_rng(41)
+    A = rng.standard_normal((m, n))
+    d = _log_uniform(rng, n)
+    drop = np.zeros(n, bool)
+    drop[rng.choice(n, 13, replace=False)] = True
+    d0 = d.copy()
+    d0[drop] = 0.0
+    h, s = oracle.hash_tables(77, N + e, n, b)
+    keep = synthetic.random_keep(N, e, 5)
+    H = oracle.sketched_gram(A, d0, b, N, e, keep=keep, h=h, sigma=s)
+    Hr = oracle.sketched_gram(A[:, ~drop], d[~drop], b, N, e, keep=keep,
+                              h=np.ascontiguousarray(h[:, ~drop]),
+                              sigma=np.ascontiguousarray(s[:, ~drop]))
+    assert np.array_equal(H, Hr)
+
+
+def test_gram_brute_force_dense_sketch():
+    # tiny case against the dense definition with S = N^{-1/2}(S_1 .. S_{N+e})
+    m, n, b, N, e = 4, 11, 3, 2, 1
+    rng = np.random.default_rng(42)
+    A = rng.standard_normal((m, n))
+    d = _log_uniform(rng, n, 1e-2, 1e2)
+    h, s = oracle.hash_tables(9, N + e, n, b)
+    keep = np.array([1, 0, 1], np.uint8)
+    H = oracle.sketched_gram(A, d, b, N, e, keep=keep, h=h, sigma=s)
+    W = A * np.sqrt(d)[None, :]
+    S = np.zeros((n, (N + e) * b))
+    for i in range(N + e):
+        for k in range(n):
+            S[k, i * b + h[i, k]] = s[i, k]
+    cols = [i * b + c for i in range(N + e) if keep[i] for c in range(b)]
+    SK = S[:, cols]
+    ref = (W @ SK) @ (W @ SK).T / keep.sum()
+    np.testing.assert_allclose(H, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_gram_is_symmetric_psd_and_unbiased():
+    # symmetric positive semidefinite for every draw; its mean over
+    # independent hash seeds tends to A D A^T (E[S_i S_i^T] = I), within a
+    # few standard errors of the empirical spread.
+    m, n, b, N, e, T = 5, 48, 8, 2, 0, 400
+    rng = np.random.default_rng(43)
+    A = rng.standard_normal((m, n))
+    d = _log_uniform(rng, n, 1e-1, 1e1)
+    ref = (A * d[None, :]) @ A.T
+    Hs = np.stack([oracle.sketched_gram(A, d, b, N, e, seed=1000 + t) for t in range(T)])
+    for H in Hs[:20]:
+        assert np.array_equal(H, H.T)
+        assert np.linalg.eigvalsh(H).min() >= -1e-9 * np.abs(H).max()
+    mean = Hs.mean(axis=0)
+    se = Hs.std(axis=0, ddof=1) / np.sqrt(T)
+    z = np.abs(mean - ref) / np.maximum(se, 1e-12)
+    assert z.max() < 5.0, z.max()
+    # a missing square root (A D^2 A^T) or a missing 1/K would be far off
+    assert oracle.rel_frob(mean, ref) < 0.1
