@@ -3,9 +3,10 @@
 // Eq. (int_point) and the Hessian after it), H = (A D^{1/2} S)(A D^{1/2} S)^T
 // / K for a batch of problems of different sizes.
 //
-// Per problem the prepared sketch and the weighted sketch of A's rows (only
-// the kept blocks stored) go to the workspace; then one persistent launch
-// computes the upper-triangle tiles of every H.  Its schedule is made on the
+// The prepared sketches of all problems are built by one hash launch and one
+// list launch; per problem the weighted sketch of A's rows (only the kept
+// blocks stored) goes to the workspace; then one persistent launch computes
+// the upper-triangle tiles of every H.  Its schedule is made on the
 // host: tiles sorted by cost (the problem's K depth) and each given to the
 // least-loaded workgroup (longest-processing-time-first), stored grouped by
 // workgroup.
@@ -41,6 +42,10 @@ struct os_gram_plan {
     std::vector<Prob> probs;
     int full = 1;
     size_t desc_off = 0;
+    size_t prep_desc_off = 0;        // osk::PrepDesc per problem (batched prepare)
+    int64_t hash_tasks = 0;
+    int64_t list_tasks = 0;
+    int32_t max_bp = 0;
     size_t tiles_off = 0;
     size_t starts_off = 0;
     size_t total = 0;
@@ -48,6 +53,23 @@ struct os_gram_plan {
     int32_t tile = 0;
     int32_t grid = 0;
     const void* ws = nullptr;        // workspace of the last configuration
+    // The sketch step runs the problems on kLanes streams (the caller's and
+    // kLanes - 1 owned ones, default priority) joined by events, so small
+    // sketches overlap; lane[k] is problem k's stream index (balanced by
+    // bytes read).  Created by the first os_gram_configure.
+    static constexpr int kLanes = 4;
+    hipStream_t aux[kLanes - 1] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kLanes - 1] = {};
+    std::vector<int32_t> lane;
+
+    ~os_gram_plan() {
+        for (auto& a : aux)
+            if (a) (void)hipStreamDestroy(a);
+        for (auto& j : join)
+            if (j) (void)hipEventDestroy(j);
+        if (fork) (void)hipEventDestroy(fork);
+    }
 };
 
 namespace {
@@ -94,23 +116,38 @@ os_status check_ws(const os_gram_plan* plan, const void* ws, size_t ws_bytes) {
 char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
 os_status enqueue(const os_gram_plan* plan, int stages, void* ws, hipStream_t s) {
-    if (stages & (OS_GRAM_PREPARE | OS_GRAM_SKETCH)) {
-        for (const auto& p : plan->probs) {
-            void* prep = at(ws, p.prep_off);
-            if (stages & OS_GRAM_PREPARE) {
-                const os_status st = prepare(&p.sk, p.n, prep, s);
-                if (st != OS_OK) return st;
-            }
-            if (!(stages & OS_GRAM_SKETCH)) continue;
+    if (stages & OS_GRAM_PREPARE) {
+        const auto* descs = reinterpret_cast<const osk::PrepDesc*>(at(ws, plan->prep_desc_off));
+        const int32_t count = (int32_t)plan->probs.size();
+        hipError_t e = osk::launch_table_batch(descs, count, plan->hash_tasks, s);
+        if (e == hipSuccess)
+            e = osk::launch_lists_batch(descs, count, plan->list_tasks, plan->max_bp, s);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    if (stages & OS_GRAM_SKETCH) {
+        constexpr int L = os_gram_plan::kLanes;
+        hipStream_t lanes[L] = {s, plan->aux[0], plan->aux[1], plan->aux[2]};
+        hipError_t e = hipEventRecord(plan->fork, s);
+        for (int j = 1; j < L && e == hipSuccess; ++j) e = hipStreamWaitEvent(lanes[j], plan->fork, 0);
+        if (e != hipSuccess) return hip_status(e);
+        os_status st = OS_OK;
+        for (size_t k = 0; k < plan->probs.size() && st == OS_OK; ++k) {
+            const auto& p = plan->probs[k];
+            const void* prep = at(ws, p.prep_off);
             Blocks bs;
-            const os_status st = block_sets(&p.sk, p.keep.data(), 1, bs);
-            if (st != OS_OK) return st;
-            const hipError_t e = osk::launch_sketch_cols(
+            if ((st = block_sets(&p.sk, p.keep.data(), 1, bs)) != OS_OK) break;
+            st = hip_status(osk::launch_sketch_cols(
                 p.A, p.m, p.n, p.lda, bs.stored, bs.nst, nblocks(&p.sk), p.bp,
                 prep_lists(prep, &p.sk, p.n), reinterpret_cast<float*>(at(ws, p.sketch_off)),
-                p.ld, s, p.d);
-            if (e != hipSuccess) return hip_status(e);
+                p.ld, lanes[plan->lane[k]], p.d));
         }
+        // join every lane back into s, also after an error (a capture must end joined)
+        for (int j = 1; j < L; ++j) {
+            hipError_t ej = hipEventRecord(plan->join[j - 1], lanes[j]);
+            if (ej == hipSuccess) ej = hipStreamWaitEvent(s, plan->join[j - 1], 0);
+            if (ej != hipSuccess && st == OS_OK) st = hip_status(ej);
+        }
+        if (st != OS_OK) return st;
     }
     if (!(stages & OS_GRAM_PRODUCT)) return OS_OK;
     return hip_status(osk::launch_gemm_batch_sym(
@@ -147,6 +184,8 @@ os_status os_gram_plan_create(const os_gram_problem* probs, int32_t count, int f
         plan->probs.resize((size_t)count);
         size_t off = align256((size_t)count * sizeof(osk::BatchProblem));
         plan->desc_off = 0;
+        plan->prep_desc_off = off;
+        off += align256((size_t)count * sizeof(osk::PrepDesc));
         int64_t ntiles = 0;
         for (int32_t k = 0; k < count && st == OS_OK; ++k) {
             const os_gram_problem& p = probs[k];
@@ -187,6 +226,11 @@ os_status os_gram_plan_create(const os_gram_problem* probs, int32_t count, int f
             plan->starts_off = off;
             off += align256((size_t)(kMaxGrid + 1) * sizeof(int32_t));
             for (auto& q : plan->probs) {
+                const int64_t nt = table_stride(q.n);
+                plan->hash_tasks += (int64_t)nblocks(&q.sk) * ((nt + 255) / 256);
+                plan->list_tasks += (int64_t)nblocks(&q.sk) * ((q.n + osk::kSketchWindow - 1) /
+                                                                osk::kSketchWindow);
+                plan->max_bp = std::max(plan->max_bp, q.bp);
                 q.prep_off = off;
                 q.prep_bytes = prepare_bytes(&q.sk, q.n);
                 off += align256(q.prep_bytes);
@@ -194,6 +238,25 @@ os_status os_gram_plan_create(const os_gram_problem* probs, int32_t count, int f
                 off += align256((size_t)q.m * (size_t)q.ld * sizeof(float));
             }
             plan->total = off;
+            // lanes of the sketch step: largest problems first, each to the
+            // lane with the fewest bytes so far
+            std::vector<int32_t> order((size_t)count);
+            for (int32_t k = 0; k < count; ++k) order[(size_t)k] = k;
+            auto bytes = [&](int32_t k) {
+                const auto& q = plan->probs[(size_t)k];
+                return (double)q.m * (double)q.n;
+            };
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int32_t a, int32_t b) { return bytes(a) > bytes(b); });
+            double load[os_gram_plan::kLanes] = {};
+            plan->lane.assign((size_t)count, 0);
+            for (int32_t k : order) {
+                int j = 0;
+                for (int t = 1; t < os_gram_plan::kLanes; ++t)
+                    if (load[t] < load[j]) j = t;
+                plan->lane[(size_t)k] = j;
+                load[j] += bytes(k);
+            }
         }
     } catch (...) {
         st = OS_EINVAL;
@@ -224,9 +287,40 @@ os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void
     if (st != OS_OK) return st;
     if (grid == 0 && (grid = default_grid(tile)) < 1) return hip_status(hipErrorInvalidDevice);
     hipStream_t s = (hipStream_t)stream;
+    if (!plan->fork) {
+        hipError_t e = hipEventCreateWithFlags(&plan->fork, hipEventDisableTiming);
+        for (int j = 0; j < os_gram_plan::kLanes - 1 && e == hipSuccess; ++j) {
+            e = hipStreamCreateWithFlags(&plan->aux[j], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->join[j], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) return hip_status(e);
+    }
     try {
         const size_t count = plan->probs.size();
         std::vector<osk::BatchProblem> desc(count);
+        std::vector<osk::PrepDesc> prep(count);
+        int64_t hash_task0 = 0, list_task0 = 0;
+        for (size_t k = 0; k < count; ++k) {
+            const auto& q = plan->probs[k];
+            osk::PrepDesc& d = prep[k];
+            d = osk::PrepDesc{};
+            d.seed = q.sk.seed;
+            d.h = q.sk.h;
+            d.sigma = q.sk.sigma;
+            d.table = reinterpret_cast<uint32_t*>(at(workspace, q.prep_off));
+            d.n = q.n;
+            d.nt = table_stride(q.n);
+            d.b = q.sk.b;
+            d.bp = q.bp;
+            d.nblk = nblocks(&q.sk);
+            d.hash_chunks = (int32_t)((d.nt + 255) / 256);
+            d.hash_task0 = hash_task0;
+            d.ell_task0 = list_task0;
+            osk::prep_desc_lists(d, const_cast<void*>(prep_lists(d.table, &q.sk, q.n)));
+            hash_task0 += (int64_t)d.nblk * d.hash_chunks;
+            list_task0 += (int64_t)d.nblk * d.nwin;
+        }
+        if (hash_task0 != plan->hash_tasks || list_task0 != plan->list_tasks) return OS_EINVAL;
         // (cost, problem, tile row, tile col), in problem and tile order
         struct Item {
             int64_t cost;
@@ -274,6 +368,9 @@ os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void
         hipError_t e = hipMemcpyAsync(at(workspace, plan->desc_off), desc.data(),
                                       desc.size() * sizeof(osk::BatchProblem),
                                       hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(at(workspace, plan->prep_desc_off), prep.data(),
+                               prep.size() * sizeof(osk::PrepDesc), hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(at(workspace, plan->tiles_off), tiles.data(),
                                tiles.size() * sizeof(int4), hipMemcpyHostToDevice, s);

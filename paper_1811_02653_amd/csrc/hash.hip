@@ -88,6 +88,33 @@ __global__ __launch_bounds__(256) void hash_fill_kernel(uint64_t seed, const int
     }
 }
 
+// Hash step of many prepared sketches: task t fills 256 indices of one
+// block of the descriptor whose hash_task0 range holds t.
+__global__ __launch_bounds__(256) void table_batch_kernel(const PrepDesc* __restrict__ descs,
+                                                          int32_t count, int64_t tasks) {
+    for (int64_t t = blockIdx.x; t < tasks; t += gridDim.x) {
+        const int32_t p = find_task(descs, count, t, [](const PrepDesc& d) {
+            return d.hash_task0;
+        });
+        const PrepDesc& d = descs[p];
+        const int64_t local = t - d.hash_task0;
+        const int64_t blk = local / d.hash_chunks;
+        const int64_t k = (local % d.hash_chunks) * 256 + threadIdx.x;
+        if (k >= d.nt) continue;
+        uint32_t v = 0;
+        if (k < d.n) {
+            if (d.h) {
+                v = clamp_bucket(d.h[blk * d.n + k], d.b) |
+                    (d.sigma[blk * d.n + k] < 0 ? 0x80000000u : 0u);
+            } else {
+                const uint64_t w = sketch_word(d.seed, (uint64_t)blk, (uint64_t)k);
+                v = word_bucket(w, (uint32_t)d.b) | ((uint32_t)(w & 1ull) << 31);
+            }
+        }
+        d.table[blk * d.nt + k] = v;
+    }
+}
+
 dim3 grid_for(int64_t len, int32_t nblk) {
     int64_t gx = (len + 255) / 256;
     if (gx > 4096) gx = 4096;
@@ -108,6 +135,14 @@ hipError_t launch_table_explicit(const int32_t* h, const int8_t* sigma, int32_t 
                                  int64_t nt, int32_t b, uint32_t* table, hipStream_t s) {
     hipLaunchKernelGGL(table_explicit_kernel, grid_for(nt, nblk), dim3(256), 0, s, h, sigma, n,
                        nt, b, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_batch(const PrepDesc* descs, int32_t count, int64_t tasks,
+                              hipStream_t s) {
+    if (count < 1 || tasks < 1) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)(tasks < (int64_t(1) << 20) ? tasks : (int64_t(1) << 20));
+    hipLaunchKernelGGL(table_batch_kernel, dim3(grid), dim3(256), 0, s, descs, count, tasks);
     return hipGetLastError();
 }
 

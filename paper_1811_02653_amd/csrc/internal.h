@@ -42,6 +42,57 @@ constexpr int64_t kMaxSketchedLen = OS_MAX_N;
 
 // Bytes of the list structures for nblk blocks of padded width bp.
 size_t list_bytes(int32_t nblk, int64_t n, int32_t bp);
+// One prepared sketch of a batch prepared in one launch per step
+// (device-resident).  The hash step writes table (nblk x nt packed entries:
+// bucket | sign << 31, from SplitMix64 of seed, or from the explicit tables
+// h / sigma when h is set); the list step builds the lists (hdr, ell) from
+// it.  Tasks: hash task t of the batch is chunk (t - hash_task0) % hash_chunks
+// of 256 indices of block (t - hash_task0) / hash_chunks; list task t is
+// window (t - ell_task0) % nwin of block (t - ell_task0) / nwin.  The task0
+// fields ascend with the descriptor index.
+struct PrepDesc {
+    uint64_t seed;
+    const int32_t* h;
+    const int8_t* sigma;
+    uint32_t* table;
+    uint32_t* hdr;
+    uint16_t* ell;
+    int64_t n;
+    int64_t nt;
+    int64_t RC;
+    int64_t hash_task0;
+    int64_t ell_task0;
+    int32_t b;
+    int32_t bp;
+    int32_t qn;
+    int32_t nwin;
+    int32_t nblk;
+    int32_t hash_chunks;
+};
+// Index of the descriptor whose task range holds t (task0 ascending, the
+// first one 0): the last p with task0(descs[p]) <= t.
+template <typename F>
+__device__ __forceinline__ int32_t find_task(const PrepDesc* descs, int32_t count, int64_t t,
+                                             F task0) {
+    int32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) / 2;
+        if (task0(descs[mid]) <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+// Sets the list fields (hdr, ell, qn, nwin, RC) of d (n, bp, nblk set) for
+// its lists region.
+void prep_desc_lists(PrepDesc& d, void* lists);
+// The hash step / the list step of every descriptor (tasks = the total
+// task count of that step; max_bp = the largest bp).
+hipError_t launch_table_batch(const PrepDesc* descs, int32_t count, int64_t tasks,
+                              hipStream_t s);
+hipError_t launch_lists_batch(const PrepDesc* descs, int32_t count, int64_t tasks,
+                              int32_t max_bp, hipStream_t s);
 // Lists for every block i < nblk of a packed table.
 hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
                               int32_t bp, void* lists, hipStream_t s);

@@ -27,6 +27,8 @@
 // lane, 1 KiB per chunk) padded to the longest bucket of the group.  An entry
 // is 16 bits: the window offset of k (bits 0..14) and the sign (bit 15); the
 // padding entry points at a zero row.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace osk {
@@ -69,17 +71,15 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t x) {
 // The per-group chunk counts sum to at most ceil(kw/8) + qn = RC, because the
 // longest bucket of a group holds at most the group's entries.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restrict__ table,
-                                                       int64_t n, int64_t nt, int32_t bp,
-                                                       int32_t qn, int32_t nwin, int64_t RC,
-                                                       uint32_t* __restrict__ hdr,
-                                                       uint16_t* __restrict__ ell) {
-    extern __shared__ uint32_t sm[];
+__device__ __forceinline__ void ell_build_region(const uint32_t* __restrict__ table, int64_t n,
+                                                 int64_t nt, int32_t bp, int32_t qn,
+                                                 int32_t nwin, int64_t RC,
+                                                 uint32_t* __restrict__ hdr,
+                                                 uint16_t* __restrict__ ell, int w, int64_t i,
+                                                 uint32_t* sm) {
     uint32_t* cnt = sm;            // [bp] counts, then cursors
     uint32_t* qbase = sm + bp;     // [qn] chunk base of each group
     uint32_t* qlen = qbase + qn;   // [qn] chunk count of each group
-    const int w = blockIdx.x;
-    const int64_t i = blockIdx.y;
     const int lane = threadIdx.x;
     const int64_t k0 = (int64_t)w * kWin;
     const int kw = (int)min((int64_t)kWin, n - k0);
@@ -146,6 +146,34 @@ __global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restric
         const uint32_t qb = qbase[q];
         for (uint32_t p = have; p < len; ++p)
             region[(int64_t)(qb + p / 8) * 512 + lane * 8 + (p & 7)] = kPad;
+    }
+}
+
+__global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restrict__ table,
+                                                       int64_t n, int64_t nt, int32_t bp,
+                                                       int32_t qn, int32_t nwin, int64_t RC,
+                                                       uint32_t* __restrict__ hdr,
+                                                       uint16_t* __restrict__ ell) {
+    extern __shared__ uint32_t sm[];
+    ell_build_region(table, n, nt, bp, qn, nwin, RC, hdr, ell, (int)blockIdx.x,
+                     (int64_t)blockIdx.y, sm);
+}
+
+// The same for many prepared sketches in one launch: task t (one wave) is
+// region (block i, window w) of the descriptor whose ell_task0 range holds
+// t; workgroups stride over the tasks.
+__global__ __launch_bounds__(64) void ell_build_batch_kernel(const PrepDesc* __restrict__ descs,
+                                                             int32_t count, int64_t tasks) {
+    extern __shared__ uint32_t sm[];
+    for (int64_t t = blockIdx.x; t < tasks; t += gridDim.x) {
+        const int32_t p = find_task(descs, count, t, [](const PrepDesc& d) {
+            return d.ell_task0;
+        });
+        const PrepDesc& d = descs[p];
+        const int64_t local = t - d.ell_task0;
+        ell_build_region(d.table, d.n, d.nt, d.bp, d.qn, d.nwin, d.RC, d.hdr, d.ell,
+                         (int)(local % d.nwin), local / d.nwin, sm);
+        __syncthreads();
     }
 }
 
@@ -499,6 +527,26 @@ size_t list_bytes(int32_t nblk, int64_t n, int32_t bp) {
     const Plan p = plan_of(n, bp);
     return (size_t)round_up((int64_t)nblk * p.nwin * p.qn * 4, 256) +
            (size_t)nblk * (size_t)p.nwin * (size_t)p.RC * 1024u;
+}
+
+void prep_desc_lists(PrepDesc& d, void* lists) {
+    const Plan p = plan_of(d.n, d.bp);
+    const ListView v = carve_lists(lists, d.nblk, d.n, d.bp);
+    d.hdr = v.hdr;
+    d.ell = reinterpret_cast<uint16_t*>(v.ell);
+    d.qn = p.qn;
+    d.nwin = p.nwin;
+    d.RC = p.RC;
+}
+
+hipError_t launch_lists_batch(const PrepDesc* descs, int32_t count, int64_t tasks,
+                              int32_t max_bp, hipStream_t s) {
+    if (count < 1 || tasks < 1 || max_bp < 1) return hipErrorInvalidValue;
+    const int32_t qn = (max_bp + 63) / 64;
+    const size_t lds = (size_t)(max_bp + 2 * qn) * 4;
+    const unsigned grid = (unsigned)std::min<int64_t>(tasks, int64_t(1) << 20);
+    hipLaunchKernelGGL(ell_build_batch_kernel, dim3(grid), dim3(64), lds, s, descs, count, tasks);
+    return hipGetLastError();
 }
 
 hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
