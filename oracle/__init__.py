@@ -224,6 +224,37 @@ def sampled_entries(A, B, rows, cols, b: int, N: int, e: int, seed: int = 0,
     return out
 
 
+def sketched_matmul_cmask(A, B, b: int, N: int, e: int, cmask, seed: int = 0,
+                          h=None, sigma=None) -> np.ndarray:
+    """OverSketch product with a keep mask per b x b block of C (Algorithm
+    "OverSketch": each block of C is assembled from the workers that
+    returned for it).  cmask[I, J, i] != 0 keeps sketch block i for C block
+    (I, J) (rows I*b.., columns J*b.., the last ones partial):
+        C_IJ = (1/K_IJ) sum_{kept i} (A_I S_i)(S_i^T B_J),
+    K_IJ its kept count; a block that keeps none is zero."""
+    A, B = _f64(A), _f64(B)
+    m, n = A.shape
+    l = B.shape[1]
+    if B.shape[0] != n:
+        raise ValueError("inner dimensions differ")
+    cmask = np.asarray(cmask, dtype=np.uint8)
+    nbI, nbJ = -(-m // b), -(-l // b)
+    if cmask.shape != (nbI, nbJ, N + e):
+        raise ValueError("cmask must be [ceil(m/b)][ceil(l/b)][N+e]")
+    if h is None:
+        h, sigma = hash_tables(seed, N + e, n, b)
+    At = sketch_cols(A, h, sigma, b)
+    Bt = sketch_rows(B, h, sigma, b)
+    C = np.zeros((m, l))
+    for I in range(nbI):
+        for J in range(nbJ):
+            if cmask[I, J].any():
+                r = slice(I * b, min(m, (I + 1) * b))
+                c = slice(J * b, min(l, (J + 1) * b))
+                C[r, c] = block_product(At[r], Bt[:, c], b, cmask[I, J])
+    return C
+
+
 def sketched_gram(A, d, b: int, N: int, e: int, seed: int = 0, keep=None,
                   h=None, sigma=None) -> np.ndarray:
     """Sketched Hessian of the log-barrier interior-point method (Section 5.2,

@@ -288,22 +288,6 @@ def test_error_paths_raise():
 # per-C-block keep masks (each b x b block of C keeps its own workers)
 # ---------------------------------------------------------------------------
 
-def _cmask_reference(A, B, b, N, e, seed, cmask):
-    """Per C block: (1/K_IJ) sum of its kept blocks' products on the oracle's
-    sketch; zero where a block keeps none."""
-    h, s = oracle.hash_tables(seed, N + e, A.shape[1], b)
-    At = oracle.sketch_cols(A, h, s, b)
-    Bt = oracle.sketch_rows(B, h, s, b)
-    m, l = A.shape[0], B.shape[1]
-    C = np.zeros((m, l))
-    for I in range(cmask.shape[0]):
-        for J in range(cmask.shape[1]):
-            r, c = slice(I * b, min(m, (I + 1) * b)), slice(J * b, min(l, (J + 1) * b))
-            if cmask[I, J].any():
-                C[r, c] = oracle.block_product(At[r], Bt[:, c], b, cmask[I, J])
-    return C
-
-
 @pytest.mark.parametrize("m,n,l,b,N,e", [(600, 2048, 520, 256, 3, 2),   # tiles = blocks
                                          (300, 1001, 250, 100, 3, 1),   # block < tile
                                          (700, 1500, 640, 300, 2, 2)])  # 2 tiles per block side
@@ -319,7 +303,7 @@ def test_matmul_per_block_masks(m, n, l, b, N, e):
         cmask[0, 1, :] = 0
         cmask[0, 1, 0] = 1                  # a block with one worker (K < N)
     C = host(osk.matmul_cmask(dev(A), dev(B, ld=l + 1), b, N, e, cmask, seed=seed))
-    ref = _cmask_reference(A, B, b, N, e, seed, cmask)
+    ref = oracle.sketched_matmul_cmask(A, B, b, N, e, cmask, seed=seed)
     assert np.all(C[:b, :b] == 0)
     assert rel(C, ref) <= PRODUCT_TOL
     # a uniform mask reproduces the global-mask path exactly

@@ -668,3 +668,44 @@ def test_gram_is_symmetric_psd_and_unbiased():
     assert z.max() < 5.0, z.max()
     # a missing square root (A D^2 A^T) or a missing 1/K would be far off
     assert oracle.rel_frob(mean, ref) < 0.1
+
+
+# ---------------------------------------------------------------------------
+# Per-C-block keep masks (Algorithm "OverSketch": every b x b block of C has
+# its own stragglers)
+# ---------------------------------------------------------------------------
+
+def test_cmask_uniform_mask_is_the_global_product():
+    m, n, l, b, N, e = 13, 40, 11, 5, 3, 1
+    rng = np.random.default_rng(50)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    keep = np.array([1, 0, 1, 1], np.uint8)
+    cm = np.broadcast_to(keep, (-(-m // b), -(-l // b), N + e)).copy()
+    C = oracle.sketched_matmul_cmask(A, B, b, N, e, cm, seed=3)
+    assert np.array_equal(C, oracle.sketched_matmul(A, B, b, N, e, seed=3, keep=keep))
+
+
+def test_cmask_blocks_follow_the_dense_definition():
+    # each C block against A_I S_K S_K^T B_J with its own kept set, dense S
+    # (S = N^{-1/2}[S_1 ..], so the 1/N factor is traded for 1/K_IJ); blocks
+    # that keep nothing are zero
+    m, n, l, b, N, e = 7, 17, 9, 3, 2, 2
+    rng = np.random.default_rng(51)
+    A, B = rng.standard_normal((m, n)), rng.standard_normal((n, l))
+    h, s = oracle.hash_tables(8, N + e, n, b)
+    nbI, nbJ = -(-m // b), -(-l // b)
+    cm = (rng.random((nbI, nbJ, N + e)) < 0.5).astype(np.uint8)
+    cm[0, 0] = 0
+    cm[1, 1] = [1, 0, 0, 0]
+    cm[-1, -1] = 1
+    C = oracle.sketched_matmul_cmask(A, B, b, N, e, cm, h=h, sigma=s)
+    for I in range(nbI):
+        for J in range(nbJ):
+            r = slice(I * b, min(m, (I + 1) * b))
+            c = slice(J * b, min(l, (J + 1) * b))
+            K = int(cm[I, J].sum())
+            if K == 0:
+                assert np.all(C[r, c] == 0)
+                continue
+            ref = oracle.literal_product(A[r], B[:, c], h, s, b, N, cm[I, J]) * (N / K)
+            np.testing.assert_allclose(C[r, c], ref, rtol=1e-12, atol=1e-12)
