@@ -25,7 +25,8 @@
 // (seed or tables, b, N, e, n): for every block i, window w and group q of 64
 // consecutive buckets, a lane-interleaved list ("chunks" of 8 entries per
 // lane, 1 KiB per chunk) padded to the longest bucket of the group.  An entry
-// is 16 bits: the window offset of k (bits 0..14) and the sign (bit 15); the
+// is 16 bits: the LDS slot of k's window offset (bits 0..14, a fixed
+// permutation of the offset, see win_slot) and the sign (bit 15); the
 // padding entry points at a zero row.
 #include <algorithm>
 
@@ -41,6 +42,14 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kPerThread = kWin / kThreads;   // window positions staged per thread (16)
 constexpr uint16_t kPad = (uint16_t)kWin;     // entry of the zero row, positive
 constexpr int kAhead = 3;              // list chunks of the next slot fetched ahead
+
+// LDS slot of window position p (p < kWin).  Thread t stages the quads of
+// positions 2048u + 4t + j (j < 4); they go to slots 2048u + 512j + t, so the
+// lanes of one staging write touch consecutive slots.  List entries hold the
+// slot of their position.
+__device__ __forceinline__ int win_slot(int p) {
+    return (p & ~2047) | ((p & 3) << 9) | ((p >> 2) & 511);
+}
 
 // Spread consecutive task ids over the 8 XCDs in contiguous runs: task T is
 // run by the workgroup with linear id L where T = (L % 8) * (tasks / 8) + L / 8,
@@ -129,7 +138,7 @@ __device__ __forceinline__ void ell_build_region(const uint32_t* __restrict__ ta
             pos = cnt[h] + (uint32_t)__popcll(peers & below);
             const uint32_t chunk = qbase[h >> 6] + pos / 8;
             region[(int64_t)chunk * 512 + (h & 63) * 8 + (pos & 7)] =
-                (uint16_t)(t | ((e >> 31) << 15));
+                (uint16_t)(win_slot(t) | ((e >> 31) << 15));
         }
         __builtin_amdgcn_wave_barrier();
         // the highest peer advances the bucket's cursor (one writer per bucket)
@@ -178,22 +187,31 @@ __global__ __launch_bounds__(64) void ell_build_batch_kernel(const PrepDesc* __r
 }
 
 // ---------------------------------------------------------------------------
-// The sketch kernel.
-//   kRowLines = true : lines are rows of X (lines x n, ld ldx); thread stages
-//                      X[line0 + r][k] for r < 4 with four 4-byte loads
-//                      (coalesced across lanes along k).
-//   kRowLines = false: lines are columns of X (n x lines, ld ldx); thread
-//                      stages X[k][line0 .. line0+3] with one 16-byte load when
-//                      vec (X 16-byte aligned, ldx % 4 == 0), else four.
-// Window position k of the staged window is handled by thread k % 512.
+// The sketch kernel.  Thread t stages window positions 2048u + 4t + j
+// (u, j < 4) into LDS slots win_slot(k) = 2048u + 512j + t; list entries
+// hold those slots.
+//   kRowLines = true : lines are rows of X (lines x n, ld ldx).  With vec
+//                      (X 16-byte aligned, ldx % 4 == 0, and the window whole
+//                      or n a multiple of 4) a line's 4 consecutive positions
+//                      come with one 16-byte load (1 KiB per wave,
+//                      coalesced): r[4*line + u] holds positions 4t + 2048u
+//                      .. +3 of that line.  Otherwise every value is loaded
+//                      on its own into the same layout.
+//   kRowLines = false: lines are columns of X (n x lines, ld ldx); r[4u + j]
+//                      holds X[k][line0 .. line0+3] for position k = 2048u +
+//                      4t + j, one 16-byte load when vec (X 16-byte aligned,
+//                      ldx % 4 == 0), else four.
+// kWeighted (row lines): every value at sketched index k is multiplied by
+// sqrt(wd[k]) (a diagonal weight, as in A D^{1/2} S for a Hessian A D A^T);
+// w[u] holds the weights of positions 4t + 2048u .. +3.  The weight is
+// applied when the window is written to LDS, not when it is loaded, so the
+// loads of the next window stay in flight while the current one is summed.
 // ---------------------------------------------------------------------------
-// kWeighted: every value at sketched index k is first multiplied by
-// sqrt(wd[k]) (a diagonal weight, as in A D^{1/2} S for a Hessian A D A^T).
 template <bool kRowLines, bool kWeighted = false>
-__device__ __forceinline__ void load_window(float4 (&r)[kPerThread], const float* __restrict__ X,
-                                            int64_t lines, int64_t ldx, int64_t line0,
-                                            int64_t k0, int kw, bool vec,
-                                            const float* __restrict__ wd = nullptr) {
+__device__ __forceinline__ void load_window(float4 (&r)[kPerThread], float4 (&w)[4],
+                                            const float* __restrict__ X, int64_t lines,
+                                            int64_t ldx, int64_t line0, int64_t k0, int kw,
+                                            bool vec, const float* __restrict__ wd = nullptr) {
     // Every load is unconditional (a branch around a load makes each use wait
     // for all loads in flight): positions past the window's end are clamped to
     // its last index (no entry refers to them) and lines past the matrix to
@@ -202,26 +220,81 @@ __device__ __forceinline__ void load_window(float4 (&r)[kPerThread], const float
     const int64_t l1 = min(line0 + 1, lines - 1) - line0;
     const int64_t l2 = min(line0 + 2, lines - 1) - line0;
     const int64_t l3 = min(line0 + 3, lines - 1) - line0;
+    if constexpr (kRowLines) {
+        const int64_t dl[4] = {0, l1, l2, l3};
+        if (vec) {
+            // kw is a multiple of 4 here: the last whole quad starts at kw - 4
 #pragma unroll
-    for (int u = 0; u < kPerThread; ++u) {
-        const int64_t kk = k0 + min(tid + u * kThreads, kw - 1);
-        if constexpr (kRowLines) {
-            const float* p = X + line0 * ldx + kk;
-            r[u] = make_float4(p[0], p[l1 * ldx], p[l2 * ldx], p[l3 * ldx]);
-            if constexpr (kWeighted) {
-                const float sw = sqrtf(wd[kk]);
-                r[u].x *= sw;
-                r[u].y *= sw;
-                r[u].z *= sw;
-                r[u].w *= sw;
+            for (int u = 0; u < 4; ++u) {
+                const int64_t kk = k0 + min(4 * tid + 2048 * u, kw - 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    r[4 * q + u] = *reinterpret_cast<const float4*>(X + (line0 + dl[q]) * ldx + kk);
+                if constexpr (kWeighted) w[u] = *reinterpret_cast<const float4*>(wd + kk);
             }
         } else {
-            const float* p = X + kk * ldx + line0;
-            if (vec && l3 == 3)      // uniform
-                r[u] = *reinterpret_cast<const float4*>(p);
-            else
-                r[u] = make_float4(p[0], p[l1], p[l2], p[l3]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int64_t kk[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) kk[j] = k0 + min(4 * tid + 2048 * u + j, kw - 1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float* p = X + (line0 + dl[q]) * ldx;
+                    r[4 * q + u] = make_float4(p[kk[0]], p[kk[1]], p[kk[2]], p[kk[3]]);
+                }
+                if constexpr (kWeighted) w[u] = make_float4(wd[kk[0]], wd[kk[1]], wd[kk[2]], wd[kk[3]]);
+            }
         }
+    } else {
+        // r[4u + j] = the 4 lines at position 2048u + 4t + j
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t kk = k0 + min(4 * tid + 2048 * u + j, kw - 1);
+                const float* p = X + kk * ldx + line0;
+                if (vec && l3 == 3)      // uniform
+                    r[4 * u + j] = *reinterpret_cast<const float4*>(p);
+                else
+                    r[4 * u + j] = make_float4(p[0], p[l1], p[l2], p[l3]);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ float comp4(const float4& v, int j) {
+    return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
+}
+
+// Writes a loaded window into LDS: win[win_slot(k)] = the 4 lines' values at
+// window position k (weighted when kWeighted).
+template <bool kRowLines, bool kWeighted>
+__device__ __forceinline__ void stage_window(float4* __restrict__ win,
+                                             const float4 (&r)[kPerThread], const float4 (&w)[4]) {
+    const int tid = threadIdx.x;
+    if constexpr (kRowLines) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float4 v = make_float4(comp4(r[u], j), comp4(r[4 + u], j), comp4(r[8 + u], j),
+                                       comp4(r[12 + u], j));
+                if constexpr (kWeighted) {
+                    const float sw = sqrtf(comp4(w[u], j));
+                    v.x *= sw;
+                    v.y *= sw;
+                    v.z *= sw;
+                    v.w *= sw;
+                }
+                win[2048 * u + 512 * j + tid] = v;      // slot of position 2048u + 4t + j
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) win[2048 * u + 512 * j + tid] = r[4 * u + j];
     }
 }
 
@@ -275,18 +348,22 @@ void sketch_kernel(
     for (int s = 0; s < kSlots; ++s) acc[s] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (tid == 0) win[kWin] = make_float4(0.f, 0.f, 0.f, 0.f);
 
+    // vec for a row-lines window: whole windows always, the last one when n % 4 == 0
+    auto vec_at = [&](int64_t k0) {
+        return kRowLines ? (vec != 0 && (k0 + kWin <= n || (n & 3) == 0)) : vec != 0;
+    };
     float4 pre[kPerThread];
-    load_window<kRowLines, kWeighted>(pre, X, lines, ldx, line0, 0, (int)min((int64_t)kWin, n), vec,
-                                      wd);
+    float4 wpre[4];
+    load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, line0, 0,
+                                      (int)min((int64_t)kWin, n), vec_at(0), wd);
     for (int w = 0; w < nwin; ++w) {
         __syncthreads();                 // the previous window is no longer read
-#pragma unroll
-        for (int u = 0; u < kPerThread; ++u) win[tid + u * kThreads] = pre[u];
+        stage_window<kRowLines, kWeighted>(win, pre, wpre);
         __syncthreads();
         if (w + 1 < nwin) {
             const int64_t k1 = (int64_t)(w + 1) * kWin;
-            load_window<kRowLines, kWeighted>(pre, X, lines, ldx, line0, k1,
-                                              (int)min((int64_t)kWin, n - k1), vec, wd);
+            load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, line0, k1,
+                                              (int)min((int64_t)kWin, n - k1), vec_at(k1), wd);
         }
         // The list chunks of slot s + 1 (up to kAhead of them) are fetched
         // while slot s is summed.  Fetches are unconditional: chunk indices
@@ -510,7 +587,8 @@ hipError_t launch_sketch(bool row_lines, const float* X, int64_t lines, int64_t 
     pass_plan(nst, p.qn, &npass, &slots);
     const int64_t groups = (lines + kLines - 1) / kLines;
     const dim3 grid((unsigned)(groups * npass));
-    const int vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (ldx & 3) == 0;
+    const int vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (ldx & 3) == 0 &&
+                    (reinterpret_cast<uintptr_t>(wd) & 15) == 0;
     if (wd && row_lines)   // weighted sketches are only taken along rows
         return launch_slots<true, true>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin,
                                         nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, wd);
