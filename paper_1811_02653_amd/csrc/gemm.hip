@@ -94,6 +94,63 @@ __device__ __forceinline__ void read_frag(float4 (&a)[4], float4 (&b)[4],
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tiles loaded straight from global memory into LDS (buffer_load_dwordx4
+// with the lds flag: no VGPR staging and no LDS store instructions, which
+// each cost the MFMA pipe about one slot when issued in the K loop).  A tile
+// of BT = 32 kU rows x 128 bytes (one K step) is stored unpadded: the
+// 16-byte chunk c of row r sits at chunk c ^ (r & 7) of LDS row r, so the
+// fragment reads (8 consecutive rows, one chunk each) hit 8 different bank
+// groups.  Load u of wave w fills LDS rows 8(kU w + u) .. +7 (1 KiB,
+// 16 bytes per lane): lane l takes row 8(kU w + u) + l/8 and physical chunk
+// l % 8, i.e. logical chunk (l % 8) ^ (l / 8).  Rows past the matrix end
+// are clamped to its last row (they only feed outputs that are not stored).
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int kU>
+__device__ __forceinline__ void direct_offsets(uint32_t (&vo)[kU], int64_t ld_bytes, int last,
+                                               int wave, int lane) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int r = 8 * (kU * wave + u) + (lane >> 3);
+        const int c = (lane & 7) ^ (lane >> 3);
+        vo[u] = (uint32_t)((int64_t)min(r, last) * ld_bytes + 16 * c);
+    }
+}
+
+// (The builtin exists only for the device target; the host pass of a
+// template kernel that names it would silently drop the kernel's launch
+// stubs, hence the guard.)
+template <int kU>
+__device__ __forceinline__ void direct_issue(__amdgpu_buffer_rsrc_t rsrc, float* lds,
+                                             const uint32_t (&vo)[kU], uint32_t kbyte, int wave) {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rsrc, (lds_void*)(lds + (kU * wave + u) * 256), 16, vo[u], kbyte, 0, 0);
+#endif
+}
+
+// Float offset in a direct tile of the fragment of quad q for tile row
+// rbase + 32 i (rbase = a wave's first row + lane % 32): lane half h reads
+// logical chunk 4h + q.
+__device__ __forceinline__ int direct_frag_off(int rbase, int q, int lane) {
+    return rbase * 32 + 4 * ((4 * (lane >> 5) + q) ^ (lane & 7));
+}
+
+// a = zero when !live (a uniform flag): a dead K step adds nothing.
+__device__ __forceinline__ void zero_unless(float4 (&a)[4], bool live) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        a[i].x = live ? a[i].x : 0.f;
+        a[i].y = live ? a[i].y : 0.f;
+        a[i].z = live ? a[i].z : 0.f;
+        a[i].w = live ? a[i].w : 0.f;
+    }
+}
+
 __device__ __forceinline__ float comp(const float4& v, int c) {
     return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
 }
@@ -152,15 +209,23 @@ struct CMask {
     int32_t tb;            // tiles per block side
 };
 
-template <typename P, bool kMask>
+// kOdd: the K step count may be odd (always with per-C-block masks, whose
+// count varies per tile): the pair loop's second step is then masked.  With
+// an even count the mask is left out (it costs about 4 % of the MFMA rate).
+template <typename P, bool kMask, bool kOdd>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __restrict__ Bt,
                       int64_t ldbt, int64_t m, int64_t l, int32_t bp, BlockList kept,
                       int32_t nkept, int32_t nsub, int64_t lo_off, float scale,
                       float* __restrict__ C, int64_t ldc, int32_t tilesM, int32_t tilesN,
                       CMask cm) {
-    __shared__ __align__(16) float As[2][BM * LDT];
-    __shared__ __align__(16) float Bs[2][BN * LDT];
+    // two K-step buffers per operand, separate arrays so that the compiler
+    // can tell the tile loads in flight (into one) from the fragment reads
+    // (from the other)
+    __shared__ __align__(1024) float As0[BM * 32];
+    __shared__ __align__(1024) float As1[BM * 32];
+    __shared__ __align__(1024) float Bs0[BN * 32];
+    __shared__ __align__(1024) float Bs1[BN * 32];
     __shared__ int32_t klist[kMask ? OS_MAX_BLOCKS + 1 : 1];   // per-tile kept list, count last
 
     const int tid = threadIdx.x;
@@ -203,10 +268,24 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         }
         scale = 1.0f / (float)nkept;
     }
-    // kept stored block of term index j
+    // kept stored block of term index j: lane i of kv[q] holds entry 64q + i
+    // of the kept list, read once here and picked with v_readlane, so the K
+    // loop issues no scalar or LDS load for it (either would make the wave
+    // wait for every LDS access in flight)
+    int32_t kv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if constexpr (kMask)
+            kv[q] = klist[64 * q + lane];
+        else
+            kv[q] = kept.idx[64 * q + lane];
+    }
     auto kept_at = [&](int j) -> int32_t {
-        if constexpr (kMask) return __builtin_amdgcn_readfirstlane(klist[j]);
-        return kept.idx[j];
+        const int32_t r0 = __builtin_amdgcn_readlane(kv[0], j & 63);
+        const int32_t r1 = __builtin_amdgcn_readlane(kv[1], j & 63);
+        const int32_t r2 = __builtin_amdgcn_readlane(kv[2], j & 63);
+        const int32_t r3 = __builtin_amdgcn_readlane(kv[3], j & 63);
+        return j < 64 ? r0 : (j < 128 ? r1 : (j < 192 ? r2 : r3));
     };
 
     v16f acc[4][4];
@@ -222,73 +301,76 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
     const int total = nkept * nsub * tpb;
     // byte offsets of the first K column of step `step` in A and in B
     // (terms in order, kStep columns per step)
-    auto step_a = [&](int step) -> uint32_t {
+    auto step_ab = [&](int step, uint32_t& ka, uint32_t& kb) {
         const int term = step / tpb;
         const int j = term / nsub;
         const int sub = term - j * nsub;
-        const int64_t c = (int64_t)kept_at(j) * bp + (int64_t)(step % tpb) * kStep +
-                          (sub == 2 ? lo_off : 0);
-        return (uint32_t)(c * P::kElem);
-    };
-    auto step_b = [&](int step) -> uint32_t {
-        const int term = step / tpb;
-        const int j = term / nsub;
-        const int sub = term - j * nsub;
-        const int64_t c = (int64_t)kept_at(j) * bp + (int64_t)(step % tpb) * kStep +
-                          (sub == 1 ? lo_off : 0);
-        return (uint32_t)(c * P::kElem);
+        const int64_t c = (int64_t)kept_at(j) * bp + (int64_t)(step % tpb) * kStep;
+        ka = (uint32_t)((c + (sub == 2 ? lo_off : 0)) * P::kElem);
+        kb = (uint32_t)((c + (sub == 1 ? lo_off : 0)) * P::kElem);
     };
 
-    const int arow = wm * 128 + (lane & 31);
-    const int brow = wn * 128 + (lane & 31);
-    const int kh = 16 * (lane >> 5);
-
-    // the tile rows this thread loads: t/8 + 32u, clamped to the last row
-    // inside the matrix
     const __amdgpu_buffer_rsrc_t ra_src =
         tile_rsrc(static_cast<const char*>(At) + row0 * ldat * P::kElem);
     const __amdgpu_buffer_rsrc_t rb_src =
         tile_rsrc(static_cast<const char*>(Bt) + col0 * ldbt * P::kElem);
-    uint32_t oa[8], ob[8];
-    tile_offsets(oa, ldat * P::kElem, tid >> 3, (int)min((int64_t)BM - 1, m - 1 - row0), tid & 7);
-    tile_offsets(ob, ldbt * P::kElem, tid >> 3, (int)min((int64_t)BN - 1, l - 1 - col0), tid & 7);
+    uint32_t va[8], vb[8];
+    direct_offsets<8>(va, ldat * P::kElem, (int)min((int64_t)BM - 1, m - 1 - row0), wave, lane);
+    direct_offsets<8>(vb, ldbt * P::kElem, (int)min((int64_t)BN - 1, l - 1 - col0), wave, lane);
+    int fa_off[4], fb_off[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        fa_off[q] = direct_frag_off(wm * 128 + (lane & 31), q, lane);
+        fb_off[q] = direct_frag_off(wn * 128 + (lane & 31), q, lane);
+    }
+    auto frag = [&](float4 (&a)[4], float4 (&b)[4], const float* as, const float* bs, int q) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a[i] = *reinterpret_cast<const float4*>(as + fa_off[q] + 1024 * i);
+            b[i] = *reinterpret_cast<const float4*>(bs + fb_off[q] + 1024 * i);
+        }
+    };
+    auto issue = [&](float* as, float* bs, int step) {
+        uint32_t ka, kb;
+        step_ab(step, ka, kb);
+        direct_issue<8>(ra_src, as, va, ka, wave);
+        direct_issue<8>(rb_src, bs, vb, kb, wave);
+    };
 
-    float4 ra[8], rb[8];
-    load_tile(ra, ra_src, step_a(0), oa);
-    load_tile(rb, rb_src, step_b(0), ob);
-    store_tile(As[0], ra, tid);
-    store_tile(Bs[0], rb, tid);
-    load_tile(ra, ra_src, step_a(min(1, total - 1)), oa);
-    load_tile(rb, rb_src, step_b(min(1, total - 1)), ob);
+    issue(As0, Bs0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-
     float4 fa[4], fb[4], ga[4], gb[4];
-    read_frag(fa, fb, As[0], Bs[0], 0, arow, brow, kh);
-    // The loop body has no branch, so the compiler can spread the LDS stores
-    // and global loads between the MFMAs: on the last two steps the tile
-    // stored (into the buffer no later step reads) and the tile loaded (step
-    // total - 1 again, a valid address) are simply never used.
-    for (int t = 0; t < total; ++t) {
-        const int cur = t & 1;
-        const float* as = As[cur];
-        const float* bs = Bs[cur];
-        read_frag(ga, gb, as, bs, 1, arow, brow, kh);
+    frag(fa, fb, As0, Bs0, 0);
+    // One K step: the next step's tiles go straight into the other buffers
+    // (last read before the previous step's barrier) while this step's four
+    // quads run; each quad's fragments are read during the previous quad's
+    // MFMAs.  The loads are pinned ahead of the MFMAs (scheduling barrier),
+    // and waited for at the step's end.  Past the last step the tile loaded
+    // is step total - 1 again, a valid address.  Steps run in pairs (one per
+    // buffer); when total is odd (kOdd kernels only) the pair's second step
+    // is dead: its A fragments are zeroed, so it adds nothing.
+    auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t, bool live) {
+        issue(na, nb, min(t + 1, total - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        frag(ga, gb, as, bs, 1);
+        if constexpr (kOdd) zero_unless(fa, live);
         P::mfma_quad(acc, fa, fb);
-        read_frag(fa, fb, as, bs, 2, arow, brow, kh);
+        frag(fa, fb, as, bs, 2);
+        if constexpr (kOdd) zero_unless(ga, live);
         P::mfma_quad(acc, ga, gb);
-        // the next step's tile goes into the other buffer (last read before
-        // the previous step's barrier); the loads for the step after are
-        // issued a whole step ahead of their use
-        store_tile(As[cur ^ 1], ra, tid);
-        store_tile(Bs[cur ^ 1], rb, tid);
-        const int ahead = min(t + 2, total - 1);
-        load_tile(ra, ra_src, step_a(ahead), oa);
-        load_tile(rb, rb_src, step_b(ahead), ob);
-        read_frag(ga, gb, as, bs, 3, arow, brow, kh);
+        frag(ga, gb, as, bs, 3);
+        if constexpr (kOdd) zero_unless(fa, live);
         P::mfma_quad(acc, fa, fb);
+        if constexpr (kOdd) zero_unless(ga, live);
         P::mfma_quad(acc, ga, gb);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        read_frag(fa, fb, As[cur ^ 1], Bs[cur ^ 1], 0, arow, brow, kh);
+        frag(fa, fb, na, nb, 0);
+    };
+    for (int t = 0; t < total; t += 2) {
+        kstep(As0, Bs0, As1, Bs1, t, true);
+        kstep(As1, Bs1, As0, Bs0, t + 1, t + 1 < total);
     }
 
     // 32x32 accumulator layout: register r of lane L holds row
@@ -480,7 +562,8 @@ void gemm_kept_fp8_kernel(const uint8_t* __restrict__ At, int64_t ldat, const ui
 //   H_k = scale_k * S_k S_k^T, S_k the line-major sketch (m_k rows) of
 //   problem k with only its kept blocks stored, so the sum over the kept
 //   blocks runs over its first ksteps * 32 columns (padding columns are
-//   zero).  One persistent launch over a tile list that holds the
+//   zero; ksteps is even, the sketch carrying one more zero step when K*bp/32
+//   is odd).  One persistent launch over a tile list that holds the
 //   upper-triangle tiles (ti <= tj) of every problem.  Workgroup g takes
 //   tiles starts[g] .. starts[g+1] - 1 (a static schedule balanced on the
 //   host; every wave reaches its end), computing each with the same FP32
@@ -494,42 +577,6 @@ struct TileShape {
     static constexpr int BT = 64 * kWT;       // tile side
     static constexpr int kU = BT / 32;        // 16-byte loads per thread per operand
 };
-
-template <int kU>
-__device__ __forceinline__ void load_rows(float4 (&r)[kU], __amdgpu_buffer_rsrc_t rsrc,
-                                          uint32_t kbyte, const uint32_t (&off)[kU]) {
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-        r[u] = __builtin_bit_cast(float4,
-                                  __builtin_amdgcn_raw_buffer_load_b128(rsrc, off[u], kbyte, 0));
-}
-
-template <int kU>
-__device__ __forceinline__ void row_offsets(uint32_t (&off)[kU], int64_t ld_bytes, int rel,
-                                            int last, int kq) {
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-        off[u] = (uint32_t)((int64_t)min(rel + 32 * u, last) * ld_bytes + 16 * kq);
-}
-
-template <int kU>
-__device__ __forceinline__ void store_rows(float* __restrict__ s, const float4 (&r)[kU], int tid) {
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-        *reinterpret_cast<float4*>(s + ((tid >> 3) + 32 * u) * LDT + 4 * (tid & 7)) = r[u];
-}
-
-template <int kWT>
-__device__ __forceinline__ void frag_rows(float4 (&a)[kWT], float4 (&b)[kWT],
-                                          const float* __restrict__ As,
-                                          const float* __restrict__ Bs, int q, int arow, int brow,
-                                          int kh) {
-#pragma unroll
-    for (int i = 0; i < kWT; ++i) {
-        a[i] = *reinterpret_cast<const float4*>(As + (arow + 32 * i) * LDT + kh + 4 * q);
-        b[i] = *reinterpret_cast<const float4*>(Bs + (brow + 32 * i) * LDT + kh + 4 * q);
-    }
-}
 
 template <int kWT>
 __device__ __forceinline__ void mfma_rows(v16f (&acc)[kWT][kWT], const float4 (&a)[kWT],
@@ -552,17 +599,30 @@ void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
     using TS = TileShape<kWT>;
     constexpr int BT = TS::BT;
     constexpr int kU = TS::kU;
-    __shared__ __align__(16) float As[2][BT * LDT];
-    __shared__ __align__(16) float Bs[2][BT * LDT];
+    // direct tiles as in gemm_kept_kernel: separate arrays per buffer
+    __shared__ __align__(1024) float As0[BT * 32];
+    __shared__ __align__(1024) float As1[BT * 32];
+    __shared__ __align__(1024) float Bs0[BT * 32];
+    __shared__ __align__(1024) float Bs1[BT * 32];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave >> 1;
     const int wn = wave & 1;
-    const int arow = wm * (BT / 2) + (lane & 31);
-    const int brow = wn * (BT / 2) + (lane & 31);
-    const int kh = 16 * (lane >> 5);
+    int fa_off[4], fb_off[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        fa_off[q] = direct_frag_off(wm * (BT / 2) + (lane & 31), q, lane);
+        fb_off[q] = direct_frag_off(wn * (BT / 2) + (lane & 31), q, lane);
+    }
+    auto frag = [&](float4 (&a)[kWT], float4 (&b)[kWT], const float* as, const float* bs, int q) {
+#pragma unroll
+        for (int i = 0; i < kWT; ++i) {
+            a[i] = *reinterpret_cast<const float4*>(as + fa_off[q] + 1024 * i);
+            b[i] = *reinterpret_cast<const float4*>(bs + fb_off[q] + 1024 * i);
+        }
+    };
 
     const int32_t w_end = starts[blockIdx.x + 1];
     for (int32_t w = starts[blockIdx.x]; w < w_end; ++w) {
@@ -571,13 +631,16 @@ void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
         const int64_t m = pr.m;
         const int64_t row0 = (int64_t)tl.y * BT;
         const int64_t col0 = (int64_t)tl.z * BT;
-        const int total = pr.ksteps;
-        auto step_col = [](int step) -> uint32_t { return (uint32_t)step * kStepBytes; };
+        const int total = pr.ksteps;          // even: the sketch is padded to whole step pairs
         const __amdgpu_buffer_rsrc_t ra_src = tile_rsrc(pr.S + row0 * pr.ld);
         const __amdgpu_buffer_rsrc_t rb_src = tile_rsrc(pr.S + col0 * pr.ld);
-        uint32_t oa[kU], ob[kU];
-        row_offsets<kU>(oa, pr.ld * 4, tid >> 3, (int)min((int64_t)BT - 1, m - 1 - row0), tid & 7);
-        row_offsets<kU>(ob, pr.ld * 4, tid >> 3, (int)min((int64_t)BT - 1, m - 1 - col0), tid & 7);
+        uint32_t va[kU], vb[kU];
+        direct_offsets<kU>(va, pr.ld * 4, (int)min((int64_t)BT - 1, m - 1 - row0), wave, lane);
+        direct_offsets<kU>(vb, pr.ld * 4, (int)min((int64_t)BT - 1, m - 1 - col0), wave, lane);
+        auto issue = [&](float* as, float* bs, int step) {
+            direct_issue<kU>(ra_src, as, va, (uint32_t)step * kStepBytes, wave);
+            direct_issue<kU>(rb_src, bs, vb, (uint32_t)step * kStepBytes, wave);
+        };
 
         v16f acc[kWT][kWT];
 #pragma unroll
@@ -587,36 +650,31 @@ void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-        float4 ra[kU], rb[kU];
-        load_rows<kU>(ra, ra_src, step_col(0), oa);
-        load_rows<kU>(rb, rb_src, step_col(0), ob);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();                       // the previous tile's last reads are done
-        store_rows<kU>(As[0], ra, tid);
-        store_rows<kU>(Bs[0], rb, tid);
-        load_rows<kU>(ra, ra_src, step_col(min(1, total - 1)), oa);
-        load_rows<kU>(rb, rb_src, step_col(min(1, total - 1)), ob);
+        issue(As0, Bs0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
 
         float4 fa[kWT], fb[kWT], ga[kWT], gb[kWT];
-        frag_rows<kWT>(fa, fb, As[0], Bs[0], 0, arow, brow, kh);
-        for (int t = 0; t < total; ++t) {
-            const int cur = t & 1;
-            const float* as = As[cur];
-            const float* bs = Bs[cur];
-            frag_rows<kWT>(ga, gb, as, bs, 1, arow, brow, kh);
+        frag(fa, fb, As0, Bs0, 0);
+        auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t) {
+            issue(na, nb, min(t + 1, total - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            frag(ga, gb, as, bs, 1);
             mfma_rows<kWT>(acc, fa, fb);
-            frag_rows<kWT>(fa, fb, as, bs, 2, arow, brow, kh);
+            frag(fa, fb, as, bs, 2);
             mfma_rows<kWT>(acc, ga, gb);
-            store_rows<kU>(As[cur ^ 1], ra, tid);
-            store_rows<kU>(Bs[cur ^ 1], rb, tid);
-            const int ahead = min(t + 2, total - 1);
-            load_rows<kU>(ra, ra_src, step_col(ahead), oa);
-            load_rows<kU>(rb, rb_src, step_col(ahead), ob);
-            frag_rows<kWT>(ga, gb, as, bs, 3, arow, brow, kh);
+            frag(ga, gb, as, bs, 3);
             mfma_rows<kWT>(acc, fa, fb);
             mfma_rows<kWT>(acc, ga, gb);
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
-            frag_rows<kWT>(fa, fb, As[cur ^ 1], Bs[cur ^ 1], 0, arow, brow, kh);
+            frag(fa, fb, na, nb, 0);
+        };
+        for (int t = 0; t < total; t += 2) {
+            kstep(As0, Bs0, As1, Bs1, t);
+            kstep(As1, Bs1, As0, Bs0, t + 1);
         }
 
         const bool mirror = full && tl.y != tl.z;
@@ -657,9 +715,11 @@ hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int6
     if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 4) || nkept < 1) return hipErrorInvalidValue;
     const int64_t tilesM = (m + BM - 1) / BM;
     const int64_t tilesN = (l + BN - 1) / BN;
-    hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, false>), dim3((unsigned)(tilesM * tilesN)),
-                       dim3(kThreads), 0, s, At, ldat, Bt, ldbt, m, l, bp, kept, nkept, 1, (int64_t)0, scale, C,
-                       ldc, (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1});
+    const bool odd = ((int64_t)nkept * (bp / 32)) % 2 != 0;
+    auto kern = odd ? gemm_kept_kernel<PrecF32, false, true> : gemm_kept_kernel<PrecF32, false, false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads), 0, s, At, ldat,
+                       Bt, ldbt, m, l, bp, kept, nkept, 1, (int64_t)0, scale, C, ldc,
+                       (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1});
     return hipGetLastError();
 }
 
@@ -674,7 +734,7 @@ hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int
     if (tilesM * tilesN > 0x7fffffff || nbJ > 0x7fffffff) return hipErrorInvalidValue;
     BlockList none;
     for (int j = 0; j < OS_MAX_BLOCKS; ++j) none.idx[j] = 0;
-    hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, true>), dim3((unsigned)(tilesM * tilesN)),
+    hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, true, true>), dim3((unsigned)(tilesM * tilesN)),
                        dim3(kThreads), 0, s, At, ldat, Bt, ldbt, m, l, bp, none, 0, 1, (int64_t)0, 1.0f, C, ldc,
                        (int32_t)tilesM, (int32_t)tilesN,
                        CMask{cmask, cblk, (int32_t)nbJ, nst, (int32_t)tb});
@@ -727,10 +787,11 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
     if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 2) || nkept < 1) return hipErrorInvalidValue;
     const int64_t tilesM = (m + BM - 1) / BM;
     const int64_t tilesN = (l + BN - 1) / BN;
-    hipLaunchKernelGGL((gemm_kept_kernel<PrecBF16, false>), dim3((unsigned)(tilesM * tilesN)),
-                       dim3(kThreads), 0, s, At, ldat, Bt, ldbt, m, l, bp, kept, nkept,
-                       split ? 3 : 1, lo_off, scale, C, ldc, (int32_t)tilesM, (int32_t)tilesN,
-                       CMask{nullptr, 0, 0, 0, 1});
+    const bool odd = ((int64_t)nkept * (split ? 3 : 1) * (bp / 64)) % 2 != 0;
+    auto kern = odd ? gemm_kept_kernel<PrecBF16, false, true> : gemm_kept_kernel<PrecBF16, false, false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads), 0, s, At, ldat,
+                       Bt, ldbt, m, l, bp, kept, nkept, split ? 3 : 1, lo_off, scale, C, ldc,
+                       (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1});
     return hipGetLastError();
 }
 

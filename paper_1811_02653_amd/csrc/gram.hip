@@ -34,7 +34,7 @@ struct os_gram_plan {
         std::vector<uint8_t> keep;   // N+e flags
         int32_t K;                   // kept (= stored) blocks
         int32_t bp;
-        int64_t ld;                  // sketch leading dimension: K * bp
+        int64_t ld;                  // sketch leading dimension: K * bp rounded up to 64
         size_t prep_off;
         size_t prep_bytes;
         size_t sketch_off;
@@ -207,7 +207,7 @@ os_status os_gram_plan_create(const os_gram_problem* probs, int32_t count, int f
             for (int32_t i = 0; i < nblocks(&p.sk); ++i) q.keep[(size_t)i] = kept[i] ? 1 : 0;
             q.K = bs.nst;
             q.bp = os_block_stride(p.sk.b);
-            q.ld = (int64_t)q.K * q.bp;
+            q.ld = osk::round_up((int64_t)q.K * q.bp, 64);   // whole pairs of 32-column steps
             if (!osk::plan_sketch_ok(p.m, q.K, q.bp, p.n) ||
                 !osk::plan_gemm_ok(p.m, p.m, q.bp, q.ld, q.ld, 4)) {
                 st = OS_EINVAL;
@@ -328,6 +328,7 @@ os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void
         };
         std::vector<Item> items;
         items.reserve((size_t)plan->max_tiles);
+        hipError_t e_pad = hipSuccess;
         for (size_t k = 0; k < count; ++k) {
             const auto& q = plan->probs[k];
             osk::BatchProblem& bp = desc[k];
@@ -337,6 +338,10 @@ os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void
             bp.ldh = q.ldh;
             bp.m = q.m;
             bp.ksteps = (int32_t)(q.ld / osk::kBlockAlign);
+            if (q.ld > (int64_t)q.K * q.bp && e_pad == hipSuccess)   // the padding step is zero
+                e_pad = hipMemset2DAsync(at(workspace, q.sketch_off) + (size_t)q.K * q.bp * 4,
+                                         (size_t)q.ld * 4, 0,
+                                         (size_t)(q.ld - (int64_t)q.K * q.bp) * 4, (size_t)q.m, s);
             bp.scale = 1.0f / (float)q.K;
             const int32_t T = (int32_t)((q.m + tile - 1) / tile);
             for (int32_t i = 0; i < T; ++i)
@@ -365,7 +370,9 @@ os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void
         for (size_t t = 0; t < items.size(); ++t)
             tiles[(size_t)fill[(size_t)owner[t]]++] =
                 make_int4(items[t].prob, items[t].ti, items[t].tj, 0);
-        hipError_t e = hipMemcpyAsync(at(workspace, plan->desc_off), desc.data(),
+        hipError_t e = e_pad;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(at(workspace, plan->desc_off), desc.data(),
                                       desc.size() * sizeof(osk::BatchProblem),
                                       hipMemcpyHostToDevice, s);
         if (e == hipSuccess)

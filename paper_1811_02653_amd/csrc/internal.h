@@ -156,9 +156,10 @@ hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int
 
 // One problem of a batched symmetric block product (device-resident): the
 // sketch S stores only the kept blocks, so its first ksteps * 32 columns
-// (ksteps = K * bp / 32) are summed over.
+// are summed over (ksteps = K * bp / 32 rounded up to even; the columns past
+// K * bp are zero).
 struct BatchProblem {
-    const float* S;      // line-major sketch, m x (K*bp), ld (floats, multiple of 4)
+    const float* S;      // line-major sketch, m x (ksteps*32), ld (floats, multiple of 4)
     float* H;            // output m x m, ld ldh
     int64_t ld;
     int64_t ldh;
