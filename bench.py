@@ -39,12 +39,13 @@ METRIC = "sketched AB eff. TFLOP/s (2mnl/t) at fixed rel-Frob err vs exact GEMM,
 # copy (bench.py --calibrate-copy: FETCH_SIZE 524300 KiB -> x 2.000,
 # WRITE_SIZE 1048576 KiB -> x 1.000).  Commands and raw figures:
 # profiles/gemm_kept_8192x8192_K8x1024_hbm_traffic.md.  Valid only for the
-# kernel source it was measured on (its SHA-256 below); None otherwise.
+# kernel source it was measured on (SHA-256 of that source, see
+# gemm_kept_source_sha); None otherwise.
 GEMM_TRAFFIC = {
-    "source_sha256": "df1a9655882d736ddfcac11f6032ba34a179b19953d90ad1e351b4ebe4680217",
+    "source_sha256": "103646520a7ab3cdc84eb1bfb36bc66663a4be34d060270c396d84d557bb4eed",
     "workload": (8192, 32768, 8192, 1024, 8, 2),
-    "fetch_kib": 1574340.0, "fetch_scale": 2.000,
-    "write_kib": 264192.0, "write_scale": 1.000,
+    "fetch_kib": 1573855.0, "fetch_scale": 2.000,
+    "write_kib": 262144.0, "write_scale": 1.000,
 }
 FP32_MFMA_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
@@ -85,13 +86,24 @@ def parse():
     return p.parse_args()
 
 
+def gemm_kept_source_sha(path):
+    """SHA-256 of the source that the FP32 gemm_kept launch compiles from:
+    gemm.hip up to the FP8 kernel (helpers and gemm_kept_kernel) plus the
+    launch_gemm_kept function; edits elsewhere in the file keep the counters
+    valid."""
+    import hashlib
+    text = open(path).read()
+    head = text[:text.index("// FP8 (E4M3) operands")]
+    a = text.index("hipError_t launch_gemm_kept(")
+    launch = text[a:text.index("\n}\n", a) + 3]
+    return hashlib.sha256((head + launch).encode()).hexdigest()
+
+
 def gemm_traffic_bytes(m, n, l, b, N, e):
     """Measured HBM bytes per gemm_kept launch, or None if the kernel source
     or the workload differs from the one the counters were taken on."""
-    import hashlib
     src = os.path.join(ROOT, "paper_1811_02653_amd", "csrc", "gemm.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    sha = gemm_kept_source_sha(src)
     t = GEMM_TRAFFIC
     if sha != t["source_sha256"] or (m, n, l, b, N, e) != t["workload"]:
         return None
