@@ -164,14 +164,15 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // feeding one 32x32x16 MFMA); A and B use the same K order.
 struct PrecF32 {
     static constexpr int kElem = 4;
-    __device__ static __forceinline__ void mfma_quad(v16f (&acc)[4][4], const float4 (&a)[4],
-                                                     const float4 (&b)[4]) {
+    template <int kI, int kJ>
+    __device__ static __forceinline__ void mfma_quad(v16f (&acc)[kI][kJ], const float4 (&a)[kI],
+                                                     const float4 (&b)[kJ]) {
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < kI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < kJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(a[i], kk), comp(b[j], kk),
                                                                      acc[i][j], 0, 0, 0);
     }
@@ -179,12 +180,13 @@ struct PrecF32 {
 
 struct PrecBF16 {
     static constexpr int kElem = 2;
-    __device__ static __forceinline__ void mfma_quad(v16f (&acc)[4][4], const float4 (&a)[4],
-                                                     const float4 (&b)[4]) {
+    template <int kI, int kJ>
+    __device__ static __forceinline__ void mfma_quad(v16f (&acc)[kI][kJ], const float4 (&a)[kI],
+                                                     const float4 (&b)[kJ]) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < kI; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < kJ; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                     __builtin_bit_cast(bf16x8, a[i]), __builtin_bit_cast(bf16x8, b[j]), acc[i][j],
                     0, 0, 0);
@@ -212,8 +214,16 @@ struct CMask {
 // kOdd: the K step count may be odd (always with per-C-block masks, whose
 // count varies per tile): the pair loop's second step is then masked.  With
 // an even count the mask is left out (it costs about 4 % of the MFMA rate).
+// Eight waves per 256x256 tile, two per SIMD: wave (wm, wn) (wm < 2,
+// wn < 4) computes rows 128 wm .. +127 and columns 64 wn .. +63 with 4x2
+// MFMA blocks of 32x32 (128 accumulators).  With two waves on a SIMD, one
+// wave's memory instructions issue while the other's MFMAs keep the pipe
+// busy (one wave per SIMD left the pipe idle for about one MFMA slot per
+// memory instruction).
+constexpr int kThreadsK = 512;
+
 template <typename P, bool kMask, bool kOdd>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(kThreadsK) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __restrict__ Bt,
                       int64_t ldbt, int64_t m, int64_t l, int32_t bp, BlockList kept,
                       int32_t nkept, int32_t nsub, int64_t lo_off, float scale,
@@ -231,8 +241,8 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = wave >> 1;
-    const int wn = wave & 1;
+    const int wm = wave >> 2;
+    const int wn = wave & 3;
 
     const int64_t ntiles = (int64_t)tilesM * tilesN;
     const int64_t T = xcd_task(blockIdx.x, ntiles);
@@ -262,7 +272,7 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         __syncthreads();
         nkept = __builtin_amdgcn_readfirstlane(klist[OS_MAX_BLOCKS]);
         if (nkept == 0) {
-            for (int64_t r = row0 + (tid >> 6); r < min(m, row0 + BM); r += kThreads / 64)
+            for (int64_t r = row0 + (tid >> 6); r < min(m, row0 + BM); r += kThreadsK / 64)
                 for (int64_t c = col0 + lane; c < min(l, col0 + BN); c += 64) C[r * ldc + c] = 0.f;
             return;
         }
@@ -288,11 +298,11 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         return j < 64 ? r0 : (j < 128 ? r1 : (j < 192 ? r2 : r3));
     };
 
-    v16f acc[4][4];
+    v16f acc[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
@@ -314,33 +324,33 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         tile_rsrc(static_cast<const char*>(At) + row0 * ldat * P::kElem);
     const __amdgpu_buffer_rsrc_t rb_src =
         tile_rsrc(static_cast<const char*>(Bt) + col0 * ldbt * P::kElem);
-    uint32_t va[8], vb[8];
-    direct_offsets<8>(va, ldat * P::kElem, (int)min((int64_t)BM - 1, m - 1 - row0), wave, lane);
-    direct_offsets<8>(vb, ldbt * P::kElem, (int)min((int64_t)BN - 1, l - 1 - col0), wave, lane);
+    // 256 tile rows per operand and step: 4 direct loads per wave
+    uint32_t va[4], vb[4];
+    direct_offsets<4>(va, ldat * P::kElem, (int)min((int64_t)BM - 1, m - 1 - row0), wave, lane);
+    direct_offsets<4>(vb, ldbt * P::kElem, (int)min((int64_t)BN - 1, l - 1 - col0), wave, lane);
     int fa_off[4], fb_off[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         fa_off[q] = direct_frag_off(wm * 128 + (lane & 31), q, lane);
-        fb_off[q] = direct_frag_off(wn * 128 + (lane & 31), q, lane);
+        fb_off[q] = direct_frag_off(wn * 64 + (lane & 31), q, lane);
     }
-    auto frag = [&](float4 (&a)[4], float4 (&b)[4], const float* as, const float* bs, int q) {
+    auto frag = [&](float4 (&a)[4], float4 (&b)[2], const float* as, const float* bs, int q) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            a[i] = *reinterpret_cast<const float4*>(as + fa_off[q] + 1024 * i);
-            b[i] = *reinterpret_cast<const float4*>(bs + fb_off[q] + 1024 * i);
-        }
+        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const float4*>(as + fa_off[q] + 1024 * i);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const float4*>(bs + fb_off[q] + 1024 * j);
     };
     auto issue = [&](float* as, float* bs, int step) {
         uint32_t ka, kb;
         step_ab(step, ka, kb);
-        direct_issue<8>(ra_src, as, va, ka, wave);
-        direct_issue<8>(rb_src, bs, vb, kb, wave);
+        direct_issue<4>(ra_src, as, va, ka, wave);
+        direct_issue<4>(rb_src, bs, vb, kb, wave);
     };
 
     issue(As0, Bs0, 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    float4 fa[4], fb[4], ga[4], gb[4];
+    float4 fa[4], fb[2], ga[4], gb[2];
     frag(fa, fb, As0, Bs0, 0);
     // One K step: the next step's tiles go straight into the other buffers
     // (last read before the previous step's barrier) while this step's four
@@ -355,15 +365,15 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         __builtin_amdgcn_sched_barrier(0);
         frag(ga, gb, as, bs, 1);
         if constexpr (kOdd) zero_unless(fa, live);
-        P::mfma_quad(acc, fa, fb);
+        P::template mfma_quad<4, 2>(acc, fa, fb);
         frag(fa, fb, as, bs, 2);
         if constexpr (kOdd) zero_unless(ga, live);
-        P::mfma_quad(acc, ga, gb);
+        P::template mfma_quad<4, 2>(acc, ga, gb);
         frag(ga, gb, as, bs, 3);
         if constexpr (kOdd) zero_unless(fa, live);
-        P::mfma_quad(acc, fa, fb);
+        P::template mfma_quad<4, 2>(acc, fa, fb);
         if constexpr (kOdd) zero_unless(ga, live);
-        P::mfma_quad(acc, ga, gb);
+        P::template mfma_quad<4, 2>(acc, ga, gb);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         frag(fa, fb, na, nb, 0);
@@ -378,8 +388,8 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t col = col0 + wn * 128 + j * 32 + (lane & 31);
+        for (int j = 0; j < 2; ++j) {
+            const int64_t col = col0 + wn * 64 + j * 32 + (lane & 31);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = row0 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -717,7 +727,7 @@ hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int6
     const int64_t tilesN = (l + BN - 1) / BN;
     const bool odd = ((int64_t)nkept * (bp / 32)) % 2 != 0;
     auto kern = odd ? gemm_kept_kernel<PrecF32, false, true> : gemm_kept_kernel<PrecF32, false, false>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads), 0, s, At, ldat,
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreadsK), 0, s, At, ldat,
                        Bt, ldbt, m, l, bp, kept, nkept, 1, (int64_t)0, scale, C, ldc,
                        (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1});
     return hipGetLastError();
@@ -735,7 +745,7 @@ hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int
     BlockList none;
     for (int j = 0; j < OS_MAX_BLOCKS; ++j) none.idx[j] = 0;
     hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, true, true>), dim3((unsigned)(tilesM * tilesN)),
-                       dim3(kThreads), 0, s, At, ldat, Bt, ldbt, m, l, bp, none, 0, 1, (int64_t)0, 1.0f, C, ldc,
+                       dim3(kThreadsK), 0, s, At, ldat, Bt, ldbt, m, l, bp, none, 0, 1, (int64_t)0, 1.0f, C, ldc,
                        (int32_t)tilesM, (int32_t)tilesN,
                        CMask{cmask, cblk, (int32_t)nbJ, nst, (int32_t)tb});
     return hipGetLastError();
@@ -789,7 +799,7 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
     const int64_t tilesN = (l + BN - 1) / BN;
     const bool odd = ((int64_t)nkept * (split ? 3 : 1) * (bp / 64)) % 2 != 0;
     auto kern = odd ? gemm_kept_kernel<PrecBF16, false, true> : gemm_kept_kernel<PrecBF16, false, false>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads), 0, s, At, ldat,
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreadsK), 0, s, At, ldat,
                        Bt, ldbt, m, l, bp, kept, nkept, split ? 3 : 1, lo_off, scale, C, ldc,
                        (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1});
     return hipGetLastError();
