@@ -135,6 +135,12 @@ def bench_hessian_batch(torch, osk, args, stream, reps):
                        stream=stream)
     tuned_ms = gb.autotune(reps=2, stream=stream)
     tile, grid = gb.config
+    # the product alone for each tile side (the autotuner times whole runs)
+    by_tile = {}
+    for t in (256, 128):
+        gb.configure(t, 0, stream=stream)
+        by_tile[t] = event_time_ms(torch, lambda: gb.run(PRODUCT, stream=stream), reps, stream)
+    gb.configure(tile, grid, stream=stream)
     g = gb.graph()                      # captured on a private stream
     t_graph = event_time_ms(torch, lambda: g.launch(stream), reps, stream)
     t_eager = event_time_ms(torch, lambda: gb.run(stream=stream), reps, stream)
@@ -171,6 +177,7 @@ def bench_hessian_batch(torch, osk, args, stream, reps):
                     "b_k = ceil(m_k/2), N=6, e=1, one block dropped per problem",
         "m_k": sizes, "input_gb": sum(4.0 * m * 20 * m for m in sizes) / 1e9,
         "tile": tile, "grid": grid, "autotune_ms": tuned_ms,
+        "product_ms_by_tile": by_tile,
         "ms_per_batch": t_graph, "ms_per_batch_eager": t_eager,
         "hessians_per_s": count / (t_graph * 1e-3),
         "eff_tflops": exact_flops / (t_graph * 1e-3) / 1e12,

@@ -579,36 +579,31 @@ void gemm_kept_fp8_kernel(const uint8_t* __restrict__ At, int64_t ldat, const ui
 //   host; every wave reaches its end), computing each with the same FP32
 //   MFMA pipeline as above; an off-diagonal tile is also stored
 //   transposed (mirror) when `full`.
-// kWT: MFMA blocks of 32 x 32 per wave side -- 4 (256 x 256 tiles) or 2
-// (128 x 128 tiles: less padding on small problems, two workgroups per CU).
+// kWT = 4: 256 x 256 tiles, eight waves of 128 x 64 (two per SIMD, as in
+// gemm_kept_kernel); kWT = 2: 128 x 128 tiles, four waves of 64 x 64 and two
+// workgroups per CU (less padding on small problems).
 // ---------------------------------------------------------------------------
 template <int kWT>
 struct TileShape {
-    static constexpr int BT = 64 * kWT;       // tile side
-    static constexpr int kU = BT / 32;        // 16-byte loads per thread per operand
+    static constexpr int BT = 64 * kWT;                // tile side
+    static constexpr int kWaves = 2 * kWT;             // 8 (256 tiles) or 4 (128 tiles)
+    static constexpr int kThreads = 64 * kWaves;
+    static constexpr int kI = kWT;                     // 32x32 blocks per wave: rows
+    static constexpr int kJ = 2;                       //   and columns
+    static constexpr int kU = BT / (8 * kWaves);       // direct loads per wave per operand
 };
 
-template <int kWT>
-__device__ __forceinline__ void mfma_rows(v16f (&acc)[kWT][kWT], const float4 (&a)[kWT],
-                                          const float4 (&b)[kWT]) {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int i = 0; i < kWT; ++i)
-#pragma unroll
-            for (int j = 0; j < kWT; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(a[i], kk), comp(b[j], kk),
-                                                                 acc[i][j], 0, 0, 0);
-}
 
 template <int kWT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 5 - kWT)))
+__global__ __launch_bounds__(TileShape<kWT>::kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
                            const int4* __restrict__ tiles, const int32_t* __restrict__ starts,
                            int full) {
     using TS = TileShape<kWT>;
     constexpr int BT = TS::BT;
     constexpr int kU = TS::kU;
+    constexpr int kI = TS::kI;
+    constexpr int kJ = TS::kJ;
     // direct tiles as in gemm_kept_kernel: separate arrays per buffer
     __shared__ __align__(1024) float As0[BT * 32];
     __shared__ __align__(1024) float As1[BT * 32];
@@ -618,20 +613,19 @@ void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = wave >> 1;
-    const int wn = wave & 1;
+    const int wm = wave / (TS::kWaves / 2);      // 2 waves along the rows
+    const int wn = wave % (TS::kWaves / 2);      // kWaves / 2 along the columns
     int fa_off[4], fb_off[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        fa_off[q] = direct_frag_off(wm * (BT / 2) + (lane & 31), q, lane);
-        fb_off[q] = direct_frag_off(wn * (BT / 2) + (lane & 31), q, lane);
+        fa_off[q] = direct_frag_off(wm * 32 * kI + (lane & 31), q, lane);
+        fb_off[q] = direct_frag_off(wn * 32 * kJ + (lane & 31), q, lane);
     }
-    auto frag = [&](float4 (&a)[kWT], float4 (&b)[kWT], const float* as, const float* bs, int q) {
+    auto frag = [&](float4 (&a)[kI], float4 (&b)[kJ], const float* as, const float* bs, int q) {
 #pragma unroll
-        for (int i = 0; i < kWT; ++i) {
-            a[i] = *reinterpret_cast<const float4*>(as + fa_off[q] + 1024 * i);
-            b[i] = *reinterpret_cast<const float4*>(bs + fb_off[q] + 1024 * i);
-        }
+        for (int i = 0; i < kI; ++i) a[i] = *reinterpret_cast<const float4*>(as + fa_off[q] + 1024 * i);
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) b[j] = *reinterpret_cast<const float4*>(bs + fb_off[q] + 1024 * j);
     };
 
     const int32_t w_end = starts[blockIdx.x + 1];
@@ -652,11 +646,11 @@ void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
             direct_issue<kU>(rb_src, bs, vb, (uint32_t)step * kStepBytes, wave);
         };
 
-        v16f acc[kWT][kWT];
+        v16f acc[kI][kJ];
 #pragma unroll
-        for (int i = 0; i < kWT; ++i)
+        for (int i = 0; i < kI; ++i)
 #pragma unroll
-            for (int j = 0; j < kWT; ++j)
+            for (int j = 0; j < kJ; ++j)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
@@ -666,18 +660,18 @@ void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
 
-        float4 fa[kWT], fb[kWT], ga[kWT], gb[kWT];
+        float4 fa[kI], fb[kJ], ga[kI], gb[kJ];
         frag(fa, fb, As0, Bs0, 0);
         auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t) {
             issue(na, nb, min(t + 1, total - 1));
             __builtin_amdgcn_sched_barrier(0);
             frag(ga, gb, as, bs, 1);
-            mfma_rows<kWT>(acc, fa, fb);
+            PrecF32::mfma_quad<kI, kJ>(acc, fa, fb);
             frag(fa, fb, as, bs, 2);
-            mfma_rows<kWT>(acc, ga, gb);
+            PrecF32::mfma_quad<kI, kJ>(acc, ga, gb);
             frag(ga, gb, as, bs, 3);
-            mfma_rows<kWT>(acc, fa, fb);
-            mfma_rows<kWT>(acc, ga, gb);
+            PrecF32::mfma_quad<kI, kJ>(acc, fa, fb);
+            PrecF32::mfma_quad<kI, kJ>(acc, ga, gb);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             frag(fa, fb, na, nb, 0);
@@ -689,13 +683,13 @@ void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
 
         const bool mirror = full && tl.y != tl.z;
 #pragma unroll
-        for (int i = 0; i < kWT; ++i) {
+        for (int i = 0; i < kI; ++i) {
 #pragma unroll
-            for (int j = 0; j < kWT; ++j) {
-                const int64_t col = col0 + wn * (BT / 2) + j * 32 + (lane & 31);
+            for (int j = 0; j < kJ; ++j) {
+                const int64_t col = col0 + wn * 32 * kJ + j * 32 + (lane & 31);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int64_t row = row0 + wm * (BT / 2) + i * 32 + 8 * (r >> 2) +
+                    const int64_t row = row0 + wm * 32 * kI + i * 32 + 8 * (r >> 2) +
                                         4 * (lane >> 5) + (r & 3);
                     if (row < m && col < m) {
                         const float v = acc[i][j][r] * pr.scale;
@@ -756,10 +750,12 @@ hipError_t launch_gemm_batch_sym(const BatchProblem* probs, const int4* tiles,
                                  hipStream_t s) {
     if (grid < 1) return hipErrorInvalidValue;
     if (tile == 256)
-        hipLaunchKernelGGL(gemm_batch_sym_kernel<4>, dim3((unsigned)grid), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL(gemm_batch_sym_kernel<4>, dim3((unsigned)grid),
+                           dim3(TileShape<4>::kThreads), 0, s,
                            probs, tiles, starts, full);
     else if (tile == 128)
-        hipLaunchKernelGGL(gemm_batch_sym_kernel<2>, dim3((unsigned)grid), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL(gemm_batch_sym_kernel<2>, dim3((unsigned)grid),
+                           dim3(TileShape<2>::kThreads), 0, s,
                            probs, tiles, starts, full);
     else
         return hipErrorInvalidValue;
@@ -770,9 +766,11 @@ int batch_sym_blocks_per_cu(int tile) {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     if (tile == 256)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_batch_sym_kernel<4>, kThreads, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_batch_sym_kernel<4>,
+                                                         TileShape<4>::kThreads, 0);
     else if (tile == 128)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_batch_sym_kernel<2>, kThreads, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_batch_sym_kernel<2>,
+                                                         TileShape<2>::kThreads, 0);
     return e == hipSuccess ? n : 0;
 }
 
