@@ -309,6 +309,28 @@ os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const
                          const uint8_t* keep_host, int kept_only, int precision, float* C,
                          int64_t ldc, void* workspace, size_t ws_bytes, void* stream);
 
+/* Workspace bytes os_matmul_ex needs for the given operand layouts and
+ * precision (0 on invalid arguments). */
+size_t os_matmul_ex_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
+                                    int a_col_major, int b_col_major, int precision);
+
+/* The whole path with more operand layouts and types: A m x n, row-major
+ * (a_col_major = 0, element (r, k) at A[r*lda + k]) or column-major
+ * (a_col_major = 1, at A[k*lda + r], lda >= m); B n x l as in os_matmul.
+ * a_dtype / b_dtype: OS_DTYPE_F32, or OS_DTYPE_BF16 for an operand that is
+ * transposed before its sketch (a column-major A, a row-major B; it is
+ * converted exactly to FP32 on the way, 2-byte aligned, ld in values); other
+ * BF16 layouts give OS_EINVAL.  With A = X^T for a row-major X (n x m: A is
+ * X read as column-major) and B = dY this is the sketched weight gradient of
+ * a linear layer, X^T S S^T dY, sketched over the n tokens (the product of
+ * Section 4 with the tokens as the inner dimension).  Other arguments as in
+ * os_matmul_prec; workspace >= os_matmul_ex_workspace_bytes. */
+os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_col_major,
+                       int64_t lda, const void* B, int b_dtype, int b_col_major, int64_t ldb,
+                       int64_t m, int64_t n, int64_t l, const uint8_t* keep_host, int kept_only,
+                       int precision, float* C, int64_t ldc, void* workspace, size_t ws_bytes,
+                       void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched sketched Gram matrices: the Hessian sketch of the interior-point
  * application (Section 5.2, Eq. (int_point) and the Hessian after it).  The

@@ -19,7 +19,7 @@ __all__ = [
     "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "sketch_cols",
     "sketch_rows", "sketch_rows_workspace_bytes", "gemm_kept", "matmul", "workspace_bytes",
     "stored_count", "PRECISIONS", "block_stride_prec", "quantized_row", "sketch_quantize",
-    "gemm_kept_prec", "gemm_kept_cmask", "matmul_cmask", "GramBatch",
+    "gemm_kept_prec", "gemm_kept_cmask", "matmul_cmask", "matmul_ex", "GramBatch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -127,6 +127,13 @@ def lib():
     L.os_matmul_prec.restype = ctypes.c_int
     L.os_matmul_prec.argtypes = [sk, vp, i64, vp, i64, ctypes.c_int, i64, i64, i64, vp,
                                  ctypes.c_int, ctypes.c_int, vp, i64, vp, sz, vp]
+    L.os_matmul_ex_workspace_bytes.restype = sz
+    L.os_matmul_ex_workspace_bytes.argtypes = [sk, i64, i64, i64, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int]
+    L.os_matmul_ex.restype = ctypes.c_int
+    L.os_matmul_ex.argtypes = [sk, vp, ctypes.c_int, ctypes.c_int, i64, vp, ctypes.c_int,
+                               ctypes.c_int, i64, i64, i64, i64, vp, ctypes.c_int, ctypes.c_int,
+                               vp, i64, vp, sz, vp]
     gp = ctypes.POINTER(_GramProblem)
     L.os_gram_plan_create.restype = ctypes.c_int
     L.os_gram_plan_create.argtypes = [gp, i32, ctypes.c_int, ctypes.POINTER(vp)]
@@ -530,6 +537,56 @@ def matmul_cmask(A, B, b, N, e, cmask, seed=0, h=None, sigma=None, out=None, wor
                                  l, _ptr(cm), _ptr(out), ldc, _ptr(workspace),
                                  workspace.numel() * workspace.element_size(), _stream(stream)),
            "os_matmul_cmask")
+    return out
+
+
+def _layout(t, name):
+    """(dtype code, col_major, rows, cols, ld) of a 2-D float32 / bfloat16
+    tensor with unit stride along one of its dimensions."""
+    torch = _torch()
+    _require_cuda(t, name)
+    if t.dtype == torch.float32:
+        code = 0
+    elif t.dtype == torch.bfloat16:
+        code = 1
+    else:
+        raise OversketchError("%s must be float32 or bfloat16" % name)
+    if t.dim() != 2:
+        raise OversketchError("%s must be 2-D" % name)
+    rows, cols = t.shape
+    if t.stride(1) == 1 and (rows == 1 or t.stride(0) >= cols):
+        return code, 0, rows, cols, t.stride(0) if rows > 1 else max(cols, 1)
+    if t.stride(0) == 1 and (cols == 1 or t.stride(1) >= rows):
+        return code, 1, rows, cols, t.stride(1) if cols > 1 else max(rows, 1)
+    raise OversketchError("%s must have unit stride along one dimension" % name)
+
+
+def matmul_ex(A, B, b, N, e, seed=0, keep=None, kept_only=False, precision="fp32", h=None,
+              sigma=None, out=None, workspace=None, stream=None):
+    """os_matmul_ex: C ~= A S S^T B for A (m x n) and B (n x l) given as
+    float32 or bfloat16 tensors, row- or column-major (a transposed view is
+    column-major).  BF16 is accepted for a column-major A and a row-major B.
+    Returns C (m x l, float32)."""
+    torch = _torch()
+    ad, acm, m, n, lda = _layout(A, "A")
+    bd, bcm, n2, l, ldb = _layout(B, "B")
+    if n2 != n:
+        raise OversketchError("inner dimensions differ")
+    sk = _sketch(b, N, e, seed, h, sigma)
+    arr, kp = _mask(keep, int(N) + int(e))
+    prec = _prec(precision)
+    L = lib()
+    need = int(L.os_matmul_ex_workspace_bytes(ctypes.byref(sk), m, n, l, acm, bcm, prec))
+    if need == 0:
+        raise OversketchError("invalid sizes or sketch parameters")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+    if out is None:
+        out = torch.empty((m, l), dtype=torch.float32, device=A.device)
+    _, _, ldc = _row_major(out, "out")
+    _check(L.os_matmul_ex(ctypes.byref(sk), _ptr(A), ad, acm, lda, _ptr(B), bd, bcm, ldb, m, n, l,
+                          kp, 1 if kept_only else 0, prec, _ptr(out), ldc, _ptr(workspace),
+                          workspace.numel(), _stream(stream)), "os_matmul_ex")
     return out
 
 

@@ -19,31 +19,22 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import OversketchError, block_stride, gemm_kept, gemm_kept_prec, sketch_prepare, \
-    sketch_quantize, sketch_rows, stored_count
+from . import OversketchError, matmul_ex
 
 
 def sketched_weight_grad(X, dY, b, N, e, seed=0, keep=None, precision="fp32", h=None,
-                         sigma=None, stream=None):
+                         sigma=None, stream=None, workspace=None):
     """(1/K) sum_{kept i} (S_i^T X)^T (S_i^T dY)  (d_in x d_out, float32):
     the count sketch runs over the rows (tokens) of X and dY (hashed from
-    seed, or explicit tables h / sigma as in the library)."""
-    import torch
+    seed, or explicit tables h / sigma as in the library).  One library call
+    (os_matmul_ex with A = X^T, read column-major, and B = dY): prepare,
+    transpose-and-sketch of X and of dY (dropped blocks skipped), the block
+    product in the given precision."""
     if X.dim() != 2 or dY.dim() != 2 or X.shape[0] != dY.shape[0]:
         raise OversketchError("X and dY must be 2-D with the same number of rows")
-    n = X.shape[0]
-    prep = sketch_prepare(n, b, N, e, seed, h=h, sigma=sigma, device=X.device, stream=stream)
     kept_keep = None if keep is None else np.asarray(keep, dtype=np.uint8)
-    Xs = sketch_rows(X, b, N, e, seed=seed, keep=kept_keep, kept_only=True, h=h, sigma=sigma,
-                     prep=prep, workspace=True, stream=stream)
-    Ds = sketch_rows(dY, b, N, e, seed=seed, keep=kept_keep, kept_only=True, h=h, sigma=sigma,
-                     prep=prep, workspace=True, stream=stream)
-    nst = stored_count(N, e, kept_keep, kept_only=True)
-    if precision == "fp32":
-        return gemm_kept(Xs, Ds, b, stream=stream)
-    QX = sketch_quantize(Xs, b, nst, precision=precision, stream=stream)
-    QD = sketch_quantize(Ds, b, nst, precision=precision, stream=stream)
-    return gemm_kept_prec(QX, QD, b, nst, precision=precision, stream=stream)
+    return matmul_ex(X.t(), dY, b, N, e, seed=seed, keep=kept_keep, kept_only=True,
+                     precision=precision, h=h, sigma=sigma, workspace=workspace, stream=stream)
 
 
 class SketchedLinearFunction:

@@ -3,6 +3,8 @@
 // termination keeps any N of the N+e blocks; K kept blocks are weighted
 // 1/K), workspace carving and the launch sequence.  Every check happens
 // before the first launch of a call.
+#include <algorithm>
+
 #include "api_common.h"
 
 namespace {
@@ -270,20 +272,29 @@ os_status os_gemm_kept_prec(const void* At, int64_t ldat, const void* Bt, int64_
                                                  1.0f / (float)K, C, ldc, (hipStream_t)stream));
 }
 
-size_t os_matmul_prec_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
-                                      int b_col_major, int precision) {
+size_t os_matmul_ex_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
+                                    int a_col_major, int b_col_major, int precision) {
     if (check_sketch(sk) != OS_OK || check_len(n) != OS_OK || check_extent(m) != OS_OK ||
         check_extent(l) != OS_OK || !valid_prec(precision))
         return 0;
     // Sized for all N+e blocks whatever the mask, so one workspace serves
-    // every call; a row-major B is transposed first; a low-precision product
-    // adds the quantized copies of both sketches.
+    // every call; an operand whose lines are not rows in memory (a
+    // column-major A, a row-major B) is transposed first, one after the
+    // other, into one buffer; a low-precision product adds the quantized
+    // copies of both sketches.
     const int64_t zp = (int64_t)nblocks(sk) * os_block_stride(sk->b);
     const int64_t qrow = quant_row_bytes(osk::round_up(quant_width(sk->b, nblocks(sk), precision),
                                                        16), precision);
+    const size_t tx = std::max(a_col_major ? osk::transpose_bytes(n, m) : 0,
+                               b_col_major ? 0 : osk::transpose_bytes(n, l));
     return align256(prepare_bytes(sk, n)) + align256((size_t)m * zp * 4u) +
-           align256((size_t)l * zp * 4u) + (b_col_major ? 0 : osk::transpose_bytes(n, l)) +
-           align256((size_t)m * qrow) + align256((size_t)l * qrow);
+           align256((size_t)l * zp * 4u) + tx + align256((size_t)m * qrow) +
+           align256((size_t)l * qrow);
+}
+
+size_t os_matmul_prec_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
+                                      int b_col_major, int precision) {
+    return os_matmul_ex_workspace_bytes(sk, m, n, l, 0, b_col_major, precision);
 }
 
 size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
@@ -291,25 +302,42 @@ size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int6
     return os_matmul_prec_workspace_bytes(sk, m, n, l, b_col_major, OS_PREC_FP32);
 }
 
-os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const float* B,
-                         int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
-                         const uint8_t* keep_host, int kept_only, int precision, float* C,
-                         int64_t ldc, void* workspace, size_t ws_bytes, void* stream) {
+os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_col_major,
+                       int64_t lda, const void* B, int b_dtype, int b_col_major, int64_t ldb,
+                       int64_t m, int64_t n, int64_t l, const uint8_t* keep_host, int kept_only,
+                       int precision, float* C, int64_t ldc, void* workspace, size_t ws_bytes,
+                       void* stream) {
     os_status st = check_sketch(sk);
     if (st != OS_OK) return st;
     if (!valid_prec(precision)) return OS_EINVAL;
+    // BF16 operands are read only by the transpose that precedes their sketch
+    if ((a_dtype != OS_DTYPE_F32 && a_dtype != OS_DTYPE_BF16) ||
+        (b_dtype != OS_DTYPE_F32 && b_dtype != OS_DTYPE_BF16) ||
+        (a_dtype == OS_DTYPE_BF16 && !a_col_major) || (b_dtype == OS_DTYPE_BF16 && b_col_major))
+        return OS_EINVAL;
     if ((st = check_len(n)) != OS_OK) return st;
     if ((st = check_extent(m)) != OS_OK || (st = check_extent(l)) != OS_OK) return st;
-    if ((st = check_matrix(A, m, n, lda, false)) != OS_OK) return st;
-    if (b_col_major) {
-        if ((st = check_matrix(B, l, n, ldb, false)) != OS_OK) return st;
+    auto check_op = [](const void* p, int dtype, int64_t rows, int64_t cols, int64_t ld) {
+        if (dtype == OS_DTYPE_F32) return check_matrix(p, rows, cols, ld, false);
+        if (!p) return OS_ENULL;
+        if (rows < 1 || cols < 1 || ld < cols) return OS_EINVAL;
+        return aligned(p, 2) ? OS_OK : OS_EALIGN;
+    };
+    if (a_col_major) {
+        if ((st = check_op(A, a_dtype, n, m, lda)) != OS_OK) return st;
     } else {
-        if ((st = check_matrix(B, n, l, ldb, false)) != OS_OK) return st;
+        if ((st = check_op(A, a_dtype, m, n, lda)) != OS_OK) return st;
+    }
+    if (b_col_major) {
+        if ((st = check_op(B, b_dtype, l, n, ldb)) != OS_OK) return st;
+    } else {
+        if ((st = check_op(B, b_dtype, n, l, ldb)) != OS_OK) return st;
     }
     if ((st = check_matrix(C, m, l, ldc, false)) != OS_OK) return st;
     Blocks bs;
     if ((st = block_sets(sk, keep_host, kept_only, bs)) != OS_OK) return st;
-    const size_t need = os_matmul_prec_workspace_bytes(sk, m, n, l, b_col_major, precision);
+    const size_t need =
+        os_matmul_ex_workspace_bytes(sk, m, n, l, a_col_major, b_col_major, precision);
     if (!workspace || !aligned(workspace, 256) || ws_bytes < need) return OS_EWORKSPACE;
     const int32_t bp = os_block_stride(sk->b);
     const int32_t bpq = quant_stride(sk->b, precision);
@@ -328,34 +356,48 @@ os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const
     const int64_t zp = (int64_t)nblocks(sk) * bp;
     const int64_t wqp = quant_row_bytes(
         osk::round_up(quant_width(sk->b, nblocks(sk), precision), 16), precision);
+    const size_t tx = std::max(a_col_major ? osk::transpose_bytes(n, m) : 0,
+                               b_col_major ? 0 : osk::transpose_bytes(n, l));
     char* ws = static_cast<char*>(workspace);
     void* prep = ws;
     char* at_p = ws + align256(prepare_bytes(sk, n));
     char* bt_p = at_p + align256((size_t)m * zp * 4u);
-    char* bx_p = bt_p + align256((size_t)l * zp * 4u);
-    char* aq_p = bx_p + (b_col_major ? 0 : osk::transpose_bytes(n, l));
+    char* tx_p = bt_p + align256((size_t)l * zp * 4u);
+    char* aq_p = tx_p + tx;
     char* bq_p = aq_p + align256((size_t)m * wqp);
     float* At = reinterpret_cast<float*>(at_p);
     float* Bt = reinterpret_cast<float*>(bt_p);
     hipStream_t s = (hipStream_t)stream;
     const void* lists = prep_lists(prep, sk, n);
 
+    // An operand's lines (rows of A, columns of B) are sketched as rows in
+    // memory: a column-major A and a row-major B are transposed first
+    // (BF16 converted exactly to FP32 on the way), so that every sketch reads
+    // whole lines (16-byte requests along a column would each bring in a
+    // separate cache line).
+    auto lines_of = [&](const void* X, int dtype, int64_t rows, int64_t cols, int64_t ldx,
+                        const float** out, int64_t* ldo) -> os_status {
+        const int64_t ldy = osk::round_up(rows, 4);
+        float* Y = reinterpret_cast<float*>(tx_p);
+        const hipError_t e =
+            dtype == OS_DTYPE_BF16
+                ? osk::launch_transpose_bf16(X, rows, cols, ldx, Y, ldy, s)
+                : osk::launch_transpose(static_cast<const float*>(X), rows, cols, ldx, Y, ldy, s);
+        *out = Y;
+        *ldo = ldy;
+        return hip_status(e);
+    };
     if ((st = prepare(sk, n, prep, s)) != OS_OK) return st;
-    if ((st = hip_status(osk::launch_sketch_cols(A, m, n, lda, bs.stored, bs.nst, nblocks(sk), bp,
+    const float* Al = static_cast<const float*>(A);
+    int64_t lal = lda;
+    if (a_col_major && (st = lines_of(A, a_dtype, n, m, lda, &Al, &lal)) != OS_OK) return st;
+    if ((st = hip_status(osk::launch_sketch_cols(Al, m, n, lal, bs.stored, bs.nst, nblocks(sk), bp,
                                                  lists, At, zs, s))) != OS_OK)
         return st;
-    // B's columns are the lines of its sketch: a row-major B is transposed
-    // first, so that both sketches read whole lines (16-byte requests along a
-    // column of a row-major B would each bring in a separate cache line)
-    const float* Bl = B;
-    int64_t ldl = ldb;
-    if (!b_col_major) {
-        ldl = osk::round_up(n, 4);
-        float* Bx = reinterpret_cast<float*>(bx_p);
-        if ((st = hip_status(osk::launch_transpose(B, n, l, ldb, Bx, ldl, s))) != OS_OK) return st;
-        Bl = Bx;
-    }
-    if ((st = hip_status(osk::launch_sketch_cols(Bl, l, n, ldl, bs.stored, bs.nst, nblocks(sk), bp,
+    const float* Bl = static_cast<const float*>(B);
+    int64_t lbl = ldb;
+    if (!b_col_major && (st = lines_of(B, b_dtype, n, l, ldb, &Bl, &lbl)) != OS_OK) return st;
+    if ((st = hip_status(osk::launch_sketch_cols(Bl, l, n, lbl, bs.stored, bs.nst, nblocks(sk), bp,
                                                  lists, Bt, zs, s))) != OS_OK)
         return st;
     if (precision == OS_PREC_FP32)
@@ -384,6 +426,14 @@ os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const
     return hip_status(osk::launch_gemm_kept_bf16(aq_p, wq, bq_p, wq, m, l, bpq, bs.kept_pos, bs.K,
                                                  split, (int64_t)bs.nst * bpq,
                                                  1.0f / (float)bs.K, C, ldc, s));
+}
+
+os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const float* B,
+                         int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
+                         const uint8_t* keep_host, int kept_only, int precision, float* C,
+                         int64_t ldc, void* workspace, size_t ws_bytes, void* stream) {
+    return os_matmul_ex(sk, A, OS_DTYPE_F32, 0, lda, B, OS_DTYPE_F32, b_col_major, ldb, m, n, l,
+                        keep_host, kept_only, precision, C, ldc, workspace, ws_bytes, stream);
 }
 
 os_status os_matmul_cmask(const os_sketch* sk, const float* A, int64_t lda, const float* B,

@@ -158,6 +158,119 @@ __device__ __forceinline__ void ell_build_region(const uint32_t* __restrict__ ta
     }
 }
 
+// The same region built by kBW = 4 waves (bp <= kBW4MaxBp): wave v counts
+// and scatters its own contiguous part of the window; its cursors start at
+// the entries of the earlier parts (an exclusive scan over the waves' counts
+// per bucket), so every bucket's list stays in ascending k.  LDS: per-wave
+// cursors [kBW][bp], totals [bp], group bases and lengths [qn] each.
+constexpr int kBW = 4;
+constexpr int kBW4MaxBp = 2048;
+
+__device__ __forceinline__ void ell_build_region4(const uint32_t* __restrict__ table, int64_t n,
+                                                  int64_t nt, int32_t bp, int32_t qn,
+                                                  int32_t nwin, int64_t RC,
+                                                  uint32_t* __restrict__ hdr,
+                                                  uint16_t* __restrict__ ell, int w, int64_t i,
+                                                  uint32_t* sm) {
+    uint32_t* cur = sm;                 // [kBW][bp] counts, then cursors
+    uint32_t* tot = sm + kBW * bp;      // [bp] entries per bucket
+    uint32_t* qbase = tot + bp;         // [qn] chunk base of each group
+    uint32_t* qlen = qbase + qn;        // [qn] chunk count of each group
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int64_t k0 = (int64_t)w * kWin;
+    const int kw = (int)min((int64_t)kWin, n - k0);
+    const uint32_t* row = table + i * nt + k0;
+    uint32_t* H = hdr + (i * nwin + w) * qn;
+    uint16_t* region = ell + (i * nwin + w) * RC * 512;
+    // this wave's part of the window: [t_beg, t_end)
+    const int part = ((kw + kBW - 1) / kBW + 63) / 64 * 64;
+    const int t_beg = min(kw, wv * part);
+    const int t_end = min(kw, t_beg + part);
+    uint32_t* mine = cur + wv * bp;
+
+    for (int c = tid; c < kBW * bp; c += 64 * kBW) cur[c] = 0;
+    __syncthreads();
+    for (int t = t_beg + lane; t < t_end; t += 64) atomicAdd(&mine[row[t] & 0x7FFFFFFFu], 1u);
+    __syncthreads();
+    for (int c = tid; c < bp; c += 64 * kBW) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int v = 0; v < kBW; ++v) {
+            const uint32_t x = cur[v * bp + c];
+            cur[v * bp + c] = run;
+            run += x;
+        }
+        tot[c] = run;
+    }
+    __syncthreads();
+
+    if (wv == 0) {
+        uint32_t base = 0;
+        for (int q = 0; q < qn; ++q) {
+            const int c = 64 * q + lane;
+            const uint32_t x = c < bp ? tot[c] : 0u;
+            const uint32_t nch = (wave_max(x) + 7) / 8;
+            if (lane == 0) {
+                H[q] = base | (nch << 16);
+                qbase[q] = base;
+                qlen[q] = nch;
+            }
+            base += nch;
+        }
+    }
+    __syncthreads();
+
+    // stable scatter of this wave's part, as in ell_build_region
+    int nbits = 1;
+    while ((1 << nbits) < bp) ++nbits;
+    const uint64_t below = lanes_below();
+    for (int t0 = t_beg; t0 < t_end; t0 += 64) {
+        const int t = t0 + lane;
+        const bool valid = t < t_end;
+        const uint32_t e = valid ? row[t] : 0u;
+        const uint32_t h = e & 0x7FFFFFFFu;
+        uint64_t peers = __ballot(valid);
+        for (int bit = 0; bit < nbits; ++bit) {
+            const bool set = (h >> bit) & 1u;
+            const uint64_t B = __ballot(valid && set);
+            peers &= set ? B : ~B;
+        }
+        if (valid) {
+            const uint32_t pos = mine[h] + (uint32_t)__popcll(peers & below);
+            const uint32_t chunk = qbase[h >> 6] + pos / 8;
+            region[(int64_t)chunk * 512 + (h & 63) * 8 + (pos & 7)] =
+                (uint16_t)(win_slot(t) | ((e >> 31) << 15));
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (valid && (peers >> lane) == 1ull) mine[h] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // padding up to each group's chunk count, groups spread over the waves
+    for (int q = wv; q < qn; q += kBW) {
+        const int c = 64 * q + lane;
+        const uint32_t have = c < bp ? tot[c] : 0u;
+        const uint32_t len = qlen[q] * 8;
+        const uint32_t qb = qbase[q];
+        for (uint32_t p = have; p < len; ++p)
+            region[(int64_t)(qb + p / 8) * 512 + lane * 8 + (p & 7)] = kPad;
+    }
+}
+
+__global__ __launch_bounds__(64 * kBW) void ell_build4_kernel(const uint32_t* __restrict__ table,
+                                                              int64_t n, int64_t nt, int32_t bp,
+                                                              int32_t qn, int32_t nwin,
+                                                              int64_t RC,
+                                                              uint32_t* __restrict__ hdr,
+                                                              uint16_t* __restrict__ ell) {
+    extern __shared__ uint32_t sm[];
+    ell_build_region4(table, n, nt, bp, qn, nwin, RC, hdr, ell, (int)blockIdx.x,
+                      (int64_t)blockIdx.y, sm);
+}
+
 __global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restrict__ table,
                                                        int64_t n, int64_t nt, int32_t bp,
                                                        int32_t qn, int32_t nwin, int64_t RC,
@@ -166,6 +279,21 @@ __global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restric
     extern __shared__ uint32_t sm[];
     ell_build_region(table, n, nt, bp, qn, nwin, RC, hdr, ell, (int)blockIdx.x,
                      (int64_t)blockIdx.y, sm);
+}
+
+__global__ __launch_bounds__(64 * kBW) void ell_build_batch4_kernel(
+    const PrepDesc* __restrict__ descs, int32_t count, int64_t tasks) {
+    extern __shared__ uint32_t sm[];
+    for (int64_t t = blockIdx.x; t < tasks; t += gridDim.x) {
+        const int32_t p = find_task(descs, count, t, [](const PrepDesc& d) {
+            return d.ell_task0;
+        });
+        const PrepDesc& d = descs[p];
+        const int64_t local = t - d.ell_task0;
+        ell_build_region4(d.table, d.n, d.nt, d.bp, d.qn, d.nwin, d.RC, d.hdr, d.ell,
+                          (int)(local % d.nwin), local / d.nwin, sm);
+        __syncthreads();
+    }
 }
 
 // The same for many prepared sketches in one launch: task t (one wave) is
@@ -621,9 +749,16 @@ hipError_t launch_lists_batch(const PrepDesc* descs, int32_t count, int64_t task
                               int32_t max_bp, hipStream_t s) {
     if (count < 1 || tasks < 1 || max_bp < 1) return hipErrorInvalidValue;
     const int32_t qn = (max_bp + 63) / 64;
-    const size_t lds = (size_t)(max_bp + 2 * qn) * 4;
     const unsigned grid = (unsigned)std::min<int64_t>(tasks, int64_t(1) << 20);
-    hipLaunchKernelGGL(ell_build_batch_kernel, dim3(grid), dim3(64), lds, s, descs, count, tasks);
+    if (max_bp <= kBW4MaxBp) {
+        const size_t lds = (size_t)((kBW + 1) * max_bp + 2 * qn) * 4;
+        hipLaunchKernelGGL(ell_build_batch4_kernel, dim3(grid), dim3(64 * kBW), lds, s, descs,
+                           count, tasks);
+    } else {
+        const size_t lds = (size_t)(max_bp + 2 * qn) * 4;
+        hipLaunchKernelGGL(ell_build_batch_kernel, dim3(grid), dim3(64), lds, s, descs, count,
+                           tasks);
+    }
     return hipGetLastError();
 }
 
@@ -631,10 +766,17 @@ hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int3
                               int32_t bp, void* lists, hipStream_t s) {
     const Plan p = plan_of(n, bp);
     const ListView v = carve_lists(lists, nblk, n, bp);
-    const size_t lds = (size_t)(bp + 2 * p.qn) * 4;
-    hipLaunchKernelGGL(ell_build_kernel, dim3((unsigned)p.nwin, (unsigned)nblk), dim3(64), lds, s,
-                       table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
-                       reinterpret_cast<uint16_t*>(v.ell));
+    if (bp <= kBW4MaxBp) {
+        const size_t lds = (size_t)((kBW + 1) * bp + 2 * p.qn) * 4;
+        hipLaunchKernelGGL(ell_build4_kernel, dim3((unsigned)p.nwin, (unsigned)nblk),
+                           dim3(64 * kBW), lds, s, table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
+                           reinterpret_cast<uint16_t*>(v.ell));
+    } else {
+        const size_t lds = (size_t)(bp + 2 * p.qn) * 4;
+        hipLaunchKernelGGL(ell_build_kernel, dim3((unsigned)p.nwin, (unsigned)nblk), dim3(64), lds,
+                           s, table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
+                           reinterpret_cast<uint16_t*>(v.ell));
+    }
     return hipGetLastError();
 }
 

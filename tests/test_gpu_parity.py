@@ -312,3 +312,38 @@ def test_matmul_per_block_masks(m, n, l, b, N, e):
     Cu = host(osk.matmul_cmask(dev(A), dev(B, ld=l + 1), b, N, e, uni, seed=seed))
     Cg = host(osk.matmul(dev(A), dev(B, ld=l + 1), b, N, e, seed=seed, keep=keep))
     np.testing.assert_array_equal(Cu, Cg)
+
+
+# ---------------------------------------------------------------------------
+# os_matmul_ex: column-major A, BF16 operands
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,l,b,N,e", [(300, 1001, 77, 100, 3, 1), (96, 4096, 130, 256, 4, 0)])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("kept_only", [False, True])
+def test_matmul_ex_column_major_a(m, n, l, b, N, e, dtype, kept_only):
+    seed = m + l
+    A, B = synthetic.gaussian_pair(m, n, l, seed)
+    keep = synthetic.random_keep(N, e, seed)
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    # A stored as X = A^T (n x m, row-major), passed as the column-major view
+    X = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().to(tdt)
+    Bd = torch.from_numpy(B).cuda().to(tdt)
+    C = host(osk.matmul_ex(X.t(), Bd, b, N, e, seed=seed, keep=keep, kept_only=kept_only))
+    Av = X.t().float().cpu().numpy()        # the values the library read
+    Bv = Bd.float().cpu().numpy()
+    ref = oracle.sketched_matmul(Av, Bv, b, N, e, seed=seed, keep=keep)
+    assert rel(C, ref) <= PRODUCT_TOL
+
+
+def test_matmul_ex_matches_matmul_and_rejects_bf16_layouts():
+    m, n, l, b, N, e, seed = 200, 2048, 150, 128, 4, 1, 9
+    A, B = synthetic.gaussian_pair(m, n, l, seed)
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C1 = host(osk.matmul(Ad, Bd, b, N, e, seed=seed))
+    C2 = host(osk.matmul_ex(Ad, Bd, b, N, e, seed=seed))
+    np.testing.assert_array_equal(C1, C2)
+    with pytest.raises(osk.OversketchError):
+        osk.matmul_ex(Ad.to(torch.bfloat16), Bd, b, N, e)            # row-major BF16 A
+    with pytest.raises(osk.OversketchError):
+        osk.matmul_ex(Ad, Bd.t().contiguous().t().to(torch.bfloat16).t().contiguous().t(), b, N, e)
