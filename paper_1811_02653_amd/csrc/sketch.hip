@@ -466,33 +466,47 @@ void sketch_kernel(
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t groups = (lines + kLines - 1) / kLines;
-    const int64_t task = xcd_task(blockIdx.x, groups * npass);
-    const int64_t line0 = task / npass * kLines;
-    const int pass = (int)(task % npass);
+    const int64_t tasks = groups * npass;
     const int gslots = nst * qn;         // groups of 64 buckets over the stored blocks
-
-    float4 acc[kSlots];
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) acc[s] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (tid == 0) win[kWin] = make_float4(0.f, 0.f, 0.f, 0.f);
 
     // vec for a row-lines window: whole windows always, the last one when n % 4 == 0
     auto vec_at = [&](int64_t k0) {
         return kRowLines ? (vec != 0 && (k0 + kWin <= n || (n & 3) == 0)) : vec != 0;
     };
+    // Persistent: workgroup g takes tasks g, g + grid, ... (task = a group
+    // of 4 lines and a pass); the first window of its next task is fetched
+    // while the last window of the current one is summed, so only the first
+    // task of a workgroup waits for its first window.
+    auto line_of = [&](int64_t it) { return xcd_task(it, tasks) / npass * kLines; };
     float4 pre[kPerThread];
     float4 wpre[4];
-    load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, line0, 0,
-                                      (int)min((int64_t)kWin, n), vec_at(0), wd);
+    if ((int64_t)blockIdx.x < tasks)
+        load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, line_of(blockIdx.x), 0,
+                                          (int)min((int64_t)kWin, n), vec_at(0), wd);
+    for (int64_t it = blockIdx.x; it < tasks; it += gridDim.x) {
+    const int64_t task = xcd_task(it, tasks);
+    const int64_t line0 = task / npass * kLines;
+    const int pass = (int)(task % npass);
+
+    float4 acc[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) acc[s] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int w = 0; w < nwin; ++w) {
         __syncthreads();                 // the previous window is no longer read
         stage_window<kRowLines, kWeighted>(win, pre, wpre);
         __syncthreads();
-        if (w + 1 < nwin) {
-            const int64_t k1 = (int64_t)(w + 1) * kWin;
-            load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, line0, k1,
-                                              (int)min((int64_t)kWin, n - k1), vec_at(k1), wd);
+        // the next window: this task's, else the first of the next task
+        int64_t l1 = line0, k1 = (int64_t)(w + 1) * kWin;
+        bool more = true;
+        if (w + 1 == nwin) {
+            more = it + gridDim.x < tasks;
+            l1 = more ? line_of(it + gridDim.x) : 0;
+            k1 = 0;
         }
+        if (more)
+            load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, l1, k1,
+                                              (int)min((int64_t)kWin, n - k1), vec_at(k1), wd);
         // The list chunks of slot s + 1 (up to kAhead of them) are fetched
         // while slot s is summed.  Fetches are unconditional: chunk indices
         // past a slot's count repeat its last chunk, and an unused slot reads
@@ -552,6 +566,7 @@ void sketch_kernel(
             }
         }
     }
+    }   // tasks
 }
 
 // Slot counts compiled: 1, 2, 4, 8, 12, 16, 20, 24 (4 registers per slot).
@@ -714,7 +729,14 @@ hipError_t launch_sketch(bool row_lines, const float* X, int64_t lines, int64_t 
     int32_t npass, slots;
     pass_plan(nst, p.qn, &npass, &slots);
     const int64_t groups = (lines + kLines - 1) / kLines;
-    const dim3 grid((unsigned)(groups * npass));
+    // persistent workgroups: one per CU (a window fills a CU's LDS)
+    int dev = 0, cus = 0;
+    int64_t nwg = groups * npass;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+        nwg = std::min<int64_t>(nwg, cus);
+    const dim3 grid((unsigned)nwg);
     const int vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (ldx & 3) == 0 &&
                     (reinterpret_cast<uintptr_t>(wd) & 15) == 0;
     if (wd && row_lines)   // weighted sketches are only taken along rows
