@@ -478,16 +478,51 @@ void sketch_kernel(
     // of 4 lines and a pass); the first window of its next task is fetched
     // while the last window of the current one is summed, so only the first
     // task of a workgroup waits for its first window.
+    //
+    // Slot bookkeeping stays out of the scalar path (a scalar load in the
+    // slot loop drains every LDS read in flight): lane s of each wave holds,
+    // for its slot s, the header index of the slot's bucket group in window
+    // 0 (hb, -1 for an unused slot), the region's chunk base in window 0
+    // (eb), the group's first output column (col) and how many of its 64
+    // buckets exist (lim, 0 for an unused slot).  A window's headers come in
+    // with one vector load, issued before the window's values are fetched.
     auto line_of = [&](int64_t it) { return xcd_task(it, tasks) / npass * kLines; };
+    struct Meta {
+        int32_t hb, eb, col, lim;
+    };
+    auto meta_of = [&](int64_t it) -> Meta {
+        const int ps = (int)(xcd_task(it, tasks) % npass);
+        const int G = (ps * kSlots + lane) * kWaves + wave;
+        Meta m{-1, 0, 0, 0};
+        if (lane < kSlots && G < gslots) {
+            const int j = G / qn;
+            const int q = G - j * qn;
+            const int32_t i = bl.idx[j];
+            m.hb = (i * nwin) * qn + q;
+            m.eb = (int32_t)((int64_t)i * nwin * RC);
+            m.col = j * bp + q * 64;
+            m.lim = min(64, bp - q * 64);
+        }
+        return m;
+    };
+    auto headers = [&](const Meta& m, int w) -> uint32_t {
+        const uint32_t h = hdr[max(m.hb, 0) + w * qn];     // unconditional: index valid
+        return m.hb >= 0 ? h : 0u;
+    };
     float4 pre[kPerThread];
     float4 wpre[4];
-    if ((int64_t)blockIdx.x < tasks)
+    Meta mnext{-1, 0, 0, 0};
+    uint32_t hnext = 0;
+    if ((int64_t)blockIdx.x < tasks) {
+        mnext = meta_of(blockIdx.x);
+        hnext = headers(mnext, 0);
         load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, line_of(blockIdx.x), 0,
                                           (int)min((int64_t)kWin, n), vec_at(0), wd);
+    }
     for (int64_t it = blockIdx.x; it < tasks; it += gridDim.x) {
     const int64_t task = xcd_task(it, tasks);
     const int64_t line0 = task / npass * kLines;
-    const int pass = (int)(task % npass);
+    const Meta meta = mnext;
 
     float4 acc[kSlots];
 #pragma unroll
@@ -496,31 +531,17 @@ void sketch_kernel(
         __syncthreads();                 // the previous window is no longer read
         stage_window<kRowLines, kWeighted>(win, pre, wpre);
         __syncthreads();
-        // the next window: this task's, else the first of the next task
-        int64_t l1 = line0, k1 = (int64_t)(w + 1) * kWin;
-        bool more = true;
-        if (w + 1 == nwin) {
-            more = it + gridDim.x < tasks;
-            l1 = more ? line_of(it + gridDim.x) : 0;
-            k1 = 0;
-        }
-        if (more)
-            load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, l1, k1,
-                                              (int)min((int64_t)kWin, n - k1), vec_at(k1), wd);
+        const uint32_t hv = hnext;       // this window's headers (lane s: slot s)
         // The list chunks of slot s + 1 (up to kAhead of them) are fetched
         // while slot s is summed.  Fetches are unconditional: chunk indices
-        // past a slot's count repeat its last chunk, and an unused slot reads
-        // chunk 0 of the first region (never summed).
+        // past a slot's count repeat its last chunk, and an unused slot
+        // (header 0) reads chunk 0 of block 0's region (never summed).
+        const int64_t wrc = (int64_t)w * RC;
         auto slot_list = [&](int s, uint32_t& nch) -> const uint4* {
-            const int G = (pass * kSlots + s) * kWaves + wave;   // wave-uniform
-            nch = 0;
-            if (G >= gslots) return ell + lane;
-            const int j = G / qn;
-            const int q = G - j * qn;
-            const int64_t i = bl.idx[j];
-            const uint32_t h = hdr[(i * nwin + w) * qn + q];
+            const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)hv, s);
+            const int64_t eb = __builtin_amdgcn_readlane(meta.eb, s);
             nch = h >> 16;
-            return ell + ((i * nwin + w) * RC + (h & 0xFFFFu)) * 64 + lane;
+            return ell + (eb + wrc + (h & 0xFFFFu)) * 64 + lane;
         };
         auto fetch = [&](uint4 (&d)[kAhead], const uint4* p, uint32_t nch) {
             const uint32_t last = nch > 0 ? nch - 1 : 0;
@@ -532,6 +553,23 @@ void sketch_kernel(
         const uint4* pcur = slot_list(0, ncur);
         const uint4* pnxt = pcur;
         fetch(cur, pcur, ncur);
+        // the next window (this task's, else the first of the next task) and
+        // its headers
+        int64_t l1 = line0, k1 = (int64_t)(w + 1) * kWin;
+        bool more = true;
+        if (w + 1 == nwin) {
+            more = it + gridDim.x < tasks;
+            if (more) {
+                mnext = meta_of(it + gridDim.x);
+                l1 = line_of(it + gridDim.x);
+            }
+            k1 = 0;
+        }
+        if (more) {
+            hnext = headers(mnext, (int)(k1 / kWin));
+            load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, l1, k1,
+                                              (int)min((int64_t)kWin, n - k1), vec_at(k1), wd);
+        }
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
             if (s + 1 < kSlots) {
@@ -553,17 +591,13 @@ void sketch_kernel(
 
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
-        const int G = (pass * kSlots + s) * kWaves + wave;
-        if (G < gslots) {
-            const int j = G / qn;
-            const int c = (G - j * qn) * 64 + lane;
-            if (c < bp) {
-                float* o = out + line0 * ldo + (int64_t)j * bp + c;
-                o[0] = acc[s].x;
-                if (line0 + 1 < lines) o[ldo] = acc[s].y;
-                if (line0 + 2 < lines) o[2 * ldo] = acc[s].z;
-                if (line0 + 3 < lines) o[3 * ldo] = acc[s].w;
-            }
+        // lanes below lim hold buckets of the block (the last group may be partial)
+        if (lane < __builtin_amdgcn_readlane(meta.lim, s)) {
+            float* o = out + line0 * ldo + __builtin_amdgcn_readlane(meta.col, s) + lane;
+            o[0] = acc[s].x;
+            if (line0 + 1 < lines) o[ldo] = acc[s].y;
+            if (line0 + 2 < lines) o[2 * ldo] = acc[s].z;
+            if (line0 + 3 < lines) o[3 * ldo] = acc[s].w;
         }
     }
     }   // tasks
