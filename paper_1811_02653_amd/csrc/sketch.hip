@@ -548,11 +548,18 @@ void sketch_kernel(
 #pragma unroll
             for (int c = 0; c < kAhead; ++c) d[c] = p[(int64_t)min((uint32_t)c, last) * 64];
         };
+        // The lists of slots 0 and 1 are fetched before the next window's
+        // values: a wave's loads complete in order, so a list fetched after
+        // them would wait for them.
         uint4 cur[kAhead], nxt[kAhead];
         uint32_t ncur, nnxt = 0;
         const uint4* pcur = slot_list(0, ncur);
         const uint4* pnxt = pcur;
         fetch(cur, pcur, ncur);
+        if (kSlots > 1) {
+            pnxt = slot_list(1, nnxt);
+            fetch(nxt, pnxt, nnxt);
+        }
         // the next window (this task's, else the first of the next task) and
         // its headers
         int64_t l1 = line0, k1 = (int64_t)(w + 1) * kWin;
@@ -572,7 +579,7 @@ void sketch_kernel(
         }
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
-            if (s + 1 < kSlots) {
+            if (s >= 1 && s + 1 < kSlots) {
                 pnxt = slot_list(s + 1, nnxt);
                 fetch(nxt, pnxt, nnxt);
             }
