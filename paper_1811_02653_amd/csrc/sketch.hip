@@ -647,77 +647,114 @@ hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const float* X, in
 
 // ---------------------------------------------------------------------------
 // Transpose: Y (cols x rows, ld ldy, FP32) = X^T for X rows x cols (ld ldx,
-// FP32 or BF16, converted exactly to FP32).  A workgroup moves one 64 x 64
-// tile through LDS (row stride 65 floats: the column reads are
-// conflict-free); both sides are coalesced, 4 values per lane in one load
-// when `vec` (X aligned to 4 values and ldx % 4 == 0).  Loads are clamped
-// into the matrix and stores are guarded.
+// FP32 or BF16, converted exactly to FP32).  A workgroup of 512 threads moves
+// a 64 x 256 tile of X through LDS (row stride 257 floats: the column reads
+// are conflict-free): every row of X contributes 256 consecutive values and
+// every row of Y 64, each lane moving 4 values per access.
+//   kWhole = true : the wr x wc whole tiles, X aligned to 4 values with
+//                   ldx % 4 == 0: vector accesses with no bounds checks and
+//                   no branches (a branch between the loads and their LDS
+//                   writes, or between the LDS reads and the stores, costs
+//                   8-10 % here);
+//   kWhole = false: every other tile (the right and bottom strips, or all
+//                   tiles when X is not aligned): loads clamped into the
+//                   matrix, stores guarded.
+// Y is 16-byte aligned with ldy % 4 == 0 (checked by the launcher).
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ float4 load4(const T* p, bool vec);
+__device__ __forceinline__ float4 load4(const T* p);
 
 template <>
-__device__ __forceinline__ float4 load4<float>(const float* p, bool vec) {
-    if (vec) return *reinterpret_cast<const float4*>(p);
-    return make_float4(p[0], p[1], p[2], p[3]);
+__device__ __forceinline__ float4 load4<float>(const float* p) {
+    return *reinterpret_cast<const float4*>(p);
 }
 
 template <>
-__device__ __forceinline__ float4 load4<__bf16>(const __bf16* p, bool vec) {
+__device__ __forceinline__ float4 load4<__bf16>(const __bf16* p) {
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-    if (vec) {
-        const bf16x4 v = *reinterpret_cast<const bf16x4*>(p);
-        return make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
-    }
-    return make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[3]);
+    const bf16x4 v = *reinterpret_cast<const bf16x4*>(p);
+    return make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ X, int64_t rows,
-                                                        int64_t cols, int64_t ldx, int vec,
-                                                        float* __restrict__ Y, int64_t ldy) {
-    __shared__ float t[64][65];
+constexpr int kTrRows = 64;
+constexpr int kTrCols = 256;
+
+template <typename T, bool kWhole>
+__global__ __launch_bounds__(512) void transpose_kernel(const T* __restrict__ X, int64_t rows,
+                                                        int64_t cols, int64_t ldx,
+                                                        float* __restrict__ Y, int64_t ldy,
+                                                        int64_t wr, int64_t wc) {
+    __shared__ float t[kTrRows][kTrCols + 1];
     const int tid = threadIdx.x;
-    const int64_t col_tiles = (cols + 63) / 64;
-    const int64_t tiles = col_tiles * ((rows + 63) / 64);
-    const int64_t Tk = xcd_task(blockIdx.x, tiles);
-    const int64_t r0 = Tk / col_tiles * 64;
-    const int64_t c0 = Tk % col_tiles * 64;
-    const int sub = tid >> 4;          // 0..15
-    const int q = 4 * (tid & 15);      // 0..60
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = sub + 16 * i;
-        const T* p = X + min(r0 + r, rows - 1) * ldx;
-        float4 v;
-        if (c0 + q + 3 < cols) {
-            v = load4<T>(p + c0 + q, vec);
+    int64_t r0, c0;
+    if constexpr (kWhole) {
+        const int64_t Tk = xcd_task(blockIdx.x, wr * wc);
+        r0 = Tk / wc * kTrRows;
+        c0 = Tk % wc * kTrCols;
+    } else {
+        // the right strip (tile rows < wr, tile columns >= wc), then the
+        // bottom strip (tile rows >= wr, every tile column)
+        const int64_t C = (cols + kTrCols - 1) / kTrCols;
+        const int64_t right = wr * (C - wc);
+        const int64_t k = blockIdx.x;
+        if (k < right) {
+            r0 = k / (C - wc) * kTrRows;
+            c0 = (wc + k % (C - wc)) * kTrCols;
         } else {
-            v.x = (float)p[min(c0 + q + 0, cols - 1)];
-            v.y = (float)p[min(c0 + q + 1, cols - 1)];
-            v.z = (float)p[min(c0 + q + 2, cols - 1)];
-            v.w = (float)p[min(c0 + q + 3, cols - 1)];
+            r0 = (wr + (k - right) / C) * kTrRows;
+            c0 = (k - right) % C * kTrCols;
         }
-        t[r][q + 0] = v.x;
-        t[r][q + 1] = v.y;
-        t[r][q + 2] = v.z;
-        t[r][q + 3] = v.w;
+    }
+    // load: row sub + 8i of the tile, columns q .. q+3
+    const int sub = tid >> 6;
+    const int q = 4 * (tid & 63);
+    float4 v[8];
+    if constexpr (kWhole) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = load4<T>(X + (r0 + sub + 8 * i) * ldx + c0 + q);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const T* p = X + min(r0 + sub + 8 * i, rows - 1) * ldx;
+            v[i].x = (float)p[min(c0 + q + 0, cols - 1)];
+            v[i].y = (float)p[min(c0 + q + 1, cols - 1)];
+            v[i].z = (float)p[min(c0 + q + 2, cols - 1)];
+            v[i].w = (float)p[min(c0 + q + 3, cols - 1)];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = sub + 8 * i;
+        t[r][q + 0] = v[i].x;
+        t[r][q + 1] = v[i].y;
+        t[r][q + 2] = v[i].z;
+        t[r][q + 3] = v[i].w;
     }
     __syncthreads();
+    // store: row cs + 32i of the tile of Y (a column of X), columns p .. p+3
+    const int cs = tid >> 4;
+    const int p = 4 * (tid & 15);
+    float4 w[8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int c = sub + 16 * i;          // column of X = row of Y
-        const int64_t yr = c0 + c;
-        const int64_t yc = r0 + q;
-        if (yr >= cols) continue;
-        const float4 v = make_float4(t[q + 0][c], t[q + 1][c], t[q + 2][c], t[q + 3][c]);
+    for (int i = 0; i < 8; ++i) {
+        const int c = cs + 32 * i;
+        w[i] = make_float4(t[p][c], t[p + 1][c], t[p + 2][c], t[p + 3][c]);
+    }
+    const int64_t yc = r0 + p;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int64_t yr = c0 + cs + 32 * i;
         float* o = Y + yr * ldy + yc;
-        if (yc + 3 < rows) {
-            *reinterpret_cast<float4*>(o) = v;
-        } else {
-            if (yc < rows) o[0] = v.x;
-            if (yc + 1 < rows) o[1] = v.y;
-            if (yc + 2 < rows) o[2] = v.z;
+        if constexpr (kWhole) {
+            *reinterpret_cast<float4*>(o) = w[i];
+        } else if (yr < cols) {
+            if (yc + 3 < rows) {
+                *reinterpret_cast<float4*>(o) = w[i];
+            } else {
+                if (yc < rows) o[0] = w[i].x;
+                if (yc + 1 < rows) o[1] = w[i].y;
+                if (yc + 2 < rows) o[2] = w[i].z;
+            }
         }
     }
 }
@@ -868,12 +905,19 @@ size_t transpose_bytes(int64_t rows, int64_t cols) {
 template <typename T>
 hipError_t launch_transpose_t(const T* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
                               int64_t ldy, hipStream_t s) {
-    const int64_t tiles = (rows + 63) / 64 * ((cols + 63) / 64);
-    if (tiles > 0x7fffffff || ldy % 4 || (reinterpret_cast<uintptr_t>(Y) & 15))
+    const int64_t R = (rows + kTrRows - 1) / kTrRows;
+    const int64_t C = (cols + kTrCols - 1) / kTrCols;
+    if (R * C > 0x7fffffff || ldy % 4 || (reinterpret_cast<uintptr_t>(Y) & 15))
         return hipErrorInvalidValue;
-    const int vec = (reinterpret_cast<uintptr_t>(X) % (4 * sizeof(T))) == 0 && (ldx & 3) == 0;
-    hipLaunchKernelGGL(transpose_kernel<T>, dim3((unsigned)tiles), dim3(256), 0, s, X, rows, cols,
-                       ldx, vec, Y, ldy);
+    const bool vec = (reinterpret_cast<uintptr_t>(X) % (4 * sizeof(T))) == 0 && (ldx & 3) == 0;
+    const int64_t wr = vec ? rows / kTrRows : 0;     // whole tiles: wr x wc
+    const int64_t wc = vec ? cols / kTrCols : 0;
+    if (wr * wc > 0)
+        hipLaunchKernelGGL((transpose_kernel<T, true>), dim3((unsigned)(wr * wc)), dim3(512), 0, s,
+                           X, rows, cols, ldx, Y, ldy, wr, wc);
+    if (R * C > wr * wc)
+        hipLaunchKernelGGL((transpose_kernel<T, false>), dim3((unsigned)(R * C - wr * wc)),
+                           dim3(512), 0, s, X, rows, cols, ldx, Y, ldy, wr, wc);
     return hipGetLastError();
 }
 

@@ -177,6 +177,30 @@ def test_sketch_rows_random(n, cols, b, N, e):
         assert rel(outT[:, i * b:(i + 1) * b], ref[:, i * b:(i + 1) * b]) <= SKETCH_TOL
 
 
+@pytest.mark.parametrize("n,cols", [(300, 600), (64, 256), (129, 513), (1000, 1024)])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_sketch_rows_transposing_tiles(n, cols, dtype):
+    # aligned leading dimensions: the transpose takes its whole-tile path
+    # (64 x 256 tiles, unguarded vector accesses) inside and its guarded path
+    # at the ragged edges; the result must equal the in-place FP32 sketch of
+    # the same values bit for bit
+    b, N, e = 100, 3, 1
+    seed = n + 3 * cols
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, cols)).astype(np.float32)
+    Xd = dev(X, ld=(cols + 7) // 8 * 8)
+    if dtype == "bf16":
+        Xd = Xd.to(torch.bfloat16)
+        X = Xd.float().cpu().numpy()          # the BF16 values, exactly
+    direct = host(osk.sketch_rows(dev(X, ld=cols + 1), b, N, e, seed=seed))
+    transposed = host(osk.sketch_rows(Xd, b, N, e, seed=seed, workspace=True))
+    np.testing.assert_array_equal(direct, transposed)
+    h, s = oracle.hash_tables(seed, N + e, n, b)
+    ref = oracle.sketch_rows(X.astype(np.float64), h, s, b).T
+    outT = unpad(transposed, N + e, b)
+    assert rel(outT, ref) <= SKETCH_TOL
+
+
 def test_sketch_cols_is_deterministic():
     X = dev(np.random.default_rng(3).standard_normal((64, 5000)))
     a = host(osk.sketch_cols(X, 256, 4, 1, seed=3))
