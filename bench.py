@@ -80,6 +80,8 @@ def parse():
                    help="skip the BF16 / split-BF16 variants of the block product")
     p.add_argument("--no-batch", action="store_true",
                    help="skip the batch of 64 sketched interior-point Hessians")
+    p.add_argument("--no-paper", action="store_true",
+                   help="skip the paper's constant-matrix workloads (Fig. 5b, Section 5.3)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 1 GiB device copy (3 times): the reference kernel "
                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -209,6 +211,111 @@ def bench_hessian_batch(torch, osk, args, stream, reps):
     return res
 
 
+def _predicted_rel_frob(nA2, nB2, nAB2, cross, K, b):
+    """RMS relative Frobenius error of the sketched product for K kept
+    count-sketch blocks of width b: Lemma 1's variance summed over the
+    entries of AB and divided by K, over |AB|_F^2."""
+    return ((nA2 * nB2 + nAB2 - 2.0 * cross) / (K * b) / nAB2) ** 0.5
+
+
+def bench_paper_workloads(torch, osk, args, stream, reps):
+    import synthetic
+    dev = "cuda"
+    res = {}
+    # Fig. 5b: A(x, y) = x + y, m = l = 10b, n = 60b, b = 2048, B = A^T,
+    # z = 30b; e of the 30 workers of every b x b block of C ignored; the
+    # paper's error is a mean over ten sketches (0.8 % at e = 4)
+    b, nb = 2048, 30
+    m, n = 10 * b, 60 * b
+    A, x, y = synthetic.paper_matrices_device(m, n, device=dev)
+    G, nA2, _, cross = synthetic.paper_exact_products(x, y)
+    nG2 = torch.sum(G * G).item()
+    bp = osk.block_stride(b)
+    At = torch.empty((m, nb * bp), dtype=torch.float32, device=dev)
+    C = torch.empty((m, m), dtype=torch.float32, device=dev)
+    es, inst = (0, 2, 4, 6, 8, 10), 10
+    errs = {e_: [] for e_ in es}
+    t_sk, t_gemm = None, {}
+    for k in range(inst):
+        seed = args.seed + 100 + k
+        prep = osk.sketch_prepare(n, b, nb, 0, seed=seed)
+        # B = A^T: the sketch of B's rows is the sketch of A's columns
+        sk = lambda: osk.sketch_cols(A, b, nb, 0, seed=seed, prep=prep, out=At, stream=stream)
+        if k == 0:
+            t_sk = event_time_ms(torch, sk, 3, stream)
+        else:
+            with torch.cuda.stream(stream):
+                sk()
+        for e_ in es:
+            cm = torch.from_numpy(synthetic.random_cmask(m // b, m // b, nb - e_, e_,
+                                                         seed * 100 + e_)).to(dev)
+            g = lambda: osk.gemm_kept_cmask(At, At, b, cm, out=C, stream=stream)
+            if k == 0:
+                t_gemm[e_] = event_time_ms(torch, g, 2, stream)
+            else:
+                with torch.cuda.stream(stream):
+                    g()
+            stream.synchronize()
+            errs[e_].append((torch.sum((C.double() - G) ** 2).item() / nG2) ** 0.5)
+    res["fig5b"] = {
+        "workload": "A(x,y) = x + y, m = l = 20480, n = 122880, B = A^T, b = 2048, z = 30b; e "
+                    "of the 30 workers of every b x b block of C dropped at random",
+        "e": list(es), "instances": inst,
+        "rel_frob_mean": [float(np.mean(errs[e_])) for e_ in es],
+        "rel_frob_predicted_rms": [_predicted_rel_frob(nA2, nA2, nG2, cross, nb - e_, b)
+                                   for e_ in es],
+        "paper_printed": {"e": 4, "rel_frob_mean": 0.008},
+        "sketch_ms": t_sk,
+        "gemm_cmask_ms": [t_gemm[e_] for e_ in es],
+        "gemm_cmask_tflops": [2.0 * m * m * (nb - e_) * bp / (t_gemm[e_] * 1e-3) / 1e12
+                              for e_ in es],
+    }
+    log("Fig. 5b: mean error by e %s (predicted %s); sketch %.2f ms, product %s ms" % (
+        ["%.4f" % v for v in res["fig5b"]["rel_frob_mean"]],
+        ["%.4f" % v for v in res["fig5b"]["rel_frob_predicted_rms"]], t_sk,
+        ["%.1f" % v for v in res["fig5b"]["gemm_cmask_ms"]]))
+    del A, G, At, C, x, y
+    torch.cuda.empty_cache()
+    # Section 5.3: A(x, y) = x + y and B(x, y) = x y, both n x n, b = 4000,
+    # z = n/2 + b, one worker per block of C ignored (error under 2 %)
+    b = 4000
+    rows = []
+    for n in (24000, 40000):
+        nb = n // (2 * b) + 1
+        A, B, x, y, z = synthetic.paper_matrices_device(n, n, n, device=dev)
+        AB, nA2, nB2, cross = synthetic.paper_exact_products(x, y, z)
+        nAB2 = torch.sum(AB * AB).item()
+        ws = torch.empty(osk.workspace_bytes(n, n, n, b, nb - 1, 1), dtype=torch.uint8, device=dev)
+        C = torch.empty((n, n), dtype=torch.float32, device=dev)
+        errs, t = [], None
+        for k in range(inst):
+            seed = args.seed + n + k
+            cm = torch.from_numpy(synthetic.random_cmask(n // b, n // b, nb - 1, 1, seed)).to(dev)
+            f = lambda: osk.matmul_cmask(A, B, b, nb - 1, 1, cm, seed=seed, out=C, workspace=ws,
+                                         stream=stream)
+            if k == 0:
+                t = event_time_ms(torch, f, 2, stream)
+            else:
+                with torch.cuda.stream(stream):
+                    f()
+            stream.synchronize()
+            errs.append((torch.sum((C.double() - AB) ** 2).item() / nAB2) ** 0.5)
+        rows.append({"n": n, "blocks": nb, "ms": t,
+                     "eff_tflops": 2.0 * n ** 3 / (t * 1e-3) / 1e12,
+                     "rel_frob_mean": float(np.mean(errs)),
+                     "rel_frob_predicted_rms": _predicted_rel_frob(nA2, nB2, nAB2, cross,
+                                                                   nb - 1, b)})
+        del A, B, AB, C, ws, x, y, z
+        torch.cuda.empty_cache()
+    res["section_5_3"] = {
+        "workload": "A(x,y) = x + y and B(x,y) = x y, n x n, b = 4000, z = n/2 + b, one of the "
+                    "z/b workers of every b x b block of C dropped at random",
+        "instances": inst, "paper_printed": "error under 2 %, decreasing with n", "runs": rows}
+    log("Section 5.3: %s" % ", ".join("n=%d err %.4f (pred %.4f) %.1f ms" % (
+        r["n"], r["rel_frob_mean"], r["rel_frob_predicted_rms"], r["ms"]) for r in rows))
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -305,13 +412,48 @@ def main():
     b2 = torch.sum(B.double() ** 2).item()
     rel_err = (diff2 / ab2) ** 0.5
     norm_err2 = diff2 / (a2 * b2)
-    del AB, Cd
-    torch.cuda.empty_cache()
+    del Cd
 
-    # ---- exact FP32 GEMM on the same GPU (vendor library) as the comparator
+    # ---- speedup against error: whole steps for N in {2, 4, 8, 16} (e = 2,
+    # two random blocks dropped, the same inputs), and the headline with the
+    # dropped blocks skipped at sketch time
+    sweep = []
+    for Ns in (2, 4, 8, 16):
+        ks = synthetic.random_keep(Ns, e, args.seed, drop=args.drop)
+        wss = torch.empty(osk.workspace_bytes(m, n, l, b, Ns, e), dtype=torch.uint8, device=dev)
+        t_s = event_time_ms(torch, lambda: osk.matmul(A, B, b, Ns, e, seed=args.seed, keep=ks,
+                                                      out=C, workspace=wss, stream=stream),
+                            reps, stream)
+        Cd = C.double()
+        sweep.append({"N": Ns, "e": e, "kept_blocks": int(np.count_nonzero(ks)), "ms": t_s,
+                      "eff_tflops": 2.0 * m * n * l / (t_s * 1e-3) / 1e12,
+                      "rel_frob_vs_exact_fp64": (torch.sum((Cd - AB) ** 2).item() / ab2) ** 0.5})
+        del wss, Cd
+    t_kept_only = event_time_ms(torch, lambda: osk.matmul(A, B, b, N, e, seed=args.seed,
+                                                          keep=keep, kept_only=True, out=C,
+                                                          workspace=ws, stream=stream),
+                                reps, stream)
+    log("N sweep: %s; kept_only step %.3f ms" %
+        (", ".join("N=%d %.2f ms err %.4f" % (r["N"], r["ms"], r["rel_frob_vs_exact_fp64"])
+                   for r in sweep), t_kept_only))
+    del AB
+    torch.cuda.empty_cache()
+    step()
+
+    # ---- exact FP32 GEMM on the same GPU: the vendor library, and the block
+    # product kernel itself run on A and B^T unsketched (the inner dimension
+    # split into 4 blocks of n/4, all kept: C = AB / 4 with the same flops as
+    # AB)
     Cx = torch.empty((m, l), dtype=torch.float32, device=dev)
     t_exact = event_time_ms(torch, lambda: torch.matmul(A, B, out=Cx), 3, stream)
+    t_exact_own = None
+    if n % 4 == 0 and (n // 4) % 32 == 0 and n // 4 <= 8192:
+        BT = B.t().contiguous()
+        t_exact_own = event_time_ms(torch, lambda: osk.gemm_kept(A, BT, n // 4, out=Cx,
+                                                                 stream=stream), 3, stream)
+        del BT
     del Cx
+    torch.cuda.empty_cache()
 
     # ---- reduced-precision block product (BF16 or FP8 operands with
     # power-of-two block scales, FP32 accumulation; split forms add residuals):
@@ -449,6 +591,12 @@ def main():
     if not args.no_batch:
         batch = bench_hessian_batch(torch, osk, args, stream, reps)
 
+    # ---- the paper's own constant-matrix workloads at its sizes: errors
+    # against its printed figures and the second-moment formula
+    paper = None
+    if not args.no_paper:
+        paper = bench_paper_workloads(torch, osk, args, stream, reps)
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
     sample_err = None
@@ -519,7 +667,14 @@ def main():
         "hessian_batch": batch,
         "exact_gemm": {"kind": "torch.matmul FP32 (hipBLASLt)", "ms": t_exact,
                        "tflops": 2.0 * m * n * l / (t_exact * 1e-3) / 1e12,
-                       "speedup_of_sketched": t_exact / ms_per_step},
+                       "speedup_of_sketched": t_exact / ms_per_step,
+                       "same_kernel": None if t_exact_own is None else {
+                           "kind": "gemm_kept on A and B^T unsketched (4 kept blocks of n/4)",
+                           "ms": t_exact_own,
+                           "tflops": 2.0 * m * n * l / (t_exact_own * 1e-3) / 1e12,
+                           "speedup_of_sketched": t_exact_own / ms_per_step}},
+        "speedup_vs_error": {"sweep": sweep, "kept_only_ms_per_step": t_kept_only},
+        "paper_workloads": paper,
     }
     print(json.dumps(out), flush=True)
 

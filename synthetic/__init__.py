@@ -88,6 +88,63 @@ def paper_times_matrix(m: int, n: int, dtype=np.float32):
     return (x * y).astype(dtype)
 
 
+def paper_matrices_device(m: int, n: int, l: int | None = None, device="cuda"):
+    """The paper's constant matrices on the device, in FP32: A(x, y) = x + y
+    (m x n, exact while m + n < 2^24) and, when l is given, B(x, y) = x * y
+    (n x l, each product rounded to FP32, relative error <= 2^-24), with
+    1-based indices.  Also returns the index vectors (FP64, on the device)
+    that define them."""
+    import torch
+    x = torch.arange(1, m + 1, device=device, dtype=torch.float64)
+    y = torch.arange(1, n + 1, device=device, dtype=torch.float64)
+    A = (x[:, None].float() + y[None, :].float())
+    if l is None:
+        return A, x, y
+    z = torch.arange(1, l + 1, device=device, dtype=torch.float64)
+    B = (y[:, None] * z[None, :]).float()
+    return A, B, x, y, z
+
+
+def paper_exact_products(x, y, z=None):
+    """Exact FP64 products of the paper's constant matrices, from their index
+    vectors (torch FP64 tensors, on any device), with the sums that the
+    sketch's error formula needs.  A = x 1^T + 1 y^T (m x n), so
+      - without z: B = A^T and AB = A A^T, entries n x_i x_j + (x_i + x_j) Sy
+        + Syy (Sy = sum y, Syy = sum y^2);
+      - with z: B = y z^T (B(k, j) = y_k z_j) and AB = (A y) z^T with
+        (A y)_i = x_i Sy + Syy.
+    Returns (AB, |A|_F^2, |B|_F^2, sum_k |A[:, k]|^2 |B[k, :]|^2)."""
+    m, n = x.numel(), y.numel()
+    Sx, Sxx = x.sum(), (x * x).sum()
+    Sy, Syy = y.sum(), (y * y).sum()
+    nA2 = n * Sxx + 2 * Sx * Sy + m * Syy
+    colA2 = Sxx + 2 * y * Sx + m * y * y           # |A[:, k]|^2
+    if z is None:
+        AB = n * x[:, None] * x[None, :] + (x[:, None] + x[None, :]) * Sy + Syy
+        return AB, float(nA2), float(nA2), float((colA2 * colA2).sum())
+    Szz = (z * z).sum()
+    Ay = x * Sy + Syy
+    AB = Ay[:, None] * z[None, :]
+    return AB, float(nA2), float(Syy * Szz), float((colA2 * y * y).sum() * Szz)
+
+
+def random_cmask(nbI: int, nbJ: int, N: int, e: int, seed: int, drop: int | None = None):
+    """Keep mask per b x b block of C, [nbI][nbJ][N+e]: every block drops
+    `drop` (default e) of its N+e workers at random, independently of the
+    other blocks and of the sketch (drawn from the mask stream)."""
+    if drop is None:
+        drop = e
+    if not 0 <= drop < N + e:
+        raise ValueError("must keep at least one block")
+    rng = mask_rng(seed)
+    cm = np.ones((nbI, nbJ, N + e), dtype=np.uint8)
+    for i in range(nbI):
+        for j in range(nbJ):
+            if drop:
+                cm[i, j, rng.choice(N + e, size=drop, replace=False)] = 0
+    return cm
+
+
 def random_keep(N: int, e: int, seed: int, drop: int | None = None) -> np.ndarray:
     """Keep-mask over N+e blocks with `drop` (default e) blocks dropped at
     random, independent of the sketch (drawn from the mask stream)."""
