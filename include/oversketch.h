@@ -187,9 +187,9 @@ os_status os_sketch_rows(const os_sketch* sk, const void* prep, size_t prep_byte
 
 /* os_sketch_rows for an X of element type x_dtype: OS_DTYPE_F32 is
  * os_sketch_rows; OS_DTYPE_BF16 reads a BF16 X (2-byte aligned, ld ldx in
- * values), converts it exactly to FP32 while transposing it into the
- * workspace (required: >= os_sketch_rows_workspace_bytes(n, cols)) and
- * sketches it as os_sketch_rows does, with FP32 sums.  Used for the sketched
+ * values), transposes it (as BF16) into the workspace (required: >=
+ * os_sketch_rows_workspace_bytes(n, cols)) and sketches it as os_sketch_rows
+ * does, each value converted exactly to FP32 as it is read, FP32 sums.  Used for the sketched
  * weight gradient of a linear layer, X^T S S^T dY with the sketch over the
  * tokens (the rows of X and dY). */
 os_status os_sketch_rows_ex(const os_sketch* sk, const void* prep, size_t prep_bytes,
@@ -317,10 +317,12 @@ size_t os_matmul_ex_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, i
 /* The whole path with more operand layouts and types: A m x n, row-major
  * (a_col_major = 0, element (r, k) at A[r*lda + k]) or column-major
  * (a_col_major = 1, at A[k*lda + r], lda >= m); B n x l as in os_matmul.
- * a_dtype / b_dtype: OS_DTYPE_F32, or OS_DTYPE_BF16 for an operand that is
- * transposed before its sketch (a column-major A, a row-major B; it is
- * converted exactly to FP32 on the way, 2-byte aligned, ld in values); other
- * BF16 layouts give OS_EINVAL.  With A = X^T for a row-major X (n x m: A is
+ * a_dtype / b_dtype: OS_DTYPE_F32 or OS_DTYPE_BF16 (2-byte aligned, ld in
+ * values), in either layout.  A column-major A and a row-major B are first
+ * transposed into the workspace in their own type; BF16 values are converted
+ * exactly to FP32 as the sketch reads them, so the result equals that of the
+ * FP32 path on the converted values, bit for bit.  With A = X^T for a
+ * row-major X (n x m: A is
  * X read as column-major) and B = dY this is the sketched weight gradient of
  * a linear layer, X^T S S^T dY, sketched over the n tokens (the product of
  * Section 4 with the tokens as the inner dimension).  Other arguments as in

@@ -565,7 +565,7 @@ def matmul_ex(A, B, b, N, e, seed=0, keep=None, kept_only=False, precision="fp32
               sigma=None, out=None, workspace=None, stream=None):
     """os_matmul_ex: C ~= A S S^T B for A (m x n) and B (n x l) given as
     float32 or bfloat16 tensors, row- or column-major (a transposed view is
-    column-major).  BF16 is accepted for a column-major A and a row-major B.
+    column-major), in either type and layout.
     Returns C (m x l, float32)."""
     torch = _torch()
     ad, acm, m, n, lda = _layout(A, "A")

@@ -162,12 +162,16 @@ os_status os_sketch_rows_ex(const os_sketch* sk, const void* prep, size_t prep_b
     if (!osk::plan_sketch_ok(cols, bs.nst, bp, n)) return OS_EINVAL;
     if (!workspace || !aligned(workspace, 256) || ws_bytes < osk::transpose_bytes(n, cols))
         return OS_EWORKSPACE;
+    // transposed as BF16 (half the bytes of an FP32 copy); the sketch converts
+    // each value exactly to FP32 as it stages it
     hipStream_t s = (hipStream_t)stream;
-    float* Xt = static_cast<float*>(workspace);
     const int64_t ldt = osk::round_up(n, 4);
-    if ((st = hip_status(osk::launch_transpose_bf16(X, n, cols, ldx, Xt, ldt, s))) != OS_OK) return st;
-    return hip_status(osk::launch_sketch_cols(Xt, cols, n, ldt, bs.stored, bs.nst, nblocks(sk), bp,
-                                              prep_lists(prep, sk, n), out, ldo, s));
+    if ((st = hip_status(osk::launch_transpose_bf16_raw(X, n, cols, ldx, workspace, ldt, s))) !=
+        OS_OK)
+        return st;
+    return hip_status(osk::launch_sketch_cols_bf16(workspace, cols, n, ldt, bs.stored, bs.nst,
+                                                   nblocks(sk), bp, prep_lists(prep, sk, n), out,
+                                                   ldo, s));
 }
 
 os_status os_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt, int64_t m,
@@ -310,10 +314,8 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
     os_status st = check_sketch(sk);
     if (st != OS_OK) return st;
     if (!valid_prec(precision)) return OS_EINVAL;
-    // BF16 operands are read only by the transpose that precedes their sketch
     if ((a_dtype != OS_DTYPE_F32 && a_dtype != OS_DTYPE_BF16) ||
-        (b_dtype != OS_DTYPE_F32 && b_dtype != OS_DTYPE_BF16) ||
-        (a_dtype == OS_DTYPE_BF16 && !a_col_major) || (b_dtype == OS_DTYPE_BF16 && b_col_major))
+        (b_dtype != OS_DTYPE_F32 && b_dtype != OS_DTYPE_BF16))
         return OS_EINVAL;
     if ((st = check_len(n)) != OS_OK) return st;
     if ((st = check_extent(m)) != OS_OK || (st = check_extent(l)) != OS_OK) return st;
@@ -371,35 +373,34 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
     const void* lists = prep_lists(prep, sk, n);
 
     // An operand's lines (rows of A, columns of B) are sketched as rows in
-    // memory: a column-major A and a row-major B are transposed first
-    // (BF16 converted exactly to FP32 on the way), so that every sketch reads
-    // whole lines (16-byte requests along a column would each bring in a
-    // separate cache line).
-    auto lines_of = [&](const void* X, int dtype, int64_t rows, int64_t cols, int64_t ldx,
-                        const float** out, int64_t* ldo) -> os_status {
-        const int64_t ldy = osk::round_up(rows, 4);
-        float* Y = reinterpret_cast<float*>(tx_p);
-        const hipError_t e =
+    // memory: a column-major A and a row-major B are transposed first (in
+    // their own type), so that every sketch reads whole lines (16-byte
+    // requests along a column would each bring in a separate cache line).
+    // BF16 values are converted exactly to FP32 as the sketch stages them.
+    auto sketch_lines = [&](const void* X, int dtype, bool transpose, int64_t lines,
+                            int64_t ldx, float* out) -> os_status {
+        const void* Xl = X;
+        int64_t ldl = ldx;
+        if (transpose) {
+            ldl = osk::round_up(n, 4);
+            const hipError_t e =
+                dtype == OS_DTYPE_BF16
+                    ? osk::launch_transpose_bf16_raw(X, n, lines, ldx, tx_p, ldl, s)
+                    : osk::launch_transpose(static_cast<const float*>(X), n, lines, ldx,
+                                            reinterpret_cast<float*>(tx_p), ldl, s);
+            if (e != hipSuccess) return hip_status(e);
+            Xl = tx_p;
+        }
+        return hip_status(
             dtype == OS_DTYPE_BF16
-                ? osk::launch_transpose_bf16(X, rows, cols, ldx, Y, ldy, s)
-                : osk::launch_transpose(static_cast<const float*>(X), rows, cols, ldx, Y, ldy, s);
-        *out = Y;
-        *ldo = ldy;
-        return hip_status(e);
+                ? osk::launch_sketch_cols_bf16(Xl, lines, n, ldl, bs.stored, bs.nst, nblocks(sk),
+                                               bp, lists, out, zs, s)
+                : osk::launch_sketch_cols(static_cast<const float*>(Xl), lines, n, ldl,
+                                          bs.stored, bs.nst, nblocks(sk), bp, lists, out, zs, s));
     };
     if ((st = prepare(sk, n, prep, s)) != OS_OK) return st;
-    const float* Al = static_cast<const float*>(A);
-    int64_t lal = lda;
-    if (a_col_major && (st = lines_of(A, a_dtype, n, m, lda, &Al, &lal)) != OS_OK) return st;
-    if ((st = hip_status(osk::launch_sketch_cols(Al, m, n, lal, bs.stored, bs.nst, nblocks(sk), bp,
-                                                 lists, At, zs, s))) != OS_OK)
-        return st;
-    const float* Bl = static_cast<const float*>(B);
-    int64_t lbl = ldb;
-    if (!b_col_major && (st = lines_of(B, b_dtype, n, l, ldb, &Bl, &lbl)) != OS_OK) return st;
-    if ((st = hip_status(osk::launch_sketch_cols(Bl, l, n, lbl, bs.stored, bs.nst, nblocks(sk), bp,
-                                                 lists, Bt, zs, s))) != OS_OK)
-        return st;
+    if ((st = sketch_lines(A, a_dtype, a_col_major != 0, m, lda, At)) != OS_OK) return st;
+    if ((st = sketch_lines(B, b_dtype, b_col_major == 0, l, ldb, Bt)) != OS_OK) return st;
     if (precision == OS_PREC_FP32)
         return hip_status(osk::launch_gemm_kept(At, zs, Bt, zs, m, l, bp, bs.kept_pos, bs.K,
                                                 1.0f / (float)bs.K, C, ldc, s));

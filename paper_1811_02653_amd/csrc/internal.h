@@ -122,6 +122,15 @@ hipError_t launch_transpose(const float* X, int64_t rows, int64_t cols, int64_t 
 // The same for a BF16 X (values converted exactly to FP32).
 hipError_t launch_transpose_bf16(const void* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
                                  int64_t ldy, hipStream_t s);
+// Y (cols x rows, BF16, ld ldy % 4 == 0, Y 8-byte aligned) = X^T, X BF16
+// rows x cols (values copied exactly).
+hipError_t launch_transpose_bf16_raw(const void* X, int64_t rows, int64_t cols, int64_t ldx,
+                                     void* Y, int64_t ldy, hipStream_t s);
+// launch_sketch_cols for a BF16 X (each value converted exactly to FP32 as
+// its window is staged; the sums are those of the FP32 path on those values).
+hipError_t launch_sketch_cols_bf16(const void* X, int64_t rows, int64_t n, int64_t ldx,
+                                   const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
+                                   const void* lists, float* out, int64_t ldo, hipStream_t s);
 
 // Shapes the block product supports for operands of elem bytes per value
 // (4: FP32, 2: BF16, 1: FP8); bp must be a multiple of 128 / elem.

@@ -335,11 +335,52 @@ __global__ __launch_bounds__(64) void ell_build_batch_kernel(const PrepDesc* __r
 // applied when the window is written to LDS, not when it is loaded, so the
 // loads of the next window stay in flight while the current one is summed.
 // ---------------------------------------------------------------------------
-template <bool kRowLines, bool kWeighted = false>
-__device__ __forceinline__ void load_window(float4 (&r)[kPerThread], float4 (&w)[4],
-                                            const float* __restrict__ X, int64_t lines,
-                                            int64_t ldx, int64_t line0, int64_t k0, int kw,
-                                            bool vec, const float* __restrict__ wd = nullptr) {
+// Input values are held in registers as loaded (4 consecutive values of a
+// line: a float4 for FP32, their 4 bit patterns in a uint2 for BF16) and
+// converted to FP32 (exactly) when the window is written to LDS.
+template <typename TI>
+struct RawQuad;
+template <>
+struct RawQuad<float> {
+    using type = float4;
+    static __device__ __forceinline__ type load(const float* __restrict__ p) {
+        return *reinterpret_cast<const float4*>(p);
+    }
+    static __device__ __forceinline__ type gather(const float* __restrict__ p,
+                                                  const int64_t (&k)[4]) {
+        return make_float4(p[k[0]], p[k[1]], p[k[2]], p[k[3]]);
+    }
+    static __device__ __forceinline__ float value(const type& v, int j) {
+        return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
+    }
+};
+template <>
+struct RawQuad<__bf16> {
+    using type = uint2;
+    static __device__ __forceinline__ uint32_t bits(const __bf16* __restrict__ p) {
+        return __builtin_bit_cast(uint16_t, *p);
+    }
+    static __device__ __forceinline__ type load(const __bf16* __restrict__ p) {
+        return *reinterpret_cast<const uint2*>(p);
+    }
+    static __device__ __forceinline__ type gather(const __bf16* __restrict__ p,
+                                                  const int64_t (&k)[4]) {
+        return make_uint2(bits(p + k[0]) | bits(p + k[1]) << 16,
+                          bits(p + k[2]) | bits(p + k[3]) << 16);
+    }
+    static __device__ __forceinline__ float value(const type& v, int j) {
+        const uint32_t w = j < 2 ? v.x : v.y;
+        return __uint_as_float((j & 1) ? (w & 0xFFFF0000u) : (w << 16));
+    }
+};
+
+template <bool kRowLines, bool kWeighted, typename TI>
+__device__ __forceinline__ void load_window(typename RawQuad<TI>::type (&r)[kPerThread],
+                                            float4 (&w)[4], const TI* __restrict__ X,
+                                            int64_t lines, int64_t ldx, int64_t line0, int64_t k0,
+                                            int kw, bool vec, const float* __restrict__ wd) {
+    using R = RawQuad<TI>;
+    static_assert(kRowLines || sizeof(TI) == 4, "column lines are read as FP32 only");
     // Every load is unconditional (a branch around a load makes each use wait
     // for all loads in flight): positions past the window's end are clamped to
     // its last index (no entry refers to them) and lines past the matrix to
@@ -356,8 +397,15 @@ __device__ __forceinline__ void load_window(float4 (&r)[kPerThread], float4 (&w)
             for (int u = 0; u < 4; ++u) {
                 const int64_t kk = k0 + min(4 * tid + 2048 * u, kw - 4);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    r[4 * q + u] = *reinterpret_cast<const float4*>(X + (line0 + dl[q]) * ldx + kk);
+                for (int q = 0; q < 4; ++q) {
+                    // (the FP32 load written here, not through R::load: through the
+                    // helper the FP32 kernels took 20 more registers and spilled)
+                    if constexpr (sizeof(TI) == 4)
+                        r[4 * q + u] =
+                            *reinterpret_cast<const float4*>(X + (line0 + dl[q]) * ldx + kk);
+                    else
+                        r[4 * q + u] = R::load(X + (line0 + dl[q]) * ldx + kk);
+                }
                 if constexpr (kWeighted) w[u] = *reinterpret_cast<const float4*>(wd + kk);
             }
         } else {
@@ -367,10 +415,7 @@ __device__ __forceinline__ void load_window(float4 (&r)[kPerThread], float4 (&w)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) kk[j] = k0 + min(4 * tid + 2048 * u + j, kw - 1);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float* p = X + (line0 + dl[q]) * ldx;
-                    r[4 * q + u] = make_float4(p[kk[0]], p[kk[1]], p[kk[2]], p[kk[3]]);
-                }
+                for (int q = 0; q < 4; ++q) r[4 * q + u] = R::gather(X + (line0 + dl[q]) * ldx, kk);
                 if constexpr (kWeighted) w[u] = make_float4(wd[kk[0]], wd[kk[1]], wd[kk[2]], wd[kk[3]]);
             }
         }
@@ -381,7 +426,7 @@ __device__ __forceinline__ void load_window(float4 (&r)[kPerThread], float4 (&w)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t kk = k0 + min(4 * tid + 2048 * u + j, kw - 1);
-                const float* p = X + kk * ldx + line0;
+                const TI* p = X + kk * ldx + line0;
                 if (vec && l3 == 3)      // uniform
                     r[4 * u + j] = *reinterpret_cast<const float4*>(p);
                 else
@@ -397,17 +442,19 @@ __device__ __forceinline__ float comp4(const float4& v, int j) {
 
 // Writes a loaded window into LDS: win[win_slot(k)] = the 4 lines' values at
 // window position k (weighted when kWeighted).
-template <bool kRowLines, bool kWeighted>
+template <bool kRowLines, bool kWeighted, typename TI>
 __device__ __forceinline__ void stage_window(float4* __restrict__ win,
-                                             const float4 (&r)[kPerThread], const float4 (&w)[4]) {
+                                             const typename RawQuad<TI>::type (&r)[kPerThread],
+                                             const float4 (&w)[4]) {
+    using R = RawQuad<TI>;
     const int tid = threadIdx.x;
     if constexpr (kRowLines) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                float4 v = make_float4(comp4(r[u], j), comp4(r[4 + u], j), comp4(r[8 + u], j),
-                                       comp4(r[12 + u], j));
+                float4 v = make_float4(R::value(r[u], j), R::value(r[4 + u], j),
+                                       R::value(r[8 + u], j), R::value(r[12 + u], j));
                 if constexpr (kWeighted) {
                     const float sw = sqrtf(comp4(w[u], j));
                     v.x *= sw;
@@ -422,7 +469,10 @@ __device__ __forceinline__ void stage_window(float4* __restrict__ win,
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) win[2048 * u + 512 * j + tid] = r[4 * u + j];
+            for (int j = 0; j < 4; ++j)
+                win[2048 * u + 512 * j + tid] =
+                    make_float4(R::value(r[4 * u + j], 0), R::value(r[4 * u + j], 1),
+                                R::value(r[4 * u + j], 2), R::value(r[4 * u + j], 3));
     }
 }
 
@@ -454,10 +504,10 @@ __device__ __forceinline__ void add_chunk(float4& acc, const float4* __restrict_
 
 // One workgroup of 8 waves fills a CU's LDS, so each SIMD runs 2 waves: the
 // compiler may use up to 256 VGPRs per lane.
-template <int kSlots, bool kRowLines, bool kWeighted>
+template <int kSlots, bool kRowLines, bool kWeighted, typename TI>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void sketch_kernel(
-    const float* __restrict__ X, int64_t lines, int64_t n, int64_t ldx, int vec, int32_t bp,
+    const TI* __restrict__ X, int64_t lines, int64_t n, int64_t ldx, int vec, int32_t bp,
     int32_t qn, int32_t nwin, int32_t nst, BlockList bl, int64_t RC,
     const uint32_t* __restrict__ hdr, const uint4* __restrict__ ell, float* __restrict__ out,
     int64_t ldo, int32_t npass, const float* __restrict__ wd) {
@@ -505,31 +555,29 @@ void sketch_kernel(
         }
         return m;
     };
-    auto headers = [&](const Meta& m, int w) -> uint32_t {
-        const uint32_t h = hdr[max(m.hb, 0) + w * qn];     // unconditional: index valid
-        return m.hb >= 0 ? h : 0u;
+    auto headers = [&](int32_t hb, int w) -> uint32_t {
+        const uint32_t h = hdr[max(hb, 0) + w * qn];     // unconditional: index valid
+        return hb >= 0 ? h : 0u;
     };
-    float4 pre[kPerThread];
+    typename RawQuad<TI>::type pre[kPerThread];
     float4 wpre[4];
-    Meta mnext{-1, 0, 0, 0};
     uint32_t hnext = 0;
     if ((int64_t)blockIdx.x < tasks) {
-        mnext = meta_of(blockIdx.x);
-        hnext = headers(mnext, 0);
-        load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, line_of(blockIdx.x), 0,
-                                          (int)min((int64_t)kWin, n), vec_at(0), wd);
+        hnext = headers(meta_of(blockIdx.x).hb, 0);
+        load_window<kRowLines, kWeighted, TI>(pre, wpre, X, lines, ldx, line_of(blockIdx.x), 0,
+                                              (int)min((int64_t)kWin, n), vec_at(0), wd);
     }
     for (int64_t it = blockIdx.x; it < tasks; it += gridDim.x) {
     const int64_t task = xcd_task(it, tasks);
     const int64_t line0 = task / npass * kLines;
-    const Meta meta = mnext;
+    const Meta meta = meta_of(it);      // (its loads complete with the window's, before staging)
 
     float4 acc[kSlots];
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) acc[s] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int w = 0; w < nwin; ++w) {
         __syncthreads();                 // the previous window is no longer read
-        stage_window<kRowLines, kWeighted>(win, pre, wpre);
+        stage_window<kRowLines, kWeighted, TI>(win, pre, wpre);
         __syncthreads();
         const uint32_t hv = hnext;       // this window's headers (lane s: slot s)
         // The list chunks of slot s + 1 (up to kAhead of them) are fetched
@@ -563,19 +611,20 @@ void sketch_kernel(
         // the next window (this task's, else the first of the next task) and
         // its headers
         int64_t l1 = line0, k1 = (int64_t)(w + 1) * kWin;
+        int32_t hb1 = meta.hb;
         bool more = true;
         if (w + 1 == nwin) {
             more = it + gridDim.x < tasks;
             if (more) {
-                mnext = meta_of(it + gridDim.x);
+                hb1 = meta_of(it + gridDim.x).hb;
                 l1 = line_of(it + gridDim.x);
             }
             k1 = 0;
         }
         if (more) {
-            hnext = headers(mnext, (int)(k1 / kWin));
-            load_window<kRowLines, kWeighted>(pre, wpre, X, lines, ldx, l1, k1,
-                                              (int)min((int64_t)kWin, n - k1), vec_at(k1), wd);
+            hnext = headers(hb1, (int)(k1 / kWin));
+            load_window<kRowLines, kWeighted, TI>(pre, wpre, X, lines, ldx, l1, k1,
+                                                  (int)min((int64_t)kWin, n - k1), vec_at(k1), wd);
         }
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
@@ -613,26 +662,26 @@ void sketch_kernel(
 // Slot counts compiled: 1, 2, 4, 8, 12, 16, 20, 24 (4 registers per slot).
 constexpr int kMaxSlots = 24;
 
-template <int S, bool R, bool W>
-hipError_t launch_one(dim3 grid, hipStream_t st, const float* X, int64_t lines, int64_t n,
+template <int S, bool R, bool W, typename TI>
+hipError_t launch_one(dim3 grid, hipStream_t st, const TI* X, int64_t lines, int64_t n,
                       int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin, int32_t nst,
                       const BlockList& bl, int64_t RC, const uint32_t* hdr, const uint4* ell,
                       float* out, int64_t ldo, int32_t npass, const float* wd) {
-    hipLaunchKernelGGL((sketch_kernel<S, R, W>), grid, dim3(kThreads), 0, st, X, lines, n, ldx, vec,
-                       bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass, wd);
+    hipLaunchKernelGGL((sketch_kernel<S, R, W, TI>), grid, dim3(kThreads), 0, st, X, lines, n,
+                       ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass, wd);
     return hipGetLastError();
 }
 
-template <bool R, bool W>
-hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const float* X, int64_t lines,
+template <bool R, bool W, typename TI>
+hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const TI* X, int64_t lines,
                         int64_t n, int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin,
                         int32_t nst, const BlockList& bl, int64_t RC, const uint32_t* hdr,
                         const uint4* ell, float* out, int64_t ldo, int32_t npass,
                         const float* wd) {
 #define OSK_SLOT_CASE(S)                                                                        \
     if (slots <= S)                                                                             \
-        return launch_one<S, R, W>(grid, st, X, lines, n, ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, \
-                                   ell, out, ldo, npass, wd);
+        return launch_one<S, R, W, TI>(grid, st, X, lines, n, ldx, vec, bp, qn, nwin, nst, bl,  \
+                                       RC, hdr, ell, out, ldo, npass, wd);
     OSK_SLOT_CASE(1)
     OSK_SLOT_CASE(2)
     OSK_SLOT_CASE(4)
@@ -679,10 +728,25 @@ __device__ __forceinline__ float4 load4<__bf16>(const __bf16* p) {
 constexpr int kTrRows = 64;
 constexpr int kTrCols = 256;
 
-template <typename T, bool kWhole>
+template <typename TO>
+__device__ __forceinline__ void store4(TO* p, const float4& v);
+
+template <>
+__device__ __forceinline__ void store4<float>(float* p, const float4& v) {
+    *reinterpret_cast<float4*>(p) = v;
+}
+
+template <>
+__device__ __forceinline__ void store4<__bf16>(__bf16* p, const float4& v) {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    const bf16x4 w = {(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+    *reinterpret_cast<bf16x4*>(p) = w;
+}
+
+template <typename T, bool kWhole, typename TO>
 __global__ __launch_bounds__(512) void transpose_kernel(const T* __restrict__ X, int64_t rows,
                                                         int64_t cols, int64_t ldx,
-                                                        float* __restrict__ Y, int64_t ldy,
+                                                        TO* __restrict__ Y, int64_t ldy,
                                                         int64_t wr, int64_t wc) {
     __shared__ float t[kTrRows][kTrCols + 1];
     const int tid = threadIdx.x;
@@ -744,16 +808,16 @@ __global__ __launch_bounds__(512) void transpose_kernel(const T* __restrict__ X,
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int64_t yr = c0 + cs + 32 * i;
-        float* o = Y + yr * ldy + yc;
+        TO* o = Y + yr * ldy + yc;
         if constexpr (kWhole) {
-            *reinterpret_cast<float4*>(o) = w[i];
+            store4<TO>(o, w[i]);
         } else if (yr < cols) {
             if (yc + 3 < rows) {
-                *reinterpret_cast<float4*>(o) = w[i];
+                store4<TO>(o, w[i]);
             } else {
-                if (yc < rows) o[0] = w[i].x;
-                if (yc + 1 < rows) o[1] = w[i].y;
-                if (yc + 2 < rows) o[2] = w[i].z;
+                if (yc < rows) o[0] = (TO)w[i].x;
+                if (yc + 1 < rows) o[1] = (TO)w[i].y;
+                if (yc + 2 < rows) o[2] = (TO)w[i].z;
             }
         }
     }
@@ -798,8 +862,9 @@ void pass_plan(int32_t nst, int32_t qn, int32_t* npass, int32_t* slots) {
     *slots = (int32_t)((need + kWaves - 1) / kWaves);
 }
 
-hipError_t launch_sketch(bool row_lines, const float* X, int64_t lines, int64_t n, int64_t ldx,
-                         const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
+// X: FP32, or BF16 when bf16 (rows only, unweighted).
+hipError_t launch_sketch(bool row_lines, const void* X, bool bf16, int64_t lines, int64_t n,
+                         int64_t ldx, const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                          const void* lists, float* out, int64_t ldo, hipStream_t s,
                          const float* wd = nullptr) {
     const Plan p = plan_of(n, bp);
@@ -815,16 +880,26 @@ hipError_t launch_sketch(bool row_lines, const float* X, int64_t lines, int64_t 
         cus > 0)
         nwg = std::min<int64_t>(nwg, cus);
     const dim3 grid((unsigned)nwg);
-    const int vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (ldx & 3) == 0 &&
+    // vec: a quad of 4 values is one aligned load (16 bytes FP32, 8 BF16)
+    const uintptr_t quad = bf16 ? 7 : 15;
+    const int vec = (reinterpret_cast<uintptr_t>(X) & quad) == 0 && (ldx & 3) == 0 &&
                     (reinterpret_cast<uintptr_t>(wd) & 15) == 0;
+    if (bf16) {
+        if (!row_lines || wd) return hipErrorInvalidValue;
+        return launch_slots<true, false>(slots, grid, s, static_cast<const __bf16*>(X), lines, n,
+                                         ldx, vec, bp, p.qn, p.nwin, nst, bl, p.RC, v.hdr, v.ell,
+                                         out, ldo, npass, nullptr);
+    }
+    const float* Xf = static_cast<const float*>(X);
     if (wd && row_lines)   // weighted sketches are only taken along rows
-        return launch_slots<true, true>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin,
+        return launch_slots<true, true>(slots, grid, s, Xf, lines, n, ldx, vec, bp, p.qn, p.nwin,
                                         nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, wd);
     if (row_lines)
-        return launch_slots<true, false>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin,
-                                         nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, nullptr);
-    return launch_slots<false, false>(slots, grid, s, X, lines, n, ldx, vec, bp, p.qn, p.nwin, nst,
-                                      bl, p.RC, v.hdr, v.ell, out, ldo, npass, nullptr);
+        return launch_slots<true, false>(slots, grid, s, Xf, lines, n, ldx, vec, bp, p.qn,
+                                         p.nwin, nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass,
+                                         nullptr);
+    return launch_slots<false, false>(slots, grid, s, Xf, lines, n, ldx, vec, bp, p.qn, p.nwin,
+                                      nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, nullptr);
 }
 
 }  // namespace
@@ -895,28 +970,28 @@ hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t l
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                               const void* lists, float* out, int64_t ldo, hipStream_t s) {
     if (!plan_sketch_ok(cols, nst, bp, n)) return hipErrorInvalidValue;
-    return launch_sketch(false, X, cols, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s);
+    return launch_sketch(false, X, false, cols, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s);
 }
 
 size_t transpose_bytes(int64_t rows, int64_t cols) {
     return (size_t)round_up(cols * round_up(rows, 4) * 4, 256);
 }
 
-template <typename T>
-hipError_t launch_transpose_t(const T* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
+template <typename T, typename TO>
+hipError_t launch_transpose_t(const T* X, int64_t rows, int64_t cols, int64_t ldx, TO* Y,
                               int64_t ldy, hipStream_t s) {
     const int64_t R = (rows + kTrRows - 1) / kTrRows;
     const int64_t C = (cols + kTrCols - 1) / kTrCols;
-    if (R * C > 0x7fffffff || ldy % 4 || (reinterpret_cast<uintptr_t>(Y) & 15))
+    if (R * C > 0x7fffffff || ldy % 4 || (reinterpret_cast<uintptr_t>(Y) % (4 * sizeof(TO))))
         return hipErrorInvalidValue;
     const bool vec = (reinterpret_cast<uintptr_t>(X) % (4 * sizeof(T))) == 0 && (ldx & 3) == 0;
     const int64_t wr = vec ? rows / kTrRows : 0;     // whole tiles: wr x wc
     const int64_t wc = vec ? cols / kTrCols : 0;
     if (wr * wc > 0)
-        hipLaunchKernelGGL((transpose_kernel<T, true>), dim3((unsigned)(wr * wc)), dim3(512), 0, s,
-                           X, rows, cols, ldx, Y, ldy, wr, wc);
+        hipLaunchKernelGGL((transpose_kernel<T, true, TO>), dim3((unsigned)(wr * wc)), dim3(512),
+                           0, s, X, rows, cols, ldx, Y, ldy, wr, wc);
     if (R * C > wr * wc)
-        hipLaunchKernelGGL((transpose_kernel<T, false>), dim3((unsigned)(R * C - wr * wc)),
+        hipLaunchKernelGGL((transpose_kernel<T, false, TO>), dim3((unsigned)(R * C - wr * wc)),
                            dim3(512), 0, s, X, rows, cols, ldx, Y, ldy, wr, wc);
     return hipGetLastError();
 }
@@ -931,12 +1006,25 @@ hipError_t launch_transpose_bf16(const void* X, int64_t rows, int64_t cols, int6
     return launch_transpose_t(static_cast<const __bf16*>(X), rows, cols, ldx, Y, ldy, s);
 }
 
+hipError_t launch_transpose_bf16_raw(const void* X, int64_t rows, int64_t cols, int64_t ldx,
+                                     void* Y, int64_t ldy, hipStream_t s) {
+    return launch_transpose_t(static_cast<const __bf16*>(X), rows, cols, ldx,
+                              static_cast<__bf16*>(Y), ldy, s);
+}
+
 hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                               const void* lists, float* out, int64_t ldo, hipStream_t s,
                               const float* wd) {
     if (!plan_sketch_ok(rows, nst, bp, n)) return hipErrorInvalidValue;
-    return launch_sketch(true, X, rows, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s, wd);
+    return launch_sketch(true, X, false, rows, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s, wd);
+}
+
+hipError_t launch_sketch_cols_bf16(const void* X, int64_t rows, int64_t n, int64_t ldx,
+                                   const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
+                                   const void* lists, float* out, int64_t ldo, hipStream_t s) {
+    if (!plan_sketch_ok(rows, nst, bp, n)) return hipErrorInvalidValue;
+    return launch_sketch(true, X, true, rows, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s);
 }
 
 }  // namespace osk

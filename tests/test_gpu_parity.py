@@ -339,7 +339,7 @@ def test_matmul_per_block_masks(m, n, l, b, N, e):
 
 
 # ---------------------------------------------------------------------------
-# os_matmul_ex: column-major A, BF16 operands
+# os_matmul_ex: column-major A, BF16 operands in either layout
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("m,n,l,b,N,e", [(300, 1001, 77, 100, 3, 1), (96, 4096, 130, 256, 4, 0)])
@@ -360,14 +360,40 @@ def test_matmul_ex_column_major_a(m, n, l, b, N, e, dtype, kept_only):
     assert rel(C, ref) <= PRODUCT_TOL
 
 
-def test_matmul_ex_matches_matmul_and_rejects_bf16_layouts():
+def test_matmul_ex_matches_matmul():
     m, n, l, b, N, e, seed = 200, 2048, 150, 128, 4, 1, 9
     A, B = synthetic.gaussian_pair(m, n, l, seed)
     Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     C1 = host(osk.matmul(Ad, Bd, b, N, e, seed=seed))
     C2 = host(osk.matmul_ex(Ad, Bd, b, N, e, seed=seed))
     np.testing.assert_array_equal(C1, C2)
-    with pytest.raises(osk.OversketchError):
-        osk.matmul_ex(Ad.to(torch.bfloat16), Bd, b, N, e)            # row-major BF16 A
-    with pytest.raises(osk.OversketchError):
-        osk.matmul_ex(Ad, Bd.t().contiguous().t().to(torch.bfloat16).t().contiguous().t(), b, N, e)
+
+
+def _in_layout(X, col_major, dtype):
+    """X (rows x cols, host) as a CUDA tensor of dtype, row-major or as the
+    transposed view of a row-major X^T (column-major)."""
+    t = torch.from_numpy(np.ascontiguousarray(X.T if col_major else X)).cuda().to(dtype)
+    return t.t() if col_major else t
+
+
+@pytest.mark.parametrize("n", [2048, 1001])
+@pytest.mark.parametrize("a_cm,b_cm", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("types", [("bf16", "bf16"), ("bf16", "f32"), ("f32", "bf16")])
+def test_matmul_ex_bf16_any_layout(n, a_cm, b_cm, types):
+    # a BF16 operand in either layout (sketched in place, or transposed as
+    # BF16 first) gives the FP32 path's result on its converted values, bit
+    # for bit; n = 1001 takes the unaligned loads
+    m, l, b, N, e, seed = 200, 150, 128, 4, 1, n + 2 * a_cm + b_cm
+    A, B = synthetic.gaussian_pair(m, n, l, seed)
+    dt = {"bf16": torch.bfloat16, "f32": torch.float32}
+    Ax = _in_layout(A, a_cm, dt[types[0]])
+    Bx = _in_layout(B, b_cm, dt[types[1]])
+    C = host(osk.matmul_ex(Ax, Bx, b, N, e, seed=seed))
+    ref = host(osk.matmul_ex(_in_layout(Ax.float().cpu().numpy(), a_cm, torch.float32),
+                             _in_layout(Bx.float().cpu().numpy(), b_cm, torch.float32),
+                             b, N, e, seed=seed))
+    np.testing.assert_array_equal(C, ref)
+    if types == ("bf16", "bf16") and n == 1001:
+        o = oracle.sketched_matmul(Ax.float().cpu().numpy(), Bx.float().cpu().numpy(), b, N, e,
+                                   seed=seed)
+        assert rel(C, o) <= PRODUCT_TOL
