@@ -377,8 +377,12 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
     // their own type), so that every sketch reads whole lines (16-byte
     // requests along a column would each bring in a separate cache line).
     // BF16 values are converted exactly to FP32 as the sketch stages them.
+    // With a BF16 block product the sketch writes its BF16 copy directly
+    // (rounded in the sketch's epilogue, bit for bit what the quantization
+    // of the FP32 sketch gives); otherwise the FP32 sketch.
+    const bool bf16_product = precision != OS_PREC_FP32 && !is_fp8(precision);
     auto sketch_lines = [&](const void* X, int dtype, bool transpose, int64_t lines,
-                            int64_t ldx, float* out) -> os_status {
+                            int64_t ldx, float* out, void* qout) -> os_status {
         const void* Xl = X;
         int64_t ldl = ldx;
         if (transpose) {
@@ -391,6 +395,10 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
             if (e != hipSuccess) return hip_status(e);
             Xl = tx_p;
         }
+        if (bf16_product)
+            return hip_status(osk::launch_sketch_cols_q(Xl, dtype == OS_DTYPE_BF16, lines, n, ldl,
+                                                        bs.stored, bs.nst, nblocks(sk), bp, lists,
+                                                        qout, wq, is_split(precision), s));
         return hip_status(
             dtype == OS_DTYPE_BF16
                 ? osk::launch_sketch_cols_bf16(Xl, lines, n, ldl, bs.stored, bs.nst, nblocks(sk),
@@ -399,8 +407,8 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
                                           bs.stored, bs.nst, nblocks(sk), bp, lists, out, zs, s));
     };
     if ((st = prepare(sk, n, prep, s)) != OS_OK) return st;
-    if ((st = sketch_lines(A, a_dtype, a_col_major != 0, m, lda, At)) != OS_OK) return st;
-    if ((st = sketch_lines(B, b_dtype, b_col_major == 0, l, ldb, Bt)) != OS_OK) return st;
+    if ((st = sketch_lines(A, a_dtype, a_col_major != 0, m, lda, At, aq_p)) != OS_OK) return st;
+    if ((st = sketch_lines(B, b_dtype, b_col_major == 0, l, ldb, Bt, bq_p)) != OS_OK) return st;
     if (precision == OS_PREC_FP32)
         return hip_status(osk::launch_gemm_kept(At, zs, Bt, zs, m, l, bp, bs.kept_pos, bs.K,
                                                 1.0f / (float)bs.K, C, ldc, s));
@@ -418,12 +426,6 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
                                                     (int64_t)bs.nst * bpq, 1.0f / (float)bs.K, C,
                                                     ldc, s));
     }
-    if ((st = hip_status(osk::launch_quant_bf16(At, m, zs, sk->b, bs.nst, split, aq_p, wq, s))) !=
-        OS_OK)
-        return st;
-    if ((st = hip_status(osk::launch_quant_bf16(Bt, l, zs, sk->b, bs.nst, split, bq_p, wq, s))) !=
-        OS_OK)
-        return st;
     return hip_status(osk::launch_gemm_kept_bf16(aq_p, wq, bq_p, wq, m, l, bpq, bs.kept_pos, bs.K,
                                                  split, (int64_t)bs.nst * bpq,
                                                  1.0f / (float)bs.K, C, ldc, s));

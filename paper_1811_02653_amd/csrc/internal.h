@@ -131,6 +131,15 @@ hipError_t launch_transpose_bf16_raw(const void* X, int64_t rows, int64_t cols, 
 hipError_t launch_sketch_cols_bf16(const void* X, int64_t rows, int64_t n, int64_t ldx,
                                    const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                                    const void* lists, float* out, int64_t ldo, hipStream_t s);
+// launch_sketch_cols (X FP32, or BF16 when x_bf16) writing the BF16 copy
+// that launch_quant_bf16 would make of the FP32 sketch, bit for bit: each
+// sum rounded to nearest even, block j at columns j*bpq .. (bpq = b rounded
+// up to 64, zero past b), with split the residuals nst*bpq columns on; Q
+// BF16 with ld ldo (in values).
+hipError_t launch_sketch_cols_q(const void* X, bool x_bf16, int64_t rows, int64_t n, int64_t ldx,
+                                const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
+                                const void* lists, void* out, int64_t ldo, int split,
+                                hipStream_t s);
 
 // Shapes the block product supports for operands of elem bytes per value
 // (4: FP32, 2: BF16, 1: FP8); bp must be a multiple of 128 / elem.

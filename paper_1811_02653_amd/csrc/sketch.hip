@@ -509,8 +509,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))
 void sketch_kernel(
     const TI* __restrict__ X, int64_t lines, int64_t n, int64_t ldx, int vec, int32_t bp,
     int32_t qn, int32_t nwin, int32_t nst, BlockList bl, int64_t RC,
-    const uint32_t* __restrict__ hdr, const uint4* __restrict__ ell, float* __restrict__ out,
-    int64_t ldo, int32_t npass, const float* __restrict__ wd) {
+    const uint32_t* __restrict__ hdr, const uint4* __restrict__ ell, void* __restrict__ out,
+    int64_t ldo, int32_t npass, const float* __restrict__ wd, int32_t obp, int32_t omode,
+    int64_t ozlo) {
     __shared__ float4 win[kWin + 1];    // row kWin stays zero
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -550,8 +551,8 @@ void sketch_kernel(
             const int32_t i = bl.idx[j];
             m.hb = (i * nwin) * qn + q;
             m.eb = (int32_t)((int64_t)i * nwin * RC);
-            m.col = j * bp + q * 64;
-            m.lim = min(64, bp - q * 64);
+            m.col = j * obp + q * 64;
+            m.lim = min(64, obp - q * 64);
         }
         return m;
     };
@@ -645,15 +646,32 @@ void sketch_kernel(
         }
     }
 
+    // Output: FP32 (omode 0, blocks obp = bp apart), or the BF16 copy the
+    // block product reads (omode 1: each sum rounded to nearest even, blocks
+    // obp = b rounded up to 64 apart; omode 2: also the residual
+    // bf16(x - hi), ozlo values after the high part).
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
         // lanes below lim hold buckets of the block (the last group may be partial)
         if (lane < __builtin_amdgcn_readlane(meta.lim, s)) {
-            float* o = out + line0 * ldo + __builtin_amdgcn_readlane(meta.col, s) + lane;
-            o[0] = acc[s].x;
-            if (line0 + 1 < lines) o[ldo] = acc[s].y;
-            if (line0 + 2 < lines) o[2 * ldo] = acc[s].z;
-            if (line0 + 3 < lines) o[3 * ldo] = acc[s].w;
+            const int64_t o0 = line0 * ldo + __builtin_amdgcn_readlane(meta.col, s) + lane;
+            const float v[4] = {acc[s].x, acc[s].y, acc[s].z, acc[s].w};
+            if (omode == 0) {
+                float* o = static_cast<float*>(out) + o0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r == 0 || line0 + r < lines) o[r * ldo] = v[r];
+            } else {
+                __bf16* o = static_cast<__bf16*>(out) + o0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r == 0 || line0 + r < lines) {
+                        const __bf16 hi = (__bf16)v[r];
+                        o[r * ldo] = hi;
+                        if (omode == 2) o[r * ldo + ozlo] = (__bf16)(v[r] - (float)hi);
+                    }
+                }
+            }
         }
     }
     }   // tasks
@@ -666,9 +684,11 @@ template <int S, bool R, bool W, typename TI>
 hipError_t launch_one(dim3 grid, hipStream_t st, const TI* X, int64_t lines, int64_t n,
                       int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin, int32_t nst,
                       const BlockList& bl, int64_t RC, const uint32_t* hdr, const uint4* ell,
-                      float* out, int64_t ldo, int32_t npass, const float* wd) {
+                      void* out, int64_t ldo, int32_t npass, const float* wd, int32_t obp,
+                      int32_t omode, int64_t ozlo) {
     hipLaunchKernelGGL((sketch_kernel<S, R, W, TI>), grid, dim3(kThreads), 0, st, X, lines, n,
-                       ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass, wd);
+                       ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass, wd, obp,
+                       omode, ozlo);
     return hipGetLastError();
 }
 
@@ -676,12 +696,12 @@ template <bool R, bool W, typename TI>
 hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const TI* X, int64_t lines,
                         int64_t n, int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin,
                         int32_t nst, const BlockList& bl, int64_t RC, const uint32_t* hdr,
-                        const uint4* ell, float* out, int64_t ldo, int32_t npass,
-                        const float* wd) {
+                        const uint4* ell, void* out, int64_t ldo, int32_t npass,
+                        const float* wd, int32_t obp, int32_t omode, int64_t ozlo) {
 #define OSK_SLOT_CASE(S)                                                                        \
     if (slots <= S)                                                                             \
         return launch_one<S, R, W, TI>(grid, st, X, lines, n, ldx, vec, bp, qn, nwin, nst, bl,  \
-                                       RC, hdr, ell, out, ldo, npass, wd);
+                                       RC, hdr, ell, out, ldo, npass, wd, obp, omode, ozlo);
     OSK_SLOT_CASE(1)
     OSK_SLOT_CASE(2)
     OSK_SLOT_CASE(4)
@@ -863,10 +883,13 @@ void pass_plan(int32_t nst, int32_t qn, int32_t* npass, int32_t* slots) {
 }
 
 // X: FP32, or BF16 when bf16 (rows only, unweighted).
+// X: FP32, or BF16 when bf16 (rows only, unweighted).  out_mode: 0 = FP32
+// sketch (blocks bp apart); 1 = its BF16 rounding, 2 = BF16 and residual
+// (blocks round_up(bp, 64) apart, the residual nst such blocks after).
 hipError_t launch_sketch(bool row_lines, const void* X, bool bf16, int64_t lines, int64_t n,
                          int64_t ldx, const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
-                         const void* lists, float* out, int64_t ldo, hipStream_t s,
-                         const float* wd = nullptr) {
+                         const void* lists, void* out, int64_t ldo, hipStream_t s,
+                         const float* wd = nullptr, int out_mode = 0) {
     const Plan p = plan_of(n, bp);
     const ListView v = carve_lists(const_cast<void*>(lists), nblk, n, bp);
     int32_t npass, slots;
@@ -880,6 +903,9 @@ hipError_t launch_sketch(bool row_lines, const void* X, bool bf16, int64_t lines
         cus > 0)
         nwg = std::min<int64_t>(nwg, cus);
     const dim3 grid((unsigned)nwg);
+    if (out_mode < 0 || out_mode > 2) return hipErrorInvalidValue;
+    const int32_t obp = out_mode ? p.qn * 64 : bp;
+    const int64_t ozlo = out_mode == 2 ? (int64_t)nst * obp : 0;
     // vec: a quad of 4 values is one aligned load (16 bytes FP32, 8 BF16)
     const uintptr_t quad = bf16 ? 7 : 15;
     const int vec = (reinterpret_cast<uintptr_t>(X) & quad) == 0 && (ldx & 3) == 0 &&
@@ -888,18 +914,20 @@ hipError_t launch_sketch(bool row_lines, const void* X, bool bf16, int64_t lines
         if (!row_lines || wd) return hipErrorInvalidValue;
         return launch_slots<true, false>(slots, grid, s, static_cast<const __bf16*>(X), lines, n,
                                          ldx, vec, bp, p.qn, p.nwin, nst, bl, p.RC, v.hdr, v.ell,
-                                         out, ldo, npass, nullptr);
+                                         out, ldo, npass, nullptr, obp, out_mode, ozlo);
     }
     const float* Xf = static_cast<const float*>(X);
     if (wd && row_lines)   // weighted sketches are only taken along rows
         return launch_slots<true, true>(slots, grid, s, Xf, lines, n, ldx, vec, bp, p.qn, p.nwin,
-                                        nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, wd);
+                                        nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, wd, obp,
+                                        out_mode, ozlo);
     if (row_lines)
         return launch_slots<true, false>(slots, grid, s, Xf, lines, n, ldx, vec, bp, p.qn,
                                          p.nwin, nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass,
-                                         nullptr);
+                                         nullptr, obp, out_mode, ozlo);
     return launch_slots<false, false>(slots, grid, s, Xf, lines, n, ldx, vec, bp, p.qn, p.nwin,
-                                      nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, nullptr);
+                                      nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, nullptr, obp,
+                                      out_mode, ozlo);
 }
 
 }  // namespace
@@ -1025,6 +1053,15 @@ hipError_t launch_sketch_cols_bf16(const void* X, int64_t rows, int64_t n, int64
                                    const void* lists, float* out, int64_t ldo, hipStream_t s) {
     if (!plan_sketch_ok(rows, nst, bp, n)) return hipErrorInvalidValue;
     return launch_sketch(true, X, true, rows, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s);
+}
+
+hipError_t launch_sketch_cols_q(const void* X, bool x_bf16, int64_t rows, int64_t n, int64_t ldx,
+                                const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
+                                const void* lists, void* out, int64_t ldo, int split,
+                                hipStream_t s) {
+    if (!plan_sketch_ok(rows, nst, bp, n)) return hipErrorInvalidValue;
+    return launch_sketch(true, X, x_bf16, rows, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s,
+                         nullptr, split ? 2 : 1);
 }
 
 }  // namespace osk

@@ -121,6 +121,31 @@ def test_matmul_bf16_within_rounding_bound(m, n, l, b, N, e):
     assert errs["bf16x3"] < errs["bf16"] / 16
 
 
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("m,n,l,b,N,e,kept_only", [(300, 1001, 77, 100, 3, 1, False),
+                                                   (256, 4096, 256, 256, 4, 1, True),
+                                                   (130, 2500, 90, 64, 2, 2, False),
+                                                   (70, 9000, 40, 1000, 2, 1, True)])
+def test_matmul_bf16_fused_rounding_is_the_staged_path(m, n, l, b, N, e, kept_only, precision):
+    # the whole path rounds each sketch to BF16 in the sketch's epilogue; it
+    # must give, bit for bit, what the staged path gives (FP32 sketches, then
+    # their BF16 copies, then the block product)
+    seed = m + n + b
+    A, B = synthetic.gaussian_pair(m, n, l, seed)
+    keep = synthetic.random_keep(N, e, seed)
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C = host(osk.matmul(Ad, Bd, b, N, e, seed=seed, keep=keep, kept_only=kept_only,
+                        precision=precision))
+    nst = osk.stored_count(N, e, keep, kept_only)
+    At = osk.sketch_cols(Ad, b, N, e, seed=seed, keep=keep, kept_only=kept_only)
+    Bt = osk.sketch_rows(Bd, b, N, e, seed=seed, keep=keep, kept_only=kept_only, workspace=True)
+    QA = osk.sketch_quantize(At, b, nst, precision=precision)
+    QB = osk.sketch_quantize(Bt, b, nst, precision=precision)
+    C2 = host(osk.gemm_kept_prec(QA, QB, b, nst, precision=precision,
+                                 keep=None if kept_only else keep))
+    np.testing.assert_array_equal(C, C2)
+
+
 # ---------------------------------------------------------------------------
 # FP8 E4M3 with one E8M0 scale per 64 values
 # ---------------------------------------------------------------------------
