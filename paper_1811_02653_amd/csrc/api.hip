@@ -379,8 +379,15 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
     // BF16 values are converted exactly to FP32 as the sketch stages them.
     // With a BF16 block product the sketch writes its BF16 copy directly
     // (rounded in the sketch's epilogue, bit for bit what the quantization
-    // of the FP32 sketch gives); otherwise the FP32 sketch.
+    // of the FP32 sketch gives); with an FP8 one its FP8 copy when every
+    // code belongs to a sketch group (b rounded up to 64 is a multiple of
+    // 128) and the sketch takes at most 20 slots (FP8 without the split
+    // form); otherwise the FP32 sketch, quantized after.
     const bool bf16_product = precision != OS_PREC_FP32 && !is_fp8(precision);
+    // (the split FP8 form stays staged: its second group maximum made the
+    // fused sketch slower than the separate quantization)
+    const bool fp8_fused =
+        is_fp8(precision) && !is_split(precision) && osk::sketch_fp8_fusable(sk->b, bs.nst);
     auto sketch_lines = [&](const void* X, int dtype, bool transpose, int64_t lines,
                             int64_t ldx, float* out, void* qout) -> os_status {
         const void* Xl = X;
@@ -399,6 +406,10 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
             return hip_status(osk::launch_sketch_cols_q(Xl, dtype == OS_DTYPE_BF16, lines, n, ldl,
                                                         bs.stored, bs.nst, nblocks(sk), bp, lists,
                                                         qout, wq, is_split(precision), s));
+        if (fp8_fused)
+            return hip_status(osk::launch_sketch_cols_fp8(Xl, dtype == OS_DTYPE_BF16, lines, n,
+                                                          ldl, bs.stored, bs.nst, nblocks(sk), bp,
+                                                          lists, qout, wq, s));
         return hip_status(
             dtype == OS_DTYPE_BF16
                 ? osk::launch_sketch_cols_bf16(Xl, lines, n, ldl, bs.stored, bs.nst, nblocks(sk),
@@ -414,12 +425,14 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
                                                 1.0f / (float)bs.K, C, ldc, s));
     const int split = is_split(precision);
     if (is_fp8(precision)) {
-        if ((st = hip_status(osk::launch_quant_fp8(At, m, zs, sk->b, bs.nst, split, aq_p, wq, s))) !=
-            OS_OK)
-            return st;
-        if ((st = hip_status(osk::launch_quant_fp8(Bt, l, zs, sk->b, bs.nst, split, bq_p, wq, s))) !=
-            OS_OK)
-            return st;
+        if (!fp8_fused) {
+            if ((st = hip_status(osk::launch_quant_fp8(At, m, zs, sk->b, bs.nst, split, aq_p, wq,
+                                                       s))) != OS_OK)
+                return st;
+            if ((st = hip_status(osk::launch_quant_fp8(Bt, l, zs, sk->b, bs.nst, split, bq_p, wq,
+                                                       s))) != OS_OK)
+                return st;
+        }
         return hip_status(osk::launch_gemm_kept_fp8(aq_p, wq, bq_p, wq,
                                                     quant_codes(sk->b, bs.nst, precision), m, l,
                                                     bpq, bs.kept_pos, bs.K, split,

@@ -140,6 +140,17 @@ hipError_t launch_sketch_cols_q(const void* X, bool x_bf16, int64_t rows, int64_
                                 const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                                 const void* lists, void* out, int64_t ldo, int split,
                                 hipStream_t s);
+// The same for the FP8 copy launch_quant_fp8 would make without the split
+// form (codes and E8M0 scales, ldo in bytes), bit for bit.  Only when
+// sketch_fp8_fusable(b, nst):
+// the FP8 block stride (b rounded up to 128) equals the sketch's 64-bucket
+// groups (b rounded up to 64), so every code of the copy belongs to a group,
+// and the sketch needs at most 20 slots per pass.
+bool sketch_fp8_fusable(int32_t b, int32_t nst);
+hipError_t launch_sketch_cols_fp8(const void* X, bool x_bf16, int64_t rows, int64_t n,
+                                  int64_t ldx, const BlockList& bl, int32_t nst, int32_t nblk,
+                                  int32_t bp, const void* lists, void* out, int64_t ldo,
+                                  hipStream_t s);
 
 // Shapes the block product supports for operands of elem bytes per value
 // (4: FP32, 2: BF16, 1: FP8); bp must be a multiple of 128 / elem.

@@ -31,6 +31,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "fp8.h"
 
 namespace osk {
 namespace {
@@ -62,6 +63,12 @@ __device__ __forceinline__ int64_t xcd_task(int64_t L, int64_t tasks) {
 __device__ __forceinline__ uint64_t lanes_below() {
     const int lane = threadIdx.x & 63;
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ float wave_maxf(float x) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) x = fmaxf(x, __shfl_xor(x, d));
+    return x;
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t x) {
@@ -504,7 +511,7 @@ __device__ __forceinline__ void add_chunk(float4& acc, const float4* __restrict_
 
 // One workgroup of 8 waves fills a CU's LDS, so each SIMD runs 2 waves: the
 // compiler may use up to 256 VGPRs per lane.
-template <int kSlots, bool kRowLines, bool kWeighted, typename TI>
+template <int kSlots, bool kRowLines, bool kWeighted, typename TI, bool kFp8Out = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void sketch_kernel(
     const TI* __restrict__ X, int64_t lines, int64_t n, int64_t ldx, int vec, int32_t bp,
@@ -646,10 +653,14 @@ void sketch_kernel(
         }
     }
 
-    // Output: FP32 (omode 0, blocks obp = bp apart), or the BF16 copy the
-    // block product reads (omode 1: each sum rounded to nearest even, blocks
-    // obp = b rounded up to 64 apart; omode 2: also the residual
-    // bf16(x - hi), ozlo values after the high part).
+    // Output: FP32 (omode 0, blocks obp = bp apart), or the copy the block
+    // product reads, blocks obp = b rounded up to 64 apart:
+    //   omode 1: BF16, each sum rounded to nearest even; omode 2: also the
+    //            residual bf16(x - hi), ozlo values after the high part;
+    //   omode 3: FP8 E4M3 codes (bytes) with one E8M0 scale per 64 codes,
+    //            i.e. per slot group and line (its max over the wave's 64
+    //            lanes); the scale bytes follow the codes (ozlo bytes into
+    //            the row), in code order.
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
         // lanes below lim hold buckets of the block (the last group may be partial)
@@ -661,7 +672,7 @@ void sketch_kernel(
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     if (r == 0 || line0 + r < lines) o[r * ldo] = v[r];
-            } else {
+            } else if (!kFp8Out) {
                 __bf16* o = static_cast<__bf16*>(out) + o0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -669,6 +680,32 @@ void sketch_kernel(
                         const __bf16 hi = (__bf16)v[r];
                         o[r * ldo] = hi;
                         if (omode == 2) o[r * ldo + ozlo] = (__bf16)(v[r] - (float)hi);
+                    }
+                }
+            } else if constexpr (kFp8Out) {
+                // (a separate instantiation: this code would make the FP32
+                // and BF16 kernels with 20 or more slots spill.)  Every lane
+                // of the wave holds a bucket here (lim is 64), so a group's
+                // maximum is taken over all 64 lanes; the four lines' maxima
+                // run in one interleaved butterfly, so that each step's
+                // cross-lane reads overlap.
+                const int64_t col = __builtin_amdgcn_readlane(meta.col, s);
+                uint8_t* row = static_cast<uint8_t*>(out) + line0 * ldo;
+                float a[4];
+                int e[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a[r] = fabsf(v[r]);
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) a[r] = fmaxf(a[r], __shfl_xor(a[r], d));
+#pragma unroll
+                for (int r = 0; r < 4; ++r) e[r] = e8m0_exponent(a[r]);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r == 0 || line0 + r < lines) {                // uniform
+                        row[r * ldo + col + lane] = (uint8_t)e4m3_rne(ldexpf(v[r], -e[r]));
+                        if (lane == 0) row[r * ldo + ozlo + col / 64] = (uint8_t)(e[r] + 127);
                     }
                 }
             }
@@ -680,19 +717,19 @@ void sketch_kernel(
 // Slot counts compiled: 1, 2, 4, 8, 12, 16, 20, 24 (4 registers per slot).
 constexpr int kMaxSlots = 24;
 
-template <int S, bool R, bool W, typename TI>
+template <int S, bool R, bool W, typename TI, bool Q8>
 hipError_t launch_one(dim3 grid, hipStream_t st, const TI* X, int64_t lines, int64_t n,
                       int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin, int32_t nst,
                       const BlockList& bl, int64_t RC, const uint32_t* hdr, const uint4* ell,
                       void* out, int64_t ldo, int32_t npass, const float* wd, int32_t obp,
                       int32_t omode, int64_t ozlo) {
-    hipLaunchKernelGGL((sketch_kernel<S, R, W, TI>), grid, dim3(kThreads), 0, st, X, lines, n,
+    hipLaunchKernelGGL((sketch_kernel<S, R, W, TI, Q8>), grid, dim3(kThreads), 0, st, X, lines, n,
                        ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass, wd, obp,
                        omode, ozlo);
     return hipGetLastError();
 }
 
-template <bool R, bool W, typename TI>
+template <bool R, bool W, typename TI, bool Q8 = false>
 hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const TI* X, int64_t lines,
                         int64_t n, int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin,
                         int32_t nst, const BlockList& bl, int64_t RC, const uint32_t* hdr,
@@ -700,7 +737,7 @@ hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const TI* X, int64
                         const float* wd, int32_t obp, int32_t omode, int64_t ozlo) {
 #define OSK_SLOT_CASE(S)                                                                        \
     if (slots <= S)                                                                             \
-        return launch_one<S, R, W, TI>(grid, st, X, lines, n, ldx, vec, bp, qn, nwin, nst, bl,  \
+        return launch_one<S, R, W, TI, Q8>(grid, st, X, lines, n, ldx, vec, bp, qn, nwin, nst, bl, \
                                        RC, hdr, ell, out, ldo, npass, wd, obp, omode, ozlo);
     OSK_SLOT_CASE(1)
     OSK_SLOT_CASE(2)
@@ -709,7 +746,9 @@ hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const TI* X, int64
     OSK_SLOT_CASE(12)
     OSK_SLOT_CASE(16)
     OSK_SLOT_CASE(20)
-    OSK_SLOT_CASE(24)
+    if constexpr (!Q8) {        // (FP8 output: at most 20 slots, see sketch_fp8_fusable)
+        OSK_SLOT_CASE(24)
+    }
 #undef OSK_SLOT_CASE
     return hipErrorInvalidValue;
 }
@@ -885,7 +924,8 @@ void pass_plan(int32_t nst, int32_t qn, int32_t* npass, int32_t* slots) {
 // X: FP32, or BF16 when bf16 (rows only, unweighted).
 // X: FP32, or BF16 when bf16 (rows only, unweighted).  out_mode: 0 = FP32
 // sketch (blocks bp apart); 1 = its BF16 rounding, 2 = BF16 and residual
-// (blocks round_up(bp, 64) apart, the residual nst such blocks after).
+// (nst blocks after), 3 = FP8 codes, then their scales (blocks
+// round_up(bp, 64) apart).
 hipError_t launch_sketch(bool row_lines, const void* X, bool bf16, int64_t lines, int64_t n,
                          int64_t ldx, const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                          const void* lists, void* out, int64_t ldo, hipStream_t s,
@@ -903,13 +943,23 @@ hipError_t launch_sketch(bool row_lines, const void* X, bool bf16, int64_t lines
         cus > 0)
         nwg = std::min<int64_t>(nwg, cus);
     const dim3 grid((unsigned)nwg);
-    if (out_mode < 0 || out_mode > 2) return hipErrorInvalidValue;
+    if (out_mode < 0 || out_mode > 3) return hipErrorInvalidValue;
     const int32_t obp = out_mode ? p.qn * 64 : bp;
-    const int64_t ozlo = out_mode == 2 ? (int64_t)nst * obp : 0;
+    const int64_t ozlo = out_mode >= 2 ? (int64_t)nst * obp : 0;
     // vec: a quad of 4 values is one aligned load (16 bytes FP32, 8 BF16)
     const uintptr_t quad = bf16 ? 7 : 15;
     const int vec = (reinterpret_cast<uintptr_t>(X) & quad) == 0 && (ldx & 3) == 0 &&
                     (reinterpret_cast<uintptr_t>(wd) & 15) == 0;
+    if (out_mode == 3) {          // FP8 copies: rows only, unweighted
+        if (!row_lines || wd) return hipErrorInvalidValue;
+        if (bf16)
+            return launch_slots<true, false, __bf16, true>(
+                slots, grid, s, static_cast<const __bf16*>(X), lines, n, ldx, vec, bp, p.qn,
+                p.nwin, nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, nullptr, obp, out_mode, ozlo);
+        return launch_slots<true, false, float, true>(
+            slots, grid, s, static_cast<const float*>(X), lines, n, ldx, vec, bp, p.qn, p.nwin,
+            nst, bl, p.RC, v.hdr, v.ell, out, ldo, npass, nullptr, obp, out_mode, ozlo);
+    }
     if (bf16) {
         if (!row_lines || wd) return hipErrorInvalidValue;
         return launch_slots<true, false>(slots, grid, s, static_cast<const __bf16*>(X), lines, n,
@@ -1062,6 +1112,24 @@ hipError_t launch_sketch_cols_q(const void* X, bool x_bf16, int64_t rows, int64_
     if (!plan_sketch_ok(rows, nst, bp, n)) return hipErrorInvalidValue;
     return launch_sketch(true, X, x_bf16, rows, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s,
                          nullptr, split ? 2 : 1);
+}
+
+bool sketch_fp8_fusable(int32_t b, int32_t nst) {
+    if (round_up(b, 64) != block_stride_fp8(b)) return false;
+    // the 24-slot kernel with the FP8 epilogue spills (400 bytes per lane)
+    int32_t npass, slots;
+    pass_plan(nst, (int32_t)(round_up(b, kBlockAlign) + 63) / 64, &npass, &slots);
+    return slots <= 20;
+}
+
+hipError_t launch_sketch_cols_fp8(const void* X, bool x_bf16, int64_t rows, int64_t n,
+                                  int64_t ldx, const BlockList& bl, int32_t nst, int32_t nblk,
+                                  int32_t bp, const void* lists, void* out, int64_t ldo,
+                                  hipStream_t s) {
+    if (!plan_sketch_ok(rows, nst, bp, n) || !sketch_fp8_fusable(bp, nst))
+        return hipErrorInvalidValue;
+    return launch_sketch(true, X, x_bf16, rows, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s,
+                         nullptr, 3);
 }
 
 }  // namespace osk

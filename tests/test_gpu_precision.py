@@ -121,15 +121,17 @@ def test_matmul_bf16_within_rounding_bound(m, n, l, b, N, e):
     assert errs["bf16x3"] < errs["bf16"] / 16
 
 
-@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3", "fp8", "fp8x3"])
 @pytest.mark.parametrize("m,n,l,b,N,e,kept_only", [(300, 1001, 77, 100, 3, 1, False),
                                                    (256, 4096, 256, 256, 4, 1, True),
                                                    (130, 2500, 90, 64, 2, 2, False),
                                                    (70, 9000, 40, 1000, 2, 1, True)])
-def test_matmul_bf16_fused_rounding_is_the_staged_path(m, n, l, b, N, e, kept_only, precision):
-    # the whole path rounds each sketch to BF16 in the sketch's epilogue; it
-    # must give, bit for bit, what the staged path gives (FP32 sketches, then
-    # their BF16 copies, then the block product)
+def test_matmul_fused_quantization_is_the_staged_path(m, n, l, b, N, e, kept_only, precision):
+    # the whole path rounds each sketch to BF16 (or quantizes it to FP8 with
+    # its block scales, when b rounded up to 64 is a multiple of 128; b = 64
+    # takes the staged path) in the sketch's epilogue; it must give, bit for
+    # bit, what the staged path gives (FP32 sketches, then their low-precision
+    # copies, then the block product)
     seed = m + n + b
     A, B = synthetic.gaussian_pair(m, n, l, seed)
     keep = synthetic.random_keep(N, e, seed)
