@@ -119,9 +119,6 @@ constexpr int64_t kMaxSketchLdBytes = (int64_t(1) << 24) - 256;
 size_t transpose_bytes(int64_t rows, int64_t cols);
 hipError_t launch_transpose(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
                             int64_t ldy, hipStream_t s);
-// The same for a BF16 X (values converted exactly to FP32).
-hipError_t launch_transpose_bf16(const void* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
-                                 int64_t ldy, hipStream_t s);
 // Y (cols x rows, BF16, ld ldy % 4 == 0, Y 8-byte aligned) = X^T, X BF16
 // rows x cols (values copied exactly).
 hipError_t launch_transpose_bf16_raw(const void* X, int64_t rows, int64_t cols, int64_t ldx,

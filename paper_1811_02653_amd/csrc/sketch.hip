@@ -754,8 +754,9 @@ hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const TI* X, int64
 }
 
 // ---------------------------------------------------------------------------
-// Transpose: Y (cols x rows, ld ldy, FP32) = X^T for X rows x cols (ld ldx,
-// FP32 or BF16, converted exactly to FP32).  A workgroup of 512 threads moves
+// Transpose: Y (cols x rows, ld ldy) = X^T for X rows x cols (ld ldx): FP32
+// to FP32, or BF16 to BF16 (values copied exactly; staged through LDS as
+// FP32, which holds every BF16 value).  A workgroup of 512 threads moves
 // a 64 x 256 tile of X through LDS (row stride 257 floats: the column reads
 // are conflict-free): every row of X contributes 256 consecutive values and
 // every row of Y 64, each lane moving 4 values per access.
@@ -767,7 +768,7 @@ hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const TI* X, int64
 //   kWhole = false: every other tile (the right and bottom strips, or all
 //                   tiles when X is not aligned): loads clamped into the
 //                   matrix, stores guarded.
-// Y is 16-byte aligned with ldy % 4 == 0 (checked by the launcher).
+// Y is aligned to 4 of its values with ldy % 4 == 0 (checked by the launcher).
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ float4 load4(const T* p);
@@ -1077,11 +1078,6 @@ hipError_t launch_transpose_t(const T* X, int64_t rows, int64_t cols, int64_t ld
 hipError_t launch_transpose(const float* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
                             int64_t ldy, hipStream_t s) {
     return launch_transpose_t(X, rows, cols, ldx, Y, ldy, s);
-}
-
-hipError_t launch_transpose_bf16(const void* X, int64_t rows, int64_t cols, int64_t ldx, float* Y,
-                                 int64_t ldy, hipStream_t s) {
-    return launch_transpose_t(static_cast<const __bf16*>(X), rows, cols, ldx, Y, ldy, s);
 }
 
 hipError_t launch_transpose_bf16_raw(const void* X, int64_t rows, int64_t cols, int64_t ldx,
