@@ -294,16 +294,19 @@ os_status os_matmul_cmask(const os_sketch* sk, const float* A, int64_t lda, cons
                           size_t ws_bytes, void* stream);
 
 /* Workspace bytes os_matmul_prec needs: those of os_matmul plus, for the
- * BF16 forms, the quantized copies of both sketches.  0 on invalid
+ * BF16 and FP8 forms, the quantized copies of both sketches.  0 on invalid
  * arguments. */
 size_t os_matmul_prec_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
                                       int b_col_major, int precision);
 
 /* The whole path with the block product in the given precision (os_matmul
  * is precision OS_PREC_FP32): prepare, sketch of A, (transpose of a
- * row-major B,) sketch of B, quantization of both sketches (BF16 forms),
- * block product.  Arguments as in os_matmul; workspace >=
- * os_matmul_prec_workspace_bytes for the same b_col_major and precision. */
+ * row-major B,) sketch of B, quantization of both sketches as
+ * os_sketch_quantize does it, block product.  The BF16 forms, and FP8 when
+ * b rounded up to 64 is a multiple of 128, quantize in the sketch itself
+ * (same values, no FP32 sketch written).  Arguments as in os_matmul;
+ * workspace >= os_matmul_prec_workspace_bytes for the same b_col_major and
+ * precision. */
 os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const float* B,
                          int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
                          const uint8_t* keep_host, int kept_only, int precision, float* C,
