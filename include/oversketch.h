@@ -303,9 +303,9 @@ size_t os_matmul_prec_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n,
  * is precision OS_PREC_FP32): prepare, sketch of A, (transpose of a
  * row-major B,) sketch of B, quantization of both sketches as
  * os_sketch_quantize does it, block product.  The BF16 forms always, and
- * plain FP8 when b rounded up to 64 is a multiple of 128 and the stored
- * blocks' buckets fit one sketch pass of at most 8 * 20 groups of 64,
- * quantize in the sketch itself (same values, no FP32 sketch written).  Arguments as in os_matmul;
+ * plain FP8 when b rounded up to 64 is a multiple of 128 and each wave of
+ * the sketch holds at most 20 groups of 64 buckets per pass, quantize in
+ * the sketch itself (same values, no FP32 sketch written).  Arguments as in os_matmul;
  * workspace >= os_matmul_prec_workspace_bytes for the same b_col_major and
  * precision. */
 os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const float* B,
