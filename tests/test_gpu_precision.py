@@ -125,7 +125,10 @@ def test_matmul_bf16_within_rounding_bound(m, n, l, b, N, e):
 @pytest.mark.parametrize("m,n,l,b,N,e,kept_only", [(300, 1001, 77, 100, 3, 1, False),
                                                    (256, 4096, 256, 256, 4, 1, True),
                                                    (130, 2500, 90, 64, 2, 2, False),
-                                                   (70, 9000, 40, 1000, 2, 1, True)])
+                                                   (70, 9000, 40, 1000, 2, 1, True),
+                                                   # 320 groups of 64 buckets: two sketch
+                                                   # passes of 20 slots per wave
+                                                   (40, 3000, 37, 2048, 8, 2, False)])
 def test_matmul_fused_quantization_is_the_staged_path(m, n, l, b, N, e, kept_only, precision):
     # the whole path rounds each sketch to BF16 (or quantizes it to FP8 with
     # its block scales, when b rounded up to 64 is a multiple of 128; b = 64
