@@ -265,6 +265,8 @@ def test_matmul_config1(kept_only, col_major):
     (129, 777, 384, 32, 2, 2, 0),      # K > N: all N+e kept
     (1, 50, 1, 1, 1, 0, 0),            # degenerate sizes
     (40, 3, 33, 8, 2, 1, 1),           # n < b
+    (70, 20000, 33, 8192, 2, 1, 1),    # the largest b: two sketch passes
+    (50, 5000, 40, 128, 190, 10, 7),   # 200 blocks: three sketch passes
 ])
 def test_matmul_ragged_and_masks(m, n, l, b, N, e, drop):
     seed = m + n
