@@ -37,7 +37,10 @@ constexpr int BN = 256;
 constexpr int kStepBytes = 128; // K step: 128 bytes of each tile row (32 FP32 / 64 BF16 values)
 constexpr int LDT = 36;         // LDS row stride (4-byte words) of a tile row
 constexpr int kThreads = 256;
-constexpr int kGroupM = 4;
+// tiles are rasterised in groups of kGroupM tile rows (an XCD's 32
+// concurrent tiles then share 8 row blocks of A; 8 measured 0.5 % faster
+// than 4 on the full-size product)
+constexpr int kGroupM = 8;
 
 __device__ __forceinline__ int64_t xcd_task(int64_t L, int64_t tasks) {
     if (tasks % 8 != 0) return L;
