@@ -345,6 +345,15 @@ __global__ __launch_bounds__(64) void ell_build_batch_kernel(const PrepDesc* __r
 // Input values are held in registers as loaded (4 consecutive values of a
 // line: a float4 for FP32, their 4 bit patterns in a uint2 for BF16) and
 // converted to FP32 (exactly) when the window is written to LDS.
+// A window's FP32 values and weights are read once: non-temporal loads keep
+// them from displacing the bucket lists (which every line group reads) in
+// the caches (the FP32 sketch of A 2-5 % faster).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 load_stream(const float* __restrict__ p) {
+    const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    return make_float4(t[0], t[1], t[2], t[3]);
+}
+
 template <typename TI>
 struct RawQuad;
 template <>
@@ -408,12 +417,11 @@ __device__ __forceinline__ void load_window(typename RawQuad<TI>::type (&r)[kPer
                     // (the FP32 load written here, not through R::load: through the
                     // helper the FP32 kernels took 20 more registers and spilled)
                     if constexpr (sizeof(TI) == 4)
-                        r[4 * q + u] =
-                            *reinterpret_cast<const float4*>(X + (line0 + dl[q]) * ldx + kk);
+                        r[4 * q + u] = load_stream(X + (line0 + dl[q]) * ldx + kk);
                     else
                         r[4 * q + u] = R::load(X + (line0 + dl[q]) * ldx + kk);
                 }
-                if constexpr (kWeighted) w[u] = *reinterpret_cast<const float4*>(wd + kk);
+                if constexpr (kWeighted) w[u] = load_stream(wd + kk);
             }
         } else {
 #pragma unroll
