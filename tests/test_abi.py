@@ -279,3 +279,15 @@ def test_gram_workspace_and_unconfigured_plan(L):
     assert not g.value
     L.os_gram_plan_destroy(h1)
     L.os_gram_plan_destroy(h2)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU only: --gpus N > 1 exits with a message
+    before it imports torch or touches a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr
+    assert r.stdout == ""
