@@ -179,6 +179,19 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _empty(shape, dtype, device, stream=None):
+    """torch.empty on the caller's device.  The caching allocator ties a
+    block to the stream that was current when it was allocated; when the
+    kernels run on another (explicit) stream, the tensor is also recorded on
+    that stream, so a temporary dropped on return is not handed to another
+    allocation while the kernels still use it."""
+    torch = _torch()
+    t = torch.empty(shape, dtype=dtype, device=device)
+    if stream is not None and stream != torch.cuda.current_stream(t.device):
+        t.record_stream(stream)
+    return t
+
+
 def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
@@ -203,7 +216,10 @@ def _row_major(t, name):
     return rows, cols, (cols + 15) // 16 * 16
 
 
-def _sketch(b, N, e, seed, h=None, sigma=None):
+def _sketch(b, N, e, seed, h=None, sigma=None, n=None):
+    """The os_sketch struct.  Explicit tables must be [N+e, n] (the kernels
+    read h[i*n + k]); n is required with them, so a table of the wrong width
+    is refused here, before any launch."""
     s = _Sketch()
     s.seed = int(seed) & (2**64 - 1)
     s.b, s.N, s.e = int(b), int(N), int(e)
@@ -213,12 +229,18 @@ def _sketch(b, N, e, seed, h=None, sigma=None):
         raise OversketchError("explicit h and sigma go together")
     if h is not None:
         torch = _torch()
+        if n is None:
+            raise OversketchError("explicit h and sigma need the sketched length n")
+        want = (int(N) + int(e), int(n))
+        for t, name in ((h, "h"), (sigma, "sigma")):
+            if not isinstance(t, torch.Tensor) or tuple(t.shape) != want:
+                raise OversketchError("%s must be an [N+e, n] = [%d, %d] tensor, got %s"
+                                      % (name, want[0], want[1],
+                                         tuple(getattr(t, "shape", ()))))
         _require_cuda(h, "h", torch.int32)
         _require_cuda(sigma, "sigma", torch.int8)
-        if not (h.is_contiguous() and sigma.is_contiguous()) or h.shape != sigma.shape:
-            raise OversketchError("h and sigma must be contiguous [N+e, n] tensors")
-        if h.shape[0] != N + e:
-            raise OversketchError("h must have N+e rows")
+        if not (h.is_contiguous() and sigma.is_contiguous()):
+            raise OversketchError("h and sigma must be contiguous")
         s.h = h.data_ptr()
         s.sigma = sigma.data_ptr()
     return s
@@ -250,9 +272,9 @@ def stored_count(N: int, e: int, keep=None, kept_only: bool = False) -> int:
 def hash_fill(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None):
     """Buckets (int32) and signs (int8), each [N+e, n], computed on the GPU."""
     torch = _torch()
-    s = _sketch(b, N, e, seed, h, sigma)
-    h_out = torch.empty((N + e, n), dtype=torch.int32, device=device)
-    s_out = torch.empty((N + e, n), dtype=torch.int8, device=device)
+    s = _sketch(b, N, e, seed, h, sigma, n)
+    h_out = _empty((N + e, n), torch.int32, device, stream)
+    s_out = _empty((N + e, n), torch.int8, device, stream)
     _check(lib().os_hash_fill(ctypes.byref(s), n, _ptr(h_out), _ptr(s_out), _stream(stream)),
            "os_hash_fill")
     return h_out, s_out
@@ -261,20 +283,20 @@ def hash_fill(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None
 def sketch_prepare(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None):
     """Prepared sketch (opaque uint8 device buffer) for an n-long sketched dimension."""
     torch = _torch()
-    s = _sketch(b, N, e, seed, h, sigma)
+    s = _sketch(b, N, e, seed, h, sigma, n)
     nbytes = int(lib().os_sketch_prepare_bytes(ctypes.byref(s), n))
     if nbytes == 0:
         raise OversketchError("invalid sketch parameters")
-    prep = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    prep = _empty(nbytes, torch.uint8, device, stream)
     _check(lib().os_sketch_prepare(ctypes.byref(s), n, _ptr(prep), nbytes, _stream(stream)),
            "os_sketch_prepare")
     return prep
 
 
-def _line_major_out(out, lines, width, device):
+def _line_major_out(out, lines, width, device, stream=None):
     torch = _torch()
     if out is None:
-        return torch.empty((lines, width), dtype=torch.float32, device=device)
+        return _empty((lines, width), torch.float32, device, stream)
     _require_cuda(out, "out", torch.float32)
     if tuple(out.shape) != (lines, width):
         raise OversketchError("out must be %d x %d" % (lines, width))
@@ -289,9 +311,9 @@ def sketch_cols(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=No
     rows, n, ldx = _row_major(X, "X")
     if prep is None:
         prep = sketch_prepare(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
-    s = _sketch(b, N, e, seed, h, sigma)
+    s = _sketch(b, N, e, seed, h, sigma, n)
     width = stored_count(N, e, keep, kept_only) * block_stride(b)
-    out = _line_major_out(out, rows, width, X.device)
+    out = _line_major_out(out, rows, width, X.device, stream)
     _, _, ldo = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
     _check(lib().os_sketch_cols(ctypes.byref(s), _ptr(prep), prep.numel(), _ptr(X), rows, n, ldx,
@@ -321,14 +343,13 @@ def sketch_rows(X, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=No
     n, cols, ldx = _row_major(X, "X")
     if prep is None:
         prep = sketch_prepare(n, b, N, e, seed, h, sigma, device=X.device, stream=stream)
-    s = _sketch(b, N, e, seed, h, sigma)
+    s = _sketch(b, N, e, seed, h, sigma, n)
     width = stored_count(N, e, keep, kept_only) * block_stride(b)
-    out = _line_major_out(out, cols, width, X.device)
+    out = _line_major_out(out, cols, width, X.device, stream)
     _, _, ldo = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
     if workspace is True or (workspace is None and X.dtype == torch.bfloat16):
-        workspace = torch.empty(sketch_rows_workspace_bytes(n, cols), dtype=torch.uint8,
-                                device=X.device)
+        workspace = _empty(sketch_rows_workspace_bytes(n, cols), torch.uint8, X.device, stream)
     wp, wn = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel())
     dtype = 1 if X.dtype == torch.bfloat16 else 0
     _check(lib().os_sketch_rows_ex(ctypes.byref(s), _ptr(prep), prep.numel(), _ptr(X), dtype, n,
@@ -351,7 +372,7 @@ def gemm_kept(At, Bt, b, keep=None, out=None, stream=None):
         raise OversketchError("At and Bt must both hold nst * block_stride(b) columns")
     nst = wa // bp
     if out is None:
-        out = torch.empty((m, l), dtype=torch.float32, device=At.device)
+        out = _empty((m, l), torch.float32, At.device, stream)
     _require_cuda(out, "out", torch.float32)
     _, _, ldc = _row_major(out, "out")
     _, pk = _mask(keep, nst)
@@ -390,8 +411,7 @@ def sketch_quantize(S, b, nst, precision="bf16", out=None, stream=None):
     dt = torch.uint8 if fp8 else torch.bfloat16
     pad = 16 if fp8 else 8                      # rows of 16 bytes
     if out is None:
-        out = torch.empty((lines, (width + pad - 1) // pad * pad), dtype=dt,
-                          device=S.device)[:, :width]
+        out = _empty((lines, (width + pad - 1) // pad * pad), dt, S.device, stream)[:, :width]
     _require_cuda(out, "out", dt)
     _, w, ldq = _row_major(out, "out")
     if w != width:
@@ -414,7 +434,7 @@ def gemm_kept_prec(At, Bt, b, nst, precision="bf16", keep=None, out=None, stream
     m, _, lda = _row_major(At, "At")
     l, _, ldb = _row_major(Bt, "Bt")
     if out is None:
-        out = torch.empty((m, l), dtype=torch.float32, device=At.device)
+        out = _empty((m, l), torch.float32, At.device, stream)
     _require_cuda(out, "out", torch.float32)
     _, _, ldc = _row_major(out, "out")
     _, pk = _mask(keep, nst)
@@ -455,14 +475,14 @@ def matmul(A, B, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None
     else:
         raise OversketchError("B must have a unit stride in one dimension")
     p = _prec(precision)
-    s = _sketch(b, N, e, seed, h, sigma)
+    s = _sketch(b, N, e, seed, h, sigma, n)
     need = int(lib().os_matmul_prec_workspace_bytes(ctypes.byref(s), m, n, l, b_col_major, p))
     if need == 0:
         raise OversketchError("invalid sizes for os_matmul")
     if workspace is None:
-        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+        workspace = _empty(need, torch.uint8, A.device, stream)
     if out is None:
-        out = torch.empty((m, l), dtype=torch.float32, device=A.device)
+        out = _empty((m, l), torch.float32, A.device, stream)
     _require_cuda(out, "out", torch.float32)
     _, _, ldc = _row_major(out, "out")
     _, pk = _mask(keep, N + e)
@@ -473,13 +493,18 @@ def matmul(A, B, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None
     return out
 
 
-def _cmask_tensor(cmask, nbI, nbJ, nst, device):
+def _cmask_tensor(cmask, nbI, nbJ, nst, device, stream=None):
     torch = _torch()
     if not isinstance(cmask, torch.Tensor):
         cmask = torch.from_numpy(np.ascontiguousarray(np.asarray(cmask, dtype=np.uint8)))
     cmask = cmask.to(device=device, dtype=torch.uint8).contiguous()
     if tuple(cmask.shape) != (nbI, nbJ, nst):
         raise OversketchError("cmask must be %d x %d x %d" % (nbI, nbJ, nst))
+    cur = torch.cuda.current_stream(cmask.device)
+    if stream is not None and stream != cur:
+        # the copy above ran on the current stream: the kernels' stream waits for it
+        stream.wait_stream(cur)
+        cmask.record_stream(stream)
     return cmask
 
 
@@ -495,9 +520,9 @@ def gemm_kept_cmask(At, Bt, b, cmask, out=None, stream=None):
     if wa != wb or wa % bp:
         raise OversketchError("At and Bt must both hold nst * block_stride(b) columns")
     nst = wa // bp
-    cm = _cmask_tensor(cmask, -(-m // b), -(-l // b), nst, At.device)
+    cm = _cmask_tensor(cmask, -(-m // b), -(-l // b), nst, At.device, stream)
     if out is None:
-        out = torch.empty((m, l), dtype=torch.float32, device=At.device)
+        out = _empty((m, l), torch.float32, At.device, stream)
     _require_cuda(out, "out", torch.float32)
     _, _, ldc = _row_major(out, "out")
     _check(lib().os_gemm_kept_cmask(_ptr(At), lda, _ptr(Bt), ldb, m, l, int(b), nst, _ptr(cm),
@@ -522,15 +547,15 @@ def matmul_cmask(A, B, b, N, e, cmask, seed=0, h=None, sigma=None, out=None, wor
         b_col_major, ldb = 1, B.stride(1) if l > 1 else (n + 3) // 4 * 4
     else:
         raise OversketchError("B must have a unit stride in one dimension")
-    s = _sketch(b, N, e, seed, h, sigma)
-    cm = _cmask_tensor(cmask, -(-m // b), -(-l // b), N + e, A.device)
+    s = _sketch(b, N, e, seed, h, sigma, n)
+    cm = _cmask_tensor(cmask, -(-m // b), -(-l // b), N + e, A.device, stream)
     need = int(lib().os_matmul_prec_workspace_bytes(ctypes.byref(s), m, n, l, b_col_major, 0))
     if need == 0:
         raise OversketchError("invalid sizes for os_matmul_cmask")
     if workspace is None:
-        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+        workspace = _empty(need, torch.uint8, A.device, stream)
     if out is None:
-        out = torch.empty((m, l), dtype=torch.float32, device=A.device)
+        out = _empty((m, l), torch.float32, A.device, stream)
     _require_cuda(out, "out", torch.float32)
     _, _, ldc = _row_major(out, "out")
     _check(lib().os_matmul_cmask(ctypes.byref(s), _ptr(A), lda, _ptr(B), ldb, b_col_major, m, n,
@@ -572,7 +597,7 @@ def matmul_ex(A, B, b, N, e, seed=0, keep=None, kept_only=False, precision="fp32
     bd, bcm, n2, l, ldb = _layout(B, "B")
     if n2 != n:
         raise OversketchError("inner dimensions differ")
-    sk = _sketch(b, N, e, seed, h, sigma)
+    sk = _sketch(b, N, e, seed, h, sigma, n)
     arr, kp = _mask(keep, int(N) + int(e))
     prec = _prec(precision)
     L = lib()
@@ -580,9 +605,9 @@ def matmul_ex(A, B, b, N, e, seed=0, keep=None, kept_only=False, precision="fp32
     if need == 0:
         raise OversketchError("invalid sizes or sketch parameters")
     if workspace is None or workspace.numel() < need:
-        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+        workspace = _empty(need, torch.uint8, A.device, stream)
     if out is None:
-        out = torch.empty((m, l), dtype=torch.float32, device=A.device)
+        out = _empty((m, l), torch.float32, A.device, stream)
     _, _, ldc = _row_major(out, "out")
     _check(L.os_matmul_ex(ctypes.byref(sk), _ptr(A), ad, acm, lda, _ptr(B), bd, bcm, ldb, m, n, l,
                           kp, 1 if kept_only else 0, prec, _ptr(out), ldc, _ptr(workspace),

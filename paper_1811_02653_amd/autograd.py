@@ -9,11 +9,18 @@ backward here forms it as the sketched product of Section 4,
 
 sketching the rows (tokens) of X and of dY with the same count-sketch blocks
 and multiplying the kept blocks (every step in the library's HIP kernels).
-dX = dY W^T stays exact.  The sketched gradient is unbiased (Lemma 2) with
-the second moment of Lemma 1; a fresh seed per backward call keeps the
-gradients of successive steps independent.
+dX = dY W^T stays exact.  The sketched gradient is unbiased over the draw of
+S (Lemma 2), with the second moment of Lemma 1.
 
-The exact products (forward Y and dX) are plain GEMMs and use torch.matmul.
+Seeds: with ``seed=None`` (the default) every forward call draws a fresh
+64-bit sketch key from torch's CPU generator and keeps it for its backward,
+so successive training steps use independent sketches and their gradient
+errors average out.  A fixed integer seed gives the same S on every call
+(for tests and reproducible runs).
+
+The exact products (forward Y and dX) are plain dense GEMMs that the layer
+needs around the method, not part of it: they go to torch.matmul (the
+vendor BLAS), and only the sketched product runs in this library.
 """
 from __future__ import annotations
 
@@ -37,6 +44,15 @@ def sketched_weight_grad(X, dY, b, N, e, seed=0, keep=None, precision="fp32", h=
                      precision=precision, h=h, sigma=sigma, workspace=workspace, stream=stream)
 
 
+def fresh_seed() -> int:
+    """A 64-bit sketch key drawn from torch's default CPU generator (so
+    torch.manual_seed makes a run reproducible)."""
+    import torch
+    hi = int(torch.randint(0, 2**32, (1,), dtype=torch.int64).item())
+    lo = int(torch.randint(0, 2**32, (1,), dtype=torch.int64).item())
+    return (hi << 32) | lo
+
+
 class SketchedLinearFunction:
     """Factory of the torch.autograd.Function (torch is imported lazily)."""
 
@@ -52,19 +68,21 @@ class SketchedLinearFunction:
             @staticmethod
             def forward(ctx, X, W, b, N, e, seed, keep, precision, h, sigma):
                 ctx.save_for_backward(X, W)
-                ctx.cfg = (b, N, e, seed, keep, precision, h, sigma)
+                # the key this call's backward uses (drawn now when not fixed)
+                key = fresh_seed() if seed is None else int(seed)
+                ctx.cfg = (b, N, e, key, keep, precision, h, sigma)
                 return torch.matmul(X, W)
 
             @staticmethod
             def backward(ctx, dY):
                 X, W = ctx.saved_tensors
-                b, N, e, seed, keep, precision, h, sigma = ctx.cfg
+                b, N, e, key, keep, precision, h, sigma = ctx.cfg
                 dX = None
                 if ctx.needs_input_grad[0]:
                     dX = torch.matmul(dY, W.t())
                 dW = None
                 if ctx.needs_input_grad[1]:
-                    dW = sketched_weight_grad(X, dY.contiguous(), b, N, e, seed=seed, keep=keep,
+                    dW = sketched_weight_grad(X, dY.contiguous(), b, N, e, seed=key, keep=keep,
                                               precision=precision, h=h, sigma=sigma).to(W.dtype)
                 return dX, dW, None, None, None, None, None, None, None, None
 
@@ -72,6 +90,7 @@ class SketchedLinearFunction:
         return cls._fn
 
 
-def sketched_linear(X, W, b, N, e, seed=0, keep=None, precision="fp32", h=None, sigma=None):
-    """Y = X W with the sketched weight gradient in backward."""
+def sketched_linear(X, W, b, N, e, seed=None, keep=None, precision="fp32", h=None, sigma=None):
+    """Y = X W with the sketched weight gradient in backward.  seed=None
+    draws a fresh sketch per forward call; an integer fixes it."""
     return SketchedLinearFunction.get().apply(X, W, b, N, e, seed, keep, precision, h, sigma)

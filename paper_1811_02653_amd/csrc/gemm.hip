@@ -9,22 +9,26 @@
 // summed in registers instead of through storage, and blocks that
 // straggled are skipped by walking only the kept-block list.
 //
-// Design (gfx950, FP32 MFMA v_mfma_f32_32x32x2_f32):
-//   - 256 x 256 output tile per workgroup of 4 waves; each wave owns a
-//     128 x 128 sub-tile = 4 x 4 MFMA blocks of 32 x 32 (256 accumulators
-//     per lane, kept in AGPRs).
-//   - K steps of 32: both operands are K-contiguous (a row of the tile is 32
-//     consecutive K values, 128 bytes), loaded with 16-byte coalesced reads
-//     and stored to LDS row by row with a row stride of 36 floats, double
-//     buffered: step t is read from one buffer while step t + 1 is stored
-//     into the other, and step t + 2 is already in flight in registers.
-//   - Lane half h of every MFMA takes k = 16h + kk (kk = 0..15), so a lane
-//     reads its 16 K values of a row as four 16-byte LDS reads; A and B use
-//     the same k order, so the dot products are unchanged (only their
-//     summation order differs).  With the 36-float stride the 16 rows read by
-//     one 16-lane pass fall in disjoint banks.
+// Design (gfx950; FP32 v_mfma_f32_32x32x2_f32, BF16 v_mfma_f32_32x32x16_bf16,
+// FP8 v_mfma_scale_f32_32x32x64_f8f6f4):
+//   - 256 x 256 output tile per workgroup of 8 waves, two per SIMD; wave
+//     (wm, wn) owns a 128 x 64 sub-tile = 4 x 2 MFMA blocks of 32 x 32 (128
+//     accumulators per lane).  With two waves on a SIMD one wave's memory
+//     instructions issue while the other's MFMAs keep the pipe busy.
+//   - K steps of 128 bytes of every tile row (32 FP32, 64 BF16 or 128 FP8
+//     values).  Both operands are K-contiguous; a step's tiles go straight
+//     from global memory into LDS (buffer_load_dwordx4 with the lds flag: no
+//     VGPR staging, no LDS stores), unpadded, with the 16-byte chunk c of
+//     row r at chunk c ^ (r & 7) so fragment reads of 8 consecutive rows hit
+//     8 different bank groups.  Two step buffers per operand: step t + 1 is
+//     loaded into one while step t is read from the other.
+//   - Lane half h of every MFMA takes the K values at byte offset 64h + 16q
+//     of the step's row (q = quad), so a lane's fragment is one 16-byte LDS
+//     read; A and B use the same K order, so the dot products are unchanged
+//     (only their summation order differs).
+//   - The kept-block list is held in VGPRs and picked with v_readlane.
 //   - Workgroup -> tile mapping keeps neighbouring tiles on one XCD (shared
-//     L2) and rasterises in groups of 4 tile rows.
+//     L2) and rasterises in groups of kGroupM = 8 tile rows.
 #include "internal.h"
 
 namespace osk {

@@ -94,9 +94,7 @@ class GramBatch:
             if bs[k] is None:
                 raise OversketchError("b is required")
             p = probs[k]
-            p.sk = _sketch(bs[k], Ns[k], es[k], seeds[k], hs[k], sigmas[k])
-            if hs[k] is not None and hs[k].shape[1] != n:
-                raise OversketchError("h[%d] must be [N+e, n]" % k)
+            p.sk = _sketch(bs[k], Ns[k], es[k], seeds[k], hs[k], sigmas[k], n)
             p.A, p.lda, p.m, p.n = A.data_ptr(), lda, m, n
             dk = d_list[k]
             if dk is not None:

@@ -291,3 +291,48 @@ def test_bench_refuses_several_gpus():
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
     assert r.stdout == ""
+
+
+@pytest.mark.parametrize("shape", [(5, 99), (5, 101), (4, 100), (6, 100), (500,)])
+def test_explicit_tables_of_the_wrong_shape_are_refused(shape):
+    """A table that is not [N+e, n] is refused in the binding, before any
+    library call (the kernels read h[i*n + k]: a short row would run past
+    the tensor, a long one would shift every later block)."""
+    torch = pytest.importorskip("torch")
+    h = torch.zeros(shape, dtype=torch.int32)
+    s = torch.ones(shape, dtype=torch.int8)
+    with pytest.raises(osk.OversketchError, match=r"\[N\+e, n\]"):
+        osk._sketch(64, 4, 1, 0, h, s, n=100)
+    # every wrapper that takes tables checks them before it launches
+    with pytest.raises(osk.OversketchError, match=r"\[N\+e, n\]"):
+        osk.hash_fill(100, 64, 4, 1, h=h, sigma=s, device="cpu")
+    with pytest.raises(osk.OversketchError, match=r"\[N\+e, n\]"):
+        osk.sketch_prepare(100, 64, 4, 1, h=h, sigma=s, device="cpu")
+
+
+def test_explicit_tables_need_n_and_a_gpu():
+    torch = pytest.importorskip("torch")
+    h = torch.zeros((5, 100), dtype=torch.int32)
+    s = torch.ones((5, 100), dtype=torch.int8)
+    with pytest.raises(osk.OversketchError, match="sketched length n"):
+        osk._sketch(64, 4, 1, 0, h, s)
+    # the right shape on the host: refused as not a device tensor
+    with pytest.raises(osk.OversketchError, match="CUDA"):
+        osk._sketch(64, 4, 1, 0, h, s, n=100)
+    with pytest.raises(osk.OversketchError, match="together"):
+        osk._sketch(64, 4, 1, 0, h, None, n=100)
+
+
+def test_fresh_sketch_keys_per_forward():
+    """The linear layer's default draws a new 64-bit key per forward call
+    (independent sketches across training steps), reproducibly under
+    torch.manual_seed."""
+    torch = pytest.importorskip("torch")
+    from paper_1811_02653_amd.autograd import fresh_seed
+    torch.manual_seed(3)
+    keys = [fresh_seed() for _ in range(8)]
+    assert len(set(keys)) == 8
+    assert all(0 <= k < 2**64 for k in keys)
+    assert any(k >= 2**32 for k in keys)
+    torch.manual_seed(3)
+    assert [fresh_seed() for _ in range(8)] == keys

@@ -95,3 +95,31 @@ def test_unbiased_over_seeds():
     # one sketch alone is much further off (the check is not vacuous)
     one = host(sketched_weight_grad(Xd, Dd, b, N, 0, seed=7))
     assert oracle.frob2(one - exact) > 10 * err2
+
+
+def test_default_seed_is_fresh_per_forward_and_kept_for_backward():
+    """seed=None: each forward draws its own key (torch's CPU generator) and
+    its backward uses exactly that key; two steps get different sketches."""
+    from paper_1811_02653_amd.autograd import fresh_seed
+    tokens, d_in, d_out, b, N = 1024, 48, 40, 128, 2
+    X, W, G = synthetic.linear_layer(tokens, d_in, d_out, 21)
+    Xd = torch.from_numpy(X).cuda()
+    Gd = torch.from_numpy(G).cuda()
+    grads = []
+    for step in range(2):
+        torch.manual_seed(100 + step)
+        key = fresh_seed()
+        torch.manual_seed(100 + step)
+        Wd = torch.from_numpy(W).cuda().requires_grad_(True)
+        sketched_linear(Xd, Wd, b, N, 0).backward(Gd)
+        ref = sketched_weight_grad(Xd, Gd, b, N, 0, seed=key)
+        assert torch.equal(Wd.grad, ref)
+        grads.append(host(Wd.grad))
+    assert not np.array_equal(grads[0], grads[1])
+    # a fixed seed gives the same sketch on every call
+    fixed = []
+    for _ in range(2):
+        Wd = torch.from_numpy(W).cuda().requires_grad_(True)
+        sketched_linear(Xd, Wd, b, N, 0, seed=5).backward(Gd)
+        fixed.append(host(Wd.grad))
+    assert np.array_equal(fixed[0], fixed[1])

@@ -279,3 +279,92 @@ def test_matmul_fp8_within_rounding_bound(m, n, l, b, N, e):
     err3 = np.sqrt(oracle.frob2(C3 - ref))
     # the residual pass recovers about four more bits
     assert err3 < err / 8
+
+
+# ---------------------------------------------------------------------------
+# The precision workload: the small validation shapes (A 256 x 4096,
+# B 4096 x 256, b = 256, N = 4, e = 1, one block dropped) with log-normal
+# (sigma = 2) row norms of A and column norms of B.  Line norms spread over
+# about five decades, so one scale per tensor would leave the small lines
+# with few significant bits; the per-64-value power-of-two scales of the
+# FP8 copies (and BF16's own exponent) keep every line's relative accuracy.
+# Each entry of C is checked against the oracle's FP64 sketched product on
+# the same S, within the rounding bound of its own operands:
+#   |C - C_o|[r,c] <= ((1+u)^2 - 1 + g) * M[r,c] + (FP8) subnormal terms,
+#   M = (|A~| |B~|^T) / K on the oracle's sketch, g = FP32 accumulation
+#   (K * stride * 2^-24, a worst case) plus, for FP8, the scaled MFMA's
+#   inner sum (2^-14 of the products' magnitude, see test_gemm_kept_fp8_vs_fp64).
+# ---------------------------------------------------------------------------
+
+LOGNORMAL_CASE = dict(m=256, n=4096, l=256, b=256, N=4, e=1)
+
+
+@pytest.fixture(scope="module")
+def lognormal_case():
+    c = LOGNORMAL_CASE
+    seed = 3
+    A, B = synthetic.lognormal_scaled_pair(c["m"], c["n"], c["l"], seed, sigma=2.0)
+    keep = synthetic.random_keep(c["N"], c["e"], seed)
+    assert keep.sum() == c["N"]
+    h, s = oracle.hash_tables(seed, c["N"] + c["e"], c["n"], c["b"])
+    At = oracle.sketch_cols(A, h, s, c["b"])
+    Bt = oracle.sketch_rows(B, h, s, c["b"])
+    ref = oracle.block_product(At, Bt, c["b"], keep)
+    # the same as the oracle's whole path
+    np.testing.assert_array_equal(
+        ref, oracle.sketched_matmul(A, B, c["b"], c["N"], c["e"], seed=seed, keep=keep))
+    return dict(A=A, B=B, seed=seed, keep=keep, At=At, Bt=Bt, ref=ref)
+
+
+def test_lognormal_inputs_span_decades(lognormal_case):
+    # the workload is what it claims: line norms spread over >= 4 decades
+    ra = np.linalg.norm(lognormal_case["A"], axis=1)
+    cb = np.linalg.norm(lognormal_case["B"], axis=0)
+    assert ra.max() / ra.min() > 1e4 and cb.max() / cb.min() > 1e4
+
+
+@pytest.mark.parametrize("precision,u", [("fp32", 0.0), ("bf16", 2.0 ** -8),
+                                         ("bf16x3", 2.0 ** -16), ("fp8", 2.0 ** -4),
+                                         ("fp8x3", 2.0 ** -8)])
+def test_lognormal_norms_entrywise_rounding_bound(lognormal_case, precision, u):
+    c, d = LOGNORMAL_CASE, lognormal_case
+    b, K = c["b"], int(d["keep"].sum())
+    Ad, Bd = torch.from_numpy(d["A"]).cuda(), torch.from_numpy(d["B"]).cuda()
+    C = host(osk.matmul(Ad, Bd, b, c["N"], c["e"], seed=d["seed"], keep=d["keep"],
+                        precision=precision))
+    ref = d["ref"]
+    Aa, Ba = np.abs(d["At"]), np.abs(d["Bt"])
+    fp8 = precision.startswith("fp8")
+    if fp8:
+        # an element's FP8 rounding is at most u |x| + c, c = (its 64-block
+        # max) / 229376 (the subnormal step; the line's maximum stands in for
+        # the block's).  Split form: |x - hi - lo| <= u_h (u_h |x| + c) + c_lo
+        # with c_lo <= u_h * blockmax / 229376, so u = u_h^2 = 2^-8 and an
+        # absolute term 2 u_h c.  Writing the absolute term as u * (c' / u)
+        # folds it into M.
+        absolute = 1.0 if precision == "fp8" else 2.0 * 2.0 ** -4
+        Aa = Aa + absolute * Aa.max(axis=1, keepdims=True) / 229376.0 / u
+        Ba = Ba + absolute * Ba.max(axis=0, keepdims=True) / 229376.0 / u
+    M = oracle.block_product(Aa, Ba, b, d["keep"])
+    stride = osk.block_stride_prec(b, precision)
+    g = K * stride * 2.0 ** -24 + (2.0 ** -14 if fp8 else 0.0)
+    bound = ((1 + u) ** 2 - 1 + g) * M
+    err = np.abs(C - ref)
+    worst = np.max(err / bound)
+    assert worst <= 1.0, (precision, worst)
+    # relative Frobenius against the oracle on the same S, per precision
+    rel = oracle.rel_frob(C, ref)
+    limit = {"fp32": 1e-5, "bf16": 2e-2, "bf16x3": 1e-4, "fp8": 2e-1, "fp8x3": 2e-2}[precision]
+    assert rel <= limit, (precision, rel)
+
+
+def test_lognormal_split_forms_recover_accuracy(lognormal_case):
+    c, d = LOGNORMAL_CASE, lognormal_case
+    Ad, Bd = torch.from_numpy(d["A"]).cuda(), torch.from_numpy(d["B"]).cuda()
+    err = {}
+    for prec in ("bf16", "bf16x3", "fp8", "fp8x3"):
+        C = host(osk.matmul(Ad, Bd, c["b"], c["N"], c["e"], seed=d["seed"], keep=d["keep"],
+                            precision=prec))
+        err[prec] = oracle.rel_frob(C, d["ref"])
+    assert err["bf16x3"] < err["bf16"] / 16
+    assert err["fp8x3"] < err["fp8"] / 8

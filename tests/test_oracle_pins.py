@@ -424,6 +424,49 @@ def test_main_theorem_tail():
     assert exceed / T <= theta + 3 * np.sqrt(theta * (1 - theta) / T)
 
 
+def test_rank_refined_bound():
+    # Section 4, after the main theorem: for rank(A) = r,
+    # ||A||_2 <= ||A||_F <= sqrt(r) ||A||_2, so d = 2/(eps theta) gives
+    # P(err^2 > eps r ||A||_2^2 ||B||_F^2) <= theta, and a sketch r times
+    # wider, z = r (d + e b), gives P(err^2 > eps ||A||_2^2 ||B||_F^2) <= theta.
+    m, n, l, r, b, N, e = 16, 256, 10, 4, 8, 4, 1
+    rng = np.random.default_rng(31)
+    # a fat rank-r A with equal singular values (||A||_F^2 = r ||A||_2^2)
+    Q1, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    A = 3.0 * Q1 @ Q2.T
+    B = rng.standard_normal((n, l))
+    s2 = np.linalg.norm(A, 2) ** 2
+    fa = oracle.frob2(A)
+    assert np.linalg.matrix_rank(A) == r
+    assert s2 <= fa + 1e-9 and fa <= r * s2 * (1 + 1e-12)
+    assert fa == pytest.approx(r * s2, rel=1e-12)
+    d = N * b
+    theta = 0.25
+    eps = 2.0 / (d * theta)
+    AB = A @ B
+    fb = oracle.frob2(B)
+    T = 200
+    slack = 3 * np.sqrt(theta * (1 - theta) / T)
+    base, wide, wide_mean = 0, 0, 0.0
+    for t in range(T):
+        seed = 900 + t
+        keep = synthetic.random_keep(N, e, seed)
+        C = oracle.sketched_matmul(A, B, b, N, e, seed=seed, keep=keep)
+        base += oracle.frob2(C - AB) > eps * r * s2 * fb
+        keep_w = synthetic.random_keep(r * N, r * e, seed)
+        Cw = oracle.sketched_matmul(A, B, b, r * N, r * e, seed=seed, keep=keep_w)
+        ew = oracle.frob2(Cw - AB)
+        wide += ew > eps * s2 * fb
+        wide_mean += ew / T
+    assert base / T <= theta + slack
+    assert wide / T <= theta + slack
+    # the wider sketch's mean error is the closed form at K = r N (so the
+    # threshold above is eps theta / (its mean) away, not vacuous)
+    assert wide_mean == pytest.approx(_second_moment_closed_form(A, B, b, r * N), rel=0.2)
+    assert wide_mean <= eps * theta * s2 * fb
+
+
 def test_graceful_degradation_more_losses_more_error():
     # Dropping more blocks than provisioned still gives an unbiased product
     # with larger error (section 4.1, "graceful degradation").
