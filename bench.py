@@ -42,7 +42,7 @@ METRIC = "sketched AB eff. TFLOP/s (2mnl/t) at fixed rel-Frob err vs exact GEMM,
 # kernel source it was measured on (SHA-256 of that source, see
 # gemm_kept_source_sha); None otherwise.
 GEMM_TRAFFIC = {
-    "source_sha256": "ee137acdc8a2b26164ec93737ebf3ba4c99d9ef096488bbb2e31815ac7a6e674",
+    "source_sha256": "a1329919d5eb325bbe80b00e0559d7b68b5ce8f1ef839801fbee476a4c0ed2cb",
     "workload": (8192, 32768, 8192, 1024, 8, 2),
     "fetch_kib": 1573130.3, "fetch_scale": 2.000,
     "write_kib": 262144.0, "write_scale": 1.000,
@@ -82,6 +82,16 @@ def parse():
                    help="skip the batch of 64 sketched interior-point Hessians")
     p.add_argument("--no-paper", action="store_true",
                    help="skip the paper's constant-matrix workloads (Fig. 5b, Section 5.3)")
+    p.add_argument("--no-ceilings", action="store_true",
+                   help="skip the measured-ceiling kernels")
+    p.add_argument("--no-small", action="store_true",
+                   help="skip the small validation case and its log-normal precision sweep")
+    p.add_argument("--no-stress", action="store_true",
+                   help="skip the independent-factor stress case")
+    p.add_argument("--profile-stage", choices=["step", "sketch_A", "sketch_B", "gemm", "prepare",
+                                               "gemm_bf16", "gemm_fp8"],
+                   help="run only this stage of the headline workload --steps times (after "
+                        "--warmup), print nothing else: for rocprofv3 counter passes")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 1 GiB device copy (3 times): the reference kernel "
                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -94,11 +104,15 @@ def gemm_kept_source_sha(path):
     launch_gemm_kept function; edits elsewhere in the file keep the counters
     valid."""
     import hashlib
+    import re
     text = open(path).read()
     head = text[:text.index("// FP8 (E4M3) operands")]
     a = text.index("hipError_t launch_gemm_kept(")
     launch = text[a:text.index("\n}\n", a) + 3]
-    return hashlib.sha256((head + launch).encode()).hexdigest()
+    # comments and blank lines do not change the kernel
+    code = re.sub(r"//[^\n]*", "", head + launch)
+    code = "\n".join(line.rstrip() for line in code.splitlines() if line.strip())
+    return hashlib.sha256(code.encode()).hexdigest()
 
 
 def gemm_traffic_bytes(m, n, l, b, N, e):
@@ -124,6 +138,109 @@ def event_time_ms(torch, fn, reps, stream):
         stop.record(stream)
     stop.synchronize()
     return start.elapsed_time(stop) / reps
+
+
+def _ceilings_lib():
+    import ctypes
+    path = os.path.join(ROOT, "paper_1811_02653_amd", "libosk_ceilings.so")
+    if not os.path.exists(path):
+        raise RuntimeError("libosk_ceilings.so is not built (python -m paper_1811_02653_amd.build)")
+    L = ctypes.CDLL(path)
+    i64, vp, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+    L.osk_ceiling_copy.argtypes = [vp, vp, i64, ci, vp]
+    L.osk_ceiling_read.argtypes = [vp, i64, vp, ci, vp]
+    L.osk_ceiling_mfma.argtypes = [ci, ci, ci, vp, vp]
+    L.osk_ceiling_lds_gather.argtypes = [ci, ci, ci, vp, vp]
+    for f in (L.osk_ceiling_copy, L.osk_ceiling_read, L.osk_ceiling_mfma,
+              L.osk_ceiling_lds_gather):
+        f.restype = ci
+    return L
+
+
+def bench_ceilings(torch, stream):
+    """Measured ceilings on this GPU (own HIP kernels, csrc/ceilings.hip):
+    HBM copy and read-only streaming, FP32 / BF16 / FP8 MFMA loops, and
+    16-byte LDS gathers at random and conflict-free addresses."""
+    import ctypes
+    L = _ceilings_lib()
+    dev = torch.device("cuda:0")
+    st = ctypes.c_void_p(stream.cuda_stream)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+
+    def run(rc):
+        if rc != 0:
+            raise RuntimeError("ceiling kernel launch failed: hipError_t %d" % rc)
+
+    out = {}
+    n4 = 1 << 26                                    # 1 GiB of 16-byte elements
+    src = torch.ones(4 * n4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    grid = 256 * 64
+    t = event_time_ms(torch, lambda: run(L.osk_ceiling_copy(p(src), p(dst), n4, grid, st)), 5,
+                      stream)
+    out["hbm_copy_gbs"] = 2 * 16.0 * n4 / (t * 1e-3) / 1e9
+    del dst
+    sink = torch.empty(grid * 256, dtype=torch.float32, device=dev)
+    t = event_time_ms(torch, lambda: run(L.osk_ceiling_read(p(src), n4, p(sink), grid, st)), 5,
+                      stream)
+    out["hbm_read_gbs"] = 16.0 * n4 / (t * 1e-3) / 1e9
+    del src, sink
+    grid = 1024
+    sink = torch.empty(grid * 512, dtype=torch.float32, device=dev)
+    for kind, name, k, iters in ((0, "mfma_fp32_tflops", 2, 1500), (1, "mfma_bf16_tflops", 16, 3000),
+                                 (2, "mfma_fp8_tflops", 64, 1500)):
+        t = event_time_ms(torch, lambda: run(L.osk_ceiling_mfma(kind, iters, grid, p(sink), st)),
+                          3, stream)
+        flops = grid * 8.0 * iters * 4 * (2 * 32 * 32 * k)
+        out[name] = flops / (t * 1e-3) / 1e12
+    for rnd, name in ((1, "lds_gather16_random"), (0, "lds_gather16_conflict_free")):
+        iters = 1000
+        t = event_time_ms(torch, lambda: run(L.osk_ceiling_lds_gather(iters, rnd, grid, p(sink),
+                                                                      st)), 3, stream)
+        reads = grid * 512.0 * iters * 8
+        out[name + "_per_s"] = reads / (t * 1e-3)
+    del sink
+    torch.cuda.empty_cache()
+    return out
+
+
+def numpy_blas_sample(oracle, A_s, B_s, b, N, e, seed, keep, C_ref):
+    """The sampled product C[:r, :r] in FP64 with NumPy/SciPy: the oracle's
+    hash tables as a sparse n x z count-sketch matrix, the two sketches as
+    sparse-dense products, the kept blocks' product through BLAS (dgemm).
+    Timed from the FP32 inputs to C; the tables are built before the clock."""
+    import scipy.sparse as sp
+    n = A_s.shape[1]
+    nblk = N + e
+    h, sg = oracle.hash_tables(seed, nblk, n, b)
+    kept = [i for i in range(nblk) if keep[i]]
+    rows = np.tile(np.arange(n), len(kept))
+    cols = np.concatenate([j * b + h[i].astype(np.int64) for j, i in enumerate(kept)])
+    vals = np.concatenate([sg[i].astype(np.float64) for i in kept])
+    S = sp.csc_matrix((vals, (rows, cols)), shape=(n, len(kept) * b))
+    threads = os.environ.get("OMP_NUM_THREADS")
+    t0 = time.perf_counter()
+    A64 = A_s.astype(np.float64)
+    B64 = B_s.astype(np.float64)
+    At = (S.T @ A64.T).T                      # r x K b
+    Bt = S.T @ B64                            # K b x r
+    Cn = (np.ascontiguousarray(At) @ np.ascontiguousarray(Bt)) / len(kept)
+    t = time.perf_counter() - t0
+    r = A_s.shape[0]
+    return {"value": 2.0 * r * n * B_s.shape[1] / t / 1e12, "unit": "TFLOP/s",
+            "seconds": t, "threads": threads,
+            "kind": "NumPy/SciPy FP64: sparse S (oracle's tables), BLAS dgemm over kept blocks",
+            "rel_frob_vs_oracle": oracle.rel_frob(Cn, C_ref)}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def bench_hessian_batch(torch, osk, args, stream, reps):
@@ -316,6 +433,50 @@ def bench_paper_workloads(torch, osk, args, stream, reps):
     return res
 
 
+def profile_stage(torch, osk, args, A, B, C, ws, keep, stream):
+    """One stage of the headline workload, alone, for counter collection."""
+    m, n, l, b, N, e = args.m, args.n, args.l, args.b, args.N, args.e
+    dev = A.device
+    nst = osk.stored_count(N, e, keep, args.kept_only)
+    bp = osk.block_stride(b)
+    prep = osk.sketch_prepare(n, b, N, e, seed=args.seed)
+    At = torch.empty((m, nst * bp), dtype=torch.float32, device=dev)
+    Bt = torch.empty((l, nst * bp), dtype=torch.float32, device=dev)
+    tws = torch.empty(osk.sketch_rows_workspace_bytes(n, l), dtype=torch.uint8, device=dev)
+    osk.sketch_cols(A, b, N, e, seed=args.seed, keep=keep, kept_only=args.kept_only, prep=prep,
+                    out=At, stream=stream)
+    osk.sketch_rows(B, b, N, e, seed=args.seed, keep=keep, kept_only=args.kept_only, prep=prep,
+                    out=Bt, workspace=tws, stream=stream)
+    stored_keep = None if args.kept_only else keep
+    QA = QB = None
+    if args.profile_stage in ("gemm_bf16", "gemm_fp8"):
+        prec = args.profile_stage[5:]
+        QA = osk.sketch_quantize(At, b, nst, precision=prec)
+        QB = osk.sketch_quantize(Bt, b, nst, precision=prec)
+    fns = {
+        "step": lambda: osk.matmul(A, B, b, N, e, seed=args.seed, keep=keep,
+                                   kept_only=args.kept_only, out=C, workspace=ws, stream=stream),
+        "prepare": lambda: osk.sketch_prepare(n, b, N, e, seed=args.seed, stream=stream),
+        "sketch_A": lambda: osk.sketch_cols(A, b, N, e, seed=args.seed, keep=keep,
+                                            kept_only=args.kept_only, prep=prep, out=At,
+                                            stream=stream),
+        "sketch_B": lambda: osk.sketch_rows(B, b, N, e, seed=args.seed, keep=keep,
+                                            kept_only=args.kept_only, prep=prep, out=Bt,
+                                            workspace=tws, stream=stream),
+        "gemm": lambda: osk.gemm_kept(At, Bt, b, keep=stored_keep, out=C, stream=stream),
+        "gemm_bf16": lambda: osk.gemm_kept_prec(QA, QB, b, nst, precision="bf16",
+                                                keep=stored_keep, out=C, stream=stream),
+        "gemm_fp8": lambda: osk.gemm_kept_prec(QA, QB, b, nst, precision="fp8",
+                                               keep=stored_keep, out=C, stream=stream),
+    }
+    fn = fns[args.profile_stage]
+    torch.cuda.synchronize()
+    for i in range(args.warmup + args.steps):
+        fn()
+        torch.cuda.synchronize()
+        log("%s %d done" % (args.profile_stage, i))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -359,6 +520,10 @@ def main():
         osk.matmul(A, B, b, N, e, seed=args.seed, keep=keep, kept_only=args.kept_only, out=C,
                    workspace=ws, stream=stream)
 
+    if args.profile_stage:
+        profile_stage(torch, osk, args, A, B, C, ws, keep, stream)
+        return
+
     # ---- timed region: K whole-path steps
     for _ in range(args.warmup):
         step()
@@ -376,7 +541,12 @@ def main():
     bp = osk.block_stride(b)
     nst = osk.stored_count(N, e, keep, args.kept_only)
     K = int(np.count_nonzero(keep))
+    # the whole path's prepared sketch (natural bucket order); the grouped
+    # order (OS_PREPARE_GROUPED) is measured beside it
     prep = osk.sketch_prepare(n, b, N, e, seed=args.seed)
+    walked, real = osk.list_entries(prep, n, b, N, e, seed=args.seed)
+    grp = osk.sketch_prepare(n, b, N, e, seed=args.seed, grouped=True)
+    walked_grp, _ = osk.list_entries(grp, n, b, N, e, seed=args.seed)
     At = torch.empty((m, nst * bp), dtype=torch.float32, device=dev)
     Bt = torch.empty((l, nst * bp), dtype=torch.float32, device=dev)
     stored_keep = None if args.kept_only else keep      # mask over the stored blocks
@@ -384,6 +554,14 @@ def main():
     reps = max(3, args.steps)
     t_prep = event_time_ms(torch, lambda: osk.sketch_prepare(n, b, N, e, seed=args.seed,
                                                              stream=stream), reps, stream)
+    t_prep_grp = event_time_ms(torch, lambda: osk.sketch_prepare(n, b, N, e, seed=args.seed,
+                                                                 stream=stream, grouped=True),
+                               reps, stream)
+    t_sa_grp = event_time_ms(torch, lambda: osk.sketch_cols(A, b, N, e, seed=args.seed,
+                                                            keep=keep, kept_only=args.kept_only,
+                                                            prep=grp, out=At, stream=stream),
+                             reps, stream)
+    del grp
     t_sa = event_time_ms(torch, lambda: osk.sketch_cols(A, b, N, e, seed=args.seed, keep=keep,
                                                         kept_only=args.kept_only, prep=prep,
                                                         out=At, stream=stream),
@@ -396,6 +574,7 @@ def main():
                                                         stream=stream), reps, stream)
     gemm_flops = 2.0 * m * l * K * bp
     gemm_tflops = gemm_flops / (t_gemm * 1e-3) / 1e12
+    sketch_entries_a = (m + 3) // 4 * float(n) * nst     # real list entries (4 lines each)
     sketch_bytes_a = 4.0 * (m * n + m * nst * bp)
     sketch_bytes_b = 4.0 * (n * l + l * nst * bp)
     log("stages: prepare %.3f, sketch A %.3f, sketch B %.3f, gemm %.3f ms" %
@@ -438,7 +617,96 @@ def main():
                    for r in sweep), t_kept_only))
     del AB
     torch.cuda.empty_cache()
+
+    # ---- stress case: the same shapes with independent factors (A's row
+    # space and B's column space unrelated), where the sketch's error is
+    # about sqrt(n / (K b)) = 200 %: the product is as fast, the answer is
+    # not useful (Lemma 3's scaling)
+    stress = None
+    if not args.no_stress:
+        A3_h, B3_h = synthetic.lowrank_pair(m, n, l, args.seed, rank=64, noise=0.1,
+                                            shared_factor=False)
+        A3 = torch.from_numpy(A3_h).to(dev)
+        B3 = torch.from_numpy(B3_h).to(dev)
+        del A3_h, B3_h
+        t_st = event_time_ms(torch, lambda: osk.matmul(A3, B3, b, N, e, seed=args.seed, keep=keep,
+                                                       out=C, workspace=ws, stream=stream),
+                             reps, stream)
+        torch.cuda.synchronize()
+        AB3 = torch.matmul(A3.double(), B3.double())
+        Cd = C.double()
+        na2, nb2 = torch.sum(A3.double() ** 2).item(), torch.sum(B3.double() ** 2).item()
+        nab2 = torch.sum(AB3 ** 2).item()
+        # the second moment's prediction (Lemma 1 summed over entries, K blocks)
+        cross = torch.sum(torch.sum(A3.double() ** 2, dim=0) *
+                          torch.sum(B3.double() ** 2, dim=1)).item()
+        stress = {"workload": "as the headline, but B = P W / 8 + 0.1 G_B with P independent of A's "
+                              "factor Q",
+                  "ms_per_step": t_st, "eff_tflops": 2.0 * m * n * l / (t_st * 1e-3) / 1e12,
+                  "rel_frob_vs_exact_fp64": (torch.sum((Cd - AB3) ** 2).item() / nab2) ** 0.5,
+                  "rel_frob_predicted_rms": _predicted_rel_frob(na2, nb2, nab2, cross, K, b)}
+        log("stress (independent factors): %.3f ms, error %.3f (predicted %.3f)" %
+            (t_st, stress["rel_frob_vs_exact_fp64"], stress["rel_frob_predicted_rms"]))
+        del A3, B3, AB3, Cd
+        torch.cuda.empty_cache()
     step()
+
+    # ---- the small validation case (A 256 x 4096, B 4096 x 256, i.i.d.
+    # N(0,1), b = 256, N = 4, e = 1, one random block dropped): latency of
+    # the whole path; then the same shapes with log-normal (sigma = 2) row
+    # norms of A and column norms of B in every operand precision, the
+    # precision workload (errors against the oracle on the same sketch are
+    # taken in the CPU leg)
+    small = None
+    small_host = None
+    if not args.no_small:
+        sm, sn, sl, sb, sN, se = 256, 4096, 256, 256, 4, 1
+        sseed = 3
+        A1_h, B1_h = synthetic.gaussian_pair(sm, sn, sl, sseed)
+        k1 = synthetic.random_keep(sN, se, sseed)
+        A1, B1 = torch.from_numpy(A1_h).to(dev), torch.from_numpy(B1_h).to(dev)
+        C1 = torch.empty((sm, sl), dtype=torch.float32, device=dev)
+        ws1 = torch.empty(max(osk.workspace_bytes(sm, sn, sl, sb, sN, se, precision=pr)
+                              for pr in osk.PRECISIONS), dtype=torch.uint8, device=dev)
+        t1 = event_time_ms(torch, lambda: osk.matmul(A1, B1, sb, sN, se, seed=sseed, keep=k1,
+                                                     out=C1, workspace=ws1, stream=stream),
+                           100, stream)
+        torch.cuda.synchronize()
+        AB1 = torch.matmul(A1.double(), B1.double())
+        e1 = (torch.linalg.norm(C1.double() - AB1) / torch.linalg.norm(AB1)).item()
+        small_host = {"gaussian": (A1_h, B1_h, k1, C1.cpu().numpy())}
+        A2_h, B2_h = synthetic.lognormal_scaled_pair(sm, sn, sl, sseed, sigma=2.0)
+        A2, B2 = torch.from_numpy(A2_h).to(dev), torch.from_numpy(B2_h).to(dev)
+        AB2 = torch.matmul(A2.double(), B2.double())
+        logn = {}
+        outs = {}
+        for prec in ("fp32", "bf16", "bf16x3", "fp8", "fp8x3"):
+            tq = event_time_ms(torch, lambda: osk.matmul(A2, B2, sb, sN, se, seed=sseed, keep=k1,
+                                                         out=C1, workspace=ws1, stream=stream,
+                                                         precision=prec), 50, stream)
+            torch.cuda.synchronize()
+            logn[prec] = {"us_per_step": 1e3 * tq,
+                          "rel_frob_vs_exact_fp64":
+                              (torch.linalg.norm(C1.double() - AB2) / torch.linalg.norm(AB2)).item()}
+            outs[prec] = C1.cpu().numpy()
+        small_host["lognormal"] = (A2_h, B2_h, k1, outs)
+        small = {"workload": "A %dx%d . B %dx%d, i.i.d. N(0,1), b=%d, N=%d, e=%d, one random block "
+                             "dropped" % (sm, sn, sn, sl, sb, sN, se),
+                 "us_per_step": 1e3 * t1, "eff_tflops": 2.0 * sm * sn * sl / (t1 * 1e-3) / 1e12,
+                 "rel_frob_vs_exact_fp64": e1,
+                 "precision_lognormal": {
+                     "workload": "the same shapes, A's row norms and B's column norms log-normal "
+                                 "(sigma = 2)", "by_precision": logn}}
+        log("small case: %.1f us per step, error %.3f; log-normal: %s" %
+            (1e3 * t1, e1, {k: "%.3e" % v["rel_frob_vs_exact_fp64"] for k, v in logn.items()}))
+        del A1, B1, C1, ws1, AB1, A2, B2, AB2
+        torch.cuda.empty_cache()
+
+    # ---- measured ceilings of the units the kernels are bound by
+    ceil = None
+    if not args.no_ceilings:
+        ceil = bench_ceilings(torch, stream)
+        log("ceilings: %s" % {k: round(v, 1) if v < 1e6 else "%.3e" % v for k, v in ceil.items()})
 
     # ---- exact FP32 GEMM on the same GPU: the vendor library, and the block
     # product kernel itself run on A and B^T unsketched (the inner dimension
@@ -616,6 +884,30 @@ def main():
         sample_err = oracle.rel_frob(C[:r, :r].cpu().numpy(), C_ref)
         log("cpu oracle sample: %.1f s, rel-Frob GPU vs oracle on the sample %.2e" %
             (t_cpu, sample_err))
+        cpu["model"] = cpu_model()
+        # a stronger CPU figure: the same sampled product with NumPy/SciPy in
+        # FP64 (sparse count-sketch matrix S of the oracle's tables, then the
+        # kept blocks' product through BLAS)
+        cpu["blas"] = numpy_blas_sample(oracle, A_s, B_s, b, N, e, args.seed, keep, C_ref)
+        log("cpu numpy/BLAS sample: %.1f s (%.3f TFLOP/s eff), agrees with the oracle to %.1e" %
+            (cpu["blas"]["seconds"], cpu["blas"]["value"], cpu["blas"]["rel_frob_vs_oracle"]))
+        del C_ref
+        if small_host is not None:
+            sb, sN, se, sseed = 256, 4, 1, 3
+            A1_h, B1_h, k1, C1_h = small_host["gaussian"]
+            t0 = time.perf_counter()
+            ref1 = oracle.sketched_matmul(A1_h, B1_h, sb, sN, se, seed=sseed, keep=k1)
+            small["oracle_ms"] = 1e3 * (time.perf_counter() - t0)
+            small["rel_frob_vs_oracle"] = oracle.rel_frob(C1_h, ref1)
+            A2_h, B2_h, k2, outs = small_host["lognormal"]
+            ref2 = oracle.sketched_matmul(A2_h, B2_h, sb, sN, se, seed=sseed, keep=k2)
+            for prec, Cq in outs.items():
+                small["precision_lognormal"]["by_precision"][prec]["rel_frob_vs_oracle"] = \
+                    oracle.rel_frob(Cq, ref2)
+            log("small case vs oracle: %.2e; log-normal by precision vs oracle: %s" %
+                (small["rel_frob_vs_oracle"],
+                 {k: "%.2e" % v["rel_frob_vs_oracle"]
+                  for k, v in small["precision_lognormal"]["by_precision"].items()}))
 
     out = {
         "metric": METRIC,
@@ -654,6 +946,11 @@ def main():
         "stages_ms": {"prepare": t_prep, "sketch_A": t_sa, "sketch_B": t_sb, "gemm": t_gemm},
         "sketch_roofline": {
             "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "list_entries_walked_per_real": walked / real,
+            "grouped_order": {"list_entries_walked_per_real": walked_grp / real,
+                              "prepare_ms": t_prep_grp, "sketch_A_ms": t_sa_grp},
+            "stage_frac": (sketch_bytes_a + sketch_bytes_b) / ((t_sa + t_sb) * 1e-3) / 1e9
+                          / HBM_PEAK_GBS,
             "sketch_A_achieved": sketch_bytes_a / (t_sa * 1e-3) / 1e9,
             "sketch_B_achieved": sketch_bytes_b / (t_sb * 1e-3) / 1e9,
             "sketch_A_frac": sketch_bytes_a / (t_sa * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -675,6 +972,25 @@ def main():
                            "speedup_of_sketched": t_exact_own / ms_per_step}},
         "speedup_vs_error": {"sweep": sweep, "kept_only_ms_per_step": t_kept_only},
         "paper_workloads": paper,
+        "small_case": small,
+        "stress_independent_factors": stress,
+        "ceilings": ceil,
+        "vs_ceilings": None if ceil is None else {
+            "gemm_fp32_frac_of_measured_mfma": gemm_tflops / ceil["mfma_fp32_tflops"],
+            "sketch_A_frac_of_measured_copy": sketch_bytes_a / (t_sa * 1e-3) / 1e9
+                                              / ceil["hbm_copy_gbs"],
+            "sketch_B_frac_of_measured_copy": sketch_bytes_b / (t_sb * 1e-3) / 1e9
+                                              / ceil["hbm_copy_gbs"],
+            # the sketch's second roofline: one 16-byte LDS gather per list
+            # entry (a window position of one stored block, 4 lines)
+            "sketch_A_lds_entries_per_s": sketch_entries_a / (t_sa * 1e-3),
+            "sketch_A_frac_of_random_lds_gather": sketch_entries_a / (t_sa * 1e-3)
+                                                  / ceil["lds_gather16_random_per_s"],
+            "bf16_gemm_frac_of_measured_mfma": None if precision is None else
+            precision["bf16"]["gemm_tflops"] / ceil["mfma_bf16_tflops"],
+            "fp8_gemm_frac_of_measured_mfma": None if precision is None else
+            precision["fp8"]["gemm_tflops"] / ceil["mfma_fp8_tflops"],
+        },
     }
     print(json.dumps(out), flush=True)
 

@@ -149,12 +149,48 @@ size_t os_sketch_prepare_bytes(const os_sketch* sk, int64_t n);
 os_status os_sketch_prepare(const os_sketch* sk, int64_t n, void* prep, size_t prep_bytes,
                             void* stream);
 
+/* Flags of os_sketch_prepare_ex. */
+#define OS_PREPARE_GROUPED 1   /* bucket order chosen for the sketch kernel */
+
+/* os_sketch_prepare with flags.  OS_PREPARE_GROUPED: within every block the
+ * buckets are laid out in an order of the library's choosing, not 0..b-1:
+ * buckets whose index lists have similar lengths share the sketch kernel's
+ * groups of 64, so the kernel walks less padding (the lanes of a group step
+ * through their lists together).  A sketch taken with such a prepared
+ * sketch holds bucket order[i*bp + p] of block i at column j*bp + p (see
+ * os_sketch_bucket_order); A's and B's sketches use the same order, so the
+ * product (1/K) sum_i (A S_i)(S_i^T B) is the same up to FP32 summation
+ * order (Eq. (sketch_matrix): any ordering of the columns of S_i).  The
+ * ordering itself costs a sort per block in the prepare step; the
+ * whole-path calls (os_matmul*, os_gram_*) use the natural order.  Other
+ * flags: OS_EINVAL. */
+os_status os_sketch_prepare_ex(const os_sketch* sk, int64_t n, int flags, void* prep,
+                               size_t prep_bytes, void* stream);
+
+/* The bucket at every column of a prepared sketch's blocks:
+ * order[i*bp + p] = the bucket held at column p of block i (p < b), and p
+ * for the empty columns b <= p < bp.  order: DEVICE int32 [(N+e) * bp].
+ * The identity for a prepared sketch made without OS_PREPARE_GROUPED. */
+os_status os_sketch_bucket_order(const os_sketch* sk, int64_t n, const void* prep,
+                                 size_t prep_bytes, int32_t* order, void* stream);
+
+/* Diagnostic (synchronous: waits for `stream`): the list entries the sketch
+ * kernel walks per group of 4 lines over all N+e blocks (walked, padding
+ * included) and the real ones (real = (N+e) * n), from a prepared sketch.
+ * walked / real is the kernel's padding factor. */
+os_status os_sketch_list_entries(const os_sketch* sk, int64_t n, const void* prep,
+                                 size_t prep_bytes, int64_t* walked, int64_t* real,
+                                 void* stream);
+
 /* Step "sketch A's columns" (Algorithm "Over sketching A in parallel" with
  * Algorithm "Calculating Count-sketch" per block) for a row-major X
  * (rows x n, ld ldx), line-major output:
  *   out[r][j*bp + c] = sum_{k : h_{s_j}(k) = c} sigma_{s_j}(k) * X[r][k]
  * for every stored block j (sketch block s_j), i.e. out = X S_{s_j} side by
- * side over j.  Each bucket is summed in FP32 in ascending k.
+ * side over j.  Each bucket is summed in FP32 in ascending k.  (With a
+ * prepared sketch made with OS_PREPARE_GROUPED, column j*bp + p holds
+ * bucket order[s_j*bp + p] in place of bucket p; see
+ * os_sketch_bucket_order.)
  * prep: a prepared sketch for the same sk and n.  keep_host: HOST uint8
  * [N+e] (nonzero = kept) or NULL (= blocks [0, N)); it selects the stored
  * blocks when kept_only != 0.  out: DEVICE rows x (nst*bp), ld ldo >=

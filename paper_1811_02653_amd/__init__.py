@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 __all__ = [
-    "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "sketch_cols",
+    "OversketchError", "lib", "block_stride", "hash_fill", "sketch_prepare", "bucket_order",
+    "list_entries",
+    "sketch_cols",
     "sketch_rows", "sketch_rows_workspace_bytes", "gemm_kept", "matmul", "workspace_bytes",
     "stored_count", "PRECISIONS", "block_stride_prec", "quantized_row", "sketch_quantize",
     "gemm_kept_prec", "gemm_kept_cmask", "matmul_cmask", "matmul_ex", "GramBatch",
@@ -91,6 +93,12 @@ def lib():
     L.os_sketch_prepare_bytes.argtypes = [sk, i64]
     L.os_sketch_prepare.restype = ctypes.c_int
     L.os_sketch_prepare.argtypes = [sk, i64, vp, sz, vp]
+    L.os_sketch_prepare_ex.restype = ctypes.c_int
+    L.os_sketch_prepare_ex.argtypes = [sk, i64, ctypes.c_int, vp, sz, vp]
+    L.os_sketch_list_entries.restype = ctypes.c_int
+    L.os_sketch_list_entries.argtypes = [sk, i64, vp, sz, vp, vp, vp]
+    L.os_sketch_bucket_order.restype = ctypes.c_int
+    L.os_sketch_bucket_order.argtypes = [sk, i64, vp, sz, vp, vp]
     L.os_sketch_cols.restype = ctypes.c_int
     L.os_sketch_cols.argtypes = [sk, vp, sz, vp, i64, i64, i64, vp, ctypes.c_int, vp, i64, vp]
     L.os_sketch_rows.restype = ctypes.c_int
@@ -280,17 +288,46 @@ def hash_fill(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None
     return h_out, s_out
 
 
-def sketch_prepare(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None):
-    """Prepared sketch (opaque uint8 device buffer) for an n-long sketched dimension."""
+OS_PREPARE_GROUPED = 1
+
+
+def sketch_prepare(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None,
+                   grouped=False):
+    """Prepared sketch (opaque uint8 device buffer) for an n-long sketched
+    dimension.  grouped=True: the library's bucket order within each block
+    (see bucket_order), as the whole-path calls use."""
     torch = _torch()
     s = _sketch(b, N, e, seed, h, sigma, n)
     nbytes = int(lib().os_sketch_prepare_bytes(ctypes.byref(s), n))
     if nbytes == 0:
         raise OversketchError("invalid sketch parameters")
     prep = _empty(nbytes, torch.uint8, device, stream)
-    _check(lib().os_sketch_prepare(ctypes.byref(s), n, _ptr(prep), nbytes, _stream(stream)),
-           "os_sketch_prepare")
+    flags = OS_PREPARE_GROUPED if grouped else 0
+    _check(lib().os_sketch_prepare_ex(ctypes.byref(s), n, flags, _ptr(prep), nbytes,
+                                      _stream(stream)), "os_sketch_prepare_ex")
     return prep
+
+
+def list_entries(prep, n, b, N, e, seed=0, h=None, sigma=None, stream=None):
+    """(walked, real): list entries the sketch kernel walks per 4 lines,
+    padding included, and the real ones (synchronous)."""
+    s = _sketch(b, N, e, seed, h, sigma, n)
+    w, r = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().os_sketch_list_entries(ctypes.byref(s), n, _ptr(prep), prep.numel(),
+                                        ctypes.byref(w), ctypes.byref(r), _stream(stream)),
+           "os_sketch_list_entries")
+    return int(w.value), int(r.value)
+
+
+def bucket_order(prep, n, b, N, e, seed=0, h=None, sigma=None, stream=None):
+    """int32 [N+e, block_stride(b)]: the bucket held at each column of each
+    block of a sketch taken with `prep` (the identity unless grouped)."""
+    torch = _torch()
+    s = _sketch(b, N, e, seed, h, sigma, n)
+    order = _empty((N + e, block_stride(b)), torch.int32, prep.device, stream)
+    _check(lib().os_sketch_bucket_order(ctypes.byref(s), n, _ptr(prep), prep.numel(),
+                                        _ptr(order), _stream(stream)), "os_sketch_bucket_order")
+    return order
 
 
 def _line_major_out(out, lines, width, device, stream=None):

@@ -4,6 +4,7 @@
 // 1/K), workspace carving and the launch sequence.  Every check happens
 // before the first launch of a call.
 #include <algorithm>
+#include <vector>
 
 #include "api_common.h"
 
@@ -83,6 +84,58 @@ os_status os_sketch_prepare(const os_sketch* sk, int64_t n, void* prep, size_t p
     if ((st = check_len(n)) != OS_OK) return st;
     if ((st = check_prep(sk, n, prep, prep_bytes)) != OS_OK) return st;
     return prepare(sk, n, prep, (hipStream_t)stream);
+}
+
+os_status os_sketch_prepare_ex(const os_sketch* sk, int64_t n, int flags, void* prep,
+                               size_t prep_bytes, void* stream) {
+    os_status st = check_sketch(sk);
+    if (st != OS_OK) return st;
+    if ((st = check_len(n)) != OS_OK) return st;
+    if (flags & ~OS_PREPARE_GROUPED) return OS_EINVAL;
+    if ((st = check_prep(sk, n, prep, prep_bytes)) != OS_OK) return st;
+    return prepare(sk, n, prep, (hipStream_t)stream, (flags & OS_PREPARE_GROUPED) != 0);
+}
+
+os_status os_sketch_bucket_order(const os_sketch* sk, int64_t n, const void* prep,
+                                 size_t prep_bytes, int32_t* order, void* stream) {
+    os_status st = check_sketch(sk);
+    if (st != OS_OK) return st;
+    if ((st = check_len(n)) != OS_OK) return st;
+    if ((st = check_prep(sk, n, prep, prep_bytes)) != OS_OK) return st;
+    if (!order) return OS_ENULL;
+    if (!aligned(order, 4)) return OS_EALIGN;
+    return hip_status(osk::launch_bucket_order(prep_inv(prep, sk, n), nblocks(sk), sk->b,
+                                               os_block_stride(sk->b), order,
+                                               (hipStream_t)stream));
+}
+
+os_status os_sketch_list_entries(const os_sketch* sk, int64_t n, const void* prep,
+                                 size_t prep_bytes, int64_t* walked, int64_t* real, void* stream) {
+    os_status st = check_sketch(sk);
+    if (st != OS_OK) return st;
+    if ((st = check_len(n)) != OS_OK) return st;
+    if ((st = check_prep(sk, n, prep, prep_bytes)) != OS_OK) return st;
+    if (!walked || !real) return OS_ENULL;
+    const int32_t bp = os_block_stride(sk->b);
+    const int32_t qn = (bp + 63) / 64;
+    const int64_t nwin = (n + osk::kSketchWindow - 1) / osk::kSketchWindow;
+    const size_t count = (size_t)nblocks(sk) * (size_t)nwin * (size_t)qn;
+    hipStream_t s = (hipStream_t)stream;
+    // the list headers come first in the lists area (see sketch.hip)
+    const void* lists = prep_lists(prep, sk, n);
+    try {
+        std::vector<uint32_t> hdr(count);
+        hipError_t e = hipMemcpyAsync(hdr.data(), lists, count * 4u, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e);
+        int64_t chunks = 0;
+        for (size_t q = 0; q < count; ++q) chunks += hdr[q] >> 16;
+        *walked = chunks * 8 * 64;
+        *real = (int64_t)nblocks(sk) * n;
+        return OS_OK;
+    } catch (...) {
+        return hip_status(hipErrorOutOfMemory);
+    }
 }
 
 os_status os_sketch_cols(const os_sketch* sk, const void* prep, size_t prep_bytes, const float* X,

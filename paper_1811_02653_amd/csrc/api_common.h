@@ -82,26 +82,44 @@ inline size_t table_bytes(const os_sketch* sk, int64_t n) {
     return (size_t)nblocks(sk) * (size_t)table_stride(n) * 4u;
 }
 
+// Prepared buffer: the packed table, the bucket lists, then the position
+// map inv [N+e][bp] (bucket -> column of the sketch).
 inline size_t prepare_bytes(const os_sketch* sk, int64_t n) {
-    return align256(table_bytes(sk, n)) +
-           osk::list_bytes(nblocks(sk), n, os_block_stride(sk->b));
+    const int32_t bp = os_block_stride(sk->b);
+    return align256(table_bytes(sk, n)) + align256(osk::list_bytes(nblocks(sk), n, bp)) +
+           align256((size_t)nblocks(sk) * (size_t)bp * 4u);
 }
 
 inline const void* prep_lists(const void* prep, const os_sketch* sk, int64_t n) {
     return static_cast<const char*>(prep) + align256(table_bytes(sk, n));
 }
 
-// Table + bucket lists into the prepared buffer.
-inline os_status prepare(const os_sketch* sk, int64_t n, void* prep, hipStream_t s) {
+inline const int32_t* prep_inv(const void* prep, const os_sketch* sk, int64_t n) {
+    return reinterpret_cast<const int32_t*>(
+        static_cast<const char*>(prep) + align256(table_bytes(sk, n)) +
+        align256(osk::list_bytes(nblocks(sk), n, os_block_stride(sk->b))));
+}
+
+// Table + position map + bucket lists into the prepared buffer.  grouped:
+// buckets of similar list lengths share the sketch kernel's 64-bucket
+// groups (the sketches' columns then hold the buckets in that order within
+// each block; products are unchanged); else the natural order.
+inline os_status prepare(const os_sketch* sk, int64_t n, void* prep, hipStream_t s,
+                         bool grouped = false) {
     const int64_t nt = table_stride(n);
+    const int32_t bp = os_block_stride(sk->b);
     uint32_t* table = static_cast<uint32_t*>(prep);
     hipError_t e = sk->h ? osk::launch_table_explicit(sk->h, sk->sigma, nblocks(sk), n, nt, sk->b,
                                                       table, s)
                          : osk::launch_table_hash(sk->seed, nblocks(sk), n, nt, sk->b, table, s);
     if (e != hipSuccess) return hip_status(e);
+    int32_t* inv = const_cast<int32_t*>(prep_inv(prep, sk, n));
+    e = grouped ? osk::launch_group_buckets(table, n, nt, nblocks(sk), sk->b, bp, inv, s)
+                : osk::launch_identity_inv(nblocks(sk), bp, inv, s);
+    if (e != hipSuccess) return hip_status(e);
     void* lists = static_cast<char*>(prep) + align256(table_bytes(sk, n));
-    return hip_status(osk::launch_build_lists(table, n, nt, nblocks(sk), os_block_stride(sk->b),
-                                              lists, s));
+    return hip_status(osk::launch_build_lists(table, n, nt, nblocks(sk), bp, lists, s,
+                                              grouped && sk->b > 64 ? inv : nullptr));
 }
 
 inline os_status check_prep(const os_sketch* sk, int64_t n, const void* prep, size_t prep_bytes) {

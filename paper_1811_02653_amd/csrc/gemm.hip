@@ -19,9 +19,10 @@
 //     values).  Both operands are K-contiguous; a step's tiles go straight
 //     from global memory into LDS (buffer_load_dwordx4 with the lds flag: no
 //     VGPR staging, no LDS stores), unpadded, with the 16-byte chunk c of
-//     row r at chunk c ^ (r & 7) so fragment reads of 8 consecutive rows hit
-//     8 different bank groups.  Two step buffers per operand: step t + 1 is
-//     loaded into one while step t is read from the other.
+//     row r at chunk c ^ key(r), key(r) = (r & 7) ^ ((r >> 3) & 1), so the
+//     16 rows a fragment read serves at once hit 16 different bank groups.
+//     Two step buffers per operand: step t + 1 is loaded into one while
+//     step t is read from the other.
 //   - Lane half h of every MFMA takes the K values at byte offset 64h + 16q
 //     of the step's row (q = quad), so a lane's fragment is one 16-byte LDS
 //     read; A and B use the same K order, so the dot products are unchanged
@@ -39,8 +40,6 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int BM = 256;
 constexpr int BN = 256;
 constexpr int kStepBytes = 128; // K step: 128 bytes of each tile row (32 FP32 / 64 BF16 values)
-constexpr int LDT = 36;         // LDS row stride (4-byte words) of a tile row
-constexpr int kThreads = 256;
 // tiles are rasterised in groups of kGroupM tile rows (an XCD's 32
 // concurrent tiles then share 8 row blocks of A; 8 measured 0.5 % faster
 // than 4 on the full-size product)
@@ -51,54 +50,10 @@ __device__ __forceinline__ int64_t xcd_task(int64_t L, int64_t tasks) {
     return (L % 8) * (tasks / 8) + L / 8;
 }
 
-// Global -> register tile loads: thread t covers tile rows t/8 + 32u
-// (u = 0..7) and the 4 K values at 4 (t % 8).  Raw buffer loads: `rsrc`
-// (wave-uniform) describes the tile's first row, `kbyte` (wave-uniform, in
-// SGPRs) is the byte offset of the step's first K column and off[u] (one
-// 32-bit VGPR each) the byte offset of the thread's row u and K quad.  Every
-// offset stays below 2^32 (a row is at most kMaxSketchLdBytes long) and
-// inside the matrix: rows past its end were clamped to its last row when the
-// offsets were made.  Those rows only feed rows or columns of C beyond the
-// matrix, which are never stored, so every load is unconditional and
-// unmasked (a branch or a select on a load would make the wave wait for it).
-__device__ __forceinline__ void load_tile(float4 (&r)[8], __amdgpu_buffer_rsrc_t rsrc,
-                                          uint32_t kbyte, const uint32_t (&off)[8]) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-        r[u] = __builtin_bit_cast(float4,
-                                  __builtin_amdgcn_raw_buffer_load_b128(rsrc, off[u], kbyte, 0));
-}
-
 // Buffer resource of a matrix starting at p: no stride, no range limit
 // (num_records = 2^32 - 1), the gfx9 data format word.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void* p) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
-}
-
-__device__ __forceinline__ void tile_offsets(uint32_t (&off)[8], int64_t ld_bytes, int rel,
-                                             int last, int kq) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-        off[u] = (uint32_t)((int64_t)min(rel + 32 * u, last) * ld_bytes + 16 * kq);
-}
-
-__device__ __forceinline__ void store_tile(float* __restrict__ s, const float4 (&r)[8], int tid) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-        *reinterpret_cast<float4*>(s + ((tid >> 3) + 32 * u) * LDT + 4 * (tid & 7)) = r[u];
-}
-
-// Fragments of quad q (kk = 4q .. 4q+3) of a step: a[i] = the 4 K values
-// 16h + 4q .. +3 of tile row arow + 32 i (h = lane half), likewise b.
-__device__ __forceinline__ void read_frag(float4 (&a)[4], float4 (&b)[4],
-                                          const float* __restrict__ As,
-                                          const float* __restrict__ Bs, int q, int arow, int brow,
-                                          int kh) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        a[i] = *reinterpret_cast<const float4*>(As + (arow + 32 * i) * LDT + kh + 4 * q);
-        b[i] = *reinterpret_cast<const float4*>(Bs + (brow + 32 * i) * LDT + kh + 4 * q);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -106,14 +61,22 @@ __device__ __forceinline__ void read_frag(float4 (&a)[4], float4 (&b)[4],
 // with the lds flag: no VGPR staging and no LDS store instructions, which
 // each cost the MFMA pipe about one slot when issued in the K loop).  A tile
 // of BT = 32 kU rows x 128 bytes (one K step) is stored unpadded: the
-// 16-byte chunk c of row r sits at chunk c ^ (r & 7) of LDS row r, so the
-// fragment reads (8 consecutive rows, one chunk each) hit 8 different bank
-// groups.  Load u of wave w fills LDS rows 8(kU w + u) .. +7 (1 KiB,
-// 16 bytes per lane): lane l takes row 8(kU w + u) + l/8 and physical chunk
-// l % 8, i.e. logical chunk (l % 8) ^ (l / 8).  Rows past the matrix end
-// are clamped to its last row (they only feed outputs that are not stored).
+// 16-byte chunk c of row r sits at chunk c ^ key(r), key(r) = (r & 7) ^
+// ((r >> 3) & 1).  A 16-byte fragment read is served 16 lanes (16
+// consecutive rows, 256 bytes) at a time over the 64 four-byte banks: rows
+// r and r + 8 share their (r & 7) and the parity of their 128-byte row
+// offset, and the (r >> 3) term sends them to different chunks, so the 16
+// reads of a pass hit 16 different bank groups (with key (r & 7) alone, they
+// met in pairs: measured as half the LDS cycles spent in bank conflicts).
+// Any 8 consecutive rows also take 8 different chunks.  Load u of wave w
+// fills LDS rows 8(kU w + u) .. +7 (1 KiB, 16 bytes per lane): lane l takes
+// row r = 8(kU w + u) + l/8 and physical chunk l % 8, i.e. logical chunk
+// (l % 8) ^ key(r).  Rows past the matrix end are clamped to its last row
+// (they only feed outputs that are not stored).
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ int chunk_key(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
 template <int kU>
 __device__ __forceinline__ void direct_offsets(uint32_t (&vo)[kU], int64_t ld_bytes, int last,
@@ -121,7 +84,7 @@ __device__ __forceinline__ void direct_offsets(uint32_t (&vo)[kU], int64_t ld_by
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         const int r = 8 * (kU * wave + u) + (lane >> 3);
-        const int c = (lane & 7) ^ (lane >> 3);
+        const int c = (lane & 7) ^ chunk_key(r);
         vo[u] = (uint32_t)((int64_t)min(r, last) * ld_bytes + 16 * c);
     }
 }
@@ -141,10 +104,10 @@ __device__ __forceinline__ void direct_issue(__amdgpu_buffer_rsrc_t rsrc, float*
 }
 
 // Float offset in a direct tile of the fragment of quad q for tile row
-// rbase + 32 i (rbase = a wave's first row + lane % 32): lane half h reads
-// logical chunk 4h + q.
+// rbase + 32 i (rbase = a wave's first row + lane % 32; 32 i changes no bit
+// of the key): lane half h reads logical chunk 4h + q.
 __device__ __forceinline__ int direct_frag_off(int rbase, int q, int lane) {
-    return rbase * 32 + 4 * ((4 * (lane >> 5) + q) ^ (lane & 7));
+    return rbase * 32 + 4 * ((4 * (lane >> 5) + q) ^ chunk_key(rbase));
 }
 
 // a = zero when !live (a uniform flag): a dead K step adds nothing.
@@ -406,48 +369,50 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
     }
 }
 
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
 // ---------------------------------------------------------------------------
 // FP8 (E4M3) operands with one E8M0 scale per 64 K values of a row, on the
 // gfx950 scaled MFMA v_mfma_scale_f32_32x32x64_f8f6f4 (FP32 accumulation; the
-// hardware multiplies the products by the row scales of A and B).  Same
-// tiles, LDS layout and pipeline as the kernel above; a K step is 128 values
-// (one 128-byte row segment, two scale blocks).  Substep q (two per step) is
-// one MFMA per 32x32 block over scale block q: lane half h holds bytes
-// 32h .. 32h + 31 of the block, and both halves pass the block's scale, so
-// the result does not depend on how the MFMA pairs scale bytes with K
-// values.  The B fragments of a substep stay in registers; the A fragments
-// are read one row block ahead.  A row of an operand holds its codes, then
-// one scale byte per 64 codes (`scales` bytes after the row's start).
+// hardware multiplies the products by the row scales of A and B).  A row of
+// an operand holds its codes, then one scale byte per 64 codes (`scales`
+// bytes after the row's start).  The pipeline is gemm_kept_kernel's: eight waves per
+// 256 x 256 tile (two per SIMD, 128 x 64 each), K steps of 128 codes (128
+// bytes of every tile row) loaded straight into LDS, two step buffers.  A
+// step is two substeps, one per 64-value scale block: substep s is one
+// scaled MFMA per 32x32 block, lane half h holding the 32 codes at byte
+// 64 s + 32 h of the step's row (two 16-byte LDS reads: logical chunks
+// 4 s + 2 h and 4 s + 2 h + 1), both halves passing the block's scale.
+// Scale bytes: the two of a step sit in one aligned 4-byte word of the row's
+// scale area (word at scales + (c / 64 & ~3) for code column c, the step's
+// pair in half hsel = (c / 128) & 1); every step each wave loads 64 such
+// words straight into LDS, A's rows by waves 0-3 and B's by waves 4-7, laid
+// out so that a fragment lane's four A rows (or two B rows) are consecutive
+// words: one 16-byte (8-byte) LDS read per lane per step.
 // ---------------------------------------------------------------------------
-typedef int i32x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ i32x8 frag32(const float* __restrict__ T, int row, int byte) {
-    const float4 lo = *reinterpret_cast<const float4*>(
-        reinterpret_cast<const char*>(T) + row * (LDT * 4) + byte);
-    const float4 hi = *reinterpret_cast<const float4*>(
-        reinterpret_cast<const char*>(T) + row * (LDT * 4) + byte + 16);
-    i32x8 v;
-    v[0] = __float_as_int(lo.x); v[1] = __float_as_int(lo.y);
-    v[2] = __float_as_int(lo.z); v[3] = __float_as_int(lo.w);
-    v[4] = __float_as_int(hi.x); v[5] = __float_as_int(hi.y);
-    v[6] = __float_as_int(hi.z); v[7] = __float_as_int(hi.w);
-    return v;
+__device__ __forceinline__ int fp8_frag_off(int rbase, int s, int p, int lane) {
+    return rbase * 32 + 4 * ((4 * s + 2 * (lane >> 5) + p) ^ chunk_key(rbase));
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gemm_kept_fp8_kernel(const uint8_t* __restrict__ At, int64_t ldat, const uint8_t* __restrict__ Bt,
-                          int64_t ldbt, int64_t scales, int64_t m, int64_t l, int32_t bp,
-                          BlockList kept, int32_t nkept, int32_t nsub, int64_t lo_off,
-                          float scale, float* __restrict__ C, int64_t ldc, int32_t tilesM,
-                          int32_t tilesN) {
-    __shared__ __align__(16) float As[2][BM * LDT];
-    __shared__ __align__(16) float Bs[2][BN * LDT];
+template <bool kOdd>
+__global__ __launch_bounds__(kThreadsK) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
+                           const uint8_t* __restrict__ Bt, int64_t ldbt, int64_t scales,
+                           int64_t m, int64_t l, int32_t bp, BlockList kept, int32_t nkept,
+                           int32_t nsub, int64_t lo_off, float scale, float* __restrict__ C,
+                           int64_t ldc, int32_t tilesM, int32_t tilesN) {
+    __shared__ __align__(1024) float As0[BM * 32];
+    __shared__ __align__(1024) float As1[BM * 32];
+    __shared__ __align__(1024) float Bs0[BN * 32];
+    __shared__ __align__(1024) float Bs1[BN * 32];
+    __shared__ __align__(16) uint32_t Sc0[BM + BN];   // scale words: A's rows, then B's
+    __shared__ __align__(16) uint32_t Sc1[BM + BN];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = wave >> 1;
-    const int wn = wave & 1;
+    const int wm = wave >> 2;
+    const int wn = wave & 3;
 
     const int64_t ntiles = (int64_t)tilesM * tilesN;
     const int64_t T = xcd_task(blockIdx.x, ntiles);
@@ -460,114 +425,180 @@ void gemm_kept_fp8_kernel(const uint8_t* __restrict__ At, int64_t ldat, const ui
     const int64_t row0 = tm * BM;
     const int64_t col0 = tn * BN;
 
-    v16f acc[4][4];
+    int32_t kv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) kv[q] = kept.idx[64 * q + lane];
+    auto kept_at = [&](int j) -> int32_t {
+        const int32_t r0 = __builtin_amdgcn_readlane(kv[0], j & 63);
+        const int32_t r1 = __builtin_amdgcn_readlane(kv[1], j & 63);
+        const int32_t r2 = __builtin_amdgcn_readlane(kv[2], j & 63);
+        const int32_t r3 = __builtin_amdgcn_readlane(kv[3], j & 63);
+        return j < 64 ? r0 : (j < 128 ? r1 : (j < 192 ? r2 : r3));
+    };
+
+    v16f acc[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    constexpr int kStep = kStepBytes;                 // 128 FP8 values per step
+    constexpr int kStep = kStepBytes;                 // 128 codes per step
     const int tpb = bp / kStep;
     const int total = nkept * nsub * tpb;
-    auto step_col = [&](int step, int which) -> uint32_t {   // which: 1 = A, 2 = B
+    // code byte offsets of step `step` in A and B (terms in order)
+    auto step_ab = [&](int step, uint32_t& ka, uint32_t& kb) {
         const int term = step / tpb;
         const int j = term / nsub;
         const int sub = term - j * nsub;
-        const int64_t c = (int64_t)kept.idx[j] * bp + (int64_t)(step % tpb) * kStep +
-                          (sub == 3 - which ? lo_off : 0);
-        return (uint32_t)c;
+        const int64_t c = (int64_t)kept_at(j) * bp + (int64_t)(step % tpb) * kStep;
+        ka = (uint32_t)(c + (sub == 2 ? lo_off : 0));
+        kb = (uint32_t)(c + (sub == 1 ? lo_off : 0));
     };
 
-    const int r32 = lane & 31;
-    const int h = lane >> 5;
-    const int arow = wm * 128 + r32;
-    const int brow = wn * 128 + r32;
     const int alast = (int)min((int64_t)BM - 1, m - 1 - row0);
     const int blast = (int)min((int64_t)BN - 1, l - 1 - col0);
-
     const __amdgpu_buffer_rsrc_t ra_src = tile_rsrc(At + row0 * ldat);
     const __amdgpu_buffer_rsrc_t rb_src = tile_rsrc(Bt + col0 * ldbt);
-    uint32_t oa[8], ob[8];
-    tile_offsets(oa, ldat, tid >> 3, alast, tid & 7);
-    tile_offsets(ob, ldbt, tid >> 3, blast, tid & 7);
-    // scale bytes (2 blocks = one step) of the lane's fragment rows
-    uint32_t sa_off[4], sb_off[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        sa_off[i] = (uint32_t)((int64_t)min(arow + 32 * i, alast) * ldat + scales);
-        sb_off[i] = (uint32_t)((int64_t)min(brow + 32 * i, blast) * ldbt + scales);
-    }
-    auto load_scales = [&](uint32_t (&wa)[4], uint32_t (&wb)[4], int step) {
-        const uint32_t ka = step_col(step, 1) / kFp8Block, kb = step_col(step, 2) / kFp8Block;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            wa[i] = __builtin_amdgcn_raw_buffer_load_b16(ra_src, sa_off[i], ka, 0);
-            wb[i] = __builtin_amdgcn_raw_buffer_load_b16(rb_src, sb_off[i], kb, 0);
-        }
+    uint32_t va[4], vb[4];
+    direct_offsets<4>(va, ldat, alast, wave, lane);
+    direct_offsets<4>(vb, ldbt, blast, wave, lane);
+    // scale word of this lane's row: word p = 64 (wave % 4) + lane of A's
+    // (waves 0-3) or B's (waves 4-7) area holds row (4 consecutive words per
+    // A fragment lane: rows wm*128 + 32 i + r; 2 per B fragment lane: rows
+    // wn*64 + 32 j + r)
+    const int p = 64 * (wave & 3) + lane;
+    const bool a_side = wave < 4;
+    const int srow = a_side ? (p >> 7) * 128 + 32 * (p & 3) + ((p >> 2) & 31)
+                            : (p >> 6) * 64 + 32 * (p & 1) + ((p >> 1) & 31);
+    const uint32_t so = a_side ? (uint32_t)((int64_t)min(srow, alast) * ldat + scales)
+                               : (uint32_t)((int64_t)min(srow, blast) * ldbt + scales);
+    const __amdgpu_buffer_rsrc_t rs_src = a_side ? ra_src : rb_src;
+    const int sbase = a_side ? 64 * (wave & 3) : BM + 64 * (wave & 3);
+
+    auto issue = [&](float* as, float* bs, uint32_t* sc, int step) {
+        uint32_t ka, kb;
+        step_ab(step, ka, kb);
+        direct_issue<4>(ra_src, as, va, ka, wave);
+        direct_issue<4>(rb_src, bs, vb, kb, wave);
+#if defined(__HIP_DEVICE_COMPILE__)
+        const uint32_t kc = a_side ? ka : kb;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_src, (lds_void*)(sc + sbase), 4, so,
+                                                 (kc / kFp8Block) & ~3u, 0, 0);
+#else
+        (void)sc;
+        (void)so;
+        (void)rs_src;
+        (void)sbase;
+#endif
+    };
+    // the half of a step's scale word that holds its pair of scale bytes
+    auto hsel = [&](int step, bool a) -> uint32_t {
+        uint32_t ka, kb;
+        step_ab(step, ka, kb);
+        return (((a ? ka : kb) / kStep) & 1u) * 16u;
     };
 
-    float4 ra[8], rb[8];
-    uint32_t wa[4], wb[4], na[4], nb[4];
-    load_tile(ra, ra_src, step_col(0, 1), oa);
-    load_tile(rb, rb_src, step_col(0, 2), ob);
-    load_scales(wa, wb, 0);
-    store_tile(As[0], ra, tid);
-    store_tile(Bs[0], rb, tid);
-    load_tile(ra, ra_src, step_col(min(1, total - 1), 1), oa);
-    load_tile(rb, rb_src, step_col(min(1, total - 1), 2), ob);
-    __syncthreads();
-
-    for (int t = 0; t < total; ++t) {
-        const int cur = t & 1;
-        const float* as = As[cur];
-        const float* bs = Bs[cur];
-        load_scales(na, nb, min(t + 1, total - 1));
+    int fa_off[2][2], fb_off[2][2];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int byte = 64 * q + 32 * h;
-            const int sh = 8 * q;                    // the substep's scale byte
-            i32x8 fb[4];
+            fa_off[s2][q] = fp8_frag_off(wm * 128 + (lane & 31), s2, q, lane);
+            fb_off[s2][q] = fp8_frag_off(wn * 64 + (lane & 31), s2, q, lane);
+        }
+    auto as_i32x8 = [](const float4& lo, const float4& hi) -> i32x8 {
+        return i32x8{__float_as_int(lo.x), __float_as_int(lo.y), __float_as_int(lo.z),
+                     __float_as_int(lo.w), __float_as_int(hi.x), __float_as_int(hi.y),
+                     __float_as_int(hi.z), __float_as_int(hi.w)};
+    };
+    // A fragment of row block i of substep s2; B fragments of substep s2
+    auto frag_a = [&](const float* as, int s2, int i) -> i32x8 {
+        return as_i32x8(*reinterpret_cast<const float4*>(as + fa_off[s2][0] + 1024 * i),
+                        *reinterpret_cast<const float4*>(as + fa_off[s2][1] + 1024 * i));
+    };
+    auto frag_b = [&](i32x8 (&b)[2], const float* bs, int s2) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) fb[j] = frag32(bs, brow + 32 * j, byte);
-            i32x8 fa = frag32(as, arow, byte);
+        for (int j = 0; j < 2; ++j)
+            b[j] = as_i32x8(*reinterpret_cast<const float4*>(bs + fb_off[s2][0] + 1024 * j),
+                            *reinterpret_cast<const float4*>(bs + fb_off[s2][1] + 1024 * j));
+    };
+    const int sa_word = 4 * (wm * 32 + (lane & 31));
+    const int sb_word = BM + 2 * (wn * 32 + (lane & 31));
+    auto read_scales = [&](uint4& wa, uint2& wb, const uint32_t* sc) {
+        wa = *reinterpret_cast<const uint4*>(sc + sa_word);
+        wb = *reinterpret_cast<const uint2*>(sc + sb_word);
+    };
+
+    issue(As0, Bs0, Sc0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    i32x8 fa, fb[2], fan, fbn[2];
+    uint4 wa;
+    uint2 wb;
+    fa = frag_a(As0, 0, 0);
+    frag_b(fb, Bs0, 0);
+    read_scales(wa, wb, Sc0);
+    // One step: the next step's tiles and scale words go straight into the
+    // other buffers while this step runs; the A fragment of the next
+    // (substep, row block) is read during the current one's two MFMAs, and
+    // substep 1's B fragments during substep 0's last row block.  A dead
+    // step (the second of a pair when total is odd) has its A fragments
+    // zeroed.
+    auto kstep = [&](const float* as, const float* bs, float* na, float* nb, uint32_t* nsc,
+                     int t, bool live) {
+        issue(na, nb, nsc, min(t + 1, total - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        const int tt = t < total ? t : total - 1;
+        const uint32_t ha = hsel(tt, true);
+        const uint32_t hb = hsel(tt, false);
+        const uint32_t sa[4] = {wa.x >> ha, wa.y >> ha, wa.z >> ha, wa.w >> ha};
+        const uint32_t sb[2] = {wb.x >> hb, wb.y >> hb};
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const i32x8 fn = frag32(as, arow + 32 * min(i + 1, 3), byte);
-                const int sa = (int)((wa[i] >> sh) & 0xFFu);
+                if (i < 3) {
+                    fan = frag_a(as, s2, i + 1);
+                } else if (s2 == 0) {
+                    fan = frag_a(as, 1, 0);
+                    frag_b(fbn, bs, 1);
+                }
+                if constexpr (kOdd) {
+                    if (!live) fa = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
+                }
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        fa, fb[j], acc[i][j], 0, 0, 0, sa, 0, (int)((wb[j] >> sh) & 0xFFu));
-                fa = fn;
+                        fa, fb[j], acc[i][j], 0, 0, 0, (int)((sa[i] >> (8 * s2)) & 0xFFu), 0,
+                        (int)((sb[j] >> (8 * s2)) & 0xFFu));
+                if (i < 3 || s2 == 0) fa = fan;
             }
-            if (q == 0) {
-                // the next step's tile into the other buffer; the step after
-                // that is loaded a whole step ahead of its use
-                store_tile(As[cur ^ 1], ra, tid);
-                store_tile(Bs[cur ^ 1], rb, tid);
-                const int ahead = min(t + 2, total - 1);
-                load_tile(ra, ra_src, step_col(ahead, 1), oa);
-                load_tile(rb, rb_src, step_col(ahead, 2), ob);
+            if (s2 == 0) {
+                fb[0] = fbn[0];
+                fb[1] = fbn[1];
             }
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            wa[i] = na[i];
-            wb[i] = nb[i];
-        }
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        fa = frag_a(na, 0, 0);
+        frag_b(fb, nb, 0);
+        read_scales(wa, wb, nsc);
+    };
+    for (int t = 0; t < total; t += 2) {
+        kstep(As0, Bs0, As1, Bs1, Sc1, t, true);
+        kstep(As1, Bs1, As0, Bs0, Sc0, t + 1, t + 1 < total);
     }
 
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t col = col0 + wn * 128 + j * 32 + r32;
+        for (int j = 0; j < 2; ++j) {
+            const int64_t col = col0 + wn * 64 + j * 32 + (lane & 31);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int64_t row = row0 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int64_t row = row0 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 if (row < m && col < l) C[row * ldc + col] = acc[i][j][r] * scale;
             }
         }
@@ -788,8 +819,10 @@ hipError_t launch_gemm_kept_fp8(const void* At, int64_t ldat, const void* Bt, in
     if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 1) || nkept < 1) return hipErrorInvalidValue;
     const int64_t tilesM = (m + BM - 1) / BM;
     const int64_t tilesN = (l + BN - 1) / BN;
-    hipLaunchKernelGGL(gemm_kept_fp8_kernel, dim3((unsigned)(tilesM * tilesN)), dim3(kThreads), 0,
-                       s, static_cast<const uint8_t*>(At), ldat, static_cast<const uint8_t*>(Bt),
+    const bool odd = ((int64_t)nkept * (split ? 3 : 1) * (bp / kStepBytes)) % 2 != 0;
+    auto kern = odd ? gemm_kept_fp8d_kernel<true> : gemm_kept_fp8d_kernel<false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreadsK), 0, s,
+                       static_cast<const uint8_t*>(At), ldat, static_cast<const uint8_t*>(Bt),
                        ldbt, scales, m, l, bp, kept, nkept, split ? 3 : 1, lo_off, scale, C, ldc,
                        (int32_t)tilesM, (int32_t)tilesN);
     return hipGetLastError();

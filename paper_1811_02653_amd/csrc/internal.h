@@ -57,6 +57,7 @@ struct PrepDesc {
     uint32_t* table;
     uint32_t* hdr;
     uint16_t* ell;
+    const int32_t* inv;     // bucket -> list position per block (nblk x bp), or nullptr
     int64_t n;
     int64_t nt;
     int64_t RC;
@@ -93,9 +94,21 @@ hipError_t launch_table_batch(const PrepDesc* descs, int32_t count, int64_t task
                               hipStream_t s);
 hipError_t launch_lists_batch(const PrepDesc* descs, int32_t count, int64_t tasks,
                               int32_t max_bp, hipStream_t s);
-// Lists for every block i < nblk of a packed table.
+// Lists for every block i < nblk of a packed table; with inv (DEVICE
+// [nblk][bp], bucket -> list position), bucket c's entries go to position
+// inv[i * bp + c] (its column in the sketch), else to position c.
 hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
-                              int32_t bp, void* lists, hipStream_t s);
+                              int32_t bp, void* lists, hipStream_t s,
+                              const int32_t* inv = nullptr);
+// inv for every block: buckets of similar list lengths grouped into the
+// same 64-bucket groups (the identity when b <= 64).
+hipError_t launch_group_buckets(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
+                                int32_t b, int32_t bp, int32_t* inv, hipStream_t s);
+// inv = the identity (natural bucket order).
+hipError_t launch_identity_inv(int32_t nblk, int32_t bp, int32_t* inv, hipStream_t s);
+// order[i * bp + p] = the bucket at position p of block i (p for p >= b).
+hipError_t launch_bucket_order(const int32_t* inv, int32_t nblk, int32_t b, int32_t bp,
+                               int32_t* order, hipStream_t s);
 // Shapes a sketch launch supports (lines = the dimension that is not sketched).
 bool plan_sketch_ok(int64_t lines, int32_t nst, int32_t bp, int64_t n);
 // out (cols x nst*bp, ld ldo) = (S^T X)^T for X n x cols row-major (ld ldx);

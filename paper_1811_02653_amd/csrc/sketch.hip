@@ -92,7 +92,7 @@ __device__ __forceinline__ void ell_build_region(const uint32_t* __restrict__ ta
                                                  int32_t nwin, int64_t RC,
                                                  uint32_t* __restrict__ hdr,
                                                  uint16_t* __restrict__ ell, int w, int64_t i,
-                                                 uint32_t* sm) {
+                                                 uint32_t* sm, const int32_t* __restrict__ inv) {
     uint32_t* cnt = sm;            // [bp] counts, then cursors
     uint32_t* qbase = sm + bp;     // [qn] chunk base of each group
     uint32_t* qlen = qbase + qn;   // [qn] chunk count of each group
@@ -102,10 +102,28 @@ __device__ __forceinline__ void ell_build_region(const uint32_t* __restrict__ ta
     const uint32_t* row = table + i * nt + k0;
     uint32_t* H = hdr + (i * nwin + w) * qn;
     uint16_t* region = ell + (i * nwin + w) * RC * 512;
+    // list position of a bucket (the bucket itself unless grouped), the
+    // block's map copied to LDS after the counts and group fields
+    uint32_t* pos = qlen + qn;
+    uint32_t* tab = pos + bp;       // [kWin] the window's table entries
+    auto at = [&](uint32_t e) -> uint32_t {
+        const uint32_t h = e & 0x7FFFFFFFu;
+        return inv ? pos[h] : h;
+    };
 
-    for (int c = lane; c < bp; c += 64) cnt[c] = 0;
+    for (int c = lane; c < bp; c += 64) {
+        cnt[c] = 0;
+        if (inv) pos[c] = (uint32_t)inv[i * bp + c];
+    }
+    for (int t0 = 0; t0 < kw; t0 += 64 * 16) {
+        uint32_t e[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) e[u] = row[min(t0 + 64 * u + lane, kw - 1)];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) tab[t0 + 64 * u + lane] = e[u];
+    }
     __syncthreads();
-    for (int t = lane; t < kw; t += 64) atomicAdd(&cnt[row[t] & 0x7FFFFFFFu], 1u);
+    for (int t = lane; t < kw; t += 64) atomicAdd(&cnt[at(tab[t])], 1u);
     __syncthreads();
 
     uint32_t base = 0;
@@ -132,8 +150,8 @@ __device__ __forceinline__ void ell_build_region(const uint32_t* __restrict__ ta
     for (int t0 = 0; t0 < kw; t0 += 64) {
         const int t = t0 + lane;
         const bool valid = t < kw;
-        const uint32_t e = valid ? row[t] : 0u;
-        const uint32_t h = e & 0x7FFFFFFFu;
+        const uint32_t e = valid ? tab[t] : 0u;
+        const uint32_t h = valid ? at(e) : 0u;
         uint64_t peers = __ballot(valid);
         for (int bit = 0; bit < nbits; ++bit) {
             const bool set = (h >> bit) & 1u;
@@ -178,7 +196,7 @@ __device__ __forceinline__ void ell_build_region4(const uint32_t* __restrict__ t
                                                   int32_t nwin, int64_t RC,
                                                   uint32_t* __restrict__ hdr,
                                                   uint16_t* __restrict__ ell, int w, int64_t i,
-                                                  uint32_t* sm) {
+                                                  uint32_t* sm, const int32_t* __restrict__ inv) {
     uint32_t* cur = sm;                 // [kBW][bp] counts, then cursors
     uint32_t* tot = sm + kBW * bp;      // [bp] entries per bucket
     uint32_t* qbase = tot + bp;         // [qn] chunk base of each group
@@ -196,10 +214,27 @@ __device__ __forceinline__ void ell_build_region4(const uint32_t* __restrict__ t
     const int t_beg = min(kw, wv * part);
     const int t_end = min(kw, t_beg + part);
     uint32_t* mine = cur + wv * bp;
+    uint32_t* pos = qlen + qn;          // [bp] the block's bucket -> position map
+    uint32_t* tab = pos + bp;           // [kWin] the window's table entries
+    auto at = [&](uint32_t e) -> uint32_t {
+        const uint32_t h = e & 0x7FFFFFFFu;
+        return inv ? pos[h] : h;
+    };
 
     for (int c = tid; c < kBW * bp; c += 64 * kBW) cur[c] = 0;
+    if (inv)
+        for (int c = tid; c < bp; c += 64 * kBW) pos[c] = (uint32_t)inv[i * bp + c];
+    {
+        // the window's entries to LDS, every load issued before the first store
+        constexpr int kU = kWin / (64 * kBW);
+        uint32_t e[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) e[u] = row[min(u * 64 * kBW + tid, kw - 1)];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) tab[u * 64 * kBW + tid] = e[u];
+    }
     __syncthreads();
-    for (int t = t_beg + lane; t < t_end; t += 64) atomicAdd(&mine[row[t] & 0x7FFFFFFFu], 1u);
+    for (int t = t_beg + lane; t < t_end; t += 64) atomicAdd(&mine[at(tab[t])], 1u);
     __syncthreads();
     for (int c = tid; c < bp; c += 64 * kBW) {
         uint32_t run = 0;
@@ -236,8 +271,8 @@ __device__ __forceinline__ void ell_build_region4(const uint32_t* __restrict__ t
     for (int t0 = t_beg; t0 < t_end; t0 += 64) {
         const int t = t0 + lane;
         const bool valid = t < t_end;
-        const uint32_t e = valid ? row[t] : 0u;
-        const uint32_t h = e & 0x7FFFFFFFu;
+        const uint32_t e = valid ? tab[t] : 0u;
+        const uint32_t h = valid ? at(e) : 0u;
         uint64_t peers = __ballot(valid);
         for (int bit = 0; bit < nbits; ++bit) {
             const bool set = (h >> bit) & 1u;
@@ -272,20 +307,22 @@ __global__ __launch_bounds__(64 * kBW) void ell_build4_kernel(const uint32_t* __
                                                               int32_t qn, int32_t nwin,
                                                               int64_t RC,
                                                               uint32_t* __restrict__ hdr,
-                                                              uint16_t* __restrict__ ell) {
+                                                              uint16_t* __restrict__ ell,
+                                                              const int32_t* __restrict__ inv) {
     extern __shared__ uint32_t sm[];
     ell_build_region4(table, n, nt, bp, qn, nwin, RC, hdr, ell, (int)blockIdx.x,
-                      (int64_t)blockIdx.y, sm);
+                      (int64_t)blockIdx.y, sm, inv);
 }
 
 __global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restrict__ table,
                                                        int64_t n, int64_t nt, int32_t bp,
                                                        int32_t qn, int32_t nwin, int64_t RC,
                                                        uint32_t* __restrict__ hdr,
-                                                       uint16_t* __restrict__ ell) {
+                                                       uint16_t* __restrict__ ell,
+                                                       const int32_t* __restrict__ inv) {
     extern __shared__ uint32_t sm[];
     ell_build_region(table, n, nt, bp, qn, nwin, RC, hdr, ell, (int)blockIdx.x,
-                     (int64_t)blockIdx.y, sm);
+                     (int64_t)blockIdx.y, sm, inv);
 }
 
 __global__ __launch_bounds__(64 * kBW) void ell_build_batch4_kernel(
@@ -298,7 +335,7 @@ __global__ __launch_bounds__(64 * kBW) void ell_build_batch4_kernel(
         const PrepDesc& d = descs[p];
         const int64_t local = t - d.ell_task0;
         ell_build_region4(d.table, d.n, d.nt, d.bp, d.qn, d.nwin, d.RC, d.hdr, d.ell,
-                          (int)(local % d.nwin), local / d.nwin, sm);
+                          (int)(local % d.nwin), local / d.nwin, sm, d.inv);
         __syncthreads();
     }
 }
@@ -316,9 +353,138 @@ __global__ __launch_bounds__(64) void ell_build_batch_kernel(const PrepDesc* __r
         const PrepDesc& d = descs[p];
         const int64_t local = t - d.ell_task0;
         ell_build_region(d.table, d.n, d.nt, d.bp, d.qn, d.nwin, d.RC, d.hdr, d.ell,
-                         (int)(local % d.nwin), local / d.nwin, sm);
+                         (int)(local % d.nwin), local / d.nwin, sm, d.inv);
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Grouping the buckets of each block (one workgroup per block).  The sketch
+// kernel's 64 lanes walk the lists of a group of 64 buckets in lockstep, so
+// a group costs its longest list in every window.  Any fixed order of the
+// buckets within a block serves the product (A's and B's sketches use the
+// same order, and C sums over the buckets), so buckets of similar list
+// lengths are put in one group: a recursive median split over the groups
+// (a k-d partition), level d sorting each node's buckets by their count in
+// the windows w with w % D == d (D levels for G = ceil(b / 64) groups), ties
+// by their current position, and splitting the node in two halves of whole
+// groups.  inv[i * bp + c] = the position of bucket c (c < b) in block i's
+// sketch; positions b .. bp - 1 stay empty.
+// ---------------------------------------------------------------------------
+constexpr int kGroupThreads = 1024;
+constexpr int kSortMax = 8192;        // >= OS_MAX_B, a power of two
+
+__global__ __launch_bounds__(kGroupThreads) void group_kernel(const uint32_t* __restrict__ table,
+                                                              int64_t n, int64_t nt, int32_t b,
+                                                              int32_t bp, int32_t nwin,
+                                                              int32_t* __restrict__ inv) {
+    __shared__ uint64_t key[kSortMax];
+    __shared__ uint32_t feat[kSortMax];
+    __shared__ int32_t bucket_at[kSortMax];
+    const int tid = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    const uint32_t* row = table + i * nt;
+    const int G = (b + 63) / 64;
+    int D = 0;
+    while ((1 << D) < G) ++D;
+    int N = 1;
+    while (N < b) N <<= 1;
+    for (int p = tid; p < b; p += kGroupThreads) bucket_at[p] = p;
+    __syncthreads();
+    for (int d = 0; d < D; ++d) {
+        for (int c = tid; c < b; c += kGroupThreads) feat[c] = 0;
+        __syncthreads();
+        for (int64_t w = d; w < nwin; w += D) {
+            const int64_t k0 = w * (int64_t)kWin;
+            const int64_t k1 = min(n, k0 + kWin);
+            // the window's entries: all loads issued before the first atomic
+            constexpr int kU = kWin / kGroupThreads;
+            uint32_t e[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t k = k0 + u * kGroupThreads + tid;
+                e[u] = row[min(k, k1 - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (k0 + u * kGroupThreads + tid < k1) atomicAdd(&feat[e[u] & 0x7FFFFFFFu], 1u);
+        }
+        __syncthreads();
+        // key = (first group of the position's level-d node, count, position)
+        for (int p = tid; p < N; p += kGroupThreads) {
+            uint64_t kk = ~0ull;
+            if (p < b) {
+                int glo = 0, ghi = G;
+                for (int lv = 0; lv < d; ++lv) {
+                    const int gm = (glo + ghi) >> 1;
+                    if ((p >> 6) < gm)
+                        ghi = gm;
+                    else
+                        glo = gm;
+                }
+                kk = ((uint64_t)glo << 50) | ((uint64_t)feat[bucket_at[p]] << 14) | (uint64_t)p;
+            }
+            key[p] = kk;
+        }
+        __syncthreads();
+        // bitonic sort of key[0, N), ascending.  Thread t exchanges the pair
+        // (lo, lo + stride), lo = 2t - t % stride.  For strides up to 64 the
+        // pairs of wave w lie in entries [128w, 128w + 128), so two such
+        // stages in a row need only the wave's own LDS ordering (a wave's
+        // LDS instructions execute in program order); a stage that crosses
+        // waves (stride >= 128, or several pairs per thread) is fenced by
+        // workgroup barriers on both sides.
+        bool prev_cross = true;          // (the keys were just written by all waves)
+        for (int size = 2; size <= N; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                const bool cross = stride >= 128 || N / 2 > kGroupThreads;
+                if (cross || prev_cross) {
+                    __syncthreads();
+                } else {
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                }
+                prev_cross = cross;
+                for (int t = tid; t < N / 2; t += kGroupThreads) {
+                    const int lo = 2 * t - (t & (stride - 1));
+                    const int hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint64_t x = key[lo], y = key[hi];
+                    if ((x > y) == up) {
+                        key[lo] = y;
+                        key[hi] = x;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // the bucket now at position p was at position key[p] & 0x3FFF
+        for (int p = tid; p < b; p += kGroupThreads) feat[p] = (uint32_t)bucket_at[key[p] & 0x3FFF];
+        __syncthreads();
+        for (int p = tid; p < b; p += kGroupThreads) bucket_at[p] = (int32_t)feat[p];
+        __syncthreads();
+    }
+    for (int p = tid; p < b; p += kGroupThreads) inv[i * bp + bucket_at[p]] = p;
+}
+
+// bucket order of block i: order[i * bp + p] = the bucket at position p
+// (p < b), p itself for the empty positions p >= b.
+__global__ __launch_bounds__(256) void bucket_order_kernel(const int32_t* __restrict__ inv,
+                                                           int32_t b, int32_t bp,
+                                                           int32_t* __restrict__ order) {
+    const int64_t i = blockIdx.y;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < bp; c += gridDim.x * blockDim.x) {
+        if (c < b)
+            order[i * bp + inv[i * bp + c]] = c;
+        else
+            order[i * bp + c] = c;
+    }
+}
+
+__global__ __launch_bounds__(256) void identity_inv_kernel(int32_t bp, int32_t* __restrict__ inv) {
+    const int64_t i = blockIdx.y;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < bp; c += gridDim.x * blockDim.x)
+        inv[i * bp + c] = c;
 }
 
 // ---------------------------------------------------------------------------
@@ -1013,11 +1179,11 @@ hipError_t launch_lists_batch(const PrepDesc* descs, int32_t count, int64_t task
     const int32_t qn = (max_bp + 63) / 64;
     const unsigned grid = (unsigned)std::min<int64_t>(tasks, int64_t(1) << 20);
     if (max_bp <= kBW4MaxBp) {
-        const size_t lds = (size_t)((kBW + 1) * max_bp + 2 * qn) * 4;
+        const size_t lds = (size_t)((kBW + 2) * max_bp + 2 * qn + kWin) * 4;
         hipLaunchKernelGGL(ell_build_batch4_kernel, dim3(grid), dim3(64 * kBW), lds, s, descs,
                            count, tasks);
     } else {
-        const size_t lds = (size_t)(max_bp + 2 * qn) * 4;
+        const size_t lds = (size_t)(2 * max_bp + 2 * qn + kWin) * 4;
         hipLaunchKernelGGL(ell_build_batch_kernel, dim3(grid), dim3(64), lds, s, descs, count,
                            tasks);
     }
@@ -1025,20 +1191,47 @@ hipError_t launch_lists_batch(const PrepDesc* descs, int32_t count, int64_t task
 }
 
 hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
-                              int32_t bp, void* lists, hipStream_t s) {
+                              int32_t bp, void* lists, hipStream_t s, const int32_t* inv) {
     const Plan p = plan_of(n, bp);
     const ListView v = carve_lists(lists, nblk, n, bp);
     if (bp <= kBW4MaxBp) {
-        const size_t lds = (size_t)((kBW + 1) * bp + 2 * p.qn) * 4;
+        const size_t lds = (size_t)((kBW + 2) * bp + 2 * p.qn + kWin) * 4;
         hipLaunchKernelGGL(ell_build4_kernel, dim3((unsigned)p.nwin, (unsigned)nblk),
                            dim3(64 * kBW), lds, s, table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
-                           reinterpret_cast<uint16_t*>(v.ell));
+                           reinterpret_cast<uint16_t*>(v.ell), inv);
     } else {
-        const size_t lds = (size_t)(bp + 2 * p.qn) * 4;
+        const size_t lds = (size_t)(2 * bp + 2 * p.qn + kWin) * 4;
         hipLaunchKernelGGL(ell_build_kernel, dim3((unsigned)p.nwin, (unsigned)nblk), dim3(64), lds,
                            s, table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
-                           reinterpret_cast<uint16_t*>(v.ell));
+                           reinterpret_cast<uint16_t*>(v.ell), inv);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_group_buckets(const uint32_t* table, int64_t n, int64_t nt, int32_t nblk,
+                                int32_t b, int32_t bp, int32_t* inv, hipStream_t s) {
+    if (b < 1 || b > kSortMax || bp < b || nblk < 1) return hipErrorInvalidValue;
+    const Plan p = plan_of(n, bp);
+    if (b <= 64) {      // one group: nothing to order
+        hipLaunchKernelGGL(identity_inv_kernel, dim3((unsigned)((bp + 255) / 256), (unsigned)nblk),
+                           dim3(256), 0, s, bp, inv);
+    } else {
+        hipLaunchKernelGGL(group_kernel, dim3((unsigned)nblk), dim3(kGroupThreads), 0, s, table,
+                           n, nt, b, bp, p.nwin, inv);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_identity_inv(int32_t nblk, int32_t bp, int32_t* inv, hipStream_t s) {
+    hipLaunchKernelGGL(identity_inv_kernel, dim3((unsigned)((bp + 255) / 256), (unsigned)nblk),
+                       dim3(256), 0, s, bp, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_order(const int32_t* inv, int32_t nblk, int32_t b, int32_t bp,
+                               int32_t* order, hipStream_t s) {
+    hipLaunchKernelGGL(bucket_order_kernel, dim3((unsigned)((bp + 255) / 256), (unsigned)nblk),
+                       dim3(256), 0, s, inv, b, bp, order);
     return hipGetLastError();
 }
 

@@ -71,9 +71,11 @@ def test_prepare_and_workspace_bytes(L):
     nwin, qn = 5, 16                          # windows of 8192 indices, groups of 64 buckets
     rc = 8192 // 8 + qn                       # 1 KiB chunks per (block, window)
     lists = r256(10 * nwin * qn * 4) + 10 * nwin * rc * 1024
-    assert prep == r256(table) + lists
+    inv = r256(10 * 1024 * 4)                 # bucket -> column map per block (bp = 1024)
+    assert prep == r256(table) + r256(lists) + inv
     small = L.os_sketch_prepare_bytes(ctypes.byref(_sk(b=64, N=1, e=0)), 100)
-    assert small == r256(1 * 100 * 4) + r256(1 * 1 * 1 * 4) + 1 * 1 * ((100 + 7) // 8 + 1) * 1024
+    assert small == (r256(1 * 100 * 4) + r256(r256(1 * 1 * 1 * 4) + 1 * 1 * ((100 + 7) // 8 + 1)
+                                               * 1024) + r256(64 * 4))
     m, l = 300, 77
     ws = L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 1)      # column-major B
     assert ws == r256(prep) + r256(300 * 10 * 1024 * 4) + r256(77 * 10 * 1024 * 4)
@@ -336,3 +338,18 @@ def test_fresh_sketch_keys_per_forward():
     assert any(k >= 2**32 for k in keys)
     torch.manual_seed(3)
     assert [fresh_seed() for _ in range(8)] == keys
+
+
+def test_prepare_ex_flags_and_diagnostics_validate(L):
+    s = _sk(b=256, N=4, e=1)
+    need = L.os_sketch_prepare_bytes(ctypes.byref(s), 4096)
+    assert L.os_sketch_prepare_ex(ctypes.byref(s), 4096, 2, FAKE, need, None) == OS_EINVAL
+    assert L.os_sketch_prepare_ex(ctypes.byref(s), 4096, 1, FAKE, need - 1, None) == OS_EWORKSPACE
+    assert L.os_sketch_prepare_ex(None, 4096, 1, FAKE, need, None) == OS_ENULL
+    w, r = ctypes.c_int64(0), ctypes.c_int64(0)
+    assert L.os_sketch_list_entries(ctypes.byref(s), 4096, FAKE, need, None, ctypes.byref(r),
+                                    None) == OS_ENULL
+    assert L.os_sketch_list_entries(ctypes.byref(s), 4096, FAKE, need - 1, ctypes.byref(w),
+                                    ctypes.byref(r), None) == OS_EWORKSPACE
+    assert L.os_sketch_bucket_order(ctypes.byref(s), 4096, FAKE, need, None, None) == OS_ENULL
+    assert L.os_sketch_bucket_order(ctypes.byref(s), 0, FAKE, need, FAKE, None) == OS_EINVAL

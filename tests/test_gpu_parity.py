@@ -399,3 +399,99 @@ def test_matmul_ex_bf16_any_layout(n, a_cm, b_cm, types):
         o = oracle.sketched_matmul(Ax.float().cpu().numpy(), Bx.float().cpu().numpy(), b, N, e,
                                    seed=seed)
         assert rel(C, o) <= PRODUCT_TOL
+
+# ---------------------------------------------------------------------------
+# grouped bucket order (the whole path's prepared sketch)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,b,N,e", [(32768, 1024, 8, 2), (9001, 100, 3, 1), (20000, 2048, 2, 1),
+                                     (3000, 64, 2, 2), (5000, 1, 2, 0), (70000, 300, 2, 1)])
+def test_grouped_order_is_a_permutation_per_block(n, b, N, e):
+    seed = n + b
+    bp = osk.block_stride(b)
+    nat = osk.sketch_prepare(n, b, N, e, seed=seed)
+    np.testing.assert_array_equal(osk.bucket_order(nat, n, b, N, e, seed=seed).cpu().numpy(),
+                                  np.tile(np.arange(bp), (N + e, 1)))
+    grp = osk.sketch_prepare(n, b, N, e, seed=seed, grouped=True)
+    order = osk.bucket_order(grp, n, b, N, e, seed=seed).cpu().numpy()
+    for i in range(N + e):
+        np.testing.assert_array_equal(np.sort(order[i, :b]), np.arange(b))
+        np.testing.assert_array_equal(order[i, b:], np.arange(b, bp))
+    # the order is a function of the sketch (reproducible)
+    grp2 = osk.sketch_prepare(n, b, N, e, seed=seed, grouped=True)
+    np.testing.assert_array_equal(osk.bucket_order(grp2, n, b, N, e, seed=seed).cpu().numpy(),
+                                  order)
+
+
+@pytest.mark.parametrize("n,b,N,e,kept_only", [(20000, 256, 4, 2, False), (9001, 100, 3, 1, True),
+                                               (40000, 1024, 3, 1, False)])
+def test_grouped_sketches_are_the_natural_ones_permuted(n, b, N, e, kept_only):
+    # the same sums (each bucket in ascending k), at the columns the order
+    # names: bit-exact, both sketch kinds
+    seed = 3 * n + b
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((37, n)).astype(np.float32)
+    Y = rng.standard_normal((n, 29)).astype(np.float32)
+    keep = synthetic.random_keep(N, e, seed)
+    bp = osk.block_stride(b)
+    nat = osk.sketch_prepare(n, b, N, e, seed=seed)
+    grp = osk.sketch_prepare(n, b, N, e, seed=seed, grouped=True)
+    order = osk.bucket_order(grp, n, b, N, e, seed=seed).cpu().numpy()
+    stored = stored_blocks(N, e, keep, kept_only)
+    for fn, M, kw in ((osk.sketch_cols, X, {}), (osk.sketch_rows, Y, {"workspace": True})):
+        a = host(fn(dev(M), b, N, e, seed=seed, keep=keep, kept_only=kept_only, prep=nat, **kw))
+        g = host(fn(dev(M), b, N, e, seed=seed, keep=keep, kept_only=kept_only, prep=grp, **kw))
+        for j, i in enumerate(stored):
+            np.testing.assert_array_equal(g[:, j * bp:(j + 1) * bp],
+                                          a[:, j * bp + order[i]])
+
+
+@pytest.mark.parametrize("n,b,N,e", [(32768, 1024, 8, 2), (65536, 512, 4, 1), (20000, 2048, 3, 0)])
+def test_grouped_order_walks_less_padding(n, b, N, e):
+    seed = 2 + n
+    nat = osk.sketch_prepare(n, b, N, e, seed=seed)
+    grp = osk.sketch_prepare(n, b, N, e, seed=seed, grouped=True)
+    w_nat, real = osk.list_entries(nat, n, b, N, e, seed=seed)
+    w_grp, real2 = osk.list_entries(grp, n, b, N, e, seed=seed)
+    assert real == real2 == (N + e) * n
+    assert real <= w_grp < w_nat, (w_nat / real, w_grp / real)
+
+
+def _grouped_order_reference(h, n, b, win=8192):
+    """The library's grouping written plainly: D levels of a k-d split of the
+    ceil(b/64) groups; level d sorts each node's buckets by their count in the
+    windows w = d (mod D), ties by current position (a stable sort)."""
+    G = (b + 63) // 64
+    D = 0
+    while (1 << D) < G:
+        D += 1
+    nwin = (n + win - 1) // win
+    at = np.arange(b)
+    for d in range(D):
+        feat = np.zeros(b, np.int64)
+        for w in range(d, nwin, D):
+            feat += np.bincount(h[w * win:min(n, (w + 1) * win)], minlength=b)
+        node = np.zeros(b, np.int64)
+        for p in range(b):
+            glo, ghi = 0, G
+            for _ in range(d):
+                gm = (glo + ghi) >> 1
+                if (p >> 6) < gm:
+                    ghi = gm
+                else:
+                    glo = gm
+            node[p] = glo
+        order = np.lexsort((np.arange(b), feat[at], node))
+        at = at[order]
+    return at
+
+
+@pytest.mark.parametrize("n,b,N,e", [(32768, 1024, 3, 1), (9001, 100, 2, 1), (20000, 2048, 2, 0),
+                                     (70000, 300, 2, 1), (16384, 4100, 1, 1)])
+def test_grouped_order_follows_its_definition(n, b, N, e):
+    seed = 7 * n + b
+    grp = osk.sketch_prepare(n, b, N, e, seed=seed, grouped=True)
+    order = osk.bucket_order(grp, n, b, N, e, seed=seed).cpu().numpy()
+    h, _ = oracle.hash_tables(seed, N + e, n, b)
+    for i in range(N + e):
+        np.testing.assert_array_equal(order[i, :b], _grouped_order_reference(h[i], n, b))

@@ -142,8 +142,10 @@ def test_matmul_fused_quantization_is_the_staged_path(m, n, l, b, N, e, kept_onl
     C = host(osk.matmul(Ad, Bd, b, N, e, seed=seed, keep=keep, kept_only=kept_only,
                         precision=precision))
     nst = osk.stored_count(N, e, keep, kept_only)
-    At = osk.sketch_cols(Ad, b, N, e, seed=seed, keep=keep, kept_only=kept_only)
-    Bt = osk.sketch_rows(Bd, b, N, e, seed=seed, keep=keep, kept_only=kept_only, workspace=True)
+    prep = osk.sketch_prepare(n, b, N, e, seed=seed)
+    At = osk.sketch_cols(Ad, b, N, e, seed=seed, keep=keep, kept_only=kept_only, prep=prep)
+    Bt = osk.sketch_rows(Bd, b, N, e, seed=seed, keep=keep, kept_only=kept_only, prep=prep,
+                         workspace=True)
     QA = osk.sketch_quantize(At, b, nst, precision=precision)
     QB = osk.sketch_quantize(Bt, b, nst, precision=precision)
     C2 = host(osk.gemm_kept_prec(QA, QB, b, nst, precision=precision,
