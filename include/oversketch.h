@@ -349,6 +349,24 @@ os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const
                          const uint8_t* keep_host, int kept_only, int precision, float* C,
                          int64_t ldc, void* workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * os_matmul_prec without a workspace argument.  The workspace lives in a
+ * fixed device array inside the library, os_noalloc_scratch_bytes() bytes
+ * (256 MiB) on every GPU the library runs on, held from module load until
+ * the process ends.  Arguments, layouts and results are those of
+ * os_matmul_prec (the same kernels, so C is bit for bit the same).  A
+ * problem whose os_matmul_prec_workspace_bytes exceeds the array returns
+ * OS_EWORKSPACE before anything is enqueued.  No call allocates or frees
+ * device memory.  All calls on one GPU share the array and the results of
+ * the previous call stay in it: calls that overlap in time on one GPU (two
+ * streams, two host threads) race and must be serialized by the caller. */
+size_t os_noalloc_scratch_bytes(void);
+os_status os_matmul_noalloc(const os_sketch* sk, const float* A, int64_t lda, const float* B,
+                            int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
+                            const uint8_t* keep_host, int kept_only, int precision, float* C,
+                            int64_t ldc, void* stream);
+
 /* Workspace bytes os_matmul_ex needs for the given operand layouts and
  * precision (0 on invalid arguments). */
 size_t os_matmul_ex_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,

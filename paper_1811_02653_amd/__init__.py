@@ -22,6 +22,7 @@ __all__ = [
     "sketch_rows", "sketch_rows_workspace_bytes", "gemm_kept", "matmul", "workspace_bytes",
     "stored_count", "PRECISIONS", "block_stride_prec", "quantized_row", "sketch_quantize",
     "gemm_kept_prec", "gemm_kept_cmask", "matmul_cmask", "matmul_ex", "GramBatch",
+    "matmul_noalloc", "noalloc_scratch_bytes",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -135,6 +136,11 @@ def lib():
     L.os_matmul_prec.restype = ctypes.c_int
     L.os_matmul_prec.argtypes = [sk, vp, i64, vp, i64, ctypes.c_int, i64, i64, i64, vp,
                                  ctypes.c_int, ctypes.c_int, vp, i64, vp, sz, vp]
+    L.os_noalloc_scratch_bytes.restype = sz
+    L.os_noalloc_scratch_bytes.argtypes = []
+    L.os_matmul_noalloc.restype = ctypes.c_int
+    L.os_matmul_noalloc.argtypes = [sk, vp, i64, vp, i64, ctypes.c_int, i64, i64, i64, vp,
+                                    ctypes.c_int, ctypes.c_int, vp, i64, vp]
     L.os_matmul_ex_workspace_bytes.restype = sz
     L.os_matmul_ex_workspace_bytes.argtypes = [sk, i64, i64, i64, ctypes.c_int, ctypes.c_int,
                                                ctypes.c_int]
@@ -527,6 +533,41 @@ def matmul(A, B, b, N, e, seed=0, keep=None, kept_only=False, h=None, sigma=None
                                 l, pk, int(bool(kept_only)), p, _ptr(out), ldc, _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream)),
            "os_matmul_prec")
+    return out
+
+
+def noalloc_scratch_bytes() -> int:
+    """Bytes of the library's fixed device scratch (os_matmul_noalloc)."""
+    return int(lib().os_noalloc_scratch_bytes())
+
+
+def matmul_noalloc(A, B, b, N, e, out, seed=0, keep=None, kept_only=False, h=None, sigma=None,
+                   stream=None, precision="fp32"):
+    """matmul with the library's fixed scratch as workspace (os_matmul_noalloc):
+    nothing is allocated, so `out` (m x l float32) is required.  Calls that
+    overlap on one GPU race on the shared scratch."""
+    torch = _torch()
+    _require_cuda(A, "A", torch.float32)
+    _require_cuda(B, "B", torch.float32)
+    _require_cuda(out, "out", torch.float32)
+    m, n, lda = _row_major(A, "A")
+    if B.dim() != 2 or B.shape[0] != n:
+        raise OversketchError("B must be n x l")
+    l = B.shape[1]
+    if B.stride(1) == 1 and (B.stride(0) != 1 or l == 1 and n > 1):
+        b_col_major, ldb = 0, B.stride(0) if n > 1 else (l + 3) // 4 * 4
+    elif B.stride(0) == 1:
+        b_col_major, ldb = 1, B.stride(1) if l > 1 else (n + 3) // 4 * 4
+    else:
+        raise OversketchError("B must have a unit stride in one dimension")
+    if tuple(out.shape) != (m, l):
+        raise OversketchError("out must be %d x %d" % (m, l))
+    _, _, ldc = _row_major(out, "out")
+    s = _sketch(b, N, e, seed, h, sigma, n)
+    _, pk = _mask(keep, N + e)
+    _check(lib().os_matmul_noalloc(ctypes.byref(s), _ptr(A), lda, _ptr(B), ldb, b_col_major, m, n,
+                                   l, pk, int(bool(kept_only)), _prec(precision), _ptr(out), ldc,
+                                   _stream(stream)), "os_matmul_noalloc")
     return out
 
 

@@ -19,7 +19,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liboversketch.so")
 CEIL_OUT = os.path.join(HERE, "libosk_ceilings.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["hash.hip", "sketch.hip", "gemm.hip", "quant.hip", "api.hip", "gram.hip"]
+SOURCES = ["hash.hip", "sketch.hip", "gemm.hip", "quant.hip", "api.hip", "gram.hip", "noalloc.hip"]
 CEIL_SOURCES = ["ceilings.hip"]
 ARCH = "gfx950"
 

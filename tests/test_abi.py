@@ -353,3 +353,17 @@ def test_prepare_ex_flags_and_diagnostics_validate(L):
                                     ctypes.byref(r), None) == OS_EWORKSPACE
     assert L.os_sketch_bucket_order(ctypes.byref(s), 4096, FAKE, need, None, None) == OS_ENULL
     assert L.os_sketch_bucket_order(ctypes.byref(s), 0, FAKE, need, FAKE, None) == OS_EINVAL
+
+
+def test_noalloc_rejects_oversized_problems_before_any_launch(L):
+    # the workspace of the full-size product exceeds the fixed scratch: the
+    # call returns OS_EWORKSPACE on the host (FAKE pointers are never used)
+    s = _sk(b=1024, N=8, e=2)
+    assert L.os_noalloc_scratch_bytes() == 256 << 20
+    assert L.os_matmul_noalloc(ctypes.byref(s), FAKE, 32768, FAKE, 8192, 0, 8192, 32768, 8192,
+                               None, 0, 0, FAKE, 8192, None) == OS_EWORKSPACE
+    bad = _sk(b=0)
+    assert L.os_matmul_noalloc(ctypes.byref(bad), FAKE, 16, FAKE, 16, 0, 4, 16, 4, None, 0, 0,
+                               FAKE, 4, None) == OS_EINVAL
+    assert L.os_matmul_noalloc(None, FAKE, 16, FAKE, 16, 0, 4, 16, 4, None, 0, 0, FAKE, 4,
+                               None) == OS_ENULL
