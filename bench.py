@@ -243,9 +243,36 @@ def cpu_model():
     return None
 
 
+def gram_tile_flops(sizes, K, bs, tile, mixed):
+    """Flops the batched product executes (whole tiles, K*bp padded to the
+    step pair) for a tile form: the work it does, against the algorithmic
+    m(m+1)Kb of the upper triangles."""
+    import paper_1811_02653_amd as osk
+    total = 0.0
+    for m, b in zip(sizes, bs):
+        ld = -(-K * osk.block_stride(b) // 64) * 64
+        if tile == mixed:
+            T = -(-m // 256)
+            big = small = 0
+            for i in range(T):
+                for j in range(i, T):
+                    if i == j:
+                        small += 3 if m - 256 * i > 128 else 1
+                    elif m - 256 * j > 128:
+                        big += 1
+                    else:
+                        small += 2
+            total += 2.0 * ld * (big * 256 * 256 + small * 128 * 128)
+        else:
+            T = -(-m // tile)
+            total += 2.0 * ld * (T * (T + 1) // 2) * tile * tile
+    return total
+
+
 def bench_hessian_batch(torch, osk, args, stream, reps):
     import synthetic
-    from paper_1811_02653_amd.gram import PRODUCT, PREPARE, SKETCH
+    from paper_1811_02653_amd.gram import MIXED, PRODUCT, PREPARE, SKETCH
+    TILE_NAMES = {MIXED: "mixed", 256: "256", 128: "128"}
     count, N, e = 64, 6, 1
     sizes, As, ds = synthetic.hessian_batch_device(count, args.seed)
     keeps = [synthetic.random_keep(N, e, args.seed + k, drop=1) for k in range(count)]
@@ -254,11 +281,13 @@ def bench_hessian_batch(torch, osk, args, stream, reps):
                        stream=stream)
     tuned_ms = gb.autotune(reps=2, stream=stream)
     tile, grid = gb.config
-    # the product alone for each tile side (the autotuner times whole runs)
+    cands = [{"tile": TILE_NAMES[t], "grid": g, "product_ms": ms} for t, g, ms in gb.candidates]
+    # the product alone for each tile form at its resident grid, re-timed
     by_tile = {}
-    for t in (256, 128):
+    for t in (MIXED, 256, 128):
         gb.configure(t, 0, stream=stream)
-        by_tile[t] = event_time_ms(torch, lambda: gb.run(PRODUCT, stream=stream), reps, stream)
+        by_tile[TILE_NAMES[t]] = event_time_ms(torch, lambda: gb.run(PRODUCT, stream=stream),
+                                               reps, stream)
     gb.configure(tile, grid, stream=stream)
     g = gb.graph()                      # captured on a private stream
     t_graph = event_time_ms(torch, lambda: g.launch(stream), reps, stream)
@@ -295,14 +324,19 @@ def bench_hessian_batch(torch, osk, args, stream, reps):
                     "m_k uniform in [500, 4000], d_k log-uniform in [1e-6, 1e6]; "
                     "b_k = ceil(m_k/2), N=6, e=1, one block dropped per problem",
         "m_k": sizes, "input_gb": sum(4.0 * m * 20 * m for m in sizes) / 1e9,
-        "tile": tile, "grid": grid, "autotune_ms": tuned_ms,
+        "tile": TILE_NAMES[tile], "grid": grid, "autotune_product_ms": tuned_ms,
+        "autotune_candidates": cands,
         "product_ms_by_tile": by_tile,
+        "computed_per_algorithmic_flops": {
+            TILE_NAMES[t]: gram_tile_flops(sizes, K, bs, t, MIXED) / prod_flops
+            for t in (MIXED, 256, 128)},
         "ms_per_batch": t_graph, "ms_per_batch_eager": t_eager,
         "hessians_per_s": count / (t_graph * 1e-3),
         "eff_tflops": exact_flops / (t_graph * 1e-3) / 1e12,
         "stages_ms": {"prepare": t_prep, "sketch": t_sketch, "product": t_prod},
         "product_roofline": {
-            "kernel": "gemm_batch_sym (FP32 v_mfma_f32_32x32x2_f32, persistent, tile %d)" % tile,
+            "kernel": "%s (FP32 v_mfma_f32_32x32x2_f32, persistent, tile %s)" %
+                      ("gemm_batch_mixed" if tile == MIXED else "gemm_batch_sym", TILE_NAMES[tile]),
             "bound": "mfma", "unit": "TFLOP/s", "peak": FP32_MFMA_PEAK_TFLOPS,
             "algorithmic_flops_per_launch": prod_flops,
             "achieved": prod_flops / (t_prod * 1e-3) / 1e12,
@@ -318,9 +352,11 @@ def bench_hessian_batch(torch, osk, args, stream, reps):
         "rel_frob_vs_exact": {"mean": float(np.mean(errs)), "max": float(np.max(errs)),
                               "min": float(np.min(errs))},
     }
-    log("hessian batch: tile %d grid %d, %.3f ms per batch (graph), %.3f eager; prepare %.3f, "
+    log("hessian batch: candidates %s" % ", ".join(
+        "%s/%d %.2f ms" % (c["tile"], c["grid"], c["product_ms"]) for c in cands))
+    log("hessian batch: tile %s grid %d, %.3f ms per batch (graph), %.3f eager; prepare %.3f, "
         "sketch %.3f, product %.3f ms (%.1f TFLOP/s); exact %.1f ms; error mean %.3e" %
-        (tile, grid, t_graph, t_eager, t_prep, t_sketch, t_prod,
+        (TILE_NAMES[tile], grid, t_graph, t_eager, t_prep, t_sketch, t_prod,
          res["product_roofline"]["achieved"], t_exact, res["rel_frob_vs_exact"]["mean"]))
     gb.close()
     del gb, As, ds

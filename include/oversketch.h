@@ -453,11 +453,25 @@ void os_gram_plan_destroy(os_gram_plan* plan);
  * serves every tile configuration.  0 for a NULL plan. */
 size_t os_gram_workspace_bytes(const os_gram_plan* plan);
 
-/* Chooses the tile side of the batched product (128 or 256; 0 = 256) and
- * its number of persistent workgroups (grid; 0 = as many as fit on the
- * device at once), computes the static schedule and copies it and the
- * per-problem descriptors into the workspace.  Synchronizes `stream`
- * before returning.  OS_EINVAL for another tile or a grid above 65536. */
+/* Tile form of the batched product (os_gram_configure's `tile`):
+ *   256 -- 256 x 256 tiles, eight waves each (the diagonal tiles computed
+ *          whole);
+ *   128 -- 128 x 128 tiles, four waves each, two workgroups per CU;
+ *   OS_GRAM_MIXED -- eight-wave workgroups computing 256 x 256 tiles inside
+ *          each upper triangle and pairs of 128 x 128 tiles along its
+ *          diagonal and in a last tile column of at most 128 columns (less
+ *          work outside the triangle than 256, fewer LDS reads per MFMA than
+ *          128 inside it).
+ * With full = 0 the entries written are those of the tiles on or above the
+ * diagonal at tile side 256, 128 and 128 respectively. */
+#define OS_GRAM_MIXED 1
+
+/* Chooses the tile form of the batched product (256, 128 or OS_GRAM_MIXED;
+ * 0 = OS_GRAM_MIXED) and its number of persistent workgroups (grid; 0 = as
+ * many as fit on the device at once), computes the static schedule and
+ * copies it and the per-problem descriptors into the workspace.
+ * Synchronizes `stream` before returning.  OS_EINVAL for another tile or a
+ * grid above 65536. */
 os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void* workspace,
                             size_t ws_bytes, void* stream);
 
@@ -481,11 +495,29 @@ void os_gram_config(const os_gram_plan* plan, int32_t* tile, int32_t* grid);
 os_status os_gram_run(const os_gram_plan* plan, int stages, void* workspace, size_t ws_bytes,
                       void* stream);
 
-/* Autotuner: configures each candidate (tile 256 and 128, each with its
- * default grid), times `reps` (>= 1) runs of each after one warm-up run
- * with HIP events on `stream`, and leaves the plan configured with the
- * fastest.  Runs every stage of the batch (the H outputs are overwritten).  *best_ms (may
- * be NULL) receives the fastest average time per run. */
+/* One configuration the autotuner timed: tile form, grid, and the average
+ * time of the product stage in milliseconds. */
+typedef struct os_gram_candidate {
+    int32_t tile;
+    int32_t grid;
+    float ms;
+} os_gram_candidate;
+
+/* Autotuner: runs the prepare and sketch stages once, then for each
+ * candidate -- tile form OS_GRAM_MIXED, 256 and 128, each with one and with
+ * two times the resident grid (workgroups that fit on the device at once)
+ * -- configures the plan, runs the product stage once to warm up and times
+ * `reps` (>= 1) further product runs with HIP events on `stream`; leaves
+ * the plan configured with the fastest.  The H outputs are overwritten.
+ * cands (HOST, may be NULL when cap = 0) receives up to cap candidates in
+ * the order timed and *count (may be NULL) how many were timed; *best_ms
+ * (may be NULL) the fastest average product time.  OS_EINVAL for reps < 1,
+ * cap < 0, or cap > 0 with cands NULL. */
+os_status os_gram_autotune_ex(os_gram_plan* plan, int32_t reps, void* workspace,
+                              size_t ws_bytes, void* stream, os_gram_candidate* cands,
+                              int32_t cap, int32_t* count, float* best_ms);
+
+/* os_gram_autotune_ex without the candidate list. */
 os_status os_gram_autotune(os_gram_plan* plan, int32_t reps, void* workspace, size_t ws_bytes,
                            void* stream, float* best_ms);
 

@@ -69,6 +69,10 @@ class _GramProblem(ctypes.Structure):
     ]
 
 
+class _GramCandidate(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("grid", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -163,6 +167,9 @@ def lib():
     L.os_gram_run.argtypes = [vp, ctypes.c_int, vp, sz, vp]
     L.os_gram_autotune.restype = ctypes.c_int
     L.os_gram_autotune.argtypes = [vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
+    L.os_gram_autotune_ex.restype = ctypes.c_int
+    L.os_gram_autotune_ex.argtypes = [vp, i32, vp, sz, vp, ctypes.POINTER(_GramCandidate), i32,
+                                      ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
     L.os_gram_graph_create.restype = ctypes.c_int
     L.os_gram_graph_create.argtypes = [vp, ctypes.c_int, vp, sz, vp, ctypes.POINTER(vp)]
     L.os_graph_launch.restype = ctypes.c_int

@@ -78,14 +78,17 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 __device__ __forceinline__ int chunk_key(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
+// (sub: LDS row r holds matrix row r - sub of the resource, for a tile
+// whose rows start sub rows into the LDS array; a multiple of 16, so the
+// key is that of r.)
 template <int kU>
 __device__ __forceinline__ void direct_offsets(uint32_t (&vo)[kU], int64_t ld_bytes, int last,
-                                               int wave, int lane) {
+                                               int wave, int lane, int sub = 0) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         const int r = 8 * (kU * wave + u) + (lane >> 3);
         const int c = (lane & 7) ^ chunk_key(r);
-        vo[u] = (uint32_t)((int64_t)min(r, last) * ld_bytes + 16 * c);
+        vo[u] = (uint32_t)((int64_t)min(r - sub, last) * ld_bytes + 16 * c);
     }
 }
 
@@ -740,6 +743,169 @@ void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Mixed-tile form of the batched symmetric product.  Eight waves per
+// workgroup, one job at a time; a job is either
+//   kind 0: one 256 x 256 tile, waves of 128 x 64 (as gemm_batch_sym_kernel
+//           with kWT = 4), or
+//   kind 1: one or two 128 x 128 tiles of one problem, waves 0-3 on the
+//           first and 4-7 on the second, each wave a 64 x 64 quarter; the
+//           LDS tiles hold the first tile's 128 rows then the second's.
+// The host gives each upper triangle's interior to kind 0 and its diagonal
+// band and ragged last tile column to kind 1, so a diagonal 256 tile (whose
+// lower-left quarter is not needed) is three 128 tiles, and a last tile
+// column of at most 128 live columns is computed 128 wide.  A job is two
+// int4: {problem, kind, tile row, tile col} and {second tile row, second
+// tile col, has second, 0}, tile indices in units of 256 (kind 0) or 128
+// (kind 1) rows.  In a kind-1 job without a second tile, waves 4-7 load
+// nothing and compute nothing; they keep to the barriers.
+// ---------------------------------------------------------------------------
+
+// One job's K loop and epilogue for one wave: kI x 2 MFMA blocks of 32 x 32
+// whose A rows start at LDS row arow and B rows at brow, output origin
+// (orow, ocol).  load: the wave issues its share of the tile loads (offsets
+// va / vb against ra / rb); live: it computes and stores.
+template <int kI>
+__device__ __forceinline__ void mixed_job(float* As0, float* As1, float* Bs0, float* Bs1,
+                                          __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb,
+                                          const uint32_t (&va)[4], const uint32_t (&vb)[4],
+                                          bool load, bool live, int total, int arow, int brow,
+                                          int wave, int lane, const BatchProblem& pr,
+                                          int64_t orow, int64_t ocol, bool mirror) {
+    constexpr int kJ = 2;
+    int fa_off[4], fb_off[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        fa_off[q] = direct_frag_off(arow + (lane & 31), q, lane);
+        fb_off[q] = direct_frag_off(brow + (lane & 31), q, lane);
+    }
+    auto frag = [&](float4 (&a)[kI], float4 (&b)[kJ], const float* as, const float* bs, int q) {
+#pragma unroll
+        for (int i = 0; i < kI; ++i) a[i] = *reinterpret_cast<const float4*>(as + fa_off[q] + 1024 * i);
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) b[j] = *reinterpret_cast<const float4*>(bs + fb_off[q] + 1024 * j);
+    };
+    auto issue = [&](float* as, float* bs, int step) {
+        if (load) {
+            direct_issue<4>(ra, as, va, (uint32_t)step * kStepBytes, wave);
+            direct_issue<4>(rb, bs, vb, (uint32_t)step * kStepBytes, wave);
+        }
+    };
+
+    v16f acc[kI][kJ];
+#pragma unroll
+    for (int i = 0; i < kI; ++i)
+#pragma unroll
+        for (int j = 0; j < kJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();                           // the previous job's last reads are done
+    issue(As0, Bs0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    float4 fa[kI], fb[kJ], ga[kI], gb[kJ];
+    if (live) frag(fa, fb, As0, Bs0, 0);
+    auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t) {
+        issue(na, nb, min(t + 1, total - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        if (live) {
+            frag(ga, gb, as, bs, 1);
+            PrecF32::mfma_quad<kI, kJ>(acc, fa, fb);
+            frag(fa, fb, as, bs, 2);
+            PrecF32::mfma_quad<kI, kJ>(acc, ga, gb);
+            frag(ga, gb, as, bs, 3);
+            PrecF32::mfma_quad<kI, kJ>(acc, fa, fb);
+            PrecF32::mfma_quad<kI, kJ>(acc, ga, gb);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (live) frag(fa, fb, na, nb, 0);
+    };
+    for (int t = 0; t < total; t += 2) {
+        kstep(As0, Bs0, As1, Bs1, t);
+        kstep(As1, Bs1, As0, Bs0, t + 1);
+    }
+    if (!live) return;
+
+    const int64_t m = pr.m;
+#pragma unroll
+    for (int i = 0; i < kI; ++i) {
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            const int64_t col = ocol + j * 32 + (lane & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = orow + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (row < m && col < m) {
+                    const float v = acc[i][j][r] * pr.scale;
+                    pr.H[row * pr.ldh + col] = v;
+                    if (mirror) pr.H[col * pr.ldh + row] = v;
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(TileShape<4>::kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void gemm_batch_mixed_kernel(const BatchProblem* __restrict__ probs,
+                             const int4* __restrict__ jobs, const int32_t* __restrict__ starts,
+                             int full) {
+    constexpr int BT = 256;
+    __shared__ __align__(1024) float As0[BT * 32];
+    __shared__ __align__(1024) float As1[BT * 32];
+    __shared__ __align__(1024) float Bs0[BT * 32];
+    __shared__ __align__(1024) float Bs1[BT * 32];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int half = wave >> 2;
+
+    const int32_t w_end = starts[blockIdx.x + 1];
+    for (int32_t w = starts[blockIdx.x]; w < w_end; ++w) {
+        const int4 j0 = jobs[2 * w];
+        const int4 j1 = jobs[2 * w + 1];
+        const BatchProblem pr = probs[j0.x];
+        const int64_t m = pr.m;
+        const bool big = j0.y == 0;
+        // this wave's tile: rows ra.. of A's side, rows rb.. of B's side
+        bool load = true;
+        int64_t ra, rb;
+        if (big) {
+            ra = (int64_t)j0.z * 256;
+            rb = (int64_t)j0.w * 256;
+        } else if (half == 0) {
+            ra = (int64_t)j0.z * 128;
+            rb = (int64_t)j0.w * 128;
+        } else {
+            load = j1.z != 0;
+            ra = (int64_t)(load ? j1.x : j0.z) * 128;
+            rb = (int64_t)(load ? j1.y : j0.w) * 128;
+        }
+        const int span = big ? 256 : 128;
+        const int sub = big ? 0 : 128 * half;
+        uint32_t va[4], vb[4];
+        direct_offsets<4>(va, pr.ld * 4, (int)min((int64_t)span - 1, m - 1 - ra), wave, lane, sub);
+        direct_offsets<4>(vb, pr.ld * 4, (int)min((int64_t)span - 1, m - 1 - rb), wave, lane, sub);
+        const __amdgpu_buffer_rsrc_t rsa = tile_rsrc(pr.S + ra * pr.ld);
+        const __amdgpu_buffer_rsrc_t rsb = tile_rsrc(pr.S + rb * pr.ld);
+        const bool mirror = full && ra != rb;
+        if (big) {
+            const int wm = wave >> 2, wn = wave & 3;
+            mixed_job<4>(As0, As1, Bs0, Bs1, rsa, rsb, va, vb, true, true, pr.ksteps, wm * 128,
+                         wn * 64, wave, lane, pr, ra + wm * 128, rb + wn * 64, mirror);
+        } else {
+            const int wm = (wave >> 1) & 1, wn = wave & 1;
+            mixed_job<2>(As0, As1, Bs0, Bs1, rsa, rsb, va, vb, load, load, pr.ksteps,
+                         sub + wm * 64, sub + wn * 64, wave, lane, pr, ra + wm * 64,
+                         rb + wn * 64, mirror);
+        }
+    }
+}
+
 }  // namespace
 
 bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt, int elem) {
@@ -795,6 +961,10 @@ hipError_t launch_gemm_batch_sym(const BatchProblem* probs, const int4* tiles,
         hipLaunchKernelGGL(gemm_batch_sym_kernel<2>, dim3((unsigned)grid),
                            dim3(TileShape<2>::kThreads), 0, s,
                            probs, tiles, starts, full);
+    else if (tile == OS_GRAM_MIXED)
+        hipLaunchKernelGGL(gemm_batch_mixed_kernel, dim3((unsigned)grid),
+                           dim3(TileShape<4>::kThreads), 0, s,
+                           probs, tiles, starts, full);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -809,6 +979,9 @@ int batch_sym_blocks_per_cu(int tile) {
     else if (tile == 128)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_batch_sym_kernel<2>,
                                                          TileShape<2>::kThreads, 0);
+    else if (tile == OS_GRAM_MIXED)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_batch_mixed_kernel,
+                                                         TileShape<4>::kThreads, 0);
     return e == hipSuccess ? n : 0;
 }
 

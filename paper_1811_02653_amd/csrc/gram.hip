@@ -106,6 +106,53 @@ int32_t default_grid(int tile) {
     return (int32_t)std::min<int64_t>((int64_t)cus * std::max(per_cu, 1), kMaxGrid);
 }
 
+// Jobs of the mixed form for one problem of m rows and ksteps K steps
+// (see launch_gemm_batch_sym): 256 tiles (i, j), i < j, with more than 128
+// live columns are kind 0; each diagonal 256 tile becomes the 128 tiles on
+// or above its diagonal, a last tile column of at most 128 live columns the
+// 128 tiles that hold them, and those 128 tiles are paired in order into
+// kind-1 jobs.  Costs are in sixteenths of a 256-tile K step on one CU:
+// a 256 tile keeps each SIMD busy with 16 MFMA blocks per step, a pair of
+// 128 tiles with 8 at about 10 % lower efficiency (more LDS reads per
+// MFMA), a lone 128 tile with 4 on one wave per SIMD (less latency hidden).
+template <typename ItemT>
+void mixed_items(int64_t m, int32_t ksteps, bool full, int32_t prob, std::vector<ItemT>& items) {
+    const int64_t T = (m + 255) / 256;
+    std::vector<std::pair<int32_t, int32_t>> small;
+    for (int64_t i = 0; i < T; ++i) {
+        const bool rows2 = m - 256 * i > 128;          // tile row i holds two 128 rows
+        for (int64_t j = i; j < T; ++j) {
+            const bool cols2 = m - 256 * j > 128;
+            if (i == j) {
+                small.push_back({(int32_t)(2 * i), (int32_t)(2 * i)});
+                if (rows2) {
+                    small.push_back({(int32_t)(2 * i), (int32_t)(2 * i + 1)});
+                    small.push_back({(int32_t)(2 * i + 1), (int32_t)(2 * i + 1)});
+                }
+            } else if (cols2) {
+                const int64_t epi = 16 * kEpilogueCost * (1 + full);
+                items.push_back({16 * (int64_t)ksteps + epi, prob, 0, (int32_t)i, (int32_t)j, 0, 0, 0});
+            } else {
+                small.push_back({(int32_t)(2 * i), (int32_t)(2 * j)});
+                small.push_back({(int32_t)(2 * i + 1), (int32_t)(2 * j)});
+            }
+        }
+    }
+    auto epi128 = [&](const std::pair<int32_t, int32_t>& t) {
+        return (int64_t)4 * kEpilogueCost * (1 + (full && t.first != t.second));
+    };
+    for (size_t t = 0; t < small.size(); t += 2) {
+        const auto& x = small[t];
+        if (t + 1 < small.size()) {
+            const auto& y = small[t + 1];
+            items.push_back({9 * (int64_t)ksteps + epi128(x) + epi128(y), prob, 1, x.first,
+                             x.second, y.first, y.second, 1});
+        } else {
+            items.push_back({6 * (int64_t)ksteps + epi128(x), prob, 1, x.first, x.second, 0, 0, 0});
+        }
+    }
+}
+
 os_status check_ws(const os_gram_plan* plan, const void* ws, size_t ws_bytes) {
     if (!ws) return OS_ENULL;
     if (!aligned(ws, 256)) return OS_EALIGN;
@@ -222,7 +269,7 @@ os_status os_gram_plan_create(const os_gram_problem* probs, int32_t count, int f
         if (st == OS_OK) {
             plan->max_tiles = ntiles;
             plan->tiles_off = off;
-            off += align256((size_t)ntiles * sizeof(int4));
+            off += align256((size_t)ntiles * 2 * sizeof(int4));   // mixed jobs: two int4
             plan->starts_off = off;
             off += align256((size_t)(kMaxGrid + 1) * sizeof(int32_t));
             for (auto& q : plan->probs) {
@@ -281,8 +328,9 @@ void os_gram_config(const os_gram_plan* plan, int32_t* tile, int32_t* grid) {
 os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void* workspace,
                             size_t ws_bytes, void* stream) {
     if (!plan) return OS_ENULL;
-    if (tile == 0) tile = 256;
-    if ((tile != 128 && tile != 256) || grid < 0 || grid > kMaxGrid) return OS_EINVAL;
+    if (tile == 0) tile = OS_GRAM_MIXED;
+    if ((tile != 128 && tile != 256 && tile != OS_GRAM_MIXED) || grid < 0 || grid > kMaxGrid)
+        return OS_EINVAL;
     os_status st = check_ws(plan, workspace, ws_bytes);
     if (st != OS_OK) return st;
     if (grid == 0 && (grid = default_grid(tile)) < 1) return hip_status(hipErrorInvalidDevice);
@@ -321,10 +369,11 @@ os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void
             list_task0 += (int64_t)d.nblk * d.nwin;
         }
         if (hash_task0 != plan->hash_tasks || list_task0 != plan->list_tasks) return OS_EINVAL;
-        // (cost, problem, tile row, tile col), in problem and tile order
+        // (cost, problem, kind, tile row, tile col, second tile), in problem
+        // and tile order; kind and the second tile are used by the mixed form
         struct Item {
             int64_t cost;
-            int32_t prob, ti, tj;
+            int32_t prob, kind, ti, tj, ti2, tj2, has2;
         };
         std::vector<Item> items;
         items.reserve((size_t)plan->max_tiles);
@@ -343,11 +392,15 @@ os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void
                                          (size_t)q.ld * 4, 0,
                                          (size_t)(q.ld - (int64_t)q.K * q.bp) * 4, (size_t)q.m, s);
             bp.scale = 1.0f / (float)q.K;
+            if (tile == OS_GRAM_MIXED) {
+                mixed_items(q.m, bp.ksteps, plan->full != 0, (int32_t)k, items);
+                continue;
+            }
             const int32_t T = (int32_t)((q.m + tile - 1) / tile);
             for (int32_t i = 0; i < T; ++i)
                 for (int32_t j = i; j < T; ++j)
                     items.push_back({bp.ksteps + kEpilogueCost * (1 + (plan->full && i != j)),
-                                     (int32_t)k, i, j});
+                                     (int32_t)k, 0, i, j, 0, 0, 0});
         }
         std::stable_sort(items.begin(), items.end(),
                          [](const Item& a, const Item& b) { return a.cost > b.cost; });
@@ -365,11 +418,19 @@ os_status os_gram_configure(os_gram_plan* plan, int32_t tile, int32_t grid, void
             heap.push({l.first + items[t].cost, l.second});
         }
         for (int32_t g = 0; g < grid; ++g) starts[(size_t)g + 1] += starts[(size_t)g];
-        std::vector<int4> tiles(items.size());
+        const int per = tile == OS_GRAM_MIXED ? 2 : 1;   // int4 per list entry
+        std::vector<int4> tiles(items.size() * per);
         std::vector<int32_t> fill(starts.begin(), starts.end() - 1);
-        for (size_t t = 0; t < items.size(); ++t)
-            tiles[(size_t)fill[(size_t)owner[t]]++] =
-                make_int4(items[t].prob, items[t].ti, items[t].tj, 0);
+        for (size_t t = 0; t < items.size(); ++t) {
+            const Item& it = items[t];
+            const size_t at_ = (size_t)fill[(size_t)owner[t]]++ * per;
+            if (per == 1) {
+                tiles[at_] = make_int4(it.prob, it.ti, it.tj, 0);
+            } else {
+                tiles[at_] = make_int4(it.prob, it.kind, it.ti, it.tj);
+                tiles[at_ + 1] = make_int4(it.ti2, it.tj2, it.has2, 0);
+            }
+        }
         hipError_t e = e_pad;
         if (e == hipSuccess)
             e = hipMemcpyAsync(at(workspace, plan->desc_off), desc.data(),
@@ -402,13 +463,21 @@ os_status os_gram_run(const os_gram_plan* plan, int stages, void* workspace, siz
     return enqueue(plan, stages, workspace, (hipStream_t)stream);
 }
 
-os_status os_gram_autotune(os_gram_plan* plan, int32_t reps, void* workspace, size_t ws_bytes,
-                           void* stream, float* best_ms) {
+os_status os_gram_autotune_ex(os_gram_plan* plan, int32_t reps, void* workspace,
+                              size_t ws_bytes, void* stream, os_gram_candidate* cands,
+                              int32_t cap, int32_t* count, float* best_ms) {
+    if (count) *count = 0;
     if (!plan) return OS_ENULL;
-    if (reps < 1) return OS_EINVAL;
+    if (reps < 1 || cap < 0 || (cap > 0 && !cands)) return OS_EINVAL;
     os_status st = check_ws(plan, workspace, ws_bytes);
     if (st != OS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    // the sketches the product reads: one run of the earlier stages in the
+    // first candidate's configuration
+    const int32_t tiles[3] = {OS_GRAM_MIXED, 256, 128};
+    if ((st = os_gram_configure(plan, tiles[0], 0, workspace, ws_bytes, stream)) != OS_OK)
+        return st;
+    if ((st = enqueue(plan, OS_GRAM_PREPARE | OS_GRAM_SKETCH, workspace, s)) != OS_OK) return st;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
@@ -416,34 +485,52 @@ os_status os_gram_autotune(os_gram_plan* plan, int32_t reps, void* workspace, si
         if (t0) (void)hipEventDestroy(t0);
         return hip_status(e);
     }
-    const int32_t cand[2] = {256, 128};
-    int32_t best_tile = 0;
+    int32_t best_tile = 0, best_grid = 0, n = 0;
     float best = 0.f;
-    for (int32_t c = 0; c < 2 && st == OS_OK; ++c) {
-        if ((st = os_gram_configure(plan, cand[c], 0, workspace, ws_bytes, stream)) != OS_OK) break;
-        if ((st = enqueue(plan, OS_GRAM_ALL, workspace, s)) != OS_OK) break;   // warm-up
-        if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
-        for (int32_t r = 0; r < reps && st == OS_OK; ++r)
-            st = enqueue(plan, OS_GRAM_ALL, workspace, s);
-        if (st != OS_OK) break;
-        float ms = 0.f;
-        if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
-            (e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
+    for (int32_t c = 0; c < 3 && st == OS_OK && e == hipSuccess; ++c) {
+        const int32_t resident = default_grid(tiles[c]);
+        if (resident < 1) {
+            st = hip_status(hipErrorInvalidDevice);
             break;
-        ms /= (float)reps;
-        if (best_tile == 0 || ms < best) {
-            best = ms;
-            best_tile = cand[c];
+        }
+        for (int32_t mult = 1; mult <= 2 && st == OS_OK; ++mult) {
+            const int32_t grid = (int32_t)std::min<int64_t>((int64_t)resident * mult, kMaxGrid);
+            if ((st = os_gram_configure(plan, tiles[c], grid, workspace, ws_bytes, stream)) != OS_OK)
+                break;
+            if ((st = enqueue(plan, OS_GRAM_PRODUCT, workspace, s)) != OS_OK) break;   // warm-up
+            if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
+            for (int32_t r = 0; r < reps && st == OS_OK; ++r)
+                st = enqueue(plan, OS_GRAM_PRODUCT, workspace, s);
+            if (st != OS_OK) break;
+            float ms = 0.f;
+            if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess)
+                break;
+            ms /= (float)reps;
+            if (n < cap) cands[n] = os_gram_candidate{tiles[c], grid, ms};
+            ++n;
+            if (best_tile == 0 || ms < best) {
+                best = ms;
+                best_tile = tiles[c];
+                best_grid = grid;
+            }
         }
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (e != hipSuccess) return hip_status(e);
     if (st != OS_OK) return st;
-    if ((st = os_gram_configure(plan, best_tile, 0, workspace, ws_bytes, stream)) != OS_OK)
+    if ((st = os_gram_configure(plan, best_tile, best_grid, workspace, ws_bytes, stream)) != OS_OK)
         return st;
+    if (count) *count = n;
     if (best_ms) *best_ms = best;
     return OS_OK;
+}
+
+os_status os_gram_autotune(os_gram_plan* plan, int32_t reps, void* workspace, size_t ws_bytes,
+                           void* stream, float* best_ms) {
+    return os_gram_autotune_ex(plan, reps, workspace, ws_bytes, stream, nullptr, 0, nullptr,
+                               best_ms);
 }
 
 os_status os_gram_graph_create(const os_gram_plan* plan, int stages, void* workspace,

@@ -210,12 +210,15 @@ struct BatchProblem {
 // tiles DEVICE int4 {problem, tile row, tile col >= tile row, 0} for tile
 // side `tile` (256 or 128), grouped by workgroup: workgroup g computes tiles
 // starts[g] .. starts[g+1] - 1 (starts DEVICE [grid + 1]).  full != 0 also
-// writes the mirror of each off-diagonal tile.
+// writes the mirror of each off-diagonal tile.  tile = OS_GRAM_MIXED: the
+// list holds jobs of two int4 each, {problem, kind, tile row, tile col} and
+// {second tile row, second tile col, has second, 0}: kind 0 one 256 tile,
+// kind 1 one or two 128 tiles of the problem; starts count jobs.
 hipError_t launch_gemm_batch_sym(const BatchProblem* probs, const int4* tiles,
                                  const int32_t* starts, int tile, int full, int32_t grid,
                                  hipStream_t s);
-// Workgroups of the batched kernel with tile side `tile` that fit on one CU
-// at once (0 on error).
+// Workgroups of the batched kernel for `tile` (256, 128 or OS_GRAM_MIXED)
+// that fit on one CU at once (0 on error).
 int batch_sym_blocks_per_cu(int tile);
 
 // BF16 copy of a line-major FP32 sketch (lines x nst*bp, ld lds): block

@@ -17,13 +17,16 @@ import ctypes
 
 import numpy as np
 
-from . import (OversketchError, _GramProblem, _check, _mask, _ptr, _require_cuda, _row_major,
-               _sketch, _stream, _torch, lib)
+from . import (OversketchError, _GramCandidate, _GramProblem, _check, _mask, _ptr, _require_cuda,
+               _row_major, _sketch, _stream, _torch, lib)
 
 
 # stages of a run (OS_GRAM_* in oversketch.h)
 PREPARE, SKETCH, PRODUCT = 1, 2, 4
 ALL = PREPARE | SKETCH | PRODUCT
+# tile form: 256 tiles inside each triangle, pairs of 128 tiles along its
+# diagonal and ragged edge (OS_GRAM_MIXED)
+MIXED = 1
 
 
 class GramGraph:
@@ -59,13 +62,14 @@ class GramBatch:
     (default k); keeps: per problem a host mask over N+e blocks or None
     (= blocks [0, N)); full: write H whole (else only the tiles on or above
     the diagonal); out: optional list of CUDA float32 m_k x m_k tensors.
-    The plan is configured with tile side `tile` (128 or 256) and `grid`
-    persistent workgroups (0 = the device's resident count); ``autotune()``
-    picks the tile side by timing.
+    The plan is configured with tile form `tile` (256, 128 or MIXED: 256
+    tiles inside each triangle, pairs of 128 tiles along its diagonal and
+    ragged edge) and `grid` persistent workgroups (0 = the device's resident
+    count); ``autotune()`` picks the form and grid by timing.
     """
 
     def __init__(self, A_list, d_list=None, b=None, N=6, e=1, seeds=None, keeps=None, full=True,
-                 out=None, tile=256, grid=0, hs=None, sigmas=None, stream=None):
+                 out=None, tile=MIXED, grid=0, hs=None, sigmas=None, stream=None):
         torch = _torch()
         count = len(A_list)
         if count < 1:
@@ -140,23 +144,30 @@ class GramBatch:
 
     @property
     def config(self):
-        """(tile side, grid) of the current configuration."""
+        """(tile form, grid) of the current configuration."""
         t, g = ctypes.c_int32(), ctypes.c_int32()
         lib().os_gram_config(self._plan, ctypes.byref(t), ctypes.byref(g))
         return t.value, g.value
 
-    def configure(self, tile=256, grid=0, stream=None):
+    def configure(self, tile=MIXED, grid=0, stream=None):
         plan, ws, nb = self._args()
         _check(lib().os_gram_configure(plan, int(tile), int(grid), ws, nb, _stream(stream)),
                "os_gram_configure")
 
     def autotune(self, reps=2, stream=None) -> float:
-        """Times each tile side (runs the batch) and keeps the fastest;
-        returns its average milliseconds per run."""
+        """Times the product for each tile form and grid (after one run of
+        the earlier stages) and keeps the fastest; returns its average
+        milliseconds per product run.  The timings are left in
+        ``self.candidates`` as (tile, grid, ms) tuples."""
         plan, ws, nb = self._args()
         ms = ctypes.c_float()
-        _check(lib().os_gram_autotune(plan, int(reps), ws, nb, _stream(stream), ctypes.byref(ms)),
-               "os_gram_autotune")
+        cap = 16
+        cands = (_GramCandidate * cap)()
+        count = ctypes.c_int32()
+        _check(lib().os_gram_autotune_ex(plan, int(reps), ws, nb, _stream(stream), cands, cap,
+                                         ctypes.byref(count), ctypes.byref(ms)),
+               "os_gram_autotune_ex")
+        self.candidates = [(c.tile, c.grid, float(c.ms)) for c in cands[:min(count.value, cap)]]
         return float(ms.value)
 
     # -- execution --------------------------------------------------------

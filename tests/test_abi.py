@@ -275,7 +275,16 @@ def test_gram_workspace_and_unconfigured_plan(L):
     assert L.os_gram_configure(h1, 64, 0, ws, w1, None) == OS_EINVAL
     assert L.os_gram_configure(h1, 256, -1, ws, w1, None) == OS_EINVAL
     assert L.os_gram_configure(h1, 256, 1 << 20, ws, w1, None) == OS_EINVAL
+    assert L.os_gram_configure(h1, 2, 0, ws, w1, None) == OS_EINVAL   # not a tile form
+    assert L.os_gram_configure(h1, -1, 0, ws, w1, None) == OS_EINVAL
     assert L.os_gram_autotune(h1, 0, ws, w1, None, None) == OS_EINVAL
+    n = ctypes.c_int32(9)
+    assert L.os_gram_autotune_ex(h1, 0, ws, w1, None, None, 0, ctypes.byref(n), None) == OS_EINVAL
+    assert n.value == 0
+    assert L.os_gram_autotune_ex(h1, 1, ws, w1, None, None, -1, None, None) == OS_EINVAL
+    assert L.os_gram_autotune_ex(h1, 1, ws, w1, None, None, 4, None, None) == OS_EINVAL
+    assert L.os_gram_autotune_ex(None, 1, ws, w1, None, None, 0, None, None) == OS_ENULL
+    assert L.os_gram_autotune_ex(h1, 1, ws, w1 - 1, None, None, 0, None, None) == OS_EWORKSPACE
     g = ctypes.c_void_p(5)
     assert L.os_gram_graph_create(h1, 7, ws, w1, ctypes.c_void_p(1), ctypes.byref(g)) == OS_EINVAL
     assert not g.value

@@ -65,7 +65,12 @@ SPECS = [
 ]
 
 
-@pytest.mark.parametrize("tile", [256, 128])
+MIXED = osk.gram.MIXED
+# side of the tiles whose upper triangle is written when full = 0
+WRITTEN_SIDE = {256: 256, 128: 128, MIXED: 128}
+
+
+@pytest.mark.parametrize("tile", [256, 128, MIXED])
 @pytest.mark.parametrize("full", [True, False])
 def test_gram_batch_vs_oracle(tile, full):
     probs = _problems(SPECS, 11)
@@ -81,11 +86,42 @@ def test_gram_batch_vs_oracle(tile, full):
             assert np.max(np.abs(H - H.T)) <= 1e-6 * np.abs(ref).max()
         else:
             # tiles on or above the diagonal are written, the others untouched
-            ti = np.arange(m)[:, None] // tile
-            tj = np.arange(m)[None, :] // tile
+            side = WRITTEN_SIDE[tile]
+            ti = np.arange(m)[:, None] // side
+            tj = np.arange(m)[None, :] // side
             upper = ti <= tj
             assert np.all(H[~upper] == -7.0)
             assert oracle.rel_frob(np.where(upper, H, 0), np.where(upper, ref, 0)) <= TOL
+
+
+# sizes around the 128 and 256 tile boundaries: a diagonal 256 tile of one,
+# two or three 128 tiles, last tile columns of at most and of more than 128
+# columns, an odd count of 128 tiles (one unpaired)
+EDGE_M = [1, 100, 128, 129, 200, 255, 256, 257, 300, 383, 384, 385, 511, 512, 513, 640, 700]
+
+
+@pytest.mark.parametrize("full", [True, False])
+def test_gram_batch_mixed_tile_edges(full):
+    specs = [(m, 64 * (1 + k % 3), 32, 2, 1, 1) for k, m in enumerate(EDGE_M)]
+    probs = _problems(specs, 15)
+    outs = [torch.full((p[0].shape[0], p[0].shape[0]), -7.0, device="cuda") for p in probs]
+    gb = _batch(probs, full=full, out=outs, tile=MIXED)
+    mixed = [host(h) for h in gb.run()]
+    gb.configure(256)
+    whole = [host(h.clone()) for h in gb.run()]
+    gb.close()
+    for p, H, W in zip(probs, mixed, whole):
+        ref = _oracle(p)
+        m = ref.shape[0]
+        upper = (np.arange(m)[:, None] // 128) <= (np.arange(m)[None, :] // 128)
+        if full:
+            assert oracle.rel_frob(H, ref) <= TOL, (m, oracle.rel_frob(H, ref))
+            assert np.array_equal(H, H.T), m
+            # the same dot products in the same K order as the 256 form
+            assert oracle.rel_frob(H, W) <= 1e-6, m
+        else:
+            assert np.all(H[~upper] == -7.0), m
+            assert oracle.rel_frob(np.where(upper, H, 0), np.where(upper, ref, 0)) <= TOL, m
 
 
 def test_gram_batch_unweighted_equals_sketched_product():
@@ -118,7 +154,13 @@ def test_gram_batch_autotune_reuse_and_graph_replays():
     gb = _batch(probs, tile=256)
     eager = [host(h) for h in gb.run()]
     ms = gb.autotune(reps=1)
-    assert ms > 0 and gb.config[0] in (128, 256)
+    assert ms > 0 and gb.config[0] in (MIXED, 128, 256)
+    # tile form x grid: three forms, each at one and two times the resident grid
+    cands = gb.candidates
+    assert len(cands) == 6 and sorted({c[0] for c in cands}) == sorted([MIXED, 128, 256])
+    assert all(c[2] > 0 for c in cands)
+    best = min(cands, key=lambda c: c[2])
+    assert ms == best[2] and gb.config == (best[0], best[1])
     tuned = [host(h) for h in gb.run()]
     for a, b in zip(eager, tuned):
         assert oracle.rel_frob(b, a) <= 1e-6
