@@ -29,6 +29,7 @@
 // permutation of the offset, see win_slot) and the sign (bit 15); the
 // padding entry points at a zero row.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 #include "fp8.h"
@@ -42,7 +43,8 @@ constexpr int kThreads = 512;          // 8 waves
 constexpr int kWaves = kThreads / 64;
 constexpr int kPerThread = kWin / kThreads;   // window positions staged per thread (16)
 constexpr uint16_t kPad = (uint16_t)kWin;     // entry of the zero row, positive
-constexpr int kAhead = 3;              // list chunks of the next slot fetched ahead
+constexpr int kAhead = 3;              // list chunks of a slot fetched ahead
+constexpr int kDist = 1;               // slots ahead whose lists are fetched
 
 // LDS slot of window position p (p < kWin).  Thread t stages the quads of
 // positions 2048u + 4t + j (j < 4); they go to slots 2048u + 512j + t, so the
@@ -50,6 +52,16 @@ constexpr int kAhead = 3;              // list chunks of the next slot fetched a
 // slot of their position.
 __device__ __forceinline__ int win_slot(int p) {
     return (p & ~2047) | ((p & 3) << 9) | ((p >> 2) & 511);
+}
+
+// f(integral_constant<int, I>) for I = B .. E - 1, unrolled by the compiler
+// whatever the size of f's body.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
 }
 
 // Spread consecutive task ids over the 8 XCDs in contiguous runs: task T is
@@ -556,11 +568,15 @@ struct RawQuad<__bf16> {
     }
 };
 
+// Loads pieces p0 .. p1 - 1 of a window (piece 4u + q: r[4q + u] of row
+// lines with w[u] at q = 0, r[4u + q] of column lines); all 16 pieces make
+// the window.  p0 and p1 are constants where the caller is unrolled.
 template <bool kRowLines, bool kWeighted, typename TI>
 __device__ __forceinline__ void load_window(typename RawQuad<TI>::type (&r)[kPerThread],
                                             float4 (&w)[4], const TI* __restrict__ X,
                                             int64_t lines, int64_t ldx, int64_t line0, int64_t k0,
-                                            int kw, bool vec, const float* __restrict__ wd) {
+                                            int kw, bool vec, const float* __restrict__ wd,
+                                            int p0 = 0, int p1 = kPerThread) {
     using R = RawQuad<TI>;
     static_assert(kRowLines || sizeof(TI) == 4, "column lines are read as FP32 only");
     // Every load is unconditional (a branch around a load makes each use wait
@@ -574,20 +590,26 @@ __device__ __forceinline__ void load_window(typename RawQuad<TI>::type (&r)[kPer
     if constexpr (kRowLines) {
         const int64_t dl[4] = {0, l1, l2, l3};
         if (vec) {
-            // kw is a multiple of 4 here: the last whole quad starts at kw - 4
+            // kw is a multiple of 4 here: the last whole quad starts at kw - 4.
+            // Uniform line bases plus a 32-bit lane offset (scalar-base
+            // addressing: a piece issued late keeps one offset register live,
+            // not a 64-bit address).
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int64_t kk = k0 + min(4 * tid + 2048 * u, kw - 4);
+                const uint32_t off = (uint32_t)min(4 * tid + 2048 * u, kw - 4);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
+                    if (4 * u + q < p0 || 4 * u + q >= p1) continue;
+                    const TI* base = X + (line0 + dl[q]) * ldx + k0;
                     // (the FP32 load written here, not through R::load: through the
                     // helper the FP32 kernels took 20 more registers and spilled)
                     if constexpr (sizeof(TI) == 4)
-                        r[4 * q + u] = load_stream(X + (line0 + dl[q]) * ldx + kk);
+                        r[4 * q + u] = load_stream(base + off);
                     else
-                        r[4 * q + u] = R::load(X + (line0 + dl[q]) * ldx + kk);
+                        r[4 * q + u] = R::load(base + off);
+                    if constexpr (kWeighted)
+                        if (q == 0) w[u] = load_stream(wd + k0 + off);
                 }
-                if constexpr (kWeighted) w[u] = load_stream(wd + kk);
             }
         } else {
 #pragma unroll
@@ -596,8 +618,12 @@ __device__ __forceinline__ void load_window(typename RawQuad<TI>::type (&r)[kPer
 #pragma unroll
                 for (int j = 0; j < 4; ++j) kk[j] = k0 + min(4 * tid + 2048 * u + j, kw - 1);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) r[4 * q + u] = R::gather(X + (line0 + dl[q]) * ldx, kk);
-                if constexpr (kWeighted) w[u] = make_float4(wd[kk[0]], wd[kk[1]], wd[kk[2]], wd[kk[3]]);
+                for (int q = 0; q < 4; ++q) {
+                    if (4 * u + q < p0 || 4 * u + q >= p1) continue;
+                    r[4 * q + u] = R::gather(X + (line0 + dl[q]) * ldx, kk);
+                    if constexpr (kWeighted)
+                        if (q == 0) w[u] = make_float4(wd[kk[0]], wd[kk[1]], wd[kk[2]], wd[kk[3]]);
+                }
             }
         }
     } else {
@@ -606,6 +632,7 @@ __device__ __forceinline__ void load_window(typename RawQuad<TI>::type (&r)[kPer
         for (int u = 0; u < 4; ++u) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
+                if (4 * u + j < p0 || 4 * u + j >= p1) continue;
                 const int64_t kk = k0 + min(4 * tid + 2048 * u + j, kw - 1);
                 const TI* p = X + kk * ldx + line0;
                 if (vec && l3 == 3)      // uniform
@@ -685,7 +712,7 @@ __device__ __forceinline__ void add_chunk(float4& acc, const float4* __restrict_
 
 // One workgroup of 8 waves fills a CU's LDS, so each SIMD runs 2 waves: the
 // compiler may use up to 256 VGPRs per lane.
-template <int kSlots, bool kRowLines, bool kWeighted, typename TI, bool kFp8Out = false>
+template <int kSlots, bool kRowLines, bool kWeighted, typename TI, bool kFp8Out, bool kSpread>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void sketch_kernel(
     const TI* __restrict__ X, int64_t lines, int64_t n, int64_t ldx, int vec, int32_t bp,
@@ -762,7 +789,7 @@ void sketch_kernel(
         stage_window<kRowLines, kWeighted, TI>(win, pre, wpre);
         __syncthreads();
         const uint32_t hv = hnext;       // this window's headers (lane s: slot s)
-        // The list chunks of slot s + 1 (up to kAhead of them) are fetched
+        // The list chunks of slot s + kDist (up to kAhead of them) are fetched
         // while slot s is summed.  Fetches are unconditional: chunk indices
         // past a slot's count repeat its last chunk, and an unused slot
         // (header 0) reads chunk 0 of block 0's region (never summed).
@@ -778,53 +805,64 @@ void sketch_kernel(
 #pragma unroll
             for (int c = 0; c < kAhead; ++c) d[c] = p[(int64_t)min((uint32_t)c, last) * 64];
         };
-        // The lists of slots 0 and 1 are fetched before the next window's
-        // values: a wave's loads complete in order, so a list fetched after
-        // them would wait for them.
-        uint4 cur[kAhead], nxt[kAhead];
-        uint32_t ncur, nnxt = 0;
-        const uint4* pcur = slot_list(0, ncur);
-        const uint4* pnxt = pcur;
-        fetch(cur, pcur, ncur);
-        if (kSlots > 1) {
-            pnxt = slot_list(1, nnxt);
-            fetch(nxt, pnxt, nnxt);
-        }
-        // the next window (this task's, else the first of the next task) and
-        // its headers
+        // The next window (this task's, else the first of the next task) is
+        // loaded in kPerThread pieces spread over the slots, each issued
+        // after the list fetch of its slot: a wave's loads complete in
+        // order, so waiting for slot s's list waits only for pieces issued
+        // kDist or more slots earlier, not for the whole window.  When no
+        // window follows, the pieces read one quad of this window again
+        // (every lane the same address; loads stay unconditional).
         int64_t l1 = line0, k1 = (int64_t)(w + 1) * kWin;
         int32_t hb1 = meta.hb;
-        bool more = true;
-        if (w + 1 == nwin) {
-            more = it + gridDim.x < tasks;
-            if (more) {
-                hb1 = meta_of(it + gridDim.x).hb;
-                l1 = line_of(it + gridDim.x);
-            }
+        int kw1;
+        if (w + 1 < nwin) {
+            kw1 = (int)min((int64_t)kWin, n - k1);
+        } else if (it + gridDim.x < tasks) {
+            hb1 = meta_of(it + gridDim.x).hb;
+            l1 = line_of(it + gridDim.x);
             k1 = 0;
+            kw1 = (int)min((int64_t)kWin, n);
+        } else {
+            k1 = (int64_t)w * kWin;
+            kw1 = (int)min((int64_t)4, n - k1);
         }
-        if (more) {
-            hnext = headers(hb1, (int)(k1 / kWin));
-            load_window<kRowLines, kWeighted, TI>(pre, wpre, X, lines, ldx, l1, k1,
-                                                  (int)min((int64_t)kWin, n - k1), vec_at(k1), wd);
-        }
+        const bool vec1 = vec_at(k1) && kw1 >= 4;
+        constexpr int kRing = kDist + 1;
+        uint4 lst[kRing][kAhead];
+        uint32_t nls[kRing];
+        const uint4* pls[kRing];
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            if (s >= 1 && s + 1 < kSlots) {
-                pnxt = slot_list(s + 1, nnxt);
-                fetch(nxt, pnxt, nnxt);
+        for (int s = 0; s < kDist && s < kSlots; ++s) {
+            pls[s] = slot_list(s, nls[s]);
+            fetch(lst[s], pls[s], nls[s]);
+        }
+        hnext = headers(hb1, (int)(k1 / kWin));
+        constexpr int kSpreadSlots = kSlots < kPerThread ? kSlots : kPerThread;
+        constexpr int kPer = (kPerThread + kSpreadSlots - 1) / kSpreadSlots;
+        // (unrolled at compile time: acc[s] and the ring stay in registers
+        // however large the body)
+        static_for<0, kSlots>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            if constexpr (s + kDist < kSlots) {
+                constexpr int r = (s + kDist) % kRing;
+                pls[r] = slot_list(s + kDist, nls[r]);
+                fetch(lst[r], pls[r], nls[r]);
             }
+            if constexpr (kSpread) {
+                if constexpr (s < kSpreadSlots)
+                    load_window<kRowLines, kWeighted, TI>(
+                        pre, wpre, X, lines, ldx, l1, k1, kw1, true, wd, s * kPer,
+                        (s + 1) * kPer < kPerThread ? (s + 1) * kPer : kPerThread);
+            } else if constexpr (s == 0) {
+                load_window<kRowLines, kWeighted, TI>(pre, wpre, X, lines, ldx, l1, k1, kw1, vec1,
+                                                      wd);
+            }
+            constexpr int r = s % kRing;
 #pragma unroll
             for (int c = 0; c < kAhead; ++c)
-                if ((uint32_t)c < ncur) add_chunk(acc[s], win, cur[c]);
-            for (uint32_t c = kAhead; c < ncur; ++c) add_chunk(acc[s], win, pcur[(int64_t)c * 64]);
-            if (s + 1 < kSlots) {
-#pragma unroll
-                for (int c = 0; c < kAhead; ++c) cur[c] = nxt[c];
-                ncur = nnxt;
-                pcur = pnxt;
-            }
-        }
+                if ((uint32_t)c < nls[r]) add_chunk(acc[s], win, lst[r][c]);
+            for (uint32_t c = kAhead; c < nls[r]; ++c) add_chunk(acc[s], win, pls[r][(int64_t)c * 64]);
+        });
     }
 
     // Output: FP32 (omode 0, blocks obp = bp apart), or the copy the block
@@ -891,15 +929,26 @@ void sketch_kernel(
 // Slot counts compiled: 1, 2, 4, 8, 12, 16, 20, 24 (4 registers per slot).
 constexpr int kMaxSlots = 24;
 
+// spread (row lines only): every window is loaded with 16-byte row loads
+// (vec and n a multiple of 4), so the next window's loads can be spread over
+// the slots (kSpread).
 template <int S, bool R, bool W, typename TI, bool Q8>
-hipError_t launch_one(dim3 grid, hipStream_t st, const TI* X, int64_t lines, int64_t n,
-                      int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin, int32_t nst,
-                      const BlockList& bl, int64_t RC, const uint32_t* hdr, const uint4* ell,
-                      void* out, int64_t ldo, int32_t npass, const float* wd, int32_t obp,
-                      int32_t omode, int64_t ozlo) {
-    hipLaunchKernelGGL((sketch_kernel<S, R, W, TI, Q8>), grid, dim3(kThreads), 0, st, X, lines, n,
-                       ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass, wd, obp,
-                       omode, ozlo);
+hipError_t launch_one(dim3 grid, hipStream_t st, bool spread, const TI* X, int64_t lines,
+                      int64_t n, int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin,
+                      int32_t nst, const BlockList& bl, int64_t RC, const uint32_t* hdr,
+                      const uint4* ell, void* out, int64_t ldo, int32_t npass, const float* wd,
+                      int32_t obp, int32_t omode, int64_t ozlo) {
+    if constexpr (R) {
+        if (spread) {
+            hipLaunchKernelGGL((sketch_kernel<S, R, W, TI, Q8, true>), grid, dim3(kThreads), 0, st,
+                               X, lines, n, ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out,
+                               ldo, npass, wd, obp, omode, ozlo);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((sketch_kernel<S, R, W, TI, Q8, false>), grid, dim3(kThreads), 0, st, X,
+                       lines, n, ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass,
+                       wd, obp, omode, ozlo);
     return hipGetLastError();
 }
 
@@ -909,10 +958,12 @@ hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const TI* X, int64
                         int32_t nst, const BlockList& bl, int64_t RC, const uint32_t* hdr,
                         const uint4* ell, void* out, int64_t ldo, int32_t npass,
                         const float* wd, int32_t obp, int32_t omode, int64_t ozlo) {
+    const bool spread = R && vec && (n & 3) == 0;
 #define OSK_SLOT_CASE(S)                                                                        \
     if (slots <= S)                                                                             \
-        return launch_one<S, R, W, TI, Q8>(grid, st, X, lines, n, ldx, vec, bp, qn, nwin, nst, bl, \
-                                       RC, hdr, ell, out, ldo, npass, wd, obp, omode, ozlo);
+        return launch_one<S, R, W, TI, Q8>(grid, st, spread, X, lines, n, ldx, vec, bp, qn, nwin, \
+                                           nst, bl, RC, hdr, ell, out, ldo, npass, wd, obp, omode, \
+                                           ozlo);
     OSK_SLOT_CASE(1)
     OSK_SLOT_CASE(2)
     OSK_SLOT_CASE(4)
