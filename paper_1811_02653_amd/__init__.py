@@ -307,8 +307,10 @@ OS_PREPARE_GROUPED = 1
 def sketch_prepare(n, b, N, e, seed=0, h=None, sigma=None, device="cuda", stream=None,
                    grouped=False):
     """Prepared sketch (opaque uint8 device buffer) for an n-long sketched
-    dimension.  grouped=True: the library's bucket order within each block
-    (see bucket_order), as the whole-path calls use."""
+    dimension.  grouped=True: buckets of similar list lengths share the
+    sketch kernel's 64-bucket groups (fewer padding entries); the sketch's
+    columns then hold each block's buckets in bucket_order.  The whole-path
+    calls prepare in the natural order."""
     torch = _torch()
     s = _sketch(b, N, e, seed, h, sigma, n)
     nbytes = int(lib().os_sketch_prepare_bytes(ctypes.byref(s), n))
