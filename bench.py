@@ -496,9 +496,10 @@ def profile_stage(torch, osk, args, A, B, C, ws, keep, stream):
         "sketch_A": lambda: osk.sketch_cols(A, b, N, e, seed=args.seed, keep=keep,
                                             kept_only=args.kept_only, prep=prep, out=At,
                                             stream=stream),
+        # B's columns read in place, as the whole path does for this B
         "sketch_B": lambda: osk.sketch_rows(B, b, N, e, seed=args.seed, keep=keep,
                                             kept_only=args.kept_only, prep=prep, out=Bt,
-                                            workspace=tws, stream=stream),
+                                            workspace=None, stream=stream),
         "gemm": lambda: osk.gemm_kept(At, Bt, b, keep=stored_keep, out=C, stream=stream),
         "gemm_bf16": lambda: osk.gemm_kept_prec(QA, QB, b, nst, precision="bf16",
                                                 keep=stored_keep, out=C, stream=stream),
@@ -602,10 +603,16 @@ def main():
                                                         kept_only=args.kept_only, prep=prep,
                                                         out=At, stream=stream),
                         reps, stream)
+    # B's columns read in place (the whole path's form for a 16-byte-aligned
+    # FP32 B with l and ldb multiples of 4), and transposed first, for reference
     t_sb = event_time_ms(torch, lambda: osk.sketch_rows(B, b, N, e, seed=args.seed, keep=keep,
                                                         kept_only=args.kept_only, prep=prep,
-                                                        out=Bt, workspace=tws, stream=stream),
+                                                        out=Bt, workspace=None, stream=stream),
                         reps, stream)
+    t_sb_tr = event_time_ms(torch, lambda: osk.sketch_rows(B, b, N, e, seed=args.seed, keep=keep,
+                                                           kept_only=args.kept_only, prep=prep,
+                                                           out=Bt, workspace=tws, stream=stream),
+                            reps, stream)
     t_gemm = event_time_ms(torch, lambda: osk.gemm_kept(At, Bt, b, keep=stored_keep, out=C,
                                                         stream=stream), reps, stream)
     gemm_flops = 2.0 * m * l * K * bp
@@ -613,8 +620,8 @@ def main():
     sketch_entries_a = (m + 3) // 4 * float(n) * nst     # real list entries (4 lines each)
     sketch_bytes_a = 4.0 * (m * n + m * nst * bp)
     sketch_bytes_b = 4.0 * (n * l + l * nst * bp)
-    log("stages: prepare %.3f, sketch A %.3f, sketch B %.3f, gemm %.3f ms" %
-        (t_prep, t_sa, t_sb, t_gemm))
+    log("stages: prepare %.3f, sketch A %.3f, sketch B %.3f (transposed first %.3f), gemm %.3f ms" %
+        (t_prep, t_sa, t_sb, t_sb_tr, t_gemm))
 
     # ---- accuracy against the exact FP64 product (computed on the GPU)
     step()
@@ -979,7 +986,8 @@ def main():
             "avg_launch_ms": t_gemm,
         },
         "cpu_baseline": cpu,
-        "stages_ms": {"prepare": t_prep, "sketch_A": t_sa, "sketch_B": t_sb, "gemm": t_gemm},
+        "stages_ms": {"prepare": t_prep, "sketch_A": t_sa, "sketch_B": t_sb, "gemm": t_gemm,
+                      "sketch_B_transposed_first": t_sb_tr},
         "sketch_roofline": {
             "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
             "list_entries_walked_per_real": walked / real,

@@ -428,7 +428,11 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
     // An operand's lines (rows of A, columns of B) are sketched as rows in
     // memory: a column-major A and a row-major B are transposed first (in
     // their own type), so that every sketch reads whole lines (16-byte
-    // requests along a column would each bring in a separate cache line).
+    // requests along a column would each bring in a separate cache line) --
+    // except an FP32 row-major B whose columns the sketch can read with
+    // 16-byte loads and its window spread over the slots
+    // (sketch_rows_in_place_ok), which is faster read in place than
+    // transposed (no fused FP8 copy in that form; the sums are the same).
     // BF16 values are converted exactly to FP32 as the sketch stages them.
     // With a BF16 block product the sketch writes its BF16 copy directly
     // (rounded in the sketch's epilogue, bit for bit what the quantization
@@ -445,6 +449,16 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
                             int64_t ldx, float* out, void* qout) -> os_status {
         const void* Xl = X;
         int64_t ldl = ldx;
+        if (transpose && dtype == OS_DTYPE_F32 && !fp8_fused &&
+            osk::sketch_rows_in_place_ok(static_cast<const float*>(X), lines, ldx)) {
+            const float* Xf = static_cast<const float*>(X);
+            if (bf16_product)
+                return hip_status(osk::launch_sketch_rows_q(Xf, n, lines, ldx, bs.stored, bs.nst,
+                                                            nblocks(sk), bp, lists, qout, wq,
+                                                            is_split(precision), s));
+            return hip_status(osk::launch_sketch_rows(Xf, n, lines, ldx, bs.stored, bs.nst,
+                                                      nblocks(sk), bp, lists, out, zs, s));
+        }
         if (transpose) {
             ldl = osk::round_up(n, 4);
             const hipError_t e =
@@ -544,16 +558,24 @@ os_status os_matmul_cmask(const os_sketch* sk, const float* A, int64_t lda, cons
     if ((st = hip_status(osk::launch_sketch_cols(A, m, n, lda, bs.stored, bs.nst, nblocks(sk), bp,
                                                  lists, At, zs, s))) != OS_OK)
         return st;
-    const float* Bl = B;
-    int64_t ldl = ldb;
-    if (!b_col_major) {
-        ldl = osk::round_up(n, 4);
-        if ((st = hip_status(osk::launch_transpose(B, n, l, ldb, Bx, ldl, s))) != OS_OK) return st;
-        Bl = Bx;
+    if (!b_col_major && osk::sketch_rows_in_place_ok(B, l, ldb)) {
+        // B's columns read in place (faster than transposed, same sums)
+        if ((st = hip_status(osk::launch_sketch_rows(B, n, l, ldb, bs.stored, bs.nst, nblocks(sk),
+                                                     bp, lists, Bt, zs, s))) != OS_OK)
+            return st;
+    } else {
+        const float* Bl = B;
+        int64_t ldl = ldb;
+        if (!b_col_major) {
+            ldl = osk::round_up(n, 4);
+            if ((st = hip_status(osk::launch_transpose(B, n, l, ldb, Bx, ldl, s))) != OS_OK)
+                return st;
+            Bl = Bx;
+        }
+        if ((st = hip_status(osk::launch_sketch_cols(Bl, l, n, ldl, bs.stored, bs.nst,
+                                                     nblocks(sk), bp, lists, Bt, zs, s))) != OS_OK)
+            return st;
     }
-    if ((st = hip_status(osk::launch_sketch_cols(Bl, l, n, ldl, bs.stored, bs.nst, nblocks(sk), bp,
-                                                 lists, Bt, zs, s))) != OS_OK)
-        return st;
     return hip_status(osk::launch_gemm_cmask(At, zs, Bt, zs, m, l, bp, bs.nst, cmask, sk->b, C,
                                              ldc, s));
 }

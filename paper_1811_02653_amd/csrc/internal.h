@@ -116,6 +116,16 @@ bool plan_sketch_ok(int64_t lines, int32_t nst, int32_t bp, int64_t n);
 hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t ldx,
                               const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
                               const void* lists, float* out, int64_t ldo, hipStream_t s);
+// True when launch_sketch_rows reads X's columns with 16-byte loads and the
+// next window spread over the slots (X 16-byte aligned, ldx and cols
+// multiples of 4): then reading them in place is faster than transposing X
+// first and sketching the rows of X^T (the sums are the same, bit for bit).
+bool sketch_rows_in_place_ok(const float* X, int64_t cols, int64_t ldx);
+// launch_sketch_rows writing the BF16 copy, as launch_sketch_cols_q.
+hipError_t launch_sketch_rows_q(const float* X, int64_t n, int64_t cols, int64_t ldx,
+                                const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
+                                const void* lists, void* out, int64_t ldo, int split,
+                                hipStream_t s);
 // out (rows x nst*bp, ld ldo) = X S for X rows x n row-major (ld ldx);
 // with wd (DEVICE [n]) it is X diag(sqrt(wd)) S.
 hipError_t launch_sketch_cols(const float* X, int64_t rows, int64_t n, int64_t ldx,

@@ -571,7 +571,7 @@ struct RawQuad<__bf16> {
 // Loads pieces p0 .. p1 - 1 of a window (piece 4u + q: r[4q + u] of row
 // lines with w[u] at q = 0, r[4u + q] of column lines); all 16 pieces make
 // the window.  p0 and p1 are constants where the caller is unrolled.
-template <bool kRowLines, bool kWeighted, typename TI>
+template <bool kRowLines, bool kWeighted, typename TI, bool kWhole = false>
 __device__ __forceinline__ void load_window(typename RawQuad<TI>::type (&r)[kPerThread],
                                             float4 (&w)[4], const TI* __restrict__ X,
                                             int64_t lines, int64_t ldx, int64_t line0, int64_t k0,
@@ -635,7 +635,9 @@ __device__ __forceinline__ void load_window(typename RawQuad<TI>::type (&r)[kPer
                 if (4 * u + j < p0 || 4 * u + j >= p1) continue;
                 const int64_t kk = k0 + min(4 * tid + 2048 * u + j, kw - 1);
                 const TI* p = X + kk * ldx + line0;
-                if (vec && l3 == 3)      // uniform
+                if constexpr (kWhole)    // vec and every line group whole
+                    r[4 * u + j] = *reinterpret_cast<const float4*>(p);
+                else if (vec && l3 == 3)      // uniform
                     r[4 * u + j] = *reinterpret_cast<const float4*>(p);
                 else
                     r[4 * u + j] = make_float4(p[0], p[l1], p[l2], p[l3]);
@@ -850,7 +852,7 @@ void sketch_kernel(
             }
             if constexpr (kSpread) {
                 if constexpr (s < kSpreadSlots)
-                    load_window<kRowLines, kWeighted, TI>(
+                    load_window<kRowLines, kWeighted, TI, true>(
                         pre, wpre, X, lines, ldx, l1, k1, kw1, true, wd, s * kPer,
                         (s + 1) * kPer < kPerThread ? (s + 1) * kPer : kPerThread);
             } else if constexpr (s == 0) {
@@ -929,22 +931,21 @@ void sketch_kernel(
 // Slot counts compiled: 1, 2, 4, 8, 12, 16, 20, 24 (4 registers per slot).
 constexpr int kMaxSlots = 24;
 
-// spread (row lines only): every window is loaded with 16-byte row loads
-// (vec and n a multiple of 4), so the next window's loads can be spread over
-// the slots (kSpread).
+// spread: every window is loaded with 16-byte loads -- row lines with vec
+// and n a multiple of 4, column lines with vec and every group of 4 lines
+// whole -- so the next window's loads can be spread over the slots
+// (kSpread).
 template <int S, bool R, bool W, typename TI, bool Q8>
 hipError_t launch_one(dim3 grid, hipStream_t st, bool spread, const TI* X, int64_t lines,
                       int64_t n, int64_t ldx, int vec, int32_t bp, int32_t qn, int32_t nwin,
                       int32_t nst, const BlockList& bl, int64_t RC, const uint32_t* hdr,
                       const uint4* ell, void* out, int64_t ldo, int32_t npass, const float* wd,
                       int32_t obp, int32_t omode, int64_t ozlo) {
-    if constexpr (R) {
-        if (spread) {
-            hipLaunchKernelGGL((sketch_kernel<S, R, W, TI, Q8, true>), grid, dim3(kThreads), 0, st,
-                               X, lines, n, ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out,
-                               ldo, npass, wd, obp, omode, ozlo);
-            return hipGetLastError();
-        }
+    if (spread) {
+        hipLaunchKernelGGL((sketch_kernel<S, R, W, TI, Q8, true>), grid, dim3(kThreads), 0, st, X,
+                           lines, n, ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo,
+                           npass, wd, obp, omode, ozlo);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL((sketch_kernel<S, R, W, TI, Q8, false>), grid, dim3(kThreads), 0, st, X,
                        lines, n, ldx, vec, bp, qn, nwin, nst, bl, RC, hdr, ell, out, ldo, npass,
@@ -958,7 +959,7 @@ hipError_t launch_slots(int slots, dim3 grid, hipStream_t st, const TI* X, int64
                         int32_t nst, const BlockList& bl, int64_t RC, const uint32_t* hdr,
                         const uint4* ell, void* out, int64_t ldo, int32_t npass,
                         const float* wd, int32_t obp, int32_t omode, int64_t ozlo) {
-    const bool spread = R && vec && (n & 3) == 0;
+    const bool spread = vec && (R ? (n & 3) == 0 : (lines & 3) == 0);
 #define OSK_SLOT_CASE(S)                                                                        \
     if (slots <= S)                                                                             \
         return launch_one<S, R, W, TI, Q8>(grid, st, spread, X, lines, n, ldx, vec, bp, qn, nwin, \
@@ -1302,6 +1303,19 @@ hipError_t launch_sketch_rows(const float* X, int64_t n, int64_t cols, int64_t l
                               const void* lists, float* out, int64_t ldo, hipStream_t s) {
     if (!plan_sketch_ok(cols, nst, bp, n)) return hipErrorInvalidValue;
     return launch_sketch(false, X, false, cols, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s);
+}
+
+bool sketch_rows_in_place_ok(const float* X, int64_t cols, int64_t ldx) {
+    return (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (ldx & 3) == 0 && (cols & 3) == 0;
+}
+
+hipError_t launch_sketch_rows_q(const float* X, int64_t n, int64_t cols, int64_t ldx,
+                                const BlockList& bl, int32_t nst, int32_t nblk, int32_t bp,
+                                const void* lists, void* out, int64_t ldo, int split,
+                                hipStream_t s) {
+    if (!plan_sketch_ok(cols, nst, bp, n)) return hipErrorInvalidValue;
+    return launch_sketch(false, X, false, cols, n, ldx, bl, nst, nblk, bp, lists, out, ldo, s,
+                         nullptr, split ? 2 : 1);
 }
 
 size_t transpose_bytes(int64_t rows, int64_t cols) {

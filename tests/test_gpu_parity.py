@@ -201,6 +201,51 @@ def test_sketch_rows_transposing_tiles(n, cols, dtype):
     assert rel(outT, ref) <= SKETCH_TOL
 
 
+@pytest.mark.parametrize("n,cols,b,N,e", [
+    (20000, 64, 1024, 12, 2),    # 3 windows (the last partial), 2 passes over the blocks
+    (9000, 128, 100, 10, 2),     # b < 64-bucket group multiple, 2 windows
+    (4100, 36, 256, 4, 0),       # one window, 9 line groups
+    (300, 8, 32, 30, 2),         # 32 blocks of one group each
+])
+def test_sketch_rows_in_place_spread(n, cols, b, N, e):
+    # X 16-byte aligned with cols and its leading dimension multiples of 4:
+    # the columns are read in place with 16-byte loads and the next window
+    # spread over the slots (the whole path's form for such a row-major B);
+    # equal bit for bit to the transposing path and within the sketch
+    # tolerance of the oracle
+    seed = 7 * n + cols
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, cols)).astype(np.float32)
+    Xd = dev(X, ld=cols + 4)
+    assert Xd.data_ptr() % 16 == 0 and Xd.stride(0) % 4 == 0 and cols % 4 == 0
+    direct = host(osk.sketch_rows(Xd, b, N, e, seed=seed))
+    transposed = host(osk.sketch_rows(Xd, b, N, e, seed=seed, workspace=True))
+    np.testing.assert_array_equal(direct, transposed)
+    h, s = oracle.hash_tables(seed, N + e, n, b)
+    ref = oracle.sketch_rows(X.astype(np.float64), h, s, b).T
+    out = unpad(direct, N + e, b)
+    for i in range(N + e):
+        assert rel(out[:, i * b:(i + 1) * b], ref[:, i * b:(i + 1) * b]) <= SKETCH_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x3", "fp8", "fp8x3"])
+def test_whole_path_row_major_b_in_place_equals_column_major(precision):
+    # a row-major B whose columns are sketched in place and the same values
+    # given column-major (B^T's rows, read directly): the same sketch sums,
+    # so the same C bit for bit, in every operand precision
+    m, n, l, b, N, e = 96, 9000, 136, 256, 4, 1
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    B = rng.standard_normal((n, l)).astype(np.float32)
+    keep = synthetic.random_keep(N, e, 31)
+    Bd = dev(B)
+    Bcm = torch.from_numpy(np.ascontiguousarray(B.T)).cuda().t()     # column-major view
+    assert Bd.stride(1) == 1 and Bcm.stride(0) == 1
+    C1 = host(osk.matmul(dev(A), Bd, b, N, e, seed=5, keep=keep, precision=precision))
+    C2 = host(osk.matmul(dev(A), Bcm, b, N, e, seed=5, keep=keep, precision=precision))
+    np.testing.assert_array_equal(C1, C2)
+
+
 def test_sketch_cols_is_deterministic():
     X = dev(np.random.default_rng(3).standard_normal((64, 5000)))
     a = host(osk.sketch_cols(X, 256, 4, 1, seed=3))
