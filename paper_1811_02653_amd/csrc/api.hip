@@ -37,6 +37,13 @@ int64_t quant_codes(int32_t b, int32_t nst, int prec) {
     return (int64_t)nst * quant_stride(b, prec) * (is_split(prec) ? 2 : 1);
 }
 
+// Partial products of the FP32 block product's split K loop (products with
+// few tiles), sized for all N+e blocks.
+size_t split_part_bytes(const os_sketch* sk, int64_t m, int64_t l, int prec) {
+    if (prec != OS_PREC_FP32) return 0;
+    return align256(osk::gemm_split_bytes(m, l, (int64_t)nblocks(sk) * os_block_stride(sk->b) / 32));
+}
+
 }  // namespace
 
 extern "C" {
@@ -346,7 +353,7 @@ size_t os_matmul_ex_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, i
                                b_col_major ? 0 : osk::transpose_bytes(n, l));
     return align256(prepare_bytes(sk, n)) + align256((size_t)m * zp * 4u) +
            align256((size_t)l * zp * 4u) + tx + align256((size_t)m * qrow) +
-           align256((size_t)l * qrow);
+           align256((size_t)l * qrow) + split_part_bytes(sk, m, l, precision);
 }
 
 size_t os_matmul_prec_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
@@ -420,6 +427,8 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
     char* tx_p = bt_p + align256((size_t)l * zp * 4u);
     char* aq_p = tx_p + tx;
     char* bq_p = aq_p + align256((size_t)m * wqp);
+    char* part_p = bq_p + align256((size_t)l * wqp);
+    const size_t part_bytes = split_part_bytes(sk, m, l, precision);
     float* At = reinterpret_cast<float*>(at_p);
     float* Bt = reinterpret_cast<float*>(bt_p);
     hipStream_t s = (hipStream_t)stream;
@@ -488,8 +497,9 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
     if ((st = sketch_lines(A, a_dtype, a_col_major != 0, m, lda, At, aq_p)) != OS_OK) return st;
     if ((st = sketch_lines(B, b_dtype, b_col_major == 0, l, ldb, Bt, bq_p)) != OS_OK) return st;
     if (precision == OS_PREC_FP32)
-        return hip_status(osk::launch_gemm_kept(At, zs, Bt, zs, m, l, bp, bs.kept_pos, bs.K,
-                                                1.0f / (float)bs.K, C, ldc, s));
+        return hip_status(osk::launch_gemm_kept_split(
+            At, zs, Bt, zs, m, l, bp, bs.kept_pos, bs.K, 1.0f / (float)bs.K, C, ldc,
+            reinterpret_cast<float*>(part_p), part_bytes, s));
     const int split = is_split(precision);
     if (is_fp8(precision)) {
         if (!fp8_fused) {

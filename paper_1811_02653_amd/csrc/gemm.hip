@@ -30,6 +30,8 @@
 //   - The kept-block list is held in VGPRs and picked with v_readlane.
 //   - Workgroup -> tile mapping keeps neighbouring tiles on one XCD (shared
 //     L2) and rasterises in groups of kGroupM = 8 tile rows.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace osk {
@@ -184,6 +186,15 @@ struct CMask {
     int32_t tb;            // tiles per block side
 };
 
+// Split K loop (kSplit kernels, for products with few tiles): workgroup
+// g = s * tiles + tile runs K steps s * chunk .. min(total, (s + 1) * chunk)
+// - 1 of its tile and stores the unscaled partial tile at part + s * m * l
+// (row-major, ld l); split_sum_kernel then adds the partials in split order.
+struct SplitK {
+    float* part;
+    int32_t chunk;
+};
+
 // kOdd: the K step count may be odd (always with per-C-block masks, whose
 // count varies per tile): the pair loop's second step is then masked.  With
 // an even count the mask is left out (it costs about 4 % of the MFMA rate).
@@ -195,13 +206,13 @@ struct CMask {
 // memory instruction).
 constexpr int kThreadsK = 512;
 
-template <typename P, bool kMask, bool kOdd>
+template <typename P, bool kMask, bool kOdd, bool kSplit = false>
 __global__ __launch_bounds__(kThreadsK) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __restrict__ Bt,
                       int64_t ldbt, int64_t m, int64_t l, int32_t bp, BlockList kept,
                       int32_t nkept, int32_t nsub, int64_t lo_off, float scale,
                       float* __restrict__ C, int64_t ldc, int32_t tilesM, int32_t tilesN,
-                      CMask cm) {
+                      CMask cm, SplitK sk) {
     // two K-step buffers per operand, separate arrays so that the compiler
     // can tell the tile loads in flight (into one) from the fragment reads
     // (from the other)
@@ -218,7 +229,14 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
     const int wn = wave & 3;
 
     const int64_t ntiles = (int64_t)tilesM * tilesN;
-    const int64_t T = xcd_task(blockIdx.x, ntiles);
+    int32_t split = 0;
+    int64_t T;
+    if constexpr (kSplit) {
+        split = (int32_t)(blockIdx.x / ntiles);
+        T = (int64_t)blockIdx.x - (int64_t)split * ntiles;
+    } else {
+        T = xcd_task(blockIdx.x, ntiles);
+    }
     const int64_t group = T / ((int64_t)kGroupM * tilesN);
     const int64_t first_m = group * kGroupM;
     const int64_t gsz = min((int64_t)kGroupM, (int64_t)tilesM - first_m);
@@ -281,7 +299,12 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
 
     constexpr int kStep = kStepBytes / P::kElem;     // K values per step
     const int tpb = bp / kStep;                       // K steps per term
-    const int total = nkept * nsub * tpb;
+    int t_begin = 0;
+    int t_end = nkept * nsub * tpb;                   // this workgroup's K steps
+    if constexpr (kSplit) {
+        t_begin = split * sk.chunk;
+        t_end = min(t_end, t_begin + sk.chunk);
+    }
     // byte offsets of the first K column of step `step` in A and in B
     // (terms in order, kStep columns per step)
     auto step_ab = [&](int step, uint32_t& ka, uint32_t& kb) {
@@ -320,7 +343,7 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         direct_issue<4>(rb_src, bs, vb, kb, wave);
     };
 
-    issue(As0, Bs0, 0);
+    issue(As0, Bs0, t_begin);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     float4 fa[4], fb[2], ga[4], gb[2];
@@ -330,11 +353,11 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
     // quads run; each quad's fragments are read during the previous quad's
     // MFMAs.  The loads are pinned ahead of the MFMAs (scheduling barrier),
     // and waited for at the step's end.  Past the last step the tile loaded
-    // is step total - 1 again, a valid address.  Steps run in pairs (one per
-    // buffer); when total is odd (kOdd kernels only) the pair's second step
-    // is dead: its A fragments are zeroed, so it adds nothing.
+    // is step t_end - 1 again, a valid address.  Steps run in pairs (one per
+    // buffer); when their count is odd (kOdd kernels only) the pair's second
+    // step is dead: its A fragments are zeroed, so it adds nothing.
     auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t, bool live) {
-        issue(na, nb, min(t + 1, total - 1));
+        issue(na, nb, min(t + 1, t_end - 1));
         __builtin_amdgcn_sched_barrier(0);
         frag(ga, gb, as, bs, 1);
         if constexpr (kOdd) zero_unless(fa, live);
@@ -351,13 +374,20 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         __syncthreads();
         frag(fa, fb, na, nb, 0);
     };
-    for (int t = 0; t < total; t += 2) {
+    for (int t = t_begin; t < t_end; t += 2) {
         kstep(As0, Bs0, As1, Bs1, t, true);
-        kstep(As1, Bs1, As0, Bs0, t + 1, t + 1 < total);
+        kstep(As1, Bs1, As0, Bs0, t + 1, t + 1 < t_end);
     }
 
     // 32x32 accumulator layout: register r of lane L holds row
     // 8*(r/4) + 4*(L/32) + r%4 and column L%32 of the block.
+    float* out = C;
+    int64_t ldo = ldc;
+    if constexpr (kSplit) {
+        out = sk.part + (int64_t)split * m * l;
+        ldo = l;
+        scale = 1.0f;
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -366,10 +396,23 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = row0 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (row < m && col < l) C[row * ldc + col] = acc[i][j][r] * scale;
+                if (row < m && col < l) out[row * ldo + col] = acc[i][j][r] * scale;
             }
         }
     }
+}
+
+// C = scale * (sum of the nsplit partial products, in split order).
+__global__ __launch_bounds__(256) void split_sum_kernel(const float* __restrict__ part,
+                                                        int32_t nsplit, int64_t m, int64_t l,
+                                                        float scale, float* __restrict__ C,
+                                                        int64_t ldc) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m * l) return;
+    const int64_t row = i / l;
+    float v = 0.f;
+    for (int32_t s = 0; s < nsplit; ++s) v += part[(int64_t)s * m * l + i];
+    C[row * ldc + (i - row * l)] = v * scale;
 }
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
@@ -927,7 +970,63 @@ hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int6
     auto kern = odd ? gemm_kept_kernel<PrecF32, false, true> : gemm_kept_kernel<PrecF32, false, false>;
     hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreadsK), 0, s, At, ldat,
                        Bt, ldbt, m, l, bp, kept, nkept, 1, (int64_t)0, scale, C, ldc,
-                       (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1});
+                       (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1},
+                       SplitK{nullptr, 0});
+    return hipGetLastError();
+}
+
+// Split K loop for products with few tiles: a single 256x256 tile runs on
+// one CU, so a small product (for example 256 x 256 over K = 1024) would leave
+// the other CUs idle.  Splits aim at kSplitSlots workgroups (the CU count of
+// the device this is tuned for) with at least kSplitMinSteps K steps (one
+// step pair) each.
+constexpr int64_t kSplitSlots = 256;
+constexpr int64_t kSplitMinSteps = 2;
+
+namespace {
+
+int64_t tiles_of_product(int64_t m, int64_t l) { return ((m + BM - 1) / BM) * ((l + BN - 1) / BN); }
+
+// Most splits a product of `tiles` tiles over `steps` K steps takes (< 2: none).
+int64_t split_bound(int64_t tiles, int64_t steps) {
+    if (tiles * 2 > kSplitSlots) return 1;
+    return std::min(kSplitSlots / tiles, steps / kSplitMinSteps);
+}
+
+}  // namespace
+
+size_t gemm_split_bytes(int64_t m, int64_t l, int64_t max_steps) {
+    if (m < 1 || l < 1) return 0;
+    const int64_t S = split_bound(tiles_of_product(m, l), max_steps);
+    return S >= 2 ? (size_t)S * (size_t)m * (size_t)l * 4u : 0;
+}
+
+hipError_t launch_gemm_kept_split(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
+                                  int64_t m, int64_t l, int32_t bp, const BlockList& kept,
+                                  int32_t nkept, float scale, float* C, int64_t ldc, float* part,
+                                  size_t part_bytes, hipStream_t s) {
+    if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 4) || nkept < 1) return hipErrorInvalidValue;
+    const int64_t tiles = tiles_of_product(m, l);
+    const int64_t total = (int64_t)nkept * (bp / 32);
+    int64_t S = split_bound(tiles, total);
+    if (S < 2 || !part)
+        return launch_gemm_kept(At, ldat, Bt, ldbt, m, l, bp, kept, nkept, scale, C, ldc, s);
+    int64_t chunk = (total + S - 1) / S;
+    chunk += chunk & 1;                            // whole step pairs, the last split may be odd
+    S = (total + chunk - 1) / chunk;               // every split has at least one step
+    if ((size_t)S * (size_t)m * (size_t)l * 4u > part_bytes || S < 2)
+        return launch_gemm_kept(At, ldat, Bt, ldbt, m, l, bp, kept, nkept, scale, C, ldc, s);
+    const int64_t tilesM = (m + BM - 1) / BM;
+    const int64_t tilesN = (l + BN - 1) / BN;
+    hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, false, true, true>),
+                       dim3((unsigned)(S * tiles)), dim3(kThreadsK), 0, s, At, ldat, Bt, ldbt, m,
+                       l, bp, kept, nkept, 1, (int64_t)0, scale, C, ldc, (int32_t)tilesM,
+                       (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1},
+                       SplitK{part, (int32_t)chunk});
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(split_sum_kernel, dim3((unsigned)((m * l + 255) / 256)), dim3(256), 0, s,
+                       part, (int32_t)S, m, l, scale, C, ldc);
     return hipGetLastError();
 }
 
@@ -945,7 +1044,7 @@ hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int
     hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, true, true>), dim3((unsigned)(tilesM * tilesN)),
                        dim3(kThreadsK), 0, s, At, ldat, Bt, ldbt, m, l, bp, none, 0, 1, (int64_t)0, 1.0f, C, ldc,
                        (int32_t)tilesM, (int32_t)tilesN,
-                       CMask{cmask, cblk, (int32_t)nbJ, nst, (int32_t)tb});
+                       CMask{cmask, cblk, (int32_t)nbJ, nst, (int32_t)tb}, SplitK{nullptr, 0});
     return hipGetLastError();
 }
 
@@ -1012,7 +1111,8 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
     auto kern = odd ? gemm_kept_kernel<PrecBF16, false, true> : gemm_kept_kernel<PrecBF16, false, false>;
     hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreadsK), 0, s, At, ldat,
                        Bt, ldbt, m, l, bp, kept, nkept, split ? 3 : 1, lo_off, scale, C, ldc,
-                       (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1});
+                       (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1},
+                       SplitK{nullptr, 0});
     return hipGetLastError();
 }
 

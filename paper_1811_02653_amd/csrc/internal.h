@@ -182,6 +182,18 @@ bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt, 
 hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
                             int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                             int32_t nkept, float scale, float* C, int64_t ldc, hipStream_t s);
+// Partial-product bytes launch_gemm_kept_split may use for an m x l product
+// of at most max_steps 32-deep K steps (0 when it never splits: enough tiles
+// to fill the device).
+size_t gemm_split_bytes(int64_t m, int64_t l, int64_t max_steps);
+// launch_gemm_kept, with the K loop split over several workgroups per tile
+// when the product has few tiles (partials in part, then summed in split
+// order: deterministic, but summed in a different order than unsplit); the
+// plain launch when it would not split or part_bytes is too small.
+hipError_t launch_gemm_kept_split(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
+                                  int64_t m, int64_t l, int32_t bp, const BlockList& kept,
+                                  int32_t nkept, float scale, float* C, int64_t ldc, float* part,
+                                  size_t part_bytes, hipStream_t s);
 // The same with BF16 sketches (block stride bp, a multiple of 64; leading
 // dimensions in BF16 values).  split != 0 adds the terms A_j * lo(B_j)^T and
 // lo(A_j) * B_j^T, the low parts lo_off columns after the high parts.

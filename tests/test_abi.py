@@ -78,7 +78,17 @@ def test_prepare_and_workspace_bytes(L):
                                                * 1024) + r256(64 * 4))
     m, l = 300, 77
     ws = L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 1)      # column-major B
-    assert ws == r256(prep) + r256(300 * 10 * 1024 * 4) + r256(77 * 10 * 1024 * 4)
+    # the FP32 product's split K loop: 2 tiles of 256 x 256, at most 10 * 1024 / 32
+    # K steps, so min(256 / 2, 320 / 2) = 128 partial products of 300 x 77
+    split = r256(128 * 300 * 77 * 4)
+    assert ws == r256(prep) + r256(300 * 10 * 1024 * 4) + r256(77 * 10 * 1024 * 4) + split
+    # no split with enough tiles to fill the device (16 x 16 tiles)
+    big = L.os_matmul_workspace_bytes(ctypes.byref(s), 4096, n, 4096, 1)
+    assert big == r256(prep) + r256(4096 * 10 * 1024 * 4) * 2
+    # BF16 operands: the BF16 copies (10 blocks of 1024 values per row), no split area
+    bf = L.os_matmul_prec_workspace_bytes(ctypes.byref(s), m, n, l, 1, 1)
+    assert bf == (r256(prep) + r256(300 * 10 * 1024 * 4) + r256(77 * 10 * 1024 * 4) +
+                  r256(300 * 10 * 1024 * 2) + r256(77 * 10 * 1024 * 2))
     transposed = r256(77 * 32772 * 4)                                   # B^T, ld n rounded to 4
     assert L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 0) == ws + transposed
     assert L.os_sketch_rows_workspace_bytes(n, l) == transposed

@@ -321,6 +321,31 @@ def test_matmul_ragged_and_masks(m, n, l, b, N, e, drop):
         assert rel(C, ref) <= PRODUCT_TOL, (kept_only, rel(C, ref))
 
 
+@pytest.mark.parametrize("m,n,l,b,N,e,drop", [
+    (256, 4096, 256, 256, 4, 1, 1),    # one tile, 32 K steps: 16 splits of one step pair
+    (300, 2000, 77, 100, 3, 2, 1),     # two tiles, bp = 128: 4 steps per block
+    (100, 3000, 520, 96, 5, 0, 0),     # 15 steps: splits of 4, the last one odd (3)
+    (1, 64, 1, 32, 1, 0, 0),           # one step: no split
+])
+def test_matmul_split_k(m, n, l, b, N, e, drop):
+    # products with few tiles split their K loop over several workgroups
+    # per tile (partials summed in split order): against the oracle, against
+    # the unsplit block product of the same sketches, and run to run
+    seed = 5 * m + l
+    keep = synthetic.random_keep(N, e, seed, drop=drop)
+    A, B = synthetic.gaussian_pair(m, n, l, seed)
+    Ad, Bd = dev(A), dev(B)
+    C1 = host(osk.matmul(Ad, Bd, b, N, e, seed=seed, keep=keep))
+    C2 = host(osk.matmul(Ad, Bd, b, N, e, seed=seed, keep=keep))
+    np.testing.assert_array_equal(C1, C2)
+    ref = oracle.sketched_matmul(A, B, b, N, e, seed=seed, keep=keep)
+    assert rel(C1, ref) <= PRODUCT_TOL
+    At = osk.sketch_cols(Ad, b, N, e, seed=seed)
+    Bt = osk.sketch_rows(Bd, b, N, e, seed=seed)
+    unsplit = host(osk.gemm_kept(At, Bt, b, keep=keep))      # os_gemm_kept never splits
+    assert rel(C1, unsplit) <= 1e-6
+
+
 def test_matmul_exact_with_permutation_sketch():
     # b = n and h a permutation in every block: S_i S_i^T = I, C = AB.
     m, n, l, N = 96, 256, 80, 2
@@ -377,12 +402,19 @@ def test_matmul_per_block_masks(m, n, l, b, N, e):
     ref = oracle.sketched_matmul_cmask(A, B, b, N, e, cmask, seed=seed)
     assert np.all(C[:b, :b] == 0)
     assert rel(C, ref) <= PRODUCT_TOL
-    # a uniform mask reproduces the global-mask path exactly
+    # a uniform mask reproduces the global-mask block product exactly (the
+    # unsplit os_gemm_kept on the same sketches), and the whole path, whose
+    # K loop is split for these few tiles (another summation order), to
+    # rounding
     keep = synthetic.random_keep(N, e, seed)
     uni = np.broadcast_to(keep, (nbI, nbJ, N + e)).copy()
-    Cu = host(osk.matmul_cmask(dev(A), dev(B, ld=l + 1), b, N, e, uni, seed=seed))
-    Cg = host(osk.matmul(dev(A), dev(B, ld=l + 1), b, N, e, seed=seed, keep=keep))
+    Ad, Bd = dev(A), dev(B, ld=l + 1)
+    Cu = host(osk.matmul_cmask(Ad, Bd, b, N, e, uni, seed=seed))
+    Cg = host(osk.gemm_kept(osk.sketch_cols(Ad, b, N, e, seed=seed),
+                            osk.sketch_rows(Bd, b, N, e, seed=seed), b, keep=keep))
     np.testing.assert_array_equal(Cu, Cg)
+    Cw = host(osk.matmul(Ad, Bd, b, N, e, seed=seed, keep=keep))
+    assert rel(Cw, Cg) <= 1e-6
 
 
 # ---------------------------------------------------------------------------
