@@ -37,11 +37,20 @@ int64_t quant_codes(int32_t b, int32_t nst, int prec) {
     return (int64_t)nst * quant_stride(b, prec) * (is_split(prec) ? 2 : 1);
 }
 
-// Partial products of the FP32 block product's split K loop (products with
-// few tiles), sized for all N+e blocks.
+// Partial products of the block product's split K loop (products with few
+// tiles), sized for all N+e blocks: K steps of 128 bytes of a row (32 FP32,
+// 64 BF16 or 128 FP8 values of each block's stride), three terms per block
+// in the split forms.
 size_t split_part_bytes(const os_sketch* sk, int64_t m, int64_t l, int prec) {
-    if (prec != OS_PREC_FP32) return 0;
-    return align256(osk::gemm_split_bytes(m, l, (int64_t)nblocks(sk) * os_block_stride(sk->b) / 32));
+    int64_t steps;
+    if (prec == OS_PREC_FP32)
+        steps = (int64_t)os_block_stride(sk->b) / 32;
+    else if (is_fp8(prec))
+        steps = (int64_t)osk::block_stride_fp8(sk->b) / 128;
+    else
+        steps = (int64_t)osk::block_stride_bf16(sk->b) / 64;
+    steps *= (int64_t)nblocks(sk) * (is_split(prec) ? 3 : 1);
+    return align256(osk::gemm_split_bytes(m, l, steps));
 }
 
 }  // namespace
@@ -510,15 +519,14 @@ os_status os_matmul_ex(const os_sketch* sk, const void* A, int a_dtype, int a_co
                                                        s))) != OS_OK)
                 return st;
         }
-        return hip_status(osk::launch_gemm_kept_fp8(aq_p, wq, bq_p, wq,
-                                                    quant_codes(sk->b, bs.nst, precision), m, l,
-                                                    bpq, bs.kept_pos, bs.K, split,
-                                                    (int64_t)bs.nst * bpq, 1.0f / (float)bs.K, C,
-                                                    ldc, s));
+        return hip_status(osk::launch_gemm_kept_fp8_split(
+            aq_p, wq, bq_p, wq, quant_codes(sk->b, bs.nst, precision), m, l, bpq, bs.kept_pos,
+            bs.K, split, (int64_t)bs.nst * bpq, 1.0f / (float)bs.K, C, ldc,
+            reinterpret_cast<float*>(part_p), part_bytes, s));
     }
-    return hip_status(osk::launch_gemm_kept_bf16(aq_p, wq, bq_p, wq, m, l, bpq, bs.kept_pos, bs.K,
-                                                 split, (int64_t)bs.nst * bpq,
-                                                 1.0f / (float)bs.K, C, ldc, s));
+    return hip_status(osk::launch_gemm_kept_bf16_split(
+        aq_p, wq, bq_p, wq, m, l, bpq, bs.kept_pos, bs.K, split, (int64_t)bs.nst * bpq,
+        1.0f / (float)bs.K, C, ldc, reinterpret_cast<float*>(part_p), part_bytes, s));
 }
 
 os_status os_matmul_prec(const os_sketch* sk, const float* A, int64_t lda, const float* B,

@@ -440,13 +440,13 @@ __device__ __forceinline__ int fp8_frag_off(int rbase, int s, int p, int lane) {
     return rbase * 32 + 4 * ((4 * s + 2 * (lane >> 5) + p) ^ chunk_key(rbase));
 }
 
-template <bool kOdd>
+template <bool kOdd, bool kSplit = false>
 __global__ __launch_bounds__(kThreadsK) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
                            const uint8_t* __restrict__ Bt, int64_t ldbt, int64_t scales,
                            int64_t m, int64_t l, int32_t bp, BlockList kept, int32_t nkept,
                            int32_t nsub, int64_t lo_off, float scale, float* __restrict__ C,
-                           int64_t ldc, int32_t tilesM, int32_t tilesN) {
+                           int64_t ldc, int32_t tilesM, int32_t tilesN, SplitK sk) {
     __shared__ __align__(1024) float As0[BM * 32];
     __shared__ __align__(1024) float As1[BM * 32];
     __shared__ __align__(1024) float Bs0[BN * 32];
@@ -461,7 +461,14 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
     const int wn = wave & 3;
 
     const int64_t ntiles = (int64_t)tilesM * tilesN;
-    const int64_t T = xcd_task(blockIdx.x, ntiles);
+    int32_t split = 0;
+    int64_t T;
+    if constexpr (kSplit) {
+        split = (int32_t)(blockIdx.x / ntiles);
+        T = (int64_t)blockIdx.x - (int64_t)split * ntiles;
+    } else {
+        T = xcd_task(blockIdx.x, ntiles);
+    }
     const int64_t group = T / ((int64_t)kGroupM * tilesN);
     const int64_t first_m = group * kGroupM;
     const int64_t gsz = min((int64_t)kGroupM, (int64_t)tilesM - first_m);
@@ -492,7 +499,12 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
 
     constexpr int kStep = kStepBytes;                 // 128 codes per step
     const int tpb = bp / kStep;
-    const int total = nkept * nsub * tpb;
+    int t_begin = 0;
+    int t_end = nkept * nsub * tpb;                   // this workgroup's K steps
+    if constexpr (kSplit) {
+        t_begin = split * sk.chunk;
+        t_end = min(t_end, t_begin + sk.chunk);
+    }
     // code byte offsets of step `step` in A and B (terms in order)
     auto step_ab = [&](int step, uint32_t& ka, uint32_t& kb) {
         const int term = step / tpb;
@@ -577,7 +589,7 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
         wb = *reinterpret_cast<const uint2*>(sc + sb_word);
     };
 
-    issue(As0, Bs0, Sc0, 0);
+    issue(As0, Bs0, Sc0, t_begin);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     i32x8 fa, fb[2], fan, fbn[2];
@@ -590,13 +602,13 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
     // other buffers while this step runs; the A fragment of the next
     // (substep, row block) is read during the current one's two MFMAs, and
     // substep 1's B fragments during substep 0's last row block.  A dead
-    // step (the second of a pair when total is odd) has its A fragments
+    // step (the second of a pair when their count is odd) has its A fragments
     // zeroed.
     auto kstep = [&](const float* as, const float* bs, float* na, float* nb, uint32_t* nsc,
                      int t, bool live) {
-        issue(na, nb, nsc, min(t + 1, total - 1));
+        issue(na, nb, nsc, min(t + 1, t_end - 1));
         __builtin_amdgcn_sched_barrier(0);
-        const int tt = t < total ? t : total - 1;
+        const int tt = t < t_end ? t : t_end - 1;
         const uint32_t ha = hsel(tt, true);
         const uint32_t hb = hsel(tt, false);
         const uint32_t sa[4] = {wa.x >> ha, wa.y >> ha, wa.z >> ha, wa.w >> ha};
@@ -632,9 +644,17 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
         frag_b(fb, nb, 0);
         read_scales(wa, wb, nsc);
     };
-    for (int t = 0; t < total; t += 2) {
+    for (int t = t_begin; t < t_end; t += 2) {
         kstep(As0, Bs0, As1, Bs1, Sc1, t, true);
-        kstep(As1, Bs1, As0, Bs0, Sc0, t + 1, t + 1 < total);
+        kstep(As1, Bs1, As0, Bs0, Sc0, t + 1, t + 1 < t_end);
+    }
+
+    float* out = C;
+    int64_t ldo = ldc;
+    if constexpr (kSplit) {
+        out = sk.part + (int64_t)split * m * l;
+        ldo = l;
+        scale = 1.0f;
     }
 
 #pragma unroll
@@ -645,7 +665,7 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = row0 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (row < m && col < l) C[row * ldc + col] = acc[i][j][r] * scale;
+                if (row < m && col < l) out[row * ldo + col] = acc[i][j][r] * scale;
             }
         }
     }
@@ -1001,33 +1021,46 @@ size_t gemm_split_bytes(int64_t m, int64_t l, int64_t max_steps) {
     return S >= 2 ? (size_t)S * (size_t)m * (size_t)l * 4u : 0;
 }
 
-hipError_t launch_gemm_kept_split(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
-                                  int64_t m, int64_t l, int32_t bp, const BlockList& kept,
-                                  int32_t nkept, float scale, float* C, int64_t ldc, float* part,
-                                  size_t part_bytes, hipStream_t s) {
-    if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 4) || nkept < 1) return hipErrorInvalidValue;
-    const int64_t tiles = tiles_of_product(m, l);
-    const int64_t total = (int64_t)nkept * (bp / 32);
-    int64_t S = split_bound(tiles, total);
-    if (S < 2 || !part)
-        return launch_gemm_kept(At, ldat, Bt, ldbt, m, l, bp, kept, nkept, scale, C, ldc, s);
-    int64_t chunk = (total + S - 1) / S;
+namespace {
+
+// Splits and steps per split for `total` K steps of an m x l product (false:
+// no split: enough tiles, too few steps, or too little partial space).
+bool split_plan(int64_t m, int64_t l, int64_t total, const float* part, size_t part_bytes,
+                int64_t& S, int64_t& chunk) {
+    S = split_bound(tiles_of_product(m, l), total);
+    if (S < 2 || !part) return false;
+    chunk = (total + S - 1) / S;
     chunk += chunk & 1;                            // whole step pairs, the last split may be odd
     S = (total + chunk - 1) / chunk;               // every split has at least one step
-    if ((size_t)S * (size_t)m * (size_t)l * 4u > part_bytes || S < 2)
-        return launch_gemm_kept(At, ldat, Bt, ldbt, m, l, bp, kept, nkept, scale, C, ldc, s);
-    const int64_t tilesM = (m + BM - 1) / BM;
-    const int64_t tilesN = (l + BN - 1) / BN;
-    hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, false, true, true>),
-                       dim3((unsigned)(S * tiles)), dim3(kThreadsK), 0, s, At, ldat, Bt, ldbt, m,
-                       l, bp, kept, nkept, 1, (int64_t)0, scale, C, ldc, (int32_t)tilesM,
-                       (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1},
-                       SplitK{part, (int32_t)chunk});
+    return S >= 2 && (size_t)S * (size_t)m * (size_t)l * 4u <= part_bytes;
+}
+
+hipError_t launch_split_sum(const float* part, int64_t S, int64_t m, int64_t l, float scale,
+                            float* C, int64_t ldc, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(split_sum_kernel, dim3((unsigned)((m * l + 255) / 256)), dim3(256), 0, s,
                        part, (int32_t)S, m, l, scale, C, ldc);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_kept_split(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
+                                  int64_t m, int64_t l, int32_t bp, const BlockList& kept,
+                                  int32_t nkept, float scale, float* C, int64_t ldc, float* part,
+                                  size_t part_bytes, hipStream_t s) {
+    if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 4) || nkept < 1) return hipErrorInvalidValue;
+    int64_t S = 0, chunk = 0;
+    if (!split_plan(m, l, (int64_t)nkept * (bp / 32), part, part_bytes, S, chunk))
+        return launch_gemm_kept(At, ldat, Bt, ldbt, m, l, bp, kept, nkept, scale, C, ldc, s);
+    const int64_t tilesM = (m + BM - 1) / BM;
+    const int64_t tilesN = (l + BN - 1) / BN;
+    hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, false, true, true>),
+                       dim3((unsigned)(S * tilesM * tilesN)), dim3(kThreadsK), 0, s, At, ldat, Bt,
+                       ldbt, m, l, bp, kept, nkept, 1, (int64_t)0, scale, C, ldc, (int32_t)tilesM,
+                       (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1}, SplitK{part, (int32_t)chunk});
+    return launch_split_sum(part, S, m, l, scale, C, ldc, s);
 }
 
 hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
@@ -1096,8 +1129,29 @@ hipError_t launch_gemm_kept_fp8(const void* At, int64_t ldat, const void* Bt, in
     hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreadsK), 0, s,
                        static_cast<const uint8_t*>(At), ldat, static_cast<const uint8_t*>(Bt),
                        ldbt, scales, m, l, bp, kept, nkept, split ? 3 : 1, lo_off, scale, C, ldc,
-                       (int32_t)tilesM, (int32_t)tilesN);
+                       (int32_t)tilesM, (int32_t)tilesN, SplitK{nullptr, 0});
     return hipGetLastError();
+}
+
+hipError_t launch_gemm_kept_fp8_split(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                                      int64_t scales, int64_t m, int64_t l, int32_t bp,
+                                      const BlockList& kept, int32_t nkept, int split,
+                                      int64_t lo_off, float scale, float* C, int64_t ldc,
+                                      float* part, size_t part_bytes, hipStream_t s) {
+    if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 1) || nkept < 1) return hipErrorInvalidValue;
+    int64_t S = 0, chunk = 0;
+    const int64_t total = (int64_t)nkept * (split ? 3 : 1) * (bp / kStepBytes);
+    if (!split_plan(m, l, total, part, part_bytes, S, chunk))
+        return launch_gemm_kept_fp8(At, ldat, Bt, ldbt, scales, m, l, bp, kept, nkept, split,
+                                    lo_off, scale, C, ldc, s);
+    const int64_t tilesM = (m + BM - 1) / BM;
+    const int64_t tilesN = (l + BN - 1) / BN;
+    hipLaunchKernelGGL((gemm_kept_fp8d_kernel<true, true>), dim3((unsigned)(S * tilesM * tilesN)),
+                       dim3(kThreadsK), 0, s, static_cast<const uint8_t*>(At), ldat,
+                       static_cast<const uint8_t*>(Bt), ldbt, scales, m, l, bp, kept, nkept,
+                       split ? 3 : 1, lo_off, scale, C, ldc, (int32_t)tilesM, (int32_t)tilesN,
+                       SplitK{part, (int32_t)chunk});
+    return launch_split_sum(part, S, m, l, scale, C, ldc, s);
 }
 
 hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
@@ -1114,6 +1168,27 @@ hipError_t launch_gemm_kept_bf16(const void* At, int64_t ldat, const void* Bt, i
                        (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1},
                        SplitK{nullptr, 0});
     return hipGetLastError();
+}
+
+hipError_t launch_gemm_kept_bf16_split(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                                       int64_t m, int64_t l, int32_t bp, const BlockList& kept,
+                                       int32_t nkept, int split, int64_t lo_off, float scale,
+                                       float* C, int64_t ldc, float* part, size_t part_bytes,
+                                       hipStream_t s) {
+    if (!plan_gemm_ok(m, l, bp, ldat, ldbt, 2) || nkept < 1) return hipErrorInvalidValue;
+    int64_t S = 0, chunk = 0;
+    const int64_t total = (int64_t)nkept * (split ? 3 : 1) * (bp / 64);
+    if (!split_plan(m, l, total, part, part_bytes, S, chunk))
+        return launch_gemm_kept_bf16(At, ldat, Bt, ldbt, m, l, bp, kept, nkept, split, lo_off,
+                                     scale, C, ldc, s);
+    const int64_t tilesM = (m + BM - 1) / BM;
+    const int64_t tilesN = (l + BN - 1) / BN;
+    hipLaunchKernelGGL((gemm_kept_kernel<PrecBF16, false, true, true>),
+                       dim3((unsigned)(S * tilesM * tilesN)), dim3(kThreadsK), 0, s, At, ldat, Bt,
+                       ldbt, m, l, bp, kept, nkept, split ? 3 : 1, lo_off, scale, C, ldc,
+                       (int32_t)tilesM, (int32_t)tilesN, CMask{nullptr, 0, 0, 0, 1},
+                       SplitK{part, (int32_t)chunk});
+    return launch_split_sum(part, S, m, l, scale, C, ldc, s);
 }
 
 }  // namespace osk

@@ -182,9 +182,10 @@ bool plan_gemm_ok(int64_t m, int64_t l, int32_t bp, int64_t ldat, int64_t ldbt, 
 hipError_t launch_gemm_kept(const float* At, int64_t ldat, const float* Bt, int64_t ldbt,
                             int64_t m, int64_t l, int32_t bp, const BlockList& kept,
                             int32_t nkept, float scale, float* C, int64_t ldc, hipStream_t s);
-// Partial-product bytes launch_gemm_kept_split may use for an m x l product
-// of at most max_steps 32-deep K steps (0 when it never splits: enough tiles
-// to fill the device).
+// Partial-product bytes the split launches may use for an m x l product of
+// at most max_steps K steps (128 bytes of every tile row each: 32 FP32, 64
+// BF16 or 128 FP8 values); 0 when it never splits (enough tiles to fill the
+// device).
 size_t gemm_split_bytes(int64_t m, int64_t l, int64_t max_steps);
 // launch_gemm_kept, with the K loop split over several workgroups per tile
 // when the product has few tiles (partials in part, then summed in split
@@ -208,6 +209,18 @@ hipError_t launch_gemm_kept_fp8(const void* At, int64_t ldat, const void* Bt, in
                                 int64_t scales, int64_t m, int64_t l, int32_t bp,
                                 const BlockList& kept, int32_t nkept, int split, int64_t lo_off,
                                 float scale, float* C, int64_t ldc, hipStream_t s);
+// launch_gemm_kept_bf16 / launch_gemm_kept_fp8 with the split K loop of
+// launch_gemm_kept_split (partials in part, summed in split order).
+hipError_t launch_gemm_kept_bf16_split(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                                       int64_t m, int64_t l, int32_t bp, const BlockList& kept,
+                                       int32_t nkept, int split, int64_t lo_off, float scale,
+                                       float* C, int64_t ldc, float* part, size_t part_bytes,
+                                       hipStream_t s);
+hipError_t launch_gemm_kept_fp8_split(const void* At, int64_t ldat, const void* Bt, int64_t ldbt,
+                                      int64_t scales, int64_t m, int64_t l, int32_t bp,
+                                      const BlockList& kept, int32_t nkept, int split,
+                                      int64_t lo_off, float scale, float* C, int64_t ldc,
+                                      float* part, size_t part_bytes, hipStream_t s);
 // FP32 block product with a keep mask per C block: cmask DEVICE [ceil(m/cblk)]
 // [ceil(l/cblk)][nst]; block (I, J) of C (cblk x cblk) = (1/K_IJ) * sum of its
 // kept blocks' products (zero when it keeps none).

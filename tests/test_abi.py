@@ -85,10 +85,12 @@ def test_prepare_and_workspace_bytes(L):
     # no split with enough tiles to fill the device (16 x 16 tiles)
     big = L.os_matmul_workspace_bytes(ctypes.byref(s), 4096, n, 4096, 1)
     assert big == r256(prep) + r256(4096 * 10 * 1024 * 4) * 2
-    # BF16 operands: the BF16 copies (10 blocks of 1024 values per row), no split area
+    # BF16 operands: the BF16 copies (10 blocks of 1024 values per row) and a split
+    # area for at most 10 * 1024 / 64 = 160 K steps: min(128, 80) partial products
     bf = L.os_matmul_prec_workspace_bytes(ctypes.byref(s), m, n, l, 1, 1)
     assert bf == (r256(prep) + r256(300 * 10 * 1024 * 4) + r256(77 * 10 * 1024 * 4) +
-                  r256(300 * 10 * 1024 * 2) + r256(77 * 10 * 1024 * 2))
+                  r256(300 * 10 * 1024 * 2) + r256(77 * 10 * 1024 * 2) +
+                  r256(80 * 300 * 77 * 4))
     transposed = r256(77 * 32772 * 4)                                   # B^T, ld n rounded to 4
     assert L.os_matmul_workspace_bytes(ctypes.byref(s), m, n, l, 0) == ws + transposed
     assert L.os_sketch_rows_workspace_bytes(n, l) == transposed

@@ -128,13 +128,18 @@ def test_matmul_bf16_within_rounding_bound(m, n, l, b, N, e):
                                                    (70, 9000, 40, 1000, 2, 1, True),
                                                    # 320 groups of 64 buckets: two sketch
                                                    # passes of 20 slots per wave
-                                                   (40, 3000, 37, 2048, 8, 2, False)])
+                                                   (40, 3000, 37, 2048, 8, 2, False),
+                                                   # 12 x 11 = 132 tiles: no split K loop
+                                                   (3072, 1500, 2816, 128, 2, 1, False)])
 def test_matmul_fused_quantization_is_the_staged_path(m, n, l, b, N, e, kept_only, precision):
     # the whole path rounds each sketch to BF16 (or quantizes it to FP8 with
     # its block scales, when b rounded up to 64 is a multiple of 128; b = 64
-    # takes the staged path) in the sketch's epilogue; it must give, bit for
-    # bit, what the staged path gives (FP32 sketches, then their low-precision
-    # copies, then the block product)
+    # takes the staged path) in the sketch's epilogue; it must give what the
+    # staged path gives (FP32 sketches, then their low-precision copies, then
+    # the block product): bit for bit when the product has enough tiles to
+    # run unsplit, and to FP32 rounding of the same terms summed in another
+    # order (1e-5, the product tolerance; up to 61440 terms here) when the
+    # whole path splits its K loop over several workgroups per tile
     seed = m + n + b
     A, B = synthetic.gaussian_pair(m, n, l, seed)
     keep = synthetic.random_keep(N, e, seed)
@@ -150,7 +155,10 @@ def test_matmul_fused_quantization_is_the_staged_path(m, n, l, b, N, e, kept_onl
     QB = osk.sketch_quantize(Bt, b, nst, precision=precision)
     C2 = host(osk.gemm_kept_prec(QA, QB, b, nst, precision=precision,
                                  keep=None if kept_only else keep))
-    np.testing.assert_array_equal(C, C2)
+    if -(-m // 256) * -(-l // 256) > 128:
+        np.testing.assert_array_equal(C, C2)
+    else:
+        assert oracle.rel_frob(C, C2) <= 1e-5
 
 
 # ---------------------------------------------------------------------------
