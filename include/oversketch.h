@@ -302,8 +302,11 @@ os_status os_gemm_kept_prec(const void* At, int64_t ldat, const void* Bt, int64_
 
 /* Workspace bytes os_matmul needs: the prepared sketch and both sketches,
  * sized for all N+e blocks so one workspace serves any mask, plus, for a
- * row-major B (b_col_major = 0), B transposed (l x n).  0 on invalid
- * arguments. */
+ * row-major B (b_col_major = 0), room for B transposed (l x n; used only when
+ * B cannot be read in place, see os_matmul), plus, for a product of at most
+ * 128 tiles of 256 x 256, the partial products of the block product's split
+ * K loop (S m x l FP32 matrices, S <= 256 / tiles, at most 64 MiB).  0 on
+ * invalid arguments. */
 size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int64_t l,
                                  int b_col_major);
 
@@ -315,7 +318,12 @@ size_t os_matmul_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, int6
  * skips the dropped blocks already in the sketch step.  C: DEVICE m x l
  * (ldc).  workspace: DEVICE, 256-byte aligned, >= os_matmul_workspace_bytes
  * for the same b_col_major.  Enqueues: prepare, sketch of A, (transpose of
- * a row-major B,) sketch of B, block product. */
+ * a row-major B,) sketch of B, block product.  A row-major B that is 16-byte
+ * aligned with ldb and l multiples of 4 has its columns sketched in place
+ * (no transpose; the same sums).  A product of at most 128 tiles splits
+ * its block product's K loop over several workgroups per tile (partials in
+ * the workspace, summed in a fixed order: repeatable bit for bit, summed in
+ * another order than os_gemm_kept). */
 os_status os_matmul(const os_sketch* sk, const float* A, int64_t lda, const float* B,
                     int64_t ldb, int b_col_major, int64_t m, int64_t n, int64_t l,
                     const uint8_t* keep_host, int kept_only, float* C, int64_t ldc,
@@ -377,7 +385,9 @@ size_t os_matmul_ex_workspace_bytes(const os_sketch* sk, int64_t m, int64_t n, i
  * (a_col_major = 1, at A[k*lda + r], lda >= m); B n x l as in os_matmul.
  * a_dtype / b_dtype: OS_DTYPE_F32 or OS_DTYPE_BF16 (2-byte aligned, ld in
  * values), in either layout.  A column-major A and a row-major B are first
- * transposed into the workspace in their own type; BF16 values are converted
+ * transposed into the workspace in their own type (an FP32 one that is
+ * 16-byte aligned with its ld and line count multiples of 4 is read in place
+ * instead, unless the FP8 copy is written by the sketch); BF16 values are converted
  * exactly to FP32 as the sketch reads them, so the result equals that of the
  * FP32 path on the converted values, bit for bit.  With A = X^T for a
  * row-major X (n x m: A is
