@@ -132,18 +132,28 @@ __device__ __forceinline__ float comp(const float4& v, int c) {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+
 // Operand precisions of the block product.  A K step is 128 bytes of a tile
 // row in both: 32 FP32 values or 64 BF16 values.  A fragment is 16 bytes:
 // lane half h of quad q holds the K values at byte offset 64h + 16q of the
 // step's row (4 FP32 values feeding four 32x32x2 MFMAs, or 8 BF16 values
 // feeding one 32x32x16 MFMA); A and B use the same K order.
+// A quad's MFMAs come in kParts parts; the K loop issues the next quad's
+// fragment reads after kHead parts and leaves the step's last kTail parts
+// until after the step's barrier (they keep the MFMA pipe busy while the
+// next step's first fragments are read).  Chosen by measurement: FP32 3 and
+// 1, BF16 1 and 0 (BF16 3-4 % faster than the compiler's own placement,
+// which read each quad's fragments just before its MFMAs; FP32 unchanged).
 struct PrecF32 {
     static constexpr int kElem = 4;
-    template <int kI, int kJ>
+    static constexpr int kParts = 4;          // parts of a quad: the four K values kk
+    static constexpr int kHead = 3;
+    static constexpr int kTail = 1;
+    template <int kI, int kJ, int kLo = 0, int kHi = kParts>
     __device__ static __forceinline__ void mfma_quad(v16f (&acc)[kI][kJ], const float4 (&a)[kI],
                                                      const float4 (&b)[kJ]) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
+        for (int kk = kLo; kk < kHi; ++kk)
 #pragma unroll
             for (int i = 0; i < kI; ++i)
 #pragma unroll
@@ -155,11 +165,14 @@ struct PrecF32 {
 
 struct PrecBF16 {
     static constexpr int kElem = 2;
-    template <int kI, int kJ>
+    static constexpr int kParts = 4;          // parts of a quad: the row blocks i (kI = 4)
+    static constexpr int kHead = 1;
+    static constexpr int kTail = 0;
+    template <int kI, int kJ, int kLo = 0, int kHi = kI>
     __device__ static __forceinline__ void mfma_quad(v16f (&acc)[kI][kJ], const float4 (&a)[kI],
                                                      const float4 (&b)[kJ]) {
 #pragma unroll
-        for (int i = 0; i < kI; ++i)
+        for (int i = kLo; i < kHi; ++i)
 #pragma unroll
             for (int j = 0; j < kJ; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
@@ -224,7 +237,7 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar M0 and selects
     const int wm = wave >> 2;
     const int wn = wave & 3;
 
@@ -351,28 +364,40 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
     // One K step: the next step's tiles go straight into the other buffers
     // (last read before the previous step's barrier) while this step's four
     // quads run; each quad's fragments are read during the previous quad's
-    // MFMAs.  The loads are pinned ahead of the MFMAs (scheduling barrier),
-    // and waited for at the step's end.  Past the last step the tile loaded
-    // is step t_end - 1 again, a valid address.  Steps run in pairs (one per
-    // buffer); when their count is odd (kOdd kernels only) the pair's second
-    // step is dead: its A fragments are zeroed, so it adds nothing.
+    // MFMAs, after its first kHead parts, and the last quad's final kTail
+    // parts run after the step's barrier, behind the reads of the next
+    // step's first fragments (scheduling barriers pin this order).  The
+    // loads are pinned ahead of the MFMAs and waited for at the step's end.
+    // Past the last step the tile loaded is step t_end - 1 again, a valid
+    // address.  Steps run in pairs (one per buffer); when their count is odd
+    // (kOdd kernels only) the pair's second step is dead: its A fragments
+    // are zeroed, so it adds nothing.
+    auto quad = [&](float4 (&a)[4], float4 (&b)[2], auto&& reads) {
+        P::template mfma_quad<4, 2, 0, P::kHead>(acc, a, b);
+        __builtin_amdgcn_sched_barrier(0);
+        reads();
+        __builtin_amdgcn_sched_barrier(0);
+        P::template mfma_quad<4, 2, P::kHead, P::kParts>(acc, a, b);
+        __builtin_amdgcn_sched_barrier(0);
+    };
     auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t, bool live) {
         issue(na, nb, min(t + 1, t_end - 1));
         __builtin_amdgcn_sched_barrier(0);
-        frag(ga, gb, as, bs, 1);
         if constexpr (kOdd) zero_unless(fa, live);
-        P::template mfma_quad<4, 2>(acc, fa, fb);
-        frag(fa, fb, as, bs, 2);
+        quad(fa, fb, [&] { frag(ga, gb, as, bs, 1); });
         if constexpr (kOdd) zero_unless(ga, live);
-        P::template mfma_quad<4, 2>(acc, ga, gb);
-        frag(ga, gb, as, bs, 3);
+        quad(ga, gb, [&] { frag(fa, fb, as, bs, 2); });
         if constexpr (kOdd) zero_unless(fa, live);
-        P::template mfma_quad<4, 2>(acc, fa, fb);
+        quad(fa, fb, [&] { frag(ga, gb, as, bs, 3); });
         if constexpr (kOdd) zero_unless(ga, live);
-        P::template mfma_quad<4, 2>(acc, ga, gb);
+        P::template mfma_quad<4, 2, 0, P::kParts - P::kTail>(acc, ga, gb);
+        __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         frag(fa, fb, na, nb, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        P::template mfma_quad<4, 2, P::kParts - P::kTail, P::kParts>(acc, ga, gb);
+        __builtin_amdgcn_sched_barrier(0);
     };
     for (int t = t_begin; t < t_end; t += 2) {
         kstep(As0, Bs0, As1, Bs1, t, true);
@@ -456,7 +481,7 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar M0 and selects
     const int wm = wave >> 2;
     const int wn = wave & 3;
 
@@ -716,7 +741,7 @@ void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / (TS::kWaves / 2);      // 2 waves along the rows
     const int wn = wave % (TS::kWaves / 2);      // kWaves / 2 along the columns
     int fa_off[4], fb_off[4];
@@ -766,19 +791,30 @@ void gemm_batch_sym_kernel(const BatchProblem* __restrict__ probs,
 
         float4 fa[kI], fb[kJ], ga[kI], gb[kJ];
         frag(fa, fb, As0, Bs0, 0);
+        // the order of gemm_kept_kernel's K step (FP32 head and tail parts)
+        auto quad = [&](float4 (&a)[kI], float4 (&b)[kJ], auto&& reads) {
+            PrecF32::mfma_quad<kI, kJ, 0, PrecF32::kHead>(acc, a, b);
+            __builtin_amdgcn_sched_barrier(0);
+            reads();
+            __builtin_amdgcn_sched_barrier(0);
+            PrecF32::mfma_quad<kI, kJ, PrecF32::kHead, PrecF32::kParts>(acc, a, b);
+            __builtin_amdgcn_sched_barrier(0);
+        };
         auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t) {
             issue(na, nb, min(t + 1, total - 1));
             __builtin_amdgcn_sched_barrier(0);
-            frag(ga, gb, as, bs, 1);
-            PrecF32::mfma_quad<kI, kJ>(acc, fa, fb);
-            frag(fa, fb, as, bs, 2);
-            PrecF32::mfma_quad<kI, kJ>(acc, ga, gb);
-            frag(ga, gb, as, bs, 3);
-            PrecF32::mfma_quad<kI, kJ>(acc, fa, fb);
-            PrecF32::mfma_quad<kI, kJ>(acc, ga, gb);
+            quad(fa, fb, [&] { frag(ga, gb, as, bs, 1); });
+            quad(ga, gb, [&] { frag(fa, fb, as, bs, 2); });
+            quad(fa, fb, [&] { frag(ga, gb, as, bs, 3); });
+            PrecF32::mfma_quad<kI, kJ, 0, PrecF32::kParts - PrecF32::kTail>(acc, ga, gb);
+            __builtin_amdgcn_sched_barrier(0);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             frag(fa, fb, na, nb, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            PrecF32::mfma_quad<kI, kJ, PrecF32::kParts - PrecF32::kTail, PrecF32::kParts>(acc, ga,
+                                                                                       gb);
+            __builtin_amdgcn_sched_barrier(0);
         };
         for (int t = 0; t < total; t += 2) {
             kstep(As0, Bs0, As1, Bs1, t);
@@ -871,21 +907,34 @@ __device__ __forceinline__ void mixed_job(float* As0, float* As1, float* Bs0, fl
 
     float4 fa[kI], fb[kJ], ga[kI], gb[kJ];
     if (live) frag(fa, fb, As0, Bs0, 0);
+    // the order of gemm_kept_kernel's K step (FP32 head and tail parts)
+    auto quad = [&](float4 (&a)[kI], float4 (&b)[kJ], auto&& reads) {
+        PrecF32::mfma_quad<kI, kJ, 0, PrecF32::kHead>(acc, a, b);
+        __builtin_amdgcn_sched_barrier(0);
+        reads();
+        __builtin_amdgcn_sched_barrier(0);
+        PrecF32::mfma_quad<kI, kJ, PrecF32::kHead, PrecF32::kParts>(acc, a, b);
+        __builtin_amdgcn_sched_barrier(0);
+    };
     auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t) {
         issue(na, nb, min(t + 1, total - 1));
         __builtin_amdgcn_sched_barrier(0);
         if (live) {
-            frag(ga, gb, as, bs, 1);
-            PrecF32::mfma_quad<kI, kJ>(acc, fa, fb);
-            frag(fa, fb, as, bs, 2);
-            PrecF32::mfma_quad<kI, kJ>(acc, ga, gb);
-            frag(ga, gb, as, bs, 3);
-            PrecF32::mfma_quad<kI, kJ>(acc, fa, fb);
-            PrecF32::mfma_quad<kI, kJ>(acc, ga, gb);
+            quad(fa, fb, [&] { frag(ga, gb, as, bs, 1); });
+            quad(ga, gb, [&] { frag(fa, fb, as, bs, 2); });
+            quad(fa, fb, [&] { frag(ga, gb, as, bs, 3); });
+            PrecF32::mfma_quad<kI, kJ, 0, PrecF32::kParts - PrecF32::kTail>(acc, ga, gb);
         }
+        __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (live) frag(fa, fb, na, nb, 0);
+        if (live) {
+            frag(fa, fb, na, nb, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            PrecF32::mfma_quad<kI, kJ, PrecF32::kParts - PrecF32::kTail, PrecF32::kParts>(acc, ga,
+                                                                                       gb);
+        }
+        __builtin_amdgcn_sched_barrier(0);
     };
     for (int t = 0; t < total; t += 2) {
         kstep(As0, Bs0, As1, Bs1, t);
@@ -924,7 +973,7 @@ void gemm_batch_mixed_kernel(const BatchProblem* __restrict__ probs,
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int half = wave >> 2;
 
     const int32_t w_end = starts[blockIdx.x + 1];
