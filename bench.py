@@ -42,9 +42,9 @@ METRIC = "sketched AB eff. TFLOP/s (2mnl/t) at fixed rel-Frob err vs exact GEMM,
 # kernel source it was measured on (SHA-256 of that source, see
 # gemm_kept_source_sha); None otherwise.
 GEMM_TRAFFIC = {
-    "source_sha256": "ab13e54bac443481a8d9e28f140e8a775ccc92f90a8006993fdd350eeff0dbe8",
+    "source_sha256": "01255d9e960e624b06cafa8f51ed1cae5cc6faab3e1d265d87e8a473cb0949f5",
     "workload": (8192, 32768, 8192, 1024, 8, 2),
-    "fetch_kib": 1573125.0, "fetch_scale": 2.000,
+    "fetch_kib": 1573223.0, "fetch_scale": 2.000,
     "write_kib": 262144.0, "write_scale": 1.000,
 }
 FP32_MFMA_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix peak
@@ -843,6 +843,38 @@ def main():
                                          precision[prec]["rel_frob_vs_exact_fp64"]))
             del wsp, QA, QB, Cd
         del AB, C32
+        torch.cuda.empty_cache()
+        # the vendor library on a product of the block product's shape
+        # (m x K*bp times (l x K*bp)^T, both operands K-contiguous): BF16
+        # torch.matmul (hipBLASLt) and FP8 E4M3 torch._scaled_mm with one
+        # scale per tensor (the block product uses one per 64 values)
+        kb = K * bp
+        gl = torch.Generator(device=dev)
+        gl.manual_seed(args.seed)
+        La = torch.randn((m, kb), generator=gl, device=dev).to(torch.bfloat16)
+        Lb = torch.randn((l, kb), generator=gl, device=dev).to(torch.bfloat16)
+        lib_flops = 2.0 * m * l * kb
+        t_lb = event_time_ms(torch, lambda: torch.matmul(La, Lb.t()), reps, stream)
+        libref = {"shape": "%d x %d . (%d x %d)^T" % (m, kb, l, kb),
+                  "bf16_matmul": {"ms": t_lb, "tflops": lib_flops / (t_lb * 1e-3) / 1e12,
+                                  "frac_of_peak": lib_flops / (t_lb * 1e-3) / 1e12 /
+                                  BF16_MFMA_PEAK_TFLOPS}}
+        try:
+            La8, Lb8 = La.to(torch.float8_e4m3fn), Lb.to(torch.float8_e4m3fn)
+            one = torch.ones((), device=dev)
+            t_l8 = event_time_ms(torch, lambda: torch._scaled_mm(La8, Lb8.t(), scale_a=one,
+                                                                 scale_b=one,
+                                                                 out_dtype=torch.float32),
+                                 reps, stream)
+            libref["fp8_scaled_mm_per_tensor"] = {
+                "ms": t_l8, "tflops": lib_flops / (t_l8 * 1e-3) / 1e12,
+                "frac_of_peak": lib_flops / (t_l8 * 1e-3) / 1e12 / FP8_MFMA_PEAK_TFLOPS}
+            del La8, Lb8
+        except (RuntimeError, AttributeError) as ex:
+            libref["fp8_scaled_mm_per_tensor"] = {"error": str(ex)[:200]}
+        precision["library_reference"] = libref
+        log("library reference: %s" % libref)
+        del La, Lb
         torch.cuda.empty_cache()
         # error on log-normal row / column norms (same shapes, same sketch)
         A2_h, B2_h = synthetic.lognormal_scaled_pair(m, n, l, args.seed, sigma=2.0)

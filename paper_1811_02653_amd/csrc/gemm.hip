@@ -460,12 +460,19 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 // words straight into LDS, A's rows by waves 0-3 and B's by waves 4-7, laid
 // out so that a fragment lane's four A rows (or two B rows) are consecutive
 // words: one 16-byte (8-byte) LDS read per lane per step.
+// Scale chunks (kChunk, when the block stride is a multiple of 1024 codes
+// and rows and the scale area are 16-byte aligned): the scale loads above
+// read 64 rows per instruction, one 4-byte piece each, and cost about as
+// much as a whole step's tile loads; instead each wave loads 16 bytes of
+// its 64 rows (the scales of 8 steps) once per 8 steps, into one of two
+// chunk buffers, and each step reads its pair of scale bytes per row from
+// there (the chunk for steps 8c .. 8c + 7 is loaded during step 8c - 8).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int fp8_frag_off(int rbase, int s, int p, int lane) {
     return rbase * 32 + 4 * ((4 * s + 2 * (lane >> 5) + p) ^ chunk_key(rbase));
 }
 
-template <bool kOdd, bool kSplit = false>
+template <bool kOdd, bool kSplit = false, bool kChunk = false>
 __global__ __launch_bounds__(kThreadsK) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
                            const uint8_t* __restrict__ Bt, int64_t ldbt, int64_t scales,
@@ -476,8 +483,11 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
     __shared__ __align__(1024) float As1[BM * 32];
     __shared__ __align__(1024) float Bs0[BN * 32];
     __shared__ __align__(1024) float Bs1[BN * 32];
-    __shared__ __align__(16) uint32_t Sc0[BM + BN];   // scale words: A's rows, then B's
-    __shared__ __align__(16) uint32_t Sc1[BM + BN];
+    // scale words of a step (A's rows, then B's), or two chunk buffers of
+    // 16 bytes per row
+    __shared__ __align__(16) uint32_t Sc0[kChunk ? 4 : BM + BN];
+    __shared__ __align__(16) uint32_t Sc1[kChunk ? 4 : BM + BN];
+    __shared__ __align__(16) uint32_t Sq[kChunk ? 2 * 4 * (BM + BN) : 4];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -566,14 +576,30 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
         direct_issue<4>(ra_src, as, va, ka, wave);
         direct_issue<4>(rb_src, bs, vb, kb, wave);
 #if defined(__HIP_DEVICE_COMPILE__)
-        const uint32_t kc = a_side ? ka : kb;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_src, (lds_void*)(sc + sbase), 4, so,
-                                                 (kc / kFp8Block) & ~3u, 0, 0);
+        if constexpr (!kChunk) {
+            const uint32_t kc = a_side ? ka : kb;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_src, (lds_void*)(sc + sbase), 4, so,
+                                                     (kc / kFp8Block) & ~3u, 0, 0);
+        }
 #else
         (void)sc;
         (void)so;
         (void)rs_src;
         (void)sbase;
+#endif
+    };
+    // the scale chunk of steps step .. step + 7 (step a multiple of 8) into
+    // chunk buffer (step / 8) % 2: 16 bytes of each of the wave's 64 rows
+    auto issue_chunk = [&](int step) {
+#if defined(__HIP_DEVICE_COMPILE__)
+        uint32_t ka, kb;
+        step_ab(step, ka, kb);
+        const uint32_t kc = a_side ? ka : kb;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs_src, (lds_void*)(Sq + ((step >> 3) & 1) * 4 * (BM + BN) + 4 * sbase), 16, so,
+            kc / kFp8Block, 0, 0);
+#else
+        (void)step;
 #endif
     };
     // the half of a step's scale word that holds its pair of scale bytes
@@ -609,20 +635,40 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
     };
     const int sa_word = 4 * (wm * 32 + (lane & 31));
     const int sb_word = BM + 2 * (wn * 32 + (lane & 31));
-    auto read_scales = [&](uint4& wa, uint2& wb, const uint32_t* sc) {
-        wa = *reinterpret_cast<const uint4*>(sc + sa_word);
-        wb = *reinterpret_cast<const uint2*>(sc + sb_word);
+    // the step's pair of scale bytes (substep 0 low, substep 1 high) of the
+    // lane's four A rows and two B rows
+    uint32_t sa[4], sb[2];
+    auto read_scales = [&](const uint32_t* sc, int step) {
+        if constexpr (kChunk) {
+            const uint16_t* q =
+                reinterpret_cast<const uint16_t*>(Sq + ((step >> 3) & 1) * 4 * (BM + BN));
+            const int h = step & 7;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sa[i] = q[8 * (sa_word + i) + h];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) sb[j] = q[8 * (sb_word + j) + h];
+        } else {
+            const uint4 wa = *reinterpret_cast<const uint4*>(sc + sa_word);
+            const uint2 wb = *reinterpret_cast<const uint2*>(sc + sb_word);
+            const uint32_t ha = hsel(step, true);
+            const uint32_t hb = hsel(step, false);
+            sa[0] = wa.x >> ha;
+            sa[1] = wa.y >> ha;
+            sa[2] = wa.z >> ha;
+            sa[3] = wa.w >> ha;
+            sb[0] = wb.x >> hb;
+            sb[1] = wb.y >> hb;
+        }
     };
 
     issue(As0, Bs0, Sc0, t_begin);
+    if constexpr (kChunk) issue_chunk(t_begin);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     i32x8 fa, fb[2], fan, fbn[2];
-    uint4 wa;
-    uint2 wb;
     fa = frag_a(As0, 0, 0);
     frag_b(fb, Bs0, 0);
-    read_scales(wa, wb, Sc0);
+    read_scales(Sc0, t_begin);
     // One step: the next step's tiles and scale words go straight into the
     // other buffers while this step runs; the A fragment of the next
     // (substep, row block) is read during the current one's two MFMAs, and
@@ -632,12 +678,10 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
     auto kstep = [&](const float* as, const float* bs, float* na, float* nb, uint32_t* nsc,
                      int t, bool live) {
         issue(na, nb, nsc, min(t + 1, t_end - 1));
+        if constexpr (kChunk) {
+            if ((t & 7) == 0 && t + 8 < t_end) issue_chunk(t + 8);
+        }
         __builtin_amdgcn_sched_barrier(0);
-        const int tt = t < t_end ? t : t_end - 1;
-        const uint32_t ha = hsel(tt, true);
-        const uint32_t hb = hsel(tt, false);
-        const uint32_t sa[4] = {wa.x >> ha, wa.y >> ha, wa.z >> ha, wa.w >> ha};
-        const uint32_t sb[2] = {wb.x >> hb, wb.y >> hb};
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
 #pragma unroll
@@ -667,7 +711,7 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
         __syncthreads();
         fa = frag_a(na, 0, 0);
         frag_b(fb, nb, 0);
-        read_scales(wa, wb, nsc);
+        read_scales(nsc, min(t + 1, t_end - 1));
     };
     for (int t = t_begin; t < t_end; t += 2) {
         kstep(As0, Bs0, As1, Bs1, Sc1, t, true);
@@ -1174,7 +1218,12 @@ hipError_t launch_gemm_kept_fp8(const void* At, int64_t ldat, const void* Bt, in
     const int64_t tilesM = (m + BM - 1) / BM;
     const int64_t tilesN = (l + BN - 1) / BN;
     const bool odd = ((int64_t)nkept * (split ? 3 : 1) * (bp / kStepBytes)) % 2 != 0;
-    auto kern = odd ? gemm_kept_fp8d_kernel<true> : gemm_kept_fp8d_kernel<false>;
+    // scale chunks of 8 steps: whole chunks per block, 16-byte aligned rows
+    // and scale area
+    const bool chunk = bp % 1024 == 0 && ldat % 16 == 0 && ldbt % 16 == 0 && scales % 16 == 0;
+    // (with chunks the step count is a multiple of 8: never odd)
+    auto kern = chunk ? gemm_kept_fp8d_kernel<false, false, true>
+                      : (odd ? gemm_kept_fp8d_kernel<true> : gemm_kept_fp8d_kernel<false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreadsK), 0, s,
                        static_cast<const uint8_t*>(At), ldat, static_cast<const uint8_t*>(Bt),
                        ldbt, scales, m, l, bp, kept, nkept, split ? 3 : 1, lo_off, scale, C, ldc,

@@ -210,7 +210,8 @@ def test_quantize_fp8_bit_exact(lines, b, nst, split):
 
 @pytest.mark.parametrize("split", [False, True])
 @pytest.mark.parametrize("m,l,b,nst", [(256, 256, 256, 5), (300, 77, 100, 3), (1, 1, 32, 1),
-                                       (513, 255, 64, 4), (64, 700, 1024, 2)])
+                                       (513, 255, 64, 4), (64, 700, 1024, 2), (300, 520, 1024, 4),
+                                       (257, 129, 2048, 3)])
 def test_gemm_kept_fp8_vs_fp64(m, l, b, nst, split):
     rng = np.random.default_rng(m * 5 + l)
     prec = "fp8x3" if split else "fp8"
@@ -273,7 +274,8 @@ def _bound_fp8(A, B, b, N, e, seed, keep, u):
     return np.sqrt(oracle.frob2(oracle.block_product(hat(At), hat(Bt).T, b, keep)))
 
 
-@pytest.mark.parametrize("m,n,l,b,N,e", [(256, 4096, 256, 256, 4, 1), (300, 1001, 77, 100, 3, 1)])
+@pytest.mark.parametrize("m,n,l,b,N,e", [(256, 4096, 256, 256, 4, 1), (300, 1001, 77, 100, 3, 1),
+                                         (300, 2600, 77, 1024, 3, 1)])
 def test_matmul_fp8_within_rounding_bound(m, n, l, b, N, e):
     seed = m + n
     A, B = synthetic.gaussian_pair(m, n, l, seed)
