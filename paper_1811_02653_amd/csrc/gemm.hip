@@ -565,8 +565,13 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
     const bool a_side = wave < 4;
     const int srow = a_side ? (p >> 7) * 128 + 32 * (p & 3) + ((p >> 2) & 31)
                             : (p >> 6) * 64 + 32 * (p & 1) + ((p >> 1) & 31);
-    const uint32_t so = a_side ? (uint32_t)((int64_t)min(srow, alast) * ldat + scales)
-                               : (uint32_t)((int64_t)min(srow, blast) * ldbt + scales);
+    // scale chunks keep rows in their natural order (entry p: row p of A,
+    // or row p - 256 of B), so that the 32 lanes of a fragment half read
+    // 16-byte-spaced entries (two lanes per bank) instead of 64-byte-spaced
+    // ones (sixteen)
+    const int crow = kChunk ? 64 * (wave & 3) + lane : srow;
+    const uint32_t so = a_side ? (uint32_t)((int64_t)min(crow, alast) * ldat + scales)
+                               : (uint32_t)((int64_t)min(crow, blast) * ldbt + scales);
     const __amdgpu_buffer_rsrc_t rs_src = a_side ? ra_src : rb_src;
     const int sbase = a_side ? 64 * (wave & 3) : BM + 64 * (wave & 3);
 
@@ -644,9 +649,9 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
                 reinterpret_cast<const uint16_t*>(Sq + ((step >> 3) & 1) * 4 * (BM + BN));
             const int h = step & 7;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) sa[i] = q[8 * (sa_word + i) + h];
+            for (int i = 0; i < 4; ++i) sa[i] = q[8 * (wm * 128 + 32 * i + (lane & 31)) + h];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) sb[j] = q[8 * (sb_word + j) + h];
+            for (int j = 0; j < 2; ++j) sb[j] = q[8 * (BM + wn * 64 + 32 * j + (lane & 31)) + h];
         } else {
             const uint4 wa = *reinterpret_cast<const uint4*>(sc + sa_word);
             const uint2 wb = *reinterpret_cast<const uint2*>(sc + sb_word);
