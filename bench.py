@@ -89,7 +89,7 @@ def parse():
     p.add_argument("--no-stress", action="store_true",
                    help="skip the independent-factor stress case")
     p.add_argument("--profile-stage", choices=["step", "sketch_A", "sketch_B", "gemm", "prepare",
-                                               "gemm_bf16", "gemm_fp8"],
+                                               "gemm_bf16", "gemm_fp8", "lib_bf16", "lib_fp8"],
                    help="run only this stage of the headline workload --steps times (after "
                         "--warmup), print nothing else: for rocprofv3 counter passes")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -489,6 +489,16 @@ def profile_stage(torch, osk, args, A, B, C, ws, keep, stream):
         prec = args.profile_stage[5:]
         QA = osk.sketch_quantize(At, b, nst, precision=prec)
         QB = osk.sketch_quantize(Bt, b, nst, precision=prec)
+    # the vendor library on a product of the block product's shape (the
+    # bench's precision_variants.library_reference), for its counters
+    La = Lb = None
+    one = torch.ones((), device=dev)
+    if args.profile_stage in ("lib_bf16", "lib_fp8"):
+        kb = osk.stored_count(N, e, keep, True) * bp
+        La = At[:, :kb].to(torch.bfloat16)
+        Lb = Bt[:, :kb].to(torch.bfloat16)
+        if args.profile_stage == "lib_fp8":
+            La, Lb = La.to(torch.float8_e4m3fn), Lb.to(torch.float8_e4m3fn)
     fns = {
         "step": lambda: osk.matmul(A, B, b, N, e, seed=args.seed, keep=keep,
                                    kept_only=args.kept_only, out=C, workspace=ws, stream=stream),
@@ -505,6 +515,9 @@ def profile_stage(torch, osk, args, A, B, C, ws, keep, stream):
                                                 keep=stored_keep, out=C, stream=stream),
         "gemm_fp8": lambda: osk.gemm_kept_prec(QA, QB, b, nst, precision="fp8",
                                                keep=stored_keep, out=C, stream=stream),
+        "lib_bf16": lambda: torch.matmul(La, Lb.t()),
+        "lib_fp8": lambda: torch._scaled_mm(La, Lb.t(), scale_a=one, scale_b=one,
+                                            out_dtype=torch.float32),
     }
     fn = fns[args.profile_stage]
     torch.cuda.synchronize()
