@@ -1172,10 +1172,14 @@ hipError_t launch_gemm_cmask(const float* At, int64_t ldat, const float* Bt, int
     if (tilesM * tilesN > 0x7fffffff || nbJ > 0x7fffffff) return hipErrorInvalidValue;
     BlockList none;
     for (int j = 0; j < OS_MAX_BLOCKS; ++j) none.idx[j] = 0;
-    hipLaunchKernelGGL((gemm_kept_kernel<PrecF32, true, true>), dim3((unsigned)(tilesM * tilesN)),
-                       dim3(kThreadsK), 0, s, At, ldat, Bt, ldbt, m, l, bp, none, 0, 1, (int64_t)0, 1.0f, C, ldc,
-                       (int32_t)tilesM, (int32_t)tilesN,
-                       CMask{cmask, cblk, (int32_t)nbJ, nst, (int32_t)tb}, SplitK{nullptr, 0});
+    // a tile's step count is (its kept blocks) * bp / 32: always even when
+    // bp / 32 is, and then the unmasked pair loop serves every tile
+    auto kern = (bp / 32) % 2 == 0 ? gemm_kept_kernel<PrecF32, true, false>
+                                   : gemm_kept_kernel<PrecF32, true, true>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tilesM * tilesN)), dim3(kThreadsK), 0, s, At, ldat,
+                       Bt, ldbt, m, l, bp, none, 0, 1, (int64_t)0, 1.0f, C, ldc, (int32_t)tilesM,
+                       (int32_t)tilesN, CMask{cmask, cblk, (int32_t)nbJ, nst, (int32_t)tb},
+                       SplitK{nullptr, 0});
     return hipGetLastError();
 }
 

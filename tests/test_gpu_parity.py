@@ -386,7 +386,8 @@ def test_error_paths_raise():
 
 @pytest.mark.parametrize("m,n,l,b,N,e", [(600, 2048, 520, 256, 3, 2),   # tiles = blocks
                                          (300, 1001, 250, 100, 3, 1),   # block < tile
-                                         (700, 1500, 640, 300, 2, 2)])  # 2 tiles per block side
+                                         (700, 1500, 640, 300, 2, 2),   # 2 tiles per block side
+                                         (200, 700, 230, 96, 3, 1)])    # odd steps per block
 def test_matmul_per_block_masks(m, n, l, b, N, e):
     seed = m + l
     A, B = synthetic.gaussian_pair(m, n, l, seed)
