@@ -115,17 +115,6 @@ __device__ __forceinline__ int direct_frag_off(int rbase, int q, int lane) {
     return rbase * 32 + 4 * ((4 * (lane >> 5) + q) ^ chunk_key(rbase));
 }
 
-// a = zero when !live (a uniform flag): a dead K step adds nothing.
-__device__ __forceinline__ void zero_unless(float4 (&a)[4], bool live) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        a[i].x = live ? a[i].x : 0.f;
-        a[i].y = live ? a[i].y : 0.f;
-        a[i].z = live ? a[i].z : 0.f;
-        a[i].w = live ? a[i].w : 0.f;
-    }
-}
-
 __device__ __forceinline__ float comp(const float4& v, int c) {
     return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
 }
@@ -208,9 +197,9 @@ struct SplitK {
     int32_t chunk;
 };
 
-// kOdd: the K step count may be odd (always with per-C-block masks, whose
-// count varies per tile): the pair loop's second step is then masked.  With
-// an even count the mask is left out (it costs about 4 % of the MFMA rate).
+// kOdd: the K step count may be odd (per-C-block masks, whose count varies
+// per tile, with an odd bp / 32; split K loops): an odd last step runs
+// alone after the step pairs.
 // Eight waves per 256x256 tile, two per SIMD: wave (wm, wn) (wm < 2,
 // wn < 4) computes rows 128 wm .. +127 and columns 64 wn .. +63 with 4x2
 // MFMA blocks of 32x32 (128 accumulators).  With two waves on a SIMD, one
@@ -370,8 +359,8 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
     // loads are pinned ahead of the MFMAs and waited for at the step's end.
     // Past the last step the tile loaded is step t_end - 1 again, a valid
     // address.  Steps run in pairs (one per buffer); when their count is odd
-    // (kOdd kernels only) the pair's second step is dead: its A fragments
-    // are zeroed, so it adds nothing.
+    // (kOdd kernels only) the last step runs alone after the pairs, from
+    // the first buffer, where the last pair loaded it.
     auto quad = [&](float4 (&a)[4], float4 (&b)[2], auto&& reads) {
         P::template mfma_quad<4, 2, 0, P::kHead>(acc, a, b);
         __builtin_amdgcn_sched_barrier(0);
@@ -380,16 +369,12 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         P::template mfma_quad<4, 2, P::kHead, P::kParts>(acc, a, b);
         __builtin_amdgcn_sched_barrier(0);
     };
-    auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t, bool live) {
+    auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t) {
         issue(na, nb, min(t + 1, t_end - 1));
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (kOdd) zero_unless(fa, live);
         quad(fa, fb, [&] { frag(ga, gb, as, bs, 1); });
-        if constexpr (kOdd) zero_unless(ga, live);
         quad(ga, gb, [&] { frag(fa, fb, as, bs, 2); });
-        if constexpr (kOdd) zero_unless(fa, live);
         quad(fa, fb, [&] { frag(ga, gb, as, bs, 3); });
-        if constexpr (kOdd) zero_unless(ga, live);
         P::template mfma_quad<4, 2, 0, P::kParts - P::kTail>(acc, ga, gb);
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_waitcnt(0);
@@ -399,9 +384,13 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         P::template mfma_quad<4, 2, P::kParts - P::kTail, P::kParts>(acc, ga, gb);
         __builtin_amdgcn_sched_barrier(0);
     };
-    for (int t = t_begin; t < t_end; t += 2) {
-        kstep(As0, Bs0, As1, Bs1, t, true);
-        kstep(As1, Bs1, As0, Bs0, t + 1, t + 1 < t_end);
+    int t = t_begin;
+    for (; t + 1 < t_end; t += 2) {
+        kstep(As0, Bs0, As1, Bs1, t);
+        kstep(As1, Bs1, As0, Bs0, t + 1);
+    }
+    if constexpr (kOdd) {
+        if (t < t_end) kstep(As0, Bs0, As1, Bs1, t);
     }
 
     // 32x32 accumulator layout: register r of lane L holds row
@@ -677,11 +666,10 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
     // One step: the next step's tiles and scale words go straight into the
     // other buffers while this step runs; the A fragment of the next
     // (substep, row block) is read during the current one's two MFMAs, and
-    // substep 1's B fragments during substep 0's last row block.  A dead
-    // step (the second of a pair when their count is odd) has its A fragments
-    // zeroed.
+    // substep 1's B fragments during substep 0's last row block.  Steps run
+    // in pairs; an odd last step (kOdd) runs alone after them.
     auto kstep = [&](const float* as, const float* bs, float* na, float* nb, uint32_t* nsc,
-                     int t, bool live) {
+                     int t) {
         issue(na, nb, nsc, min(t + 1, t_end - 1));
         if constexpr (kChunk) {
             if ((t & 7) == 0 && t + 8 < t_end) issue_chunk(t + 8);
@@ -696,9 +684,6 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
                 } else if (s2 == 0) {
                     fan = frag_a(as, 1, 0);
                     frag_b(fbn, bs, 1);
-                }
-                if constexpr (kOdd) {
-                    if (!live) fa = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
                 }
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
@@ -718,9 +703,13 @@ void gemm_kept_fp8d_kernel(const uint8_t* __restrict__ At, int64_t ldat,
         frag_b(fb, nb, 0);
         read_scales(nsc, min(t + 1, t_end - 1));
     };
-    for (int t = t_begin; t < t_end; t += 2) {
-        kstep(As0, Bs0, As1, Bs1, Sc1, t, true);
-        kstep(As1, Bs1, As0, Bs0, Sc0, t + 1, t + 1 < t_end);
+    int t = t_begin;
+    for (; t + 1 < t_end; t += 2) {
+        kstep(As0, Bs0, As1, Bs1, Sc1, t);
+        kstep(As1, Bs1, As0, Bs0, Sc0, t + 1);
+    }
+    if constexpr (kOdd) {
+        if (t < t_end) kstep(As0, Bs0, As1, Bs1, Sc1, t);
     }
 
     float* out = C;
