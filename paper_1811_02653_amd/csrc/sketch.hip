@@ -195,15 +195,15 @@ __device__ __forceinline__ void ell_build_region(const uint32_t* __restrict__ ta
     }
 }
 
-// The same region built by kBW = 4 waves (bp <= kBW4MaxBp): wave v counts
+// The same region built by kBW = 8 waves (bp <= kBWMaxBp): wave v counts
 // and scatters its own contiguous part of the window; its cursors start at
 // the entries of the earlier parts (an exclusive scan over the waves' counts
 // per bucket), so every bucket's list stays in ascending k.  LDS: per-wave
 // cursors [kBW][bp], totals [bp], group bases and lengths [qn] each.
-constexpr int kBW = 4;
-constexpr int kBW4MaxBp = 2048;
+constexpr int kBW = 8;
+constexpr int kBWMaxBp = 2048;
 
-__device__ __forceinline__ void ell_build_region4(const uint32_t* __restrict__ table, int64_t n,
+__device__ __forceinline__ void ell_build_region_waves(const uint32_t* __restrict__ table, int64_t n,
                                                   int64_t nt, int32_t bp, int32_t qn,
                                                   int32_t nwin, int64_t RC,
                                                   uint32_t* __restrict__ hdr,
@@ -314,7 +314,7 @@ __device__ __forceinline__ void ell_build_region4(const uint32_t* __restrict__ t
     }
 }
 
-__global__ __launch_bounds__(64 * kBW) void ell_build4_kernel(const uint32_t* __restrict__ table,
+__global__ __launch_bounds__(64 * kBW) void ell_buildw_kernel(const uint32_t* __restrict__ table,
                                                               int64_t n, int64_t nt, int32_t bp,
                                                               int32_t qn, int32_t nwin,
                                                               int64_t RC,
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(64 * kBW) void ell_build4_kernel(const uint32_t* __
                                                               uint16_t* __restrict__ ell,
                                                               const int32_t* __restrict__ inv) {
     extern __shared__ uint32_t sm[];
-    ell_build_region4(table, n, nt, bp, qn, nwin, RC, hdr, ell, (int)blockIdx.x,
+    ell_build_region_waves(table, n, nt, bp, qn, nwin, RC, hdr, ell, (int)blockIdx.x,
                       (int64_t)blockIdx.y, sm, inv);
 }
 
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restric
                      (int64_t)blockIdx.y, sm, inv);
 }
 
-__global__ __launch_bounds__(64 * kBW) void ell_build_batch4_kernel(
+__global__ __launch_bounds__(64 * kBW) void ell_build_batchw_kernel(
     const PrepDesc* __restrict__ descs, int32_t count, int64_t tasks) {
     extern __shared__ uint32_t sm[];
     for (int64_t t = blockIdx.x; t < tasks; t += gridDim.x) {
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(64 * kBW) void ell_build_batch4_kernel(
         });
         const PrepDesc& d = descs[p];
         const int64_t local = t - d.ell_task0;
-        ell_build_region4(d.table, d.n, d.nt, d.bp, d.qn, d.nwin, d.RC, d.hdr, d.ell,
+        ell_build_region_waves(d.table, d.n, d.nt, d.bp, d.qn, d.nwin, d.RC, d.hdr, d.ell,
                           (int)(local % d.nwin), local / d.nwin, sm, d.inv);
         __syncthreads();
     }
@@ -1230,9 +1230,9 @@ hipError_t launch_lists_batch(const PrepDesc* descs, int32_t count, int64_t task
     if (count < 1 || tasks < 1 || max_bp < 1) return hipErrorInvalidValue;
     const int32_t qn = (max_bp + 63) / 64;
     const unsigned grid = (unsigned)std::min<int64_t>(tasks, int64_t(1) << 20);
-    if (max_bp <= kBW4MaxBp) {
+    if (max_bp <= kBWMaxBp) {
         const size_t lds = (size_t)((kBW + 2) * max_bp + 2 * qn + kWin) * 4;
-        hipLaunchKernelGGL(ell_build_batch4_kernel, dim3(grid), dim3(64 * kBW), lds, s, descs,
+        hipLaunchKernelGGL(ell_build_batchw_kernel, dim3(grid), dim3(64 * kBW), lds, s, descs,
                            count, tasks);
     } else {
         const size_t lds = (size_t)(2 * max_bp + 2 * qn + kWin) * 4;
@@ -1246,9 +1246,9 @@ hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int3
                               int32_t bp, void* lists, hipStream_t s, const int32_t* inv) {
     const Plan p = plan_of(n, bp);
     const ListView v = carve_lists(lists, nblk, n, bp);
-    if (bp <= kBW4MaxBp) {
+    if (bp <= kBWMaxBp) {
         const size_t lds = (size_t)((kBW + 2) * bp + 2 * p.qn + kWin) * 4;
-        hipLaunchKernelGGL(ell_build4_kernel, dim3((unsigned)p.nwin, (unsigned)nblk),
+        hipLaunchKernelGGL(ell_buildw_kernel, dim3((unsigned)p.nwin, (unsigned)nblk),
                            dim3(64 * kBW), lds, s, table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
                            reinterpret_cast<uint16_t*>(v.ell), inv);
     } else {
