@@ -195,14 +195,19 @@ __device__ __forceinline__ void ell_build_region(const uint32_t* __restrict__ ta
     }
 }
 
-// The same region built by kBW = 8 waves (bp <= kBWMaxBp): wave v counts
+// The same region built by kBW waves (bp <= kBWMaxBp): wave v counts
 // and scatters its own contiguous part of the window; its cursors start at
 // the entries of the earlier parts (an exclusive scan over the waves' counts
 // per bucket), so every bucket's list stays in ascending k.  LDS: per-wave
-// cursors [kBW][bp], totals [bp], group bases and lengths [qn] each.
-constexpr int kBW = 8;
+// cursors [kBW][bp], totals [bp], group bases and lengths [qn] each.  The
+// single-sketch build takes 8 waves per region (full-size prepare 0.030 ms
+// against 0.041 with 4); the batch build, which strides over many regions
+// per workgroup, keeps 4 (8 were 20 % slower there).
+constexpr int kBWSingle = 8;
+constexpr int kBWBatch = 4;
 constexpr int kBWMaxBp = 2048;
 
+template <int kBW>
 __device__ __forceinline__ void ell_build_region_waves(const uint32_t* __restrict__ table, int64_t n,
                                                   int64_t nt, int32_t bp, int32_t qn,
                                                   int32_t nwin, int64_t RC,
@@ -314,7 +319,7 @@ __device__ __forceinline__ void ell_build_region_waves(const uint32_t* __restric
     }
 }
 
-__global__ __launch_bounds__(64 * kBW) void ell_buildw_kernel(const uint32_t* __restrict__ table,
+__global__ __launch_bounds__(64 * kBWSingle) void ell_buildw_kernel(const uint32_t* __restrict__ table,
                                                               int64_t n, int64_t nt, int32_t bp,
                                                               int32_t qn, int32_t nwin,
                                                               int64_t RC,
@@ -322,8 +327,8 @@ __global__ __launch_bounds__(64 * kBW) void ell_buildw_kernel(const uint32_t* __
                                                               uint16_t* __restrict__ ell,
                                                               const int32_t* __restrict__ inv) {
     extern __shared__ uint32_t sm[];
-    ell_build_region_waves(table, n, nt, bp, qn, nwin, RC, hdr, ell, (int)blockIdx.x,
-                      (int64_t)blockIdx.y, sm, inv);
+    ell_build_region_waves<kBWSingle>(table, n, nt, bp, qn, nwin, RC, hdr, ell,
+                                      (int)blockIdx.x, (int64_t)blockIdx.y, sm, inv);
 }
 
 __global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restrict__ table,
@@ -337,7 +342,7 @@ __global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restric
                      (int64_t)blockIdx.y, sm, inv);
 }
 
-__global__ __launch_bounds__(64 * kBW) void ell_build_batchw_kernel(
+__global__ __launch_bounds__(64 * kBWBatch) void ell_build_batchw_kernel(
     const PrepDesc* __restrict__ descs, int32_t count, int64_t tasks) {
     extern __shared__ uint32_t sm[];
     for (int64_t t = blockIdx.x; t < tasks; t += gridDim.x) {
@@ -346,8 +351,9 @@ __global__ __launch_bounds__(64 * kBW) void ell_build_batchw_kernel(
         });
         const PrepDesc& d = descs[p];
         const int64_t local = t - d.ell_task0;
-        ell_build_region_waves(d.table, d.n, d.nt, d.bp, d.qn, d.nwin, d.RC, d.hdr, d.ell,
-                          (int)(local % d.nwin), local / d.nwin, sm, d.inv);
+        ell_build_region_waves<kBWBatch>(d.table, d.n, d.nt, d.bp, d.qn, d.nwin, d.RC, d.hdr,
+                                         d.ell, (int)(local % d.nwin), local / d.nwin, sm,
+                                         d.inv);
         __syncthreads();
     }
 }
@@ -1231,8 +1237,8 @@ hipError_t launch_lists_batch(const PrepDesc* descs, int32_t count, int64_t task
     const int32_t qn = (max_bp + 63) / 64;
     const unsigned grid = (unsigned)std::min<int64_t>(tasks, int64_t(1) << 20);
     if (max_bp <= kBWMaxBp) {
-        const size_t lds = (size_t)((kBW + 2) * max_bp + 2 * qn + kWin) * 4;
-        hipLaunchKernelGGL(ell_build_batchw_kernel, dim3(grid), dim3(64 * kBW), lds, s, descs,
+        const size_t lds = (size_t)((kBWBatch + 2) * max_bp + 2 * qn + kWin) * 4;
+        hipLaunchKernelGGL(ell_build_batchw_kernel, dim3(grid), dim3(64 * kBWBatch), lds, s, descs,
                            count, tasks);
     } else {
         const size_t lds = (size_t)(2 * max_bp + 2 * qn + kWin) * 4;
@@ -1247,9 +1253,9 @@ hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int3
     const Plan p = plan_of(n, bp);
     const ListView v = carve_lists(lists, nblk, n, bp);
     if (bp <= kBWMaxBp) {
-        const size_t lds = (size_t)((kBW + 2) * bp + 2 * p.qn + kWin) * 4;
+        const size_t lds = (size_t)((kBWSingle + 2) * bp + 2 * p.qn + kWin) * 4;
         hipLaunchKernelGGL(ell_buildw_kernel, dim3((unsigned)p.nwin, (unsigned)nblk),
-                           dim3(64 * kBW), lds, s, table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
+                           dim3(64 * kBWSingle), lds, s, table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
                            reinterpret_cast<uint16_t*>(v.ell), inv);
     } else {
         const size_t lds = (size_t)(2 * bp + 2 * p.qn + kWin) * 4;
