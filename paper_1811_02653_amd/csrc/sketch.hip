@@ -200,10 +200,13 @@ __device__ __forceinline__ void ell_build_region(const uint32_t* __restrict__ ta
 // the entries of the earlier parts (an exclusive scan over the waves' counts
 // per bucket), so every bucket's list stays in ascending k.  LDS: per-wave
 // cursors [kBW][bp], totals [bp], group bases and lengths [qn] each.  The
-// single-sketch build takes 8 waves per region (full-size prepare 0.030 ms
-// against 0.041 with 4); the batch build, which strides over many regions
-// per workgroup, keeps 4 (8 were 20 % slower there).
+// single-sketch build takes 16 waves per region for bp <= 1024 and 8 up to
+// 2048 (full-size prepare 0.026 ms, against 0.030 with 8 and 0.041 with 4);
+// the batch build, which strides over many regions per workgroup, keeps 4
+// (8 were 20 % slower there).
 constexpr int kBWSingle = 8;
+constexpr int kBWWide = 16;            // single-sketch regions with bp <= kBWWideMaxBp
+constexpr int kBWWideMaxBp = 1024;
 constexpr int kBWBatch = 4;
 constexpr int kBWMaxBp = 2048;
 
@@ -319,16 +322,16 @@ __device__ __forceinline__ void ell_build_region_waves(const uint32_t* __restric
     }
 }
 
-__global__ __launch_bounds__(64 * kBWSingle) void ell_buildw_kernel(const uint32_t* __restrict__ table,
-                                                              int64_t n, int64_t nt, int32_t bp,
-                                                              int32_t qn, int32_t nwin,
-                                                              int64_t RC,
-                                                              uint32_t* __restrict__ hdr,
-                                                              uint16_t* __restrict__ ell,
-                                                              const int32_t* __restrict__ inv) {
+template <int kW>
+__global__ __launch_bounds__(64 * kW) void ell_buildw_kernel(const uint32_t* __restrict__ table,
+                                                             int64_t n, int64_t nt, int32_t bp,
+                                                             int32_t qn, int32_t nwin, int64_t RC,
+                                                             uint32_t* __restrict__ hdr,
+                                                             uint16_t* __restrict__ ell,
+                                                             const int32_t* __restrict__ inv) {
     extern __shared__ uint32_t sm[];
-    ell_build_region_waves<kBWSingle>(table, n, nt, bp, qn, nwin, RC, hdr, ell,
-                                      (int)blockIdx.x, (int64_t)blockIdx.y, sm, inv);
+    ell_build_region_waves<kW>(table, n, nt, bp, qn, nwin, RC, hdr, ell, (int)blockIdx.x,
+                               (int64_t)blockIdx.y, sm, inv);
 }
 
 __global__ __launch_bounds__(64) void ell_build_kernel(const uint32_t* __restrict__ table,
@@ -1252,9 +1255,14 @@ hipError_t launch_build_lists(const uint32_t* table, int64_t n, int64_t nt, int3
                               int32_t bp, void* lists, hipStream_t s, const int32_t* inv) {
     const Plan p = plan_of(n, bp);
     const ListView v = carve_lists(lists, nblk, n, bp);
-    if (bp <= kBWMaxBp) {
+    if (bp <= kBWWideMaxBp) {
+        const size_t lds = (size_t)((kBWWide + 2) * bp + 2 * p.qn + kWin) * 4;
+        hipLaunchKernelGGL(ell_buildw_kernel<kBWWide>, dim3((unsigned)p.nwin, (unsigned)nblk),
+                           dim3(64 * kBWWide), lds, s, table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
+                           reinterpret_cast<uint16_t*>(v.ell), inv);
+    } else if (bp <= kBWMaxBp) {
         const size_t lds = (size_t)((kBWSingle + 2) * bp + 2 * p.qn + kWin) * 4;
-        hipLaunchKernelGGL(ell_buildw_kernel, dim3((unsigned)p.nwin, (unsigned)nblk),
+        hipLaunchKernelGGL(ell_buildw_kernel<kBWSingle>, dim3((unsigned)p.nwin, (unsigned)nblk),
                            dim3(64 * kBWSingle), lds, s, table, n, nt, bp, p.qn, p.nwin, p.RC, v.hdr,
                            reinterpret_cast<uint16_t*>(v.ell), inv);
     } else {
