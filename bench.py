@@ -728,8 +728,8 @@ def main():
                                                      out=C1, workspace=ws1, stream=stream),
                            100, stream)
         torch.cuda.synchronize()
-        # the GPU time of one step without the host's call overhead: one call
-        # captured into a HIP graph (the path enqueues kernels only), replayed;
+        # one call captured into a HIP graph (the path enqueues kernels only)
+        # and replayed back to back, for callers that replay captured steps;
         # the replay must give the eager result bit for bit
         eager = C1.clone()
         gs = torch.cuda.Stream()
