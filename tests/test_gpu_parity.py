@@ -4,6 +4,8 @@ same seeded inputs and the same sketch.
 Tolerances (FP32 path against the FP64 oracle):
   - buckets and signs: bit-exact;
   - sketches of permutation / identity inputs (one term per bucket): bit-exact;
+  - sketches of random inputs against the FP32 sum of each bucket taken term
+    by term in ascending k (the order the bucket lists fix): bit-exact;
   - sketches of random inputs: relative Frobenius error <= 1e-6 per block
     (an FP32 sum of about n/b terms);
   - the product C: relative Frobenius error <= 1e-5.
@@ -226,6 +228,46 @@ def test_sketch_rows_in_place_spread(n, cols, b, N, e):
     out = unpad(direct, N + e, b)
     for i in range(N + e):
         assert rel(out[:, i * b:(i + 1) * b], ref[:, i * b:(i + 1) * b]) <= SKETCH_TOL
+
+
+def _fp32_ascending_sums(X, h, s, b):
+    """Every bucket of every block summed in FP32, one rounding per term, in
+    ascending k: out[i, c, r] = (...((0 + s[i,k0] X[r,k0]) + s[i,k1] X[r,k1])
+    ...) over the k with h[i, k] = c, k0 < k1 < ...  (X: lines x n)."""
+    nblk, n = h.shape
+    acc = np.zeros((nblk, b, X.shape[0]), np.float32)
+    blk = np.arange(nblk)
+    for k in range(n):
+        acc[blk, h[:, k]] += s[:, k, None].astype(np.float32) * X[None, :, k]
+    return acc
+
+
+@pytest.mark.parametrize("n,b", [
+    (20000, 1000),    # block stride <= 1024: lists built by 16 waves per region
+    (20000, 1500),    # <= 2048: 8 waves per region
+    (9500, 2500),     # > 2048: one wave per region
+])
+def test_sketch_sums_each_bucket_in_ascending_k(n, b):
+    # The bucket lists hold every bucket's positions in ascending k (any
+    # number of waves builds the same lists), and the sketch kernel adds a
+    # bucket's terms in list order across the windows: the FP32 sketch
+    # equals the FP32 sum taken term by term in ascending k, bit for bit,
+    # reading rows (A S) and reading columns in place (S^T B).
+    N, e, seed = 2, 1, n + b
+    rng = np.random.default_rng(seed)
+    h, s = oracle.hash_tables(seed, N + e, n, b)
+    X = rng.standard_normal((8, n)).astype(np.float32)
+    ref = _fp32_ascending_sums(X, h, s, b)
+    out = unpad(host(osk.sketch_cols(dev(X), b, N, e, seed=seed)), N + e, b)
+    for i in range(N + e):
+        np.testing.assert_array_equal(out[:, i * b:(i + 1) * b], ref[i].T)
+    Y = rng.standard_normal((n, 12)).astype(np.float32)
+    Yd = dev(Y, ld=16)
+    assert Yd.data_ptr() % 16 == 0
+    ref = _fp32_ascending_sums(np.ascontiguousarray(Y.T), h, s, b)
+    out = unpad(host(osk.sketch_rows(Yd, b, N, e, seed=seed)), N + e, b)
+    for i in range(N + e):
+        np.testing.assert_array_equal(out[:, i * b:(i + 1) * b], ref[i].T)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x3", "fp8", "fp8x3"])
