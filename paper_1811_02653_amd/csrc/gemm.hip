@@ -355,8 +355,11 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
     // quads run; each quad's fragments are read during the previous quad's
     // MFMAs, after its first kHead parts, and the last quad's final kTail
     // parts run after the step's barrier, behind the reads of the next
-    // step's first fragments (scheduling barriers pin this order).  The
-    // loads are pinned ahead of the MFMAs and waited for at the step's end.
+    // step's first fragments (scheduling barriers pin this order).  The A
+    // tile's loads are issued at the step's start and the B tile's after the
+    // first quad, which halves the burst of line requests a CU sends at once
+    // (the same loads; 2-3 % faster for BF16, 1 % for FP32); all are waited
+    // for at the step's end.
     // Past the last step the tile loaded is step t_end - 1 again, a valid
     // address.  Steps run in pairs (one per buffer); when their count is odd
     // (kOdd kernels only) the last step runs alone after the pairs, from
@@ -370,9 +373,13 @@ void gemm_kept_kernel(const void* __restrict__ At, int64_t ldat, const void* __r
         __builtin_amdgcn_sched_barrier(0);
     };
     auto kstep = [&](const float* as, const float* bs, float* na, float* nb, int t) {
-        issue(na, nb, min(t + 1, t_end - 1));
+        uint32_t ka, kb;
+        step_ab(min(t + 1, t_end - 1), ka, kb);
+        direct_issue<4>(ra_src, na, va, ka, wave);
         __builtin_amdgcn_sched_barrier(0);
         quad(fa, fb, [&] { frag(ga, gb, as, bs, 1); });
+        direct_issue<4>(rb_src, nb, vb, kb, wave);
+        __builtin_amdgcn_sched_barrier(0);
         quad(ga, gb, [&] { frag(fa, fb, as, bs, 2); });
         quad(fa, fb, [&] { frag(ga, gb, as, bs, 3); });
         P::template mfma_quad<4, 2, 0, P::kParts - P::kTail>(acc, ga, gb);
